@@ -1,0 +1,817 @@
+/*
+ * Plain FP64 CPU reference of the explicit finite-volume Euler residual and
+ * the SSP-RK3 time update on structured multi-block grids.
+ *
+ * TEST INFRASTRUCTURE ONLY.  The test-suite, the package smoke check and the
+ * benchmark's CPU-baseline leg load it; the product path never does.  It
+ * shares no code with the HIP library.  It is written to be read against the
+ * paper, not to be fast: every face flux is formed once from ghost-padded
+ * arrays, every cell residual is summed from stored face fluxes, and the
+ * stages run one after another over whole arrays.  OpenMP splits the loops
+ * over independent faces or cells only; every sum over cells runs serially in
+ * natural order (block, k, j, i).
+ *
+ * Where it follows the paper:
+ *   Q and the inviscid normal flux F_{i,n} ........ Sec. 2 (conserved vector, flux definitions)
+ *   semi-discrete form |Omega| dU/dt + R = 0 ....... Sec. 3.1, Eq. (spatial_residual)
+ *   R = sum over the f faces of F_{i,n} ds ......... Sec. 3.1, Eq. (residual), no source, no viscous part
+ *   explicit RK in Butcher form ..................... Sec. 3.2, Eq. (runge_kutta)
+ *   MUSCL face states with limiter values Psi ...... Sec. 5, Eq. (flux)
+ *   ghost cells refreshed before every RK substep .. Sec. 4 (workflow) and Sec. 5 (ghost extrapolation)
+ *   cell-update counting (ssspnt) ................... Sec. 7, Eq. (ssspnt)
+ * Readings where the paper is silent (named at each function): Roe's flux with
+ * Harten's entropy fix, minmod limiter, SSP-RK3 in Shu-Osher form, a global
+ * CFL time step from U^n, the ghost rules per boundary kind, an RMS residual
+ * norm.
+ */
+#include "fv_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef long long i64;
+
+typedef struct {
+  int ni, nj, nk;      /* interior cells */
+  int pi, pj, pk;      /* padded extents (2 ghost layers per side) */
+  int gk;              /* ghost offset along k: 2 in 3D, 0 in 2D */
+  i64 npad;            /* padded cells per variable */
+  i64 ncell;           /* interior cells */
+  double* xn;          /* 2D node coordinates (owned copy) or NULL when uniform */
+  double* yn;
+  double h[3];
+  orc_bc bc[6];
+  double* q;           /* nv * npad: state of the current stage, with ghosts */
+  double* qn;          /* nv * npad: U^n */
+  double* res;         /* nv * ncell: residual */
+  double* flux;        /* nv * (faces of one direction): area-weighted face fluxes */
+  i64 nflux;           /* capacity of flux per variable */
+} blk_t;
+
+struct orc_grid {
+  int ndim, nv, nblocks;
+  double gamma;
+  blk_t* b;
+  i64 ncells;
+  /* time-marching record */
+  double t, dt_last, raw_min;
+  i64 steps;
+  double norms[5], norm, norm_first, drop;
+  int have_first, physical;
+};
+
+/* ------------------------------------------------------------------------ */
+/* indexing                                                                  */
+/* ------------------------------------------------------------------------ */
+static inline i64 pidx(const blk_t* b, int i, int j, int k) {
+  return ((i64)(k + b->gk) * b->pj + (j + 2)) * b->pi + (i + 2);
+}
+static inline i64 cidx(const blk_t* b, int i, int j, int k) {
+  return ((i64)k * b->nj + j) * b->ni + i;
+}
+static inline int ext(const blk_t* b, int d) { return d == 0 ? b->ni : (d == 1 ? b->nj : b->nk); }
+
+/* ------------------------------------------------------------------------ */
+/* geometry (Sec. 3.1: face area ds, outward unit normal, volume |Omega|)   */
+/* ------------------------------------------------------------------------ */
+static inline double X(const blk_t* b, int i, int j) { return b->xn[(i64)j * (b->ni + 1) + i]; }
+static inline double Y(const blk_t* b, int i, int j) { return b->yn[(i64)j * (b->ni + 1) + i]; }
+
+/* Area vector of face (i,j,k) along direction d, pointing towards +index.
+ * Face (i,j,k) of direction 0 separates cells (i-1,j,k) and (i,j,k).
+ * 2D: the face is the segment between two nodes; its area vector is that
+ * segment turned by -90 degrees (length = face length, per unit depth). */
+static void face_vec(const blk_t* b, int nd, int d, int i, int j, int k, double S[3]) {
+  (void)k;
+  S[0] = S[1] = S[2] = 0.0;
+  if (b->xn) {
+    if (d == 0) {
+      S[0] = Y(b, i, j + 1) - Y(b, i, j);
+      S[1] = -(X(b, i, j + 1) - X(b, i, j));
+    } else {
+      S[0] = -(Y(b, i + 1, j) - Y(b, i, j));
+      S[1] = X(b, i + 1, j) - X(b, i, j);
+    }
+    return;
+  }
+  if (nd == 2) {
+    S[d] = (d == 0) ? b->h[1] : b->h[0];
+  } else {
+    S[d] = (d == 0) ? b->h[1] * b->h[2] : (d == 1 ? b->h[0] * b->h[2] : b->h[0] * b->h[1]);
+  }
+}
+
+/* Cell volume: half the cross product of the two diagonals (2D), or hx*hy[*hz]. */
+static double cell_vol(const blk_t* b, int nd, int i, int j, int k) {
+  (void)k;
+  if (b->xn) {
+    double a = (X(b, i + 1, j + 1) - X(b, i, j)) * (Y(b, i, j + 1) - Y(b, i + 1, j));
+    double c = (X(b, i, j + 1) - X(b, i + 1, j)) * (Y(b, i + 1, j + 1) - Y(b, i, j));
+    return 0.5 * (a - c);
+  }
+  return nd == 2 ? b->h[0] * b->h[1] : b->h[0] * b->h[1] * b->h[2];
+}
+
+/* ------------------------------------------------------------------------ */
+/* gas relations and the inviscid normal flux (Sec. 2)                      */
+/* ------------------------------------------------------------------------ */
+static void primitives(const double* q, int nd, double g, double* rho, double v[3], double* p,
+                       double* H) {
+  double ke = 0.0;
+  *rho = q[0];
+  v[0] = v[1] = v[2] = 0.0;
+  for (int a = 0; a < nd; ++a) {
+    v[a] = q[1 + a] / q[0];
+    ke += v[a] * v[a];
+  }
+  *p = (g - 1.0) * (q[nd + 1] - 0.5 * q[0] * ke);
+  *H = (q[nd + 1] + *p) / q[0];
+}
+
+/* F_{i,n} = (rho V_n, rho u V_n + n_x p, ..., rho h_t V_n) with V_n = n . u */
+static void normal_flux(const double* q, const double* n, int nd, double g, double* F) {
+  double rho, v[3], p, H;
+  primitives(q, nd, g, &rho, v, &p, &H);
+  double Vn = 0.0;
+  for (int a = 0; a < nd; ++a) Vn += v[a] * n[a];
+  F[0] = rho * Vn;
+  for (int a = 0; a < nd; ++a) F[1 + a] = rho * v[a] * Vn + n[a] * p;
+  F[nd + 1] = rho * H * Vn;
+}
+
+static void cons_from_prim(const double prim[5], int nd, double g, double* q) {
+  double ke = 0.0;
+  q[0] = prim[0];
+  for (int a = 0; a < nd; ++a) {
+    q[1 + a] = prim[0] * prim[1 + a];
+    ke += prim[1 + a] * prim[1 + a];
+  }
+  q[nd + 1] = prim[4] / (g - 1.0) + 0.5 * prim[0] * ke;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Roe's approximate Riemann solver (the paper names no flux function; Roe  */
+/* is the reading taken), written as the explicit sum over waves            */
+/*     D = sum_k |lambda_k| alpha_k r_k                                     */
+/* with Roe-averaged eigenvalues lambda, wave strengths alpha and right     */
+/* eigenvectors r of the normal-flux Jacobian.  mode 0: |lambda| with       */
+/* Harten's fix on the two acoustic waves (delta = entropy_fix * c);        */
+/* mode 1: signed lambda (then D = F(Q_R).n - F(Q_L).n, Roe's property);    */
+/* mode 2: lambda = 1 (then D = Q_R - Q_L, the wave decomposition).          */
+/* ------------------------------------------------------------------------ */
+static double harten(double l, double delta) {
+  l = fabs(l);
+  if (delta > 0.0 && l < delta) l = (l * l + delta * delta) / (2.0 * delta);
+  return l;
+}
+
+static void roe_waves(const double* qL, const double* qR, const double* n, int nd, double g,
+                      double efix, int mode, double* D) {
+  double rL, vL[3], pL, HL, rR, vR[3], pR, HR;
+  primitives(qL, nd, g, &rL, vL, &pL, &HL);
+  primitives(qR, nd, g, &rR, vR, &pR, &HR);
+
+  /* Roe averages */
+  double Rt = sqrt(rR / rL);
+  double rho_t = Rt * rL;
+  double ut[3] = {0.0, 0.0, 0.0};
+  double q2 = 0.0, Vn = 0.0;
+  for (int a = 0; a < nd; ++a) {
+    ut[a] = (vL[a] + Rt * vR[a]) / (1.0 + Rt);
+    q2 += ut[a] * ut[a];
+    Vn += ut[a] * n[a];
+  }
+  double Ht = (HL + Rt * HR) / (1.0 + Rt);
+  double c2 = (g - 1.0) * (Ht - 0.5 * q2);
+  double c = sqrt(c2);
+
+  /* jumps of the primitive variables */
+  double drho = rR - rL, dp = pR - pL, du[3] = {0.0, 0.0, 0.0}, dVn = 0.0, udu = 0.0;
+  for (int a = 0; a < nd; ++a) {
+    du[a] = vR[a] - vL[a];
+    dVn += du[a] * n[a];
+    udu += ut[a] * du[a];
+  }
+
+  /* eigenvalues: V_n - c, V_n (entropy and shear waves), V_n + c */
+  double l1 = Vn - c, l2 = Vn, l5 = Vn + c;
+  if (mode == 0) {
+    l1 = harten(l1, efix * c);
+    l2 = fabs(l2);
+    l5 = harten(l5, efix * c);
+  } else if (mode == 2) {
+    l1 = l2 = l5 = 1.0;
+  }
+
+  /* wave strengths */
+  double a1 = (dp - rho_t * c * dVn) / (2.0 * c2);
+  double a5 = (dp + rho_t * c * dVn) / (2.0 * c2);
+  double a2 = drho - dp / c2;
+
+  /* acoustic wave  (1, u - c n, H - c V_n)
+   * entropy wave   (1, u, |u|^2/2)
+   * shear waves    rho (0, du - dV_n n, u.du - V_n dV_n)
+   * acoustic wave  (1, u + c n, H + c V_n) */
+  D[0] = l1 * a1 + l2 * a2 + l5 * a5;
+  for (int a = 0; a < nd; ++a)
+    D[1 + a] = l1 * a1 * (ut[a] - c * n[a]) + l2 * (a2 * ut[a] + rho_t * (du[a] - dVn * n[a])) +
+               l5 * a5 * (ut[a] + c * n[a]);
+  D[nd + 1] = l1 * a1 * (Ht - c * Vn) + l2 * (a2 * 0.5 * q2 + rho_t * (udu - Vn * dVn)) +
+              l5 * a5 * (Ht + c * Vn);
+}
+
+/* Numerical flux per unit area: F = (F(Q_L).n + F(Q_R).n)/2 - D/2. */
+static void roe_flux(const double* qL, const double* qR, const double* n, int nd, double g,
+                     double efix, double* F) {
+  double FL[5], FR[5], D[5];
+  normal_flux(qL, n, nd, g, FL);
+  normal_flux(qR, n, nd, g, FR);
+  roe_waves(qL, qR, n, nd, g, efix, 0, D);
+  for (int v = 0; v < nd + 2; ++v) F[v] = 0.5 * (FL[v] + FR[v]) - 0.5 * D[v];
+}
+
+void orc_roe(const double* qL, const double* qR, const double* n, int nd, double gamma,
+             double entropy_fix, int mode, double* out) {
+  if (mode < 0) {
+    roe_flux(qL, qR, n, nd, gamma, entropy_fix, out);
+  } else if (mode == 3) {
+    normal_flux(qL, n, nd, gamma, out);
+  } else {
+    roe_waves(qL, qR, n, nd, gamma, entropy_fix, mode, out);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* MUSCL extrapolation, Sec. 5, Eq. (flux).  For the face between cells m   */
+/* and m+1, with Q = (Q_{m-1}, Q_m, Q_{m+1}, Q_{m+2}):                       */
+/*   Q^L = Q_m     + eps/4 [(1-k) Psi+_{m-1/2} (Q_m - Q_{m-1})              */
+/*                        + (1+k) Psi-_{m+1/2} (Q_{m+1} - Q_m)]             */
+/*   Q^R = Q_{m+1} - eps/4 [(1+k) Psi+_{m+1/2} (Q_{m+1} - Q_m)              */
+/*                        + (1-k) Psi-_{m+3/2} (Q_{m+2} - Q_{m+1})]         */
+/* Reading of the limiter values (the paper only calls them limiter         */
+/* function values): Psi+_{m-1/2} = Psi(r) with r = (Q_{m+1}-Q_m)/(Q_m -    */
+/* Q_{m-1}), Psi-_{m+1/2} = Psi(r) with r = (Q_m - Q_{m-1})/(Q_{m+1}-Q_m),  */
+/* and likewise one cell on for Q^R.  Psi is minmod, Psi(r) = max(0,        */
+/* min(1, r)); the unlimited scheme takes Psi = 1 and the first-order       */
+/* scheme eps = 0.  The product Psi(num/den) * den is what enters; for a    */
+/* zero den it is taken as its limit 0 (minmod is bounded by 1).            */
+/* ------------------------------------------------------------------------ */
+static double psi_times(int limiter, double num, double den) {
+  if (limiter == ORC_UNLIMITED) return den;
+  if (den == 0.0) return 0.0;
+  double r = num / den;
+  double psi = r < 1.0 ? r : 1.0;
+  if (psi < 0.0) psi = 0.0;
+  return psi * den;
+}
+
+static void muscl(const double q[4], int limiter, double eps, double kappa, double* qL,
+                  double* qR) {
+  if (limiter == ORC_FIRST_ORDER) eps = 0.0;
+  double dm = q[1] - q[0]; /* Q_m     - Q_{m-1} */
+  double d0 = q[2] - q[1]; /* Q_{m+1} - Q_m     */
+  double dp = q[3] - q[2]; /* Q_{m+2} - Q_{m+1} */
+  *qL = q[1] + 0.25 * eps *
+                   ((1.0 - kappa) * psi_times(limiter, d0, dm) +
+                    (1.0 + kappa) * psi_times(limiter, dm, d0));
+  *qR = q[2] - 0.25 * eps *
+                   ((1.0 + kappa) * psi_times(limiter, dp, d0) +
+                    (1.0 - kappa) * psi_times(limiter, d0, dp));
+}
+
+void orc_reconstruct(const double* q4, int limiter, double eps, double kappa, double* qL,
+                     double* qR) {
+  muscl(q4, limiter, eps, kappa, qL, qR);
+}
+
+/* ------------------------------------------------------------------------ */
+/* ghost cells (2 layers), refreshed before every residual evaluation.      */
+/* Readings of the boundary rules (the paper names only ghost extrapolation */
+/* and inter-block exchange):                                                */
+/*   PERIODIC  ghost = interior cell the same distance in from the opposite  */
+/*             face of the same block                                        */
+/*   BLOCK     ghost = neighbour block's interior cell the same distance in  */
+/*             from its matching face (1:1 points, same orientation)         */
+/*   INFLOW    ghost = Q of the prescribed primitive state                   */
+/*   EXTRAP    ghost = nearest interior cell (zeroth-order extrapolation)    */
+/*   SLIPWALL  ghost g = interior cell g-1 from the wall with its momentum   */
+/*             mirrored about the unit normal of that wall face; rho and     */
+/*             rho*e_t copied                                                */
+/* Corner ghosts are never read (the stencil is one direction at a time).   */
+/* ------------------------------------------------------------------------ */
+static void set3(int d, int along, int t1, int t2, int* i, int* j, int* k) {
+  if (d == 0) { *i = along; *j = t1; *k = t2; }
+  else if (d == 1) { *i = t1; *j = along; *k = t2; }
+  else { *i = t1; *j = t2; *k = along; }
+}
+static void trans_ext(const blk_t* b, int d, int* n1, int* n2) {
+  if (d == 0) { *n1 = b->nj; *n2 = b->nk; }
+  else if (d == 1) { *n1 = b->ni; *n2 = b->nk; }
+  else { *n1 = b->ni; *n2 = b->nj; }
+}
+
+/* ghost value of block b, face f, layer g (1 or 2), transverse (t1, t2) */
+static void ghost_value(const orc_grid* G, int bi, int f, int g, int t1, int t2, double* out) {
+  const blk_t* b = &G->b[bi];
+  const int nd = G->ndim, nv = G->nv;
+  const int d = f / 2, side = f % 2, n = ext(b, d);
+  const orc_bc* bc = &b->bc[f];
+  const blk_t* src = b;
+  int along;
+  int i, j, k;
+  switch (bc->kind) {
+    case ORC_PERIODIC:
+      along = side == 0 ? n - g : g - 1;
+      break;
+    case ORC_BLOCK:
+      src = &G->b[bc->nbr_block];
+      along = side == 0 ? ext(src, d) - g : g - 1;
+      break;
+    case ORC_INFLOW:
+      cons_from_prim(bc->prim, nd, G->gamma, out);
+      return;
+    case ORC_EXTRAP:
+      along = side == 0 ? 0 : n - 1;
+      break;
+    case ORC_SLIPWALL:
+      along = side == 0 ? g - 1 : n - g;
+      break;
+    default:
+      for (int v = 0; v < nv; ++v) out[v] = NAN;
+      return;
+  }
+  set3(d, along, t1, t2, &i, &j, &k);
+  i64 p = pidx(src, i, j, k);
+  for (int v = 0; v < nv; ++v) out[v] = src->q[v * src->npad + p];
+  if (bc->kind == ORC_SLIPWALL) {
+    double S[3];
+    int wi, wj, wk;
+    set3(d, side == 0 ? 0 : n, t1, t2, &wi, &wj, &wk);
+    face_vec(b, nd, d, wi, wj, wk, S);
+    double A = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+    double nh[3] = {S[0] / A, S[1] / A, S[2] / A};
+    double mn = 0.0;
+    for (int a = 0; a < nd; ++a) mn += out[1 + a] * nh[a];
+    for (int a = 0; a < nd; ++a) out[1 + a] -= 2.0 * mn * nh[a];
+  }
+}
+
+static void fill_ghosts(orc_grid* G) {
+  const int nd = G->ndim, nv = G->nv;
+  for (int bi = 0; bi < G->nblocks; ++bi) {
+    blk_t* b = &G->b[bi];
+    for (int f = 0; f < 2 * nd; ++f) {
+      const int d = f / 2, side = f % 2, n = ext(b, d);
+      int n1, n2;
+      trans_ext(b, d, &n1, &n2);
+      for (int t2 = 0; t2 < n2; ++t2)
+        for (int t1 = 0; t1 < n1; ++t1)
+          for (int g = 1; g <= 2; ++g) {
+            double val[5];
+            ghost_value(G, bi, f, g, t1, t2, val);
+            int i, j, k;
+            set3(d, side == 0 ? -g : n - 1 + g, t1, t2, &i, &j, &k);
+            i64 p = pidx(b, i, j, k);
+            for (int v = 0; v < nv; ++v) b->q[v * b->npad + p] = val[v];
+          }
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* residual, Sec. 3.1, Eq. (residual) with no source and no viscous part:   */
+/*   R_cell = sum over its f faces of F_{i,n} ds (outward normals).         */
+/* Each face flux is formed once, stored times its area, then each cell     */
+/* sums, direction by direction (i, j, k), the flux leaving through its     */
+/* +face minus the flux entering through its -face.                          */
+/* ------------------------------------------------------------------------ */
+static void face_flux_at(const orc_grid* G, const blk_t* b, const orc_params* P, int d, int i,
+                         int j, int k, double* F) {
+  const int nd = G->ndim, nv = G->nv;
+  int e[3] = {0, 0, 0};
+  e[d] = 1;
+  double qL[5], qR[5];
+  for (int v = 0; v < nv; ++v) {
+    const double* q = b->q + (i64)v * b->npad;
+    double s[4];
+    for (int m = 0; m < 4; ++m) {
+      int o = m - 2; /* cells f-2, f-1, f, f+1 along d */
+      s[m] = q[pidx(b, i + o * e[0], j + o * e[1], k + o * e[2])];
+    }
+    muscl(s, P->limiter, P->eps, P->kappa, &qL[v], &qR[v]);
+  }
+  double S[3];
+  face_vec(b, nd, d, i, j, k, S);
+  double A = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]);
+  double n[3] = {S[0] / A, S[1] / A, S[2] / A};
+  double Fu[5];
+  roe_flux(qL, qR, n, nd, G->gamma, P->entropy_fix, Fu);
+  for (int v = 0; v < nv; ++v) F[v] = Fu[v] * A;
+}
+
+static void residual_block(const orc_grid* G, blk_t* b, const orc_params* P, double* scale) {
+  const int nd = G->ndim, nv = G->nv;
+  memset(b->res, 0, sizeof(double) * (size_t)nv * (size_t)b->ncell);
+  if (scale) memset(scale, 0, sizeof(double) * (size_t)nv * (size_t)b->ncell);
+  for (int d = 0; d < nd; ++d) {
+    const int fi = b->ni + (d == 0), fj = b->nj + (d == 1), fk = b->nk + (d == 2);
+    const i64 nf = (i64)fi * fj * fk;
+    double* fl = b->flux;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < fk; ++k)
+      for (int j = 0; j < fj; ++j)
+        for (int i = 0; i < fi; ++i) {
+          double F[5];
+          face_flux_at(G, b, P, d, i, j, k, F);
+          i64 f = ((i64)k * fj + j) * fi + i;
+          for (int v = 0; v < nv; ++v) fl[v * nf + f] = F[v];
+        }
+    int e[3] = {0, 0, 0};
+    e[d] = 1;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < b->nk; ++k)
+      for (int j = 0; j < b->nj; ++j)
+        for (int i = 0; i < b->ni; ++i) {
+          i64 c = cidx(b, i, j, k);
+          i64 fm = ((i64)k * fj + j) * fi + i;
+          i64 fp = ((i64)(k + e[2]) * fj + (j + e[1])) * fi + (i + e[0]);
+          for (int v = 0; v < nv; ++v) {
+            b->res[v * b->ncell + c] += fl[v * nf + fp] - fl[v * nf + fm];
+            if (scale) scale[v * b->ncell + c] += fabs(fl[v * nf + fp]) + fabs(fl[v * nf + fm]);
+          }
+        }
+  }
+}
+
+static void residual_all(orc_grid* G, const orc_params* P, double** scales) {
+  fill_ghosts(G);
+  for (int bi = 0; bi < G->nblocks; ++bi)
+    residual_block(G, &G->b[bi], P, scales ? scales[bi] : NULL);
+}
+
+/* RMS of R/|Omega| per variable over every interior cell of every block,
+ * in natural order; combined norm sqrt(sum_v (r_v / qref_v)^2).           */
+static void norms_of_residual(orc_grid* G, const orc_params* P, double* norms, double* comb) {
+  const int nd = G->ndim, nv = G->nv;
+  double s[5] = {0, 0, 0, 0, 0};
+  for (int bi = 0; bi < G->nblocks; ++bi) {
+    blk_t* b = &G->b[bi];
+    for (int k = 0; k < b->nk; ++k)
+      for (int j = 0; j < b->nj; ++j)
+        for (int i = 0; i < b->ni; ++i) {
+          double vol = cell_vol(b, nd, i, j, k);
+          i64 c = cidx(b, i, j, k);
+          for (int v = 0; v < nv; ++v) {
+            double r = b->res[v * b->ncell + c] / vol;
+            s[v] += r * r;
+          }
+        }
+  }
+  double cs = 0.0;
+  for (int v = 0; v < 5; ++v) norms[v] = 0.0;
+  for (int v = 0; v < nv; ++v) {
+    norms[v] = sqrt(s[v] / (double)G->ncells);
+    double qv = P->qref[v] != 0.0 ? P->qref[v] : 1.0;
+    cs += (norms[v] / qv) * (norms[v] / qv);
+  }
+  *comb = sqrt(cs);
+}
+
+/* ------------------------------------------------------------------------ */
+/* time step (reading: global CFL step from U^n).  For each cell the local  */
+/* limit is |Omega| / sum_d (|u . Sbar_d| + c |Sbar_d|), Sbar_d the mean of */
+/* the cell's two face vectors of direction d; dt = CFL * min over every    */
+/* cell of every block.  The state is also checked: rho > 0, p > 0, finite. */
+/* ------------------------------------------------------------------------ */
+int orc_spectral_min(orc_grid* G, double* raw_min) {
+  const int nd = G->ndim, nv = G->nv;
+  double mn = INFINITY;
+  int ok = 1;
+  for (int bi = 0; bi < G->nblocks; ++bi) {
+    blk_t* b = &G->b[bi];
+    for (int k = 0; k < b->nk; ++k)
+      for (int j = 0; j < b->nj; ++j)
+        for (int i = 0; i < b->ni; ++i) {
+          double q[5], rho, v[3], p, H;
+          i64 pp = pidx(b, i, j, k);
+          for (int a = 0; a < nv; ++a) {
+            q[a] = b->q[a * b->npad + pp];
+            if (!isfinite(q[a])) ok = 0;
+          }
+          primitives(q, nd, G->gamma, &rho, v, &p, &H);
+          if (!(rho > 0.0) || !(p > 0.0)) {
+            ok = 0;
+            continue;
+          }
+          double c = sqrt(G->gamma * p / rho);
+          double lam = 0.0;
+          for (int d = 0; d < nd; ++d) {
+            double Sm[3], Sp[3];
+            int e[3] = {0, 0, 0};
+            e[d] = 1;
+            face_vec(b, nd, d, i, j, k, Sm);
+            face_vec(b, nd, d, i + e[0], j + e[1], k + e[2], Sp);
+            double Sb[3] = {0.5 * (Sm[0] + Sp[0]), 0.5 * (Sm[1] + Sp[1]), 0.5 * (Sm[2] + Sp[2])};
+            double us = v[0] * Sb[0] + v[1] * Sb[1] + v[2] * Sb[2];
+            lam += fabs(us) + c * sqrt(Sb[0] * Sb[0] + Sb[1] * Sb[1] + Sb[2] * Sb[2]);
+          }
+          double loc = cell_vol(b, nd, i, j, k) / lam;
+          if (loc < mn) mn = loc;
+        }
+  }
+  *raw_min = mn;
+  G->raw_min = mn;
+  G->physical = ok;
+  return ok ? ORC_OK : ORC_E_NONPHYSICAL;
+}
+
+/* ------------------------------------------------------------------------ */
+/* SSP-RK3 (Shu-Osher form), the explicit RK of Sec. 3.2, Eq. (runge_kutta) */
+/* with c = (0, 1, 1/2), a21 = 1, a31 = a32 = 1/4, b = (1/6, 1/6, 2/3) and  */
+/* the step scaled by 1/|Omega| as Eq. (spatial_residual) requires:         */
+/*   U1 = U^n + dt L(U^n)                                                   */
+/*   U2 = 3/4 U^n + 1/4 (U1 + dt L(U1))                                     */
+/*   U^{n+1} = 1/3 U^n + 2/3 (U2 + dt L(U2)),   L(U) = -R(U)/|Omega|.       */
+/* Ghosts are refreshed before every L.  Norms come from R(U^n).            */
+/* ------------------------------------------------------------------------ */
+static const double RK_A[3] = {0.0, 0.75, 1.0 / 3.0};
+static const double RK_B[3] = {1.0, 0.25, 2.0 / 3.0};
+
+static void rk3_step(orc_grid* G, const orc_params* P, double dt) {
+  const int nd = G->ndim, nv = G->nv;
+  for (int bi = 0; bi < G->nblocks; ++bi) {
+    blk_t* b = &G->b[bi];
+    memcpy(b->qn, b->q, sizeof(double) * (size_t)nv * (size_t)b->npad);
+  }
+  for (int s = 0; s < 3; ++s) {
+    residual_all(G, P, NULL);
+    if (s == 0) norms_of_residual(G, P, G->norms, &G->norm);
+    for (int bi = 0; bi < G->nblocks; ++bi) {
+      blk_t* b = &G->b[bi];
+#pragma omp parallel for collapse(2) schedule(static)
+      for (int k = 0; k < b->nk; ++k)
+        for (int j = 0; j < b->nj; ++j)
+          for (int i = 0; i < b->ni; ++i) {
+            double vol = cell_vol(b, nd, i, j, k);
+            i64 c = cidx(b, i, j, k), p = pidx(b, i, j, k);
+            for (int v = 0; v < nv; ++v) {
+              double un = b->qn[v * b->npad + p];
+              double us = b->q[v * b->npad + p];
+              double r = b->res[v * b->ncell + c];
+              b->q[v * b->npad + p] = RK_A[s] * un + RK_B[s] * (us - dt / vol * r);
+            }
+          }
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* public entry points                                                      */
+/* ------------------------------------------------------------------------ */
+orc_grid* orc_create(int ndim, int nblocks, const orc_block_desc* desc, double gamma) {
+  if ((ndim != 2 && ndim != 3) || nblocks <= 0 || !desc) return NULL;
+  orc_grid* G = (orc_grid*)calloc(1, sizeof(orc_grid));
+  if (!G) return NULL;
+  G->ndim = ndim;
+  G->nv = ndim + 2;
+  G->nblocks = nblocks;
+  G->gamma = gamma;
+  G->b = (blk_t*)calloc((size_t)nblocks, sizeof(blk_t));
+  if (!G->b) { free(G); return NULL; }
+  for (int bi = 0; bi < nblocks; ++bi) {
+    const orc_block_desc* d = &desc[bi];
+    blk_t* b = &G->b[bi];
+    b->ni = d->ni;
+    b->nj = d->nj;
+    b->nk = ndim == 3 ? d->nk : 1;
+    if (b->ni <= 0 || b->nj <= 0 || b->nk <= 0) { orc_destroy(G); return NULL; }
+    b->pi = b->ni + 4;
+    b->pj = b->nj + 4;
+    b->pk = ndim == 3 ? b->nk + 4 : 1;
+    b->gk = ndim == 3 ? 2 : 0;
+    b->npad = (i64)b->pi * b->pj * b->pk;
+    b->ncell = (i64)b->ni * b->nj * b->nk;
+    for (int a = 0; a < 3; ++a) b->h[a] = d->h[a];
+    memcpy(b->bc, d->bc, sizeof(b->bc));
+    if (ndim == 2 && d->x && d->y) {
+      size_t nn = (size_t)(b->ni + 1) * (size_t)(b->nj + 1);
+      b->xn = (double*)malloc(nn * sizeof(double));
+      b->yn = (double*)malloc(nn * sizeof(double));
+      if (!b->xn || !b->yn) { orc_destroy(G); return NULL; }
+      memcpy(b->xn, d->x, nn * sizeof(double));
+      memcpy(b->yn, d->y, nn * sizeof(double));
+    }
+    i64 nfmax = 0;
+    for (int dd = 0; dd < ndim; ++dd) {
+      i64 nf = (i64)(b->ni + (dd == 0)) * (b->nj + (dd == 1)) * (b->nk + (dd == 2));
+      if (nf > nfmax) nfmax = nf;
+    }
+    b->nflux = nfmax;
+    b->q = (double*)calloc((size_t)G->nv * (size_t)b->npad, sizeof(double));
+    b->qn = (double*)calloc((size_t)G->nv * (size_t)b->npad, sizeof(double));
+    b->res = (double*)calloc((size_t)G->nv * (size_t)b->ncell, sizeof(double));
+    b->flux = (double*)calloc((size_t)G->nv * (size_t)nfmax, sizeof(double));
+    if (!b->q || !b->qn || !b->res || !b->flux) { orc_destroy(G); return NULL; }
+    G->ncells += b->ncell;
+  }
+  /* block connectivity must pair opposite faces of equal transverse size */
+  for (int bi = 0; bi < nblocks; ++bi)
+    for (int f = 0; f < 2 * ndim; ++f) {
+      const orc_bc* bc = &G->b[bi].bc[f];
+      if (bc->kind < ORC_PERIODIC || bc->kind > ORC_SLIPWALL) { orc_destroy(G); return NULL; }
+      if (bc->kind != ORC_BLOCK) continue;
+      int nb = bc->nbr_block;
+      if (nb < 0 || nb >= nblocks || bc->nbr_face != (f ^ 1)) { orc_destroy(G); return NULL; }
+      int n1, n2, m1, m2;
+      trans_ext(&G->b[bi], f / 2, &n1, &n2);
+      trans_ext(&G->b[nb], f / 2, &m1, &m2);
+      if (n1 != m1 || n2 != m2) { orc_destroy(G); return NULL; }
+    }
+  return G;
+}
+
+void orc_destroy(orc_grid* G) {
+  if (!G) return;
+  if (G->b) {
+    for (int bi = 0; bi < G->nblocks; ++bi) {
+      blk_t* b = &G->b[bi];
+      free(b->xn); free(b->yn); free(b->q); free(b->qn); free(b->res); free(b->flux);
+    }
+    free(G->b);
+  }
+  free(G);
+}
+
+int orc_set_state(orc_grid* G, const double* U) {
+  const int nv = G->nv;
+  i64 o = 0;
+  for (int bi = 0; bi < G->nblocks; ++bi) {
+    blk_t* b = &G->b[bi];
+    for (int v = 0; v < nv; ++v)
+      for (int k = 0; k < b->nk; ++k)
+        for (int j = 0; j < b->nj; ++j)
+          for (int i = 0; i < b->ni; ++i) b->q[v * b->npad + pidx(b, i, j, k)] = U[o++];
+  }
+  G->t = 0.0;
+  G->steps = 0;
+  G->dt_last = 0.0;
+  G->have_first = 0;
+  G->norm = G->norm_first = G->drop = 0.0;
+  for (int v = 0; v < 5; ++v) G->norms[v] = 0.0;
+  double mn;
+  return orc_spectral_min(G, &mn);
+}
+
+void orc_get_state(const orc_grid* G, double* U) {
+  const int nv = G->nv;
+  i64 o = 0;
+  for (int bi = 0; bi < G->nblocks; ++bi) {
+    const blk_t* b = &G->b[bi];
+    for (int v = 0; v < nv; ++v)
+      for (int k = 0; k < b->nk; ++k)
+        for (int j = 0; j < b->nj; ++j)
+          for (int i = 0; i < b->ni; ++i) U[o++] = b->q[v * b->npad + pidx(b, i, j, k)];
+  }
+}
+
+int orc_residual(orc_grid* G, const orc_params* P, double* R, double* norms, double* scale) {
+  const int nv = G->nv;
+  double** scales = NULL;
+  if (scale) {
+    scales = (double**)malloc(sizeof(double*) * (size_t)G->nblocks);
+    i64 o = 0;
+    for (int bi = 0; bi < G->nblocks; ++bi) {
+      scales[bi] = scale + o;
+      o += (i64)nv * G->b[bi].ncell;
+    }
+  }
+  residual_all(G, P, scales);
+  free(scales);
+  if (R) {
+    i64 o = 0;
+    for (int bi = 0; bi < G->nblocks; ++bi) {
+      blk_t* b = &G->b[bi];
+      memcpy(R + o, b->res, sizeof(double) * (size_t)nv * (size_t)b->ncell);
+      o += (i64)nv * b->ncell;
+    }
+  }
+  if (norms) {
+    double comb;
+    norms_of_residual(G, P, norms, &comb);
+  }
+  return ORC_OK;
+}
+
+void orc_get_info(const orc_grid* G, orc_info* info) {
+  info->steps = G->steps;
+  info->t = G->t;
+  info->dt_last = G->dt_last;
+  for (int v = 0; v < 5; ++v) info->norms[v] = G->norms[v];
+  info->norm = G->norm;
+  info->norm_first = G->norm_first;
+  info->drop = G->drop;
+  info->status = G->physical ? ORC_OK : ORC_E_NONPHYSICAL;
+}
+
+/* Advance up to nsteps steps.  dt = dt_fixed if positive, else CFL times the
+ * spectral minimum of U^n; a positive t_end clamps the last step so that t
+ * lands on t_end and no step starts at or after it.  After each step the new
+ * state is checked (rho > 0, p > 0, finite) and its spectral minimum kept for
+ * the next dt.  With drop_tol > 0 the run also ends after the first step whose
+ * residual norm (from R(U^n)) is at most drop_tol times the first step's. */
+int orc_run(orc_grid* G, const orc_params* P, long long nsteps, double drop_tol, orc_info* info,
+            double* dt_hist) {
+  int status = G->physical ? ORC_OK : ORC_E_NONPHYSICAL;
+  for (long long s = 0; s < nsteps && status == ORC_OK; ++s) {
+    double dt = P->dt_fixed > 0.0 ? P->dt_fixed : P->cfl * G->raw_min;
+    int last = 0;
+    if (P->t_end > 0.0) {
+      if (G->t >= P->t_end) break;
+      if (dt >= P->t_end - G->t) {
+        dt = P->t_end - G->t;
+        last = 1;
+      }
+    }
+    rk3_step(G, P, dt);
+    G->t = last ? P->t_end : G->t + dt;
+    G->dt_last = dt;
+    if (dt_hist) dt_hist[s] = dt;
+    if (!G->have_first) {
+      G->norm_first = G->norm;
+      G->have_first = 1;
+    }
+    G->drop = G->norm_first > 0.0 ? G->norm / G->norm_first : 0.0;
+    G->steps++;
+    double mn;
+    status = orc_spectral_min(G, &mn);
+    if (drop_tol > 0.0 && G->drop <= drop_tol) break;
+  }
+  if (info) {
+    orc_get_info(G, info);
+    info->status = status;
+  }
+  return status;
+}
+
+/* Ghost values of the current state, laid out [block][face][layer g=1,2]
+ * [var][t2][t1] with (t1, t2) = (j, k) on i-faces, (i, k) on j-faces and
+ * (i, j) on k-faces. */
+int orc_ghosts(orc_grid* G, double* out) {
+  const int nd = G->ndim, nv = G->nv;
+  i64 o = 0;
+  for (int bi = 0; bi < G->nblocks; ++bi) {
+    blk_t* b = &G->b[bi];
+    for (int f = 0; f < 2 * nd; ++f) {
+      int n1, n2;
+      trans_ext(b, f / 2, &n1, &n2);
+      for (int g = 1; g <= 2; ++g)
+        for (int v = 0; v < nv; ++v)
+          for (int t2 = 0; t2 < n2; ++t2)
+            for (int t1 = 0; t1 < n1; ++t1) {
+              double val[5];
+              ghost_value(G, bi, f, g, t1, t2, val);
+              out[o++] = val[v];
+            }
+    }
+  }
+  return ORC_OK;
+}
+
+int orc_face_flux(orc_grid* G, const orc_params* P, int block, int dir, int i, int j, int k,
+                  double* F) {
+  if (block < 0 || block >= G->nblocks || dir < 0 || dir >= G->ndim) return ORC_E_INVAL;
+  fill_ghosts(G);
+  face_flux_at(G, &G->b[block], P, dir, i, j, k, F);
+  return ORC_OK;
+}
+
+void orc_metrics_2d(const orc_grid* G, int block, double* Sxi, double* Seta, double* vol) {
+  const blk_t* b = &G->b[block];
+  double S[3];
+  for (int j = 0; j < b->nj; ++j)
+    for (int i = 0; i <= b->ni; ++i) {
+      face_vec(b, 2, 0, i, j, 0, S);
+      Sxi[2 * ((i64)j * (b->ni + 1) + i)] = S[0];
+      Sxi[2 * ((i64)j * (b->ni + 1) + i) + 1] = S[1];
+    }
+  for (int j = 0; j <= b->nj; ++j)
+    for (int i = 0; i < b->ni; ++i) {
+      face_vec(b, 2, 1, i, j, 0, S);
+      Seta[2 * ((i64)j * b->ni + i)] = S[0];
+      Seta[2 * ((i64)j * b->ni + i) + 1] = S[1];
+    }
+  for (int j = 0; j < b->nj; ++j)
+    for (int i = 0; i < b->ni; ++i) vol[(i64)j * b->ni + i] = cell_vol(b, 2, i, j, 0);
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}

@@ -1,0 +1,228 @@
+"""Python handle on the plain FP64 CPU reference (``oracle/fv_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the package smoke check
+and by the benchmark's CPU-baseline leg.  The product path never imports it.
+It marshals a case description (duck-typed: ``ndim``, ``gamma``, ``blocks``,
+``state_flat()``) into the oracle's own C structures; no arithmetic of the
+method happens here.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "fv_oracle.c")
+LIB = os.path.join(HERE, "liborc.so")
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math", "-ffp-contract=off"]
+
+OK, E_INVAL, E_NOMEM, E_NONPHYSICAL = 0, -1, -2, -4
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(LIB):
+        cmd = ["gcc", *CFLAGS, "-o", LIB + ".tmp", SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class _BC(C.Structure):
+    _fields_ = [("kind", C.c_int), ("nbr_block", C.c_int), ("nbr_face", C.c_int),
+                ("prim", C.c_double * 5)]
+
+
+class _Block(C.Structure):
+    _fields_ = [("ni", C.c_int), ("nj", C.c_int), ("nk", C.c_int),
+                ("x", C.POINTER(C.c_double)), ("y", C.POINTER(C.c_double)),
+                ("origin", C.c_double * 3), ("h", C.c_double * 3), ("bc", _BC * 6)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("cfl", C.c_double), ("dt_fixed", C.c_double), ("t_end", C.c_double),
+                ("limiter", C.c_int), ("eps", C.c_double), ("kappa", C.c_double),
+                ("entropy_fix", C.c_double), ("qref", C.c_double * 5)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("steps", C.c_longlong), ("t", C.c_double), ("dt_last", C.c_double),
+                ("norms", C.c_double * 5), ("norm", C.c_double), ("norm_first", C.c_double),
+                ("drop", C.c_double), ("status", C.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=True)
+        L = C.CDLL(LIB)
+        dp = C.POINTER(C.c_double)
+        L.orc_create.restype = C.c_void_p
+        L.orc_create.argtypes = [C.c_int, C.c_int, C.POINTER(_Block), C.c_double]
+        L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_set_state.argtypes = [C.c_void_p, dp]
+        L.orc_get_state.argtypes = [C.c_void_p, dp]
+        L.orc_residual.argtypes = [C.c_void_p, C.POINTER(_Params), dp, dp, dp]
+        L.orc_run.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_longlong, C.c_double,
+                              C.POINTER(_Info), dp]
+        L.orc_get_info.argtypes = [C.c_void_p, C.POINTER(_Info)]
+        L.orc_ghosts.argtypes = [C.c_void_p, dp]
+        L.orc_spectral_min.argtypes = [C.c_void_p, dp]
+        L.orc_face_flux.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_int, C.c_int, C.c_int,
+                                    C.c_int, C.c_int, dp]
+        L.orc_metrics_2d.argtypes = [C.c_void_p, C.c_int, dp, dp, dp]
+        L.orc_roe.argtypes = [dp, dp, dp, C.c_int, C.c_double, C.c_double, C.c_int, dp]
+        L.orc_reconstruct.argtypes = [dp, C.c_int, C.c_double, C.c_double, dp, dp]
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_params(p) -> _Params:
+    q = list(p.qref) + [1.0] * (5 - len(p.qref))
+    return _Params(p.cfl, p.dt_fixed, p.t_end, p.limiter, p.eps, p.kappa, p.entropy_fix,
+                   (C.c_double * 5)(*q[:5]))
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+# ---------------------------------------------------------------------------
+# point functions (used by the pins)
+# ---------------------------------------------------------------------------
+def roe(qL, qR, n, gamma=1.4, entropy_fix=0.1, mode=-1):
+    """mode -1: Roe flux per unit area; 0: |lambda| wave sum; 1: signed wave
+    sum; 2: unit-eigenvalue wave sum; 3: F(Q_L).n."""
+    qL = np.ascontiguousarray(qL, dtype=np.float64)
+    qR = np.ascontiguousarray(qR, dtype=np.float64)
+    nn = np.zeros(3)
+    nn[:len(n)] = n
+    nd = len(qL) - 2
+    out = np.zeros(5)
+    lib().orc_roe(_ptr(qL), _ptr(qR), _ptr(nn), nd, gamma, entropy_fix, mode, _ptr(out))
+    return out[:nd + 2]
+
+
+def reconstruct(q4, limiter=0, eps=1.0, kappa=-1.0):
+    q4 = np.ascontiguousarray(q4, dtype=np.float64)
+    a, b = np.zeros(1), np.zeros(1)
+    lib().orc_reconstruct(_ptr(q4), limiter, eps, kappa, _ptr(a), _ptr(b))
+    return float(a[0]), float(b[0])
+
+
+# ---------------------------------------------------------------------------
+# grid handle
+# ---------------------------------------------------------------------------
+class OracleGrid:
+    def __init__(self, case):
+        self.case = case
+        self.ndim = case.ndim
+        self.nv = case.ndim + 2
+        nb = len(case.blocks)
+        arr = (_Block * nb)()
+        self._keep = []
+        for b, blk in enumerate(case.blocks):
+            d = arr[b]
+            d.ni, d.nj, d.nk = blk.ni, blk.nj, blk.nk
+            if blk.x is not None:
+                x = np.ascontiguousarray(blk.x, dtype=np.float64)
+                y = np.ascontiguousarray(blk.y, dtype=np.float64)
+                self._keep += [x, y]
+                d.x, d.y = _ptr(x), _ptr(y)
+            for a in range(3):
+                d.origin[a] = blk.origin[a]
+                d.h[a] = blk.h[a]
+            for f in range(6):
+                bc = blk.bc[f]
+                d.bc[f].kind = bc.kind
+                d.bc[f].nbr_block = bc.nbr_block
+                d.bc[f].nbr_face = bc.nbr_face
+                for a in range(5):
+                    d.bc[f].prim[a] = bc.prim[a]
+        self._h = lib().orc_create(case.ndim, nb, arr, case.gamma)
+        if not self._h:
+            raise ValueError("oracle rejected the grid description")
+        self.size = sum(self.nv * b.ncells for b in case.blocks)
+        self.status = self.set_state(case.state_flat())
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_destroy(h)
+            self._h = None
+
+    def set_state(self, U) -> int:
+        U = np.ascontiguousarray(U, dtype=np.float64).ravel()
+        assert U.size == self.size
+        self.status = lib().orc_set_state(self._h, _ptr(U))
+        return self.status
+
+    def get_state(self) -> np.ndarray:
+        out = np.empty(self.size)
+        lib().orc_get_state(self._h, _ptr(out))
+        return out
+
+    def residual(self, params, with_scale=False):
+        R = np.empty(self.size)
+        norms = np.zeros(5)
+        scale = np.empty(self.size) if with_scale else None
+        P = make_params(params)
+        lib().orc_residual(self._h, C.byref(P), _ptr(R), _ptr(norms),
+                           _ptr(scale) if with_scale else None)
+        return (R, norms, scale) if with_scale else (R, norms)
+
+    def run(self, params, nsteps, drop_tol=0.0, dt_hist=False):
+        P = make_params(params)
+        info = _Info()
+        hist = np.zeros(max(int(nsteps), 1)) if dt_hist else None
+        st = lib().orc_run(self._h, C.byref(P), int(nsteps), float(drop_tol), C.byref(info),
+                           _ptr(hist) if dt_hist else None)
+        d = dict(status=st, steps=info.steps, t=info.t, dt_last=info.dt_last,
+                 norms=np.array(info.norms[:]), norm=info.norm, norm_first=info.norm_first,
+                 drop=info.drop)
+        if dt_hist:
+            d["dt_hist"] = hist[:info.steps]
+        return d
+
+    def ghosts(self) -> np.ndarray:
+        n = 0
+        for b in self.case.blocks:
+            dims = (b.ni, b.nj, b.nk)
+            for f in range(2 * self.ndim):
+                d = f // 2
+                t = [dims[a] for a in range(3) if a != d]
+                n += 2 * self.nv * t[0] * t[1]
+        out = np.empty(n)
+        lib().orc_ghosts(self._h, _ptr(out))
+        return out
+
+    def spectral_min(self):
+        out = np.zeros(1)
+        st = lib().orc_spectral_min(self._h, _ptr(out))
+        return st, float(out[0])
+
+    def face_flux(self, params, block, d, i, j, k=0):
+        out = np.zeros(5)
+        P = make_params(params)
+        lib().orc_face_flux(self._h, C.byref(P), block, d, i, j, k, _ptr(out))
+        return out[:self.nv]
+
+    def metrics_2d(self, block):
+        b = self.case.blocks[block]
+        Sxi = np.empty((b.nj, b.ni + 1, 2))
+        Seta = np.empty((b.nj + 1, b.ni, 2))
+        vol = np.empty((b.nj, b.ni))
+        lib().orc_metrics_2d(self._h, block, _ptr(Sxi), _ptr(Seta), _ptr(vol))
+        return Sxi, Seta, vol

@@ -1,0 +1,369 @@
+"""Seeded synthetic inputs: meshes, initial conserved states, boundary specs.
+
+This module holds none of the method's arithmetic.  It only lays out node
+coordinates, converts prescribed primitive fields (rho, velocity, p) into the
+conserved vector Q = (rho, rho*u, rho*v[, rho*w], rho*e_t) that the method
+takes as input (Sec. 2, conserved vector), and names the boundary condition of
+each block face.  Both the HIP path and the CPU reference consume the objects
+built here; neither side's arithmetic lives here.
+
+Workloads (all synthetic; the paper's inlet grid is not public):
+
+* ``vortex_2d``  - 128x64 periodic uniform block, isentropic vortex of
+  strength 5 in a Mach 0.5 free stream plus a seeded density perturbation.
+* ``inlet_2d``   - 4 blocks of 512x256 cells on the sheared, wavy
+  inlet-like mesh x = I*dx + 0.05 sin(2 pi J/Nj), y = J*dy*(1 + 0.2 I/Ni)
+  (global node indices I, J), supersonic inflow with the state of the
+  paper's inflow table (Sec. 8: M = 4, p = 12270 Pa, T = 217 K), slip walls
+  at J = 0 and J = Nj, zeroth-order extrapolation at the outflow.
+* ``blobs_3d``   - 256^3 uniform block, Mach 2 free stream carrying seeded
+  Gaussian density blobs, inflow at x-min, extrapolation at x-max,
+  periodic in y and z.
+* ``batch_2d``   - 64 seeded inlet-like instances of uneven size, 1-4 blocks.
+* ``serving_trace`` - a seeded Poisson arrival stream of mixed 2D/3D solves.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+# boundary kinds (match the C ABI enumeration)
+PERIODIC, BLOCK, INFLOW, EXTRAP, SLIPWALL = 0, 1, 2, 3, 4
+# face order
+IMIN, IMAX, JMIN, JMAX, KMIN, KMAX = 0, 1, 2, 3, 4, 5
+# reconstruction
+MINMOD, UNLIMITED, FIRST_ORDER = 0, 1, 2
+# arithmetic of the reconstruction + flux
+FP64, FP32_FLUX = 0, 1
+
+GAMMA = 1.4
+R_GAS = 287.0  # J/(kg K): gas constant of air, used to turn (p, T) into rho
+
+# Inflow state of the paper's supersonic inlet (Sec. 8, inflow table).
+INLET_MACH = 4.0
+INLET_P = 12270.0
+INLET_T = 217.0
+
+
+@dataclass
+class BC:
+    kind: int
+    nbr_block: int = -1
+    nbr_face: int = -1
+    prim: Sequence[float] = (0.0, 0.0, 0.0, 0.0, 0.0)  # rho, u, v, w, p
+
+
+@dataclass
+class Block:
+    ni: int
+    nj: int
+    nk: int = 1
+    x: Optional[np.ndarray] = None  # 2D node coordinates, shape (nj+1, ni+1)
+    y: Optional[np.ndarray] = None
+    origin: Sequence[float] = (0.0, 0.0, 0.0)
+    h: Sequence[float] = (1.0, 1.0, 1.0)
+    bc: List[BC] = field(default_factory=list)
+
+    @property
+    def ncells(self) -> int:
+        return self.ni * self.nj * self.nk
+
+
+@dataclass
+class Params:
+    cfl: float = 0.5
+    dt_fixed: float = 0.0
+    t_end: float = 0.0
+    precision: int = FP64
+    limiter: int = MINMOD
+    eps: float = 1.0
+    kappa: float = -1.0
+    entropy_fix: float = 0.1
+    qref: Sequence[float] = (1.0, 1.0, 1.0, 1.0, 1.0)
+
+
+@dataclass
+class Case:
+    name: str
+    ndim: int
+    blocks: List[Block]
+    U0: List[np.ndarray]  # per block, float64 (nv, nk, nj, ni)
+    params: Params
+    nsteps: int = 1
+    gamma: float = GAMMA
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nv(self) -> int:
+        return self.ndim + 2
+
+    @property
+    def ncells(self) -> int:
+        return sum(b.ncells for b in self.blocks)
+
+    def state_flat(self) -> np.ndarray:
+        """Interior state, layout [block][var][k][j][i], float64."""
+        return np.concatenate([np.ascontiguousarray(u, dtype=np.float64).ravel() for u in self.U0])
+
+    def split_flat(self, flat: np.ndarray) -> List[np.ndarray]:
+        out, o = [], 0
+        for b in self.blocks:
+            n = self.nv * b.ncells
+            out.append(np.asarray(flat[o:o + n]).reshape(self.nv, b.nk, b.nj, b.ni))
+            o += n
+        return out
+
+
+# --------------------------------------------------------------------------
+# primitive -> conserved (input construction only)
+# --------------------------------------------------------------------------
+def conserved(rho, vel, p, gamma=GAMMA):
+    """Stack Q = (rho, rho*u_a..., rho*e_t) with rho*e_t = p/(g-1) + rho|u|^2/2."""
+    rho = np.asarray(rho, dtype=np.float64)
+    vel = [np.broadcast_to(np.asarray(v, dtype=np.float64), rho.shape) for v in vel]
+    ke = sum(v * v for v in vel)
+    out = [rho] + [rho * v for v in vel] + [np.asarray(p, dtype=np.float64) / (gamma - 1.0) + 0.5 * rho * ke]
+    return np.stack([np.broadcast_to(a, rho.shape) for a in out]).astype(np.float64)
+
+
+def inlet_freestream(mach=INLET_MACH, angle_deg=0.0, ndim=2):
+    """(rho, u, v, w, p) of the inlet inflow table at a given Mach number."""
+    rho = INLET_P / (R_GAS * INLET_T)
+    c = math.sqrt(GAMMA * INLET_P / rho)
+    a = math.radians(angle_deg)
+    return (rho, mach * c * math.cos(a), mach * c * math.sin(a), 0.0, INLET_P)
+
+
+def qref_of(prim, ndim):
+    rho, u, v, w, p = prim
+    speed = math.sqrt(u * u + v * v + w * w)
+    rhoE = p / (GAMMA - 1.0) + 0.5 * rho * speed * speed
+    q = [rho] + [rho * speed] * ndim + [rhoE]
+    q += [1.0] * (5 - len(q))
+    return tuple(q)
+
+
+def _round8(v, lo):
+    return max(lo, int(round(v / 8.0)) * 8)
+
+
+def _split_even(n, nb, quantum=8):
+    """Split n cells into nb chunks that are multiples of ``quantum`` when possible."""
+    q = n // quantum
+    nb = max(1, min(nb, q if q > 0 else 1))
+    if q == 0:
+        return [n]
+    sizes = [(q // nb + (1 if b < q % nb else 0)) * quantum for b in range(nb)]
+    sizes[-1] += n - sum(sizes)
+    return sizes
+
+
+# --------------------------------------------------------------------------
+# workload 1: isentropic vortex on a periodic uniform block
+# --------------------------------------------------------------------------
+def vortex_fields(xc, yc, x, y, beta=5.0, uinf=0.5 * math.sqrt(GAMMA), vinf=0.0, gamma=GAMMA):
+    """Primitive fields of the translating isentropic vortex (rho_inf = p_inf = 1)."""
+    dx, dy = x - xc, y - yc
+    r2 = dx * dx + dy * dy
+    e = np.exp(0.5 * (1.0 - r2))
+    u = uinf - beta / (2.0 * math.pi) * e * dy
+    v = vinf + beta / (2.0 * math.pi) * e * dx
+    T = 1.0 - (gamma - 1.0) * beta * beta / (8.0 * gamma * math.pi ** 2) * e * e
+    rho = T ** (1.0 / (gamma - 1.0))
+    p = rho ** gamma
+    return rho, u, v, p
+
+
+def vortex_2d(ni=128, nj=64, seed=1, noise=1e-3, Lx=20.0, Ly=10.0, beta=5.0,
+              limiter=MINMOD, nsteps=100, cfl=0.5):
+    h = (Lx / ni, Ly / nj, 1.0)
+    xc = (np.arange(ni) + 0.5) * h[0]
+    yc = (np.arange(nj) + 0.5) * h[1]
+    X, Y = np.meshgrid(xc, yc)  # (nj, ni)
+    rho, u, v, p = vortex_fields(0.5 * Lx, 0.5 * Ly, X, Y, beta=beta)
+    if noise > 0:
+        rng = np.random.default_rng(seed)
+        rho = rho + rng.uniform(-noise, noise, size=rho.shape)
+    U = conserved(rho, [u, v], p)[:, None, :, :]
+    bcs = [BC(PERIODIC) for _ in range(4)] + [BC(PERIODIC), BC(PERIODIC)]
+    blk = Block(ni, nj, 1, None, None, (0.0, 0.0, 0.0), h, bcs)
+    uinf = 0.5 * math.sqrt(GAMMA)
+    qref = qref_of((1.0, uinf, 0.0, 0.0, 1.0), 2)
+    prm = Params(cfl=cfl, limiter=limiter, qref=qref)
+    return Case("vortex_2d", 2, [blk], [U], prm, nsteps,
+                meta=dict(Lx=Lx, Ly=Ly, beta=beta, uinf=uinf, seed=seed))
+
+
+# --------------------------------------------------------------------------
+# workload 2: inlet-like multi-block curvilinear mesh
+# --------------------------------------------------------------------------
+def inlet_mesh(Ni, Nj, Lx=4.0, Ly=1.0, wave=0.05, shear=0.2):
+    """Global node coordinates (Nj+1, Ni+1) of the sheared wavy inlet-like mesh."""
+    I = np.arange(Ni + 1, dtype=np.float64)[None, :]
+    J = np.arange(Nj + 1, dtype=np.float64)[:, None]
+    dx, dy = Lx / Ni, Ly / Nj
+    x = I * dx + wave * np.sin(2.0 * math.pi * J / Nj)
+    y = J * dy * (1.0 + shear * I / Ni)
+    return np.ascontiguousarray(x), np.ascontiguousarray(y)
+
+
+def inlet_case(Ni, Nj, nblocks, mach=INLET_MACH, angle_deg=0.0, name="inlet_2d",
+               nsteps=500, precision=FP64, cfl=0.5):
+    X, Y = inlet_mesh(Ni, Nj)
+    prim = inlet_freestream(mach, angle_deg)
+    sizes = _split_even(Ni, nblocks)
+    nb = len(sizes)
+    blocks, U0 = [], []
+    i0 = 0
+    for b, n in enumerate(sizes):
+        bcs = [BC(BLOCK, b - 1, IMAX) if b > 0 else BC(INFLOW, prim=prim),
+               BC(BLOCK, b + 1, IMIN) if b < nb - 1 else BC(EXTRAP),
+               BC(SLIPWALL), BC(SLIPWALL), BC(PERIODIC), BC(PERIODIC)]
+        x = np.ascontiguousarray(X[:, i0:i0 + n + 1])
+        y = np.ascontiguousarray(Y[:, i0:i0 + n + 1])
+        blocks.append(Block(n, Nj, 1, x, y, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), bcs))
+        U = conserved(np.full((Nj, n), prim[0]), [np.full((Nj, n), prim[1]), np.full((Nj, n), prim[2])],
+                      np.full((Nj, n), prim[4]))
+        U0.append(U[:, None, :, :].copy())
+        i0 += n
+    prm = Params(cfl=cfl, precision=precision, qref=qref_of(prim, 2))
+    return Case(name, 2, blocks, U0, prm, nsteps,
+                meta=dict(Ni=Ni, Nj=Nj, mach=mach, angle=angle_deg, prim=prim))
+
+
+def inlet_2d(nblocks=4, ni=512, nj=256, precision=FP64, nsteps=500):
+    return inlet_case(nblocks * ni, nj, nblocks, name="inlet_2d", nsteps=nsteps, precision=precision)
+
+
+# --------------------------------------------------------------------------
+# workload 3: 3D uniform block with seeded density blobs
+# --------------------------------------------------------------------------
+def blobs_fields(n, centres, amp=0.05, width_cells=8.0, rho_inf=1.0, chunk=16):
+    """rho(k, j, i) = rho_inf (1 + amp sum_b exp(-|x - x_b|^2 / (2 w^2))).
+
+    Distances use the minimum image in y and z (periodic directions).
+    """
+    h = 1.0 / n
+    w = width_cells * h
+    c = (np.arange(n) + 0.5) * h
+    rho = np.zeros((n, n, n), dtype=np.float64)
+    for (bx, by, bz) in centres:
+        dx = (c - bx)[None, None, :]
+        dy = c - by
+        dy = (dy - np.round(dy))[None, :, None]
+        dz = c - bz
+        dz = (dz - np.round(dz))[:, None, None]
+        ex = np.exp(-(dx * dx) / (2 * w * w))
+        ey = np.exp(-(dy * dy) / (2 * w * w))
+        ez = np.exp(-(dz * dz) / (2 * w * w))
+        rho += ez * ey * ex
+    return rho_inf * (1.0 + amp * rho)
+
+
+def blobs_case(n, nblobs=16, seed=3, mach=2.0, name="blobs_3d", nsteps=50, precision=FP64,
+               cfl=0.5, amp=0.05, width_cells=8.0):
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.0, 1.0, size=(nblobs, 3))
+    prim = inlet_freestream(mach, 0.0)
+    rho = blobs_fields(n, centres, amp, width_cells, prim[0])
+    U = conserved(rho, [np.full_like(rho, prim[1]), 0.0, 0.0], np.full_like(rho, prim[4]))
+    h = 1.0 / n
+    bcs = [BC(INFLOW, prim=prim), BC(EXTRAP), BC(PERIODIC), BC(PERIODIC), BC(PERIODIC), BC(PERIODIC)]
+    blk = Block(n, n, n, None, None, (0.0, 0.0, 0.0), (h, h, h), bcs)
+    prm = Params(cfl=cfl, precision=precision, qref=qref_of(prim, 3))
+    return Case(name, 3, [blk], [U], prm, nsteps,
+                meta=dict(n=n, seed=seed, mach=mach, prim=prim, centres=centres))
+
+
+def blobs_3d(n=256, precision=FP64, nsteps=50):
+    return blobs_case(n, 16, 3, 2.0, "blobs_3d", nsteps, precision)
+
+
+# --------------------------------------------------------------------------
+# workload 4: batch of uneven inlet-like instances
+# --------------------------------------------------------------------------
+def batch_2d(count=64, seed=4, precision=FP32_FLUX, nsteps=100):
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(count):
+        Ni = _round8(math.exp(rng.uniform(math.log(64), math.log(1024))), 64)
+        Nj = _round8(math.exp(rng.uniform(math.log(64), math.log(512))), 64)
+        mach = rng.uniform(1.5, 4.0)
+        nb = int(rng.integers(1, 5))
+        out.append(inlet_case(Ni, Nj, nb, mach=mach, name=f"batch_{r}", nsteps=nsteps, precision=precision))
+    return out
+
+
+# --------------------------------------------------------------------------
+# workload 5: Poisson arrival stream of mixed 2D / 3D solves
+# --------------------------------------------------------------------------
+@dataclass
+class Request:
+    arrival: float  # seconds after the stream starts
+    kind: str       # "2d" or "3d"
+    spec: dict      # arguments that build the case (see ``build_request``)
+
+
+def serving_trace(count=256, seed=5, rate=200.0, max_steps=2000, drop_tol=1e-8):
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    reqs = []
+    for r in range(count):
+        t += rng.exponential(1.0 / rate)
+        if rng.uniform() < 0.5:
+            Ni = _round8(math.exp(rng.uniform(math.log(64), math.log(2048))), 64)
+            Nj = _round8(math.exp(rng.uniform(math.log(64), math.log(1024))), 64)
+            spec = dict(Ni=Ni, Nj=Nj, mach=float(rng.uniform(1.5, 4.0)),
+                        angle=float(rng.uniform(0.0, 10.0)), nblocks=int(rng.integers(1, 5)))
+            kind = "2d"
+        else:
+            n = _round8(math.exp(rng.uniform(math.log(32), math.log(192))), 32)
+            spec = dict(n=n, mach=float(rng.uniform(1.5, 4.0)), seed=int(rng.integers(0, 2**31 - 1)))
+            kind = "3d"
+        spec.update(max_steps=max_steps, drop_tol=drop_tol)
+        reqs.append(Request(t, kind, spec))
+    return reqs
+
+
+def build_request(req: Request, precision=FP32_FLUX) -> Case:
+    s = req.spec
+    if req.kind == "2d":
+        return inlet_case(s["Ni"], s["Nj"], s["nblocks"], mach=s["mach"], angle_deg=s["angle"],
+                          name="req2d", nsteps=s["max_steps"], precision=precision)
+    return blobs_case(s["n"], nblobs=8, seed=s["seed"], mach=s["mach"], name="req3d",
+                      nsteps=s["max_steps"], precision=precision)
+
+
+# --------------------------------------------------------------------------
+# small cases used by the correctness pins
+# --------------------------------------------------------------------------
+def uniform_2d(ni, nj, prim, bcs, h=(1.0, 1.0, 1.0), x=None, y=None, name="uniform_2d"):
+    U = conserved(np.full((nj, ni), prim[0]), [np.full((nj, ni), prim[1]), np.full((nj, ni), prim[2])],
+                  np.full((nj, ni), prim[4]))[:, None]
+    blk = Block(ni, nj, 1, x, y, (0.0, 0.0, 0.0), h, bcs)
+    return Case(name, 2, [blk], [U.copy()], Params(qref=qref_of(prim, 2)), 1)
+
+
+def sod_2d(n=400, nj=4, x0=0.5, t_end=0.2, limiter=MINMOD, cfl=0.5, transpose=False):
+    """Sod shock tube along x (or along y when ``transpose``), slip walls on the sides."""
+    h = 1.0 / n
+    xc = (np.arange(n) + 0.5) * h
+    rho1 = np.where(xc < x0, 1.0, 0.125)
+    p1 = np.where(xc < x0, 1.0, 0.1)
+    if not transpose:
+        rho = np.tile(rho1, (nj, 1))
+        p = np.tile(p1, (nj, 1))
+        U = conserved(rho, [np.zeros_like(rho), np.zeros_like(rho)], p)[:, None]
+        bcs = [BC(EXTRAP), BC(EXTRAP), BC(SLIPWALL), BC(SLIPWALL), BC(PERIODIC), BC(PERIODIC)]
+        blk = Block(n, nj, 1, None, None, (0.0, 0.0, 0.0), (h, h, 1.0), bcs)
+    else:
+        rho = np.tile(rho1[:, None], (1, nj))
+        p = np.tile(p1[:, None], (1, nj))
+        U = conserved(rho, [np.zeros_like(rho), np.zeros_like(rho)], p)[:, None]
+        bcs = [BC(SLIPWALL), BC(SLIPWALL), BC(EXTRAP), BC(EXTRAP), BC(PERIODIC), BC(PERIODIC)]
+        blk = Block(nj, n, 1, None, None, (0.0, 0.0, 0.0), (h, h, 1.0), bcs)
+    prm = Params(cfl=cfl, t_end=t_end, limiter=limiter, qref=(1.0, 1.0, 1.0, 2.5, 1.0))
+    return Case("sod", 2, [blk], [U.copy()], prm, 10 ** 6, meta=dict(x0=x0, t_end=t_end))
