@@ -1,0 +1,252 @@
+/*
+ * fv.h - C ABI of the MI355X (gfx950) explicit finite-volume Euler library.
+ *
+ * The library evaluates, on one GPU, the hot path of a cell-centred
+ * finite-volume solver for the compressible Euler equations on structured
+ * multi-block grids:
+ *   - ghost-cell / boundary fill before every RK substep and block-to-block
+ *     halo exchange (Sec. 4 workflow; Sec. 5 "ghost cell extrapolation on
+ *     the GPU"; exchange between workers becomes on-device reads),
+ *   - MUSCL extrapolation of the face states with limiter values
+ *     (Sec. 5, Eq. (flux)),
+ *   - an upwind numerical normal flux of the inviscid flux F_{i,n}
+ *     (Sec. 2, flux definitions; Roe's solver is the reading taken),
+ *   - the residual R = sum over the cell's faces of F_{i,n} ds
+ *     (Sec. 3.1, Eq. (residual); no source, no viscous part),
+ *   - the explicit Runge-Kutta update |Omega| dU/dt + R = 0
+ *     (Sec. 3.1, Eq. (spatial_residual); Sec. 3.2, Eq. (runge_kutta),
+ *     taken as the three-stage strong-stability-preserving scheme),
+ *   - the residual norm ("residual print", Sec. 4) and the CFL time step.
+ *
+ * Conventions
+ *   - Status codes: 0 success, > 0 informational, < 0 error.  No C++
+ *     exception crosses this interface.  fv_last_error() returns a detail
+ *     string for the calling thread's last failing call.
+ *   - The library never allocates device memory.  Device workspace and arena
+ *     are supplied by the caller (e.g. PyTorch tensors) and must outlive the
+ *     handle that uses them.  Every host array passed in is copied before the
+ *     call returns; the caller keeps ownership.
+ *   - State layout (host or device): [block][var][k][j][i], i fastest,
+ *     interior cells only, IEEE binary64.  2D: var = rho, rho*u, rho*v,
+ *     rho*e_t (4 vars); 3D: rho, rho*u, rho*v, rho*w, rho*e_t (5 vars).
+ *   - Units are the caller's, consistent with gamma.
+ *   - A grid handle is single-threaded and works on the HIP stream given at
+ *     creation.  fv_step / fv_solve / fv_residual block until their results
+ *     are on the host.
+ */
+#ifndef FV_H
+#define FV_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+enum {
+  FV_OK = 0,
+  FV_PENDING = 1,          /* fv_poll: request not finished yet */
+  FV_E_INVAL = -1,         /* bad argument or descriptor */
+  FV_E_NOMEM = -2,         /* workspace or arena too small */
+  FV_E_DEVICE = -3,        /* a HIP call failed */
+  FV_E_NONPHYSICAL = -4,   /* rho <= 0, p <= 0 or a non-finite state value */
+  FV_E_UNSUPPORTED = -5,   /* valid request this build does not provide */
+  FV_E_BUSY = -6,          /* server queue full */
+  FV_E_NOTFOUND = -7,      /* unknown ticket */
+  FV_E_CANCELLED = -8      /* request cancelled before it finished */
+};
+
+/* boundary kinds.  Ghost rules (two ghost layers per face):
+ *   PERIODIC  ghost = interior cell the same distance in from the opposite
+ *             face of the same block
+ *   BLOCK     ghost = interior cell of block nbr_block, the same distance in
+ *             from its face nbr_face, which must be the opposite face of the
+ *             same direction with the same transverse extents (1:1 points,
+ *             same orientation)
+ *   INFLOW    ghost = conserved state of prim_in = (rho, u, v, w, p)
+ *   EXTRAP    ghost = nearest interior cell (zeroth-order extrapolation)
+ *   SLIPWALL  ghost layer g = interior cell g-1 from the wall with its
+ *             momentum mirrored about the unit normal of that wall face;
+ *             rho and rho*e_t copied */
+enum { FV_BC_PERIODIC = 0, FV_BC_BLOCK = 1, FV_BC_INFLOW = 2, FV_BC_EXTRAP = 3, FV_BC_SLIPWALL = 4 };
+enum { FV_IMIN = 0, FV_IMAX = 1, FV_JMIN = 2, FV_JMAX = 3, FV_KMIN = 4, FV_KMAX = 5 };
+
+/* arithmetic of reconstruction + flux: FP64 throughout, or FP32 from the
+ * face states through F.ds with the state, the residual sum, the RK update,
+ * the norms and the time step kept in FP64 */
+enum { FV_FP64 = 0, FV_FP32_FLUX = 1 };
+
+/* MUSCL variants (Sec. 5, Eq. (flux)): minmod limiter values, no limiter
+ * (Psi = 1), or first order (eps = 0) */
+enum { FV_LIM_MINMOD = 0, FV_LIM_NONE = 1, FV_FIRST_ORDER = 2 };
+
+/* fv_step_info.flags */
+enum {
+  FV_FLAG_NONPHYSICAL = 1,  /* the state after the last step is not physical */
+  FV_FLAG_CONVERGED = 2,    /* residual drop reached drop_tol (fv_solve) */
+  FV_FLAG_T_END = 4,        /* t reached t_end */
+  FV_FLAG_STEP_LIMIT = 8    /* the step budget of the call was used up */
+};
+
+typedef struct fv_bc {
+  int kind;          /* FV_BC_* */
+  int nbr_block;     /* FV_BC_BLOCK: neighbour block index */
+  int nbr_face;      /* FV_BC_BLOCK: neighbour face (FV_IMIN..FV_KMAX) */
+  double prim_in[5]; /* FV_BC_INFLOW: rho, u, v, w, p */
+} fv_bc;
+
+typedef struct fv_block_desc {
+  int ni, nj, nk;          /* interior cells; nk = 1 in 2D */
+  const double *x, *y, *z; /* 2D: node coordinates (nj+1)*(ni+1), i fastest;
+                              NULL => uniform spacing h.  3D grids are
+                              uniform (z is reserved, must be NULL). */
+  double origin[3], h[3];  /* uniform spacing per direction */
+  fv_bc face[6];           /* imin, imax, jmin, jmax, kmin, kmax */
+} fv_block_desc;
+
+typedef struct fv_grid_desc {
+  int ndim;                     /* 2 or 3 */
+  int nblocks;
+  const fv_block_desc* blocks;
+  double gamma;                 /* ratio of specific heats */
+} fv_grid_desc;
+
+typedef struct fv_params {
+  double cfl;          /* CFL number of the global time step */
+  double dt_fixed;     /* > 0: use this time step instead of the CFL step */
+  double t_end;        /* > 0: clamp the last step so that t lands on t_end */
+  int precision;       /* FV_FP64 or FV_FP32_FLUX */
+  int limiter;         /* FV_LIM_MINMOD, FV_LIM_NONE, FV_FIRST_ORDER */
+  double eps, kappa;   /* MUSCL parameters of Eq. (flux) */
+  double entropy_fix;  /* Harten's delta / c on the acoustic waves (0: off) */
+  int rk;              /* 3: SSP-RK3 (the only scheme provided) */
+  double qref[5];      /* reference magnitudes of the combined residual norm
+                          (0 entries count as 1) */
+} fv_params;
+
+typedef struct fv_step_info {
+  long long steps;     /* steps taken since the last fv_set_state */
+  double t;            /* simulated time */
+  double dt_last;      /* time step of the last step */
+  double norms[5];     /* RMS over cells of R_v/|Omega| at the last step's U^n */
+  double norm;         /* sqrt(sum_v (norms_v / qref_v)^2) */
+  double drop;         /* norm / norm of the first step after fv_set_state */
+  int flags;           /* FV_FLAG_* */
+} fv_step_info;
+
+typedef struct fv_grid fv_grid;
+
+/* Human-readable text of a status code (static storage). */
+const char* fv_strerror(int status);
+/* Detail of the calling thread's last failing call ("" if none). */
+const char* fv_last_error(void);
+/* Defaults: cfl 0.5, FP64, minmod, eps 1, kappa -1, entropy_fix 0.1, rk 3. */
+void fv_default_params(fv_params* p);
+
+/* Device bytes a grid needs (state buffers, node coordinates, descriptors,
+ * tile list and reduction partials).  Returns 0 for an invalid descriptor. */
+size_t fv_grid_workspace_bytes(const fv_grid_desc* desc, int precision);
+
+/* Build a grid in the caller's device workspace (d_workspace, >= the bytes
+ * above, 256-byte aligned) on the HIP stream hip_stream (NULL: the null
+ * stream).  Validates the descriptor (FV_E_INVAL), copies node coordinates
+ * and boundary data to the device, and lays out the tile work-list with the
+ * tile shape the autotune table (or the default) gives for this grid. */
+int fv_create_grid(const fv_grid_desc* desc, void* d_workspace, size_t bytes, void* hip_stream,
+                   fv_grid** out);
+int fv_destroy_grid(fv_grid* g);
+
+/* Copy a conserved state in (U: host or device pointer per on_device), reset
+ * t, the step count and the first-step norm, and compute the time-step
+ * bound.  Returns FV_E_NONPHYSICAL (state kept) if a cell is not physical. */
+int fv_set_state(fv_grid* g, const double* U, int on_device);
+int fv_get_state(const fv_grid* g, double* U, int on_device);
+
+/* Residual R(U) of the current state (Sec. 3.1, Eq. (residual)) after the
+ * ghost fill, in the state layout; norms (may be NULL) receives the RMS of
+ * R_v/|Omega| per variable.  The state is not changed. */
+int fv_residual(fv_grid* g, const fv_params* p, double* R, int on_device, double norms[5]);
+
+/* Ghost values the boundary rules give for the current state, laid out
+ * [block][face][layer g = 1, 2][var][t2][t1], (t1, t2) = (j, k) on i-faces,
+ * (i, k) on j-faces, (i, j) on k-faces, faces of a 2D grid: imin..jmax. */
+size_t fv_ghost_count(const fv_grid* g);
+int fv_ghosts(fv_grid* g, double* G, int on_device);
+
+/* Advance nsteps SSP-RK3 steps (fewer if t_end is reached or the state
+ * turns non-physical: then FV_E_NONPHYSICAL and info->steps counts the
+ * completed steps).  The time step is dt_fixed, or cfl times the minimum
+ * over cells of |Omega| / sum_d(|u . S_d| + c |S_d|) at U^n. */
+int fv_step(fv_grid* g, const fv_params* p, int nsteps, fv_step_info* info);
+
+/* Step until the residual drop (norm / first-step norm) is <= drop_tol, or
+ * max_steps steps in this call, or t_end.  Chunked internally; the stop is
+ * taken on the device at exactly the step where it holds. */
+int fv_solve(fv_grid* g, const fv_params* p, double drop_tol, long long max_steps,
+             fv_step_info* info);
+
+/* Measurement variant of fv_step: the same kernels launched one by one (no
+ * graph) with HIP events around each launch on the grid's stream.
+ * stage_ms[0..2] receives the summed device time of the three RK stage
+ * kernels and stage_ms[3] that of the step-end reductions, over the call. */
+int fv_step_timed(fv_grid* g, const fv_params* p, int nsteps, fv_step_info* info,
+                  double stage_ms[4]);
+
+/* Time the candidate tile shapes of this grid's size class on the device,
+ * keep the fastest for this grid and record it in the autotune table
+ * (cache_path: JSON file, NULL: environment FV_AUTOTUNE_CACHE or none).
+ * The state is saved and restored. */
+int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path);
+
+typedef struct fv_grid_stats {
+  long long cells;        /* interior cells */
+  long long tiles;        /* work-list entries */
+  int tile_rows;          /* 2D: rows per tile; 3D: planes per tile */
+  int tile_cols;          /* cells per tile row (i) */
+  int tile_ny;            /* 3D: j-rows per tile (1 in 2D) */
+  int launch_blocks;      /* persistent workgroups per stage launch */
+  size_t workspace_bytes;
+  double last_stage_ms[4];/* last timed launch of stage 1, 2, 3, finalize */
+} fv_grid_stats;
+int fv_grid_get_stats(const fv_grid* g, fv_grid_stats* out);
+
+/* ---------------------------------------------------------------------- */
+/* Batched execution and serving (continuous batching over one arena).     */
+/* ---------------------------------------------------------------------- */
+typedef struct fv_server_desc {
+  void* d_arena;           /* caller's device memory for resident instances */
+  size_t arena_bytes;
+  void* hip_stream;        /* stream the server launches on */
+  int max_instances;       /* resident slots */
+  const char* autotune_cache; /* JSON autotune table or NULL */
+  int precision;           /* FV_FP64 or FV_FP32_FLUX for every instance */
+  int steps_per_launch;    /* RK steps per batched graph launch (0: 10) */
+} fv_server_desc;
+
+typedef struct fv_server fv_server;
+
+int fv_server_create(const fv_server_desc* desc, fv_server** out);
+/* Queue a solve (thread-safe): grid, initial state (host), parameters,
+ * stop rule (drop <= drop_tol or max_steps steps).  The descriptor and U0
+ * are copied.  FV_E_NOMEM if the request can never fit the arena. */
+int fv_submit(fv_server* s, const fv_grid_desc* desc, const double* U0, const fv_params* p,
+              double drop_tol, long long max_steps, unsigned long long* ticket);
+/* FV_PENDING until done; then the final state (host, cap_doubles >= state
+ * size) and its info, and the request's own status.  Thread-safe. */
+int fv_poll(fv_server* s, unsigned long long ticket, double* U_out, size_t cap_doubles,
+            fv_step_info* info);
+int fv_cancel(fv_server* s, unsigned long long ticket);
+typedef struct fv_server_stats {
+  long long submitted, admitted, completed, cancelled, failed;
+  long long launches, cell_steps;
+  int resident, queued;
+  size_t arena_used, arena_peak;
+} fv_server_stats;
+int fv_server_get_stats(fv_server* s, fv_server_stats* out);
+int fv_server_destroy(fv_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FV_H */

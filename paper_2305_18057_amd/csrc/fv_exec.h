@@ -1,0 +1,54 @@
+// Launch sequencing shared by the grid API and the server: a step plan is a
+// set of tile lists (2D, 3D with 4 or 8 rows per tile) over one block table
+// and one instance table.  One step = stage 1, 2, 3 over every list, then the
+// per-instance finalize.  Steps are replayed from captured hipGraphs.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <vector>
+
+#include "fv_device.h"
+
+namespace fvexec {
+
+enum { kSet2D = 0, kSet3D4 = 1, kSet3D8 = 2 };
+
+struct LaunchSet {
+  fvk::DevTile* tiles = nullptr;
+  int* ntiles_dev = nullptr;  // device-resident count (graphs read it at run time)
+  int ntiles = 0;             // host view, sizes the persistent grid
+  int kind = kSet2D;
+  int max_grid = 0;           // 0: as many workgroups as co-reside on the device
+};
+
+struct StepPlan {
+  fvk::DevBlock* blocks = nullptr;
+  fvk::DevInstance* insts = nullptr;
+  const int* active = nullptr;  // device list of instance indices (nullptr: 0..ninst-1)
+  int ninst = 0;
+  std::vector<LaunchSet> sets;
+};
+
+class GraphCache {
+ public:
+  ~GraphCache() { clear(); }
+  void clear();
+  hipGraphExec_t get(int key) const {
+    auto it = m_.find(key);
+    return it == m_.end() ? nullptr : it->second;
+  }
+  void put(int key, hipGraphExec_t e) { m_[key] = e; }
+
+ private:
+  std::map<int, hipGraphExec_t> m_;
+};
+
+int graph_chunk();                       // steps per captured graph
+int launch_grid(const LaunchSet& s, int fp32);
+int enqueue_stage(const StepPlan& P, int mode, int fp32, double* rout, hipStream_t s);
+int enqueue_cfl(const StepPlan& P, hipStream_t s);
+// nsteps full steps; with a cache, replays (and captures on first use) a graph
+int enqueue_steps(const StepPlan& P, int fp32, int nsteps, hipStream_t s, GraphCache* cache);
+
+}  // namespace fvexec

@@ -1,0 +1,136 @@
+// Launch sequencing and hipGraph capture of RK steps.
+#include "fv_exec.h"
+
+#include <algorithm>
+#include <cstdlib>
+
+#include "fv_launch.h"
+#include "fv_runtime.h"
+
+namespace fvexec {
+
+void GraphCache::clear() {
+  for (auto& kv : m_)
+    if (kv.second) (void)hipGraphExecDestroy(kv.second);
+  m_.clear();
+}
+
+int graph_chunk() {
+  static int c = 0;
+  if (c == 0) {
+    const char* e = getenv("FV_GRAPH_STEPS");
+    c = e ? std::max(1, atoi(e)) : 10;
+  }
+  return c;
+}
+
+static bool graphs_enabled() {
+  static int on = -1;
+  if (on < 0) {
+    const char* e = getenv("FV_NO_GRAPH");
+    on = (e && e[0] == '1') ? 0 : 1;
+  }
+  return on == 1;
+}
+
+int launch_grid(const LaunchSet& s, int fp32) {
+  if (s.ntiles <= 0) return 0;
+  int cap;
+  if (s.kind == kSet2D) {
+    cap = fvrt::occupancy_blocks(fvk::stage2d_kernel_ptr(1, fp32), 256);
+    const int need = (s.ntiles + 3) / 4;
+    cap = std::min(cap, need);
+  } else {
+    const int ny = s.kind == kSet3D8 ? 8 : 4;
+    cap = fvrt::occupancy_blocks(fvk::stage3d_kernel_ptr(1, fp32, ny), 64 * (ny + 1));
+    cap = std::min(cap, s.ntiles);
+  }
+  if (s.max_grid > 0) cap = std::min(cap, s.max_grid);
+  return std::max(cap, 1);
+}
+
+int enqueue_stage(const StepPlan& P, int mode, int fp32, double* rout, hipStream_t st) {
+  for (const LaunchSet& s : P.sets) {
+    if (s.ntiles <= 0) continue;
+    const int grid = launch_grid(s, fp32);
+    hipError_t e;
+    if (s.kind == kSet2D)
+      e = fvk::launch_stage2d(mode, fp32, grid, 256, st, s.tiles, s.ntiles_dev, P.blocks, P.insts, rout);
+    else
+      e = fvk::launch_stage3d(mode, fp32, s.kind == kSet3D8 ? 8 : 4, grid, st, s.tiles, s.ntiles_dev,
+                              P.blocks, P.insts, rout);
+    if (e != hipSuccess)
+      return fvrt::set_error(FV_E_DEVICE, "stage launch failed: %s", hipGetErrorString(e));
+  }
+  return FV_OK;
+}
+
+int enqueue_cfl(const StepPlan& P, hipStream_t st) {
+  for (const LaunchSet& s : P.sets) {
+    if (s.ntiles <= 0) continue;
+    hipError_t e;
+    if (s.kind == kSet2D)
+      e = fvk::launch_cfl2d(std::max(1, std::min((s.ntiles + 3) / 4, 4096)), 256, st, s.tiles,
+                            s.ntiles_dev, P.blocks, P.insts);
+    else
+      e = fvk::launch_cfl3d(std::max(1, std::min(s.ntiles, 8192)), 256, st, s.tiles, s.ntiles_dev,
+                            P.blocks, P.insts);
+    if (e != hipSuccess)
+      return fvrt::set_error(FV_E_DEVICE, "time-step pass launch failed: %s", hipGetErrorString(e));
+  }
+  return FV_OK;
+}
+
+static int enqueue_one_step(const StepPlan& P, int fp32, hipStream_t st) {
+  for (int m = 1; m <= 3; ++m) {
+    const int e = enqueue_stage(P, m, fp32, nullptr, st);
+    if (e) return e;
+  }
+  const hipError_t e = fvk::launch_finalize(st, P.insts, P.active, P.ninst);
+  if (e != hipSuccess)
+    return fvrt::set_error(FV_E_DEVICE, "finalize launch failed: %s", hipGetErrorString(e));
+  return FV_OK;
+}
+
+int enqueue_steps(const StepPlan& P, int fp32, int nsteps, hipStream_t st, GraphCache* cache) {
+  if (nsteps <= 0) return FV_OK;
+  if (!cache || !graphs_enabled()) {
+    for (int k = 0; k < nsteps; ++k) {
+      const int e = enqueue_one_step(P, fp32, st);
+      if (e) return e;
+    }
+    return FV_OK;
+  }
+  const int key = nsteps * 2 + (fp32 ? 1 : 0);
+  hipGraphExec_t ex = cache->get(key);
+  if (!ex) {
+    hipStream_t cs;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+      return fvrt::set_error(FV_E_DEVICE, "capture stream creation failed");
+    hipGraph_t gr = nullptr;
+    int err = FV_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      return fvrt::set_error(FV_E_DEVICE, "graph capture could not start");
+    }
+    for (int k = 0; k < nsteps && !err; ++k) err = enqueue_one_step(P, fp32, cs);
+    const hipError_t ec = hipStreamEndCapture(cs, &gr);
+    (void)hipStreamDestroy(cs);
+    if (err) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return err;
+    }
+    if (ec != hipSuccess || !gr)
+      return fvrt::set_error(FV_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (ei != hipSuccess)
+      return fvrt::set_error(FV_E_DEVICE, "graph instantiation failed: %s", hipGetErrorString(ei));
+    cache->put(key, ex);
+  }
+  const hipError_t e = hipGraphLaunch(ex, st);
+  if (e != hipSuccess) return fvrt::set_error(FV_E_DEVICE, "graph launch failed: %s", hipGetErrorString(e));
+  return FV_OK;
+}
+
+}  // namespace fvexec

@@ -1,0 +1,463 @@
+// Grid API of the C ABI: one instance in a caller-supplied workspace.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "fv_exec.h"
+#include "fv_runtime.h"
+
+using namespace fvrt;
+
+struct fv_grid {
+  HostGrid hg;
+  InstLayout L;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  fvk::DevBlock* d_blocks = nullptr;
+  fvk::DevInstance* d_inst = nullptr;
+  int* d_ntiles = nullptr;
+  fvk::DevTile* d_tiles = nullptr;
+  double* d_part = nullptr;
+  fvk::GhostSeg* d_segs = nullptr;
+  double* d_u[3] = {nullptr, nullptr, nullptr};
+  std::vector<fvk::DevBlock> hblocks;
+  std::vector<fvk::DevTile> htiles;
+  fvk::DevInstance hinst;
+  TileShape shape;
+  fvexec::StepPlan plan;
+  fvexec::GraphCache graphs;
+  int have_state = 0;
+  double last_ms[4] = {0, 0, 0, 0};
+};
+
+namespace {
+
+int upload_tiles(fv_grid* g) {
+  build_tiles(g->hg, g->shape, 0, 0, g->htiles);
+  const int nt = (int)g->htiles.size();
+  if (nt > g->L.max_tiles) return set_error(FV_E_INVAL, "tile list exceeds its capacity");
+  FV_HIP(hipMemcpyAsync(g->d_tiles, g->htiles.data(), sizeof(fvk::DevTile) * nt,
+                        hipMemcpyHostToDevice, g->stream));
+  FV_HIP(hipMemcpyAsync(g->d_ntiles, &nt, sizeof(int), hipMemcpyHostToDevice, g->stream));
+  g->hinst.ntiles = nt;
+  g->plan = fvexec::StepPlan();
+  g->plan.blocks = g->d_blocks;
+  g->plan.insts = g->d_inst;
+  g->plan.active = nullptr;
+  g->plan.ninst = 1;
+  fvexec::LaunchSet ls;
+  ls.tiles = g->d_tiles;
+  ls.ntiles_dev = g->d_ntiles;
+  ls.ntiles = nt;
+  ls.kind = g->hg.ndim == 2 ? fvexec::kSet2D : (g->shape.ny == 8 ? fvexec::kSet3D8 : fvexec::kSet3D4);
+  g->plan.sets.push_back(ls);
+  g->graphs.clear();
+  // the tile list and the instance's tile count must be on the device before
+  // the next launch; the caller's stream orders that
+  FV_HIP(hipStreamSynchronize(g->stream));
+  return FV_OK;
+}
+
+int put_inst(fv_grid* g, bool whole) {
+  const size_t n = whole ? sizeof(fvk::DevInstance) : offsetof(fvk::DevInstance, t);
+  FV_HIP(hipMemcpyAsync(g->d_inst, &g->hinst, n, hipMemcpyHostToDevice, g->stream));
+  return FV_OK;
+}
+
+int get_inst(fv_grid* g) {
+  FV_HIP(hipMemcpyAsync(&g->hinst, g->d_inst, sizeof(fvk::DevInstance), hipMemcpyDeviceToHost,
+                        g->stream));
+  FV_HIP(hipStreamSynchronize(g->stream));
+  return FV_OK;
+}
+
+void fill_info(const fv_grid* g, fv_step_info* info) {
+  if (!info) return;
+  const fvk::DevInstance& I = g->hinst;
+  info->steps = I.steps;
+  info->t = I.t;
+  info->dt_last = I.dt_last;
+  for (int v = 0; v < 5; ++v) info->norms[v] = I.norms[v];
+  info->norm = I.norm;
+  info->drop = I.drop;
+  info->flags = I.flags;
+}
+
+int cfl_pass(fv_grid* g) {
+  const int err = fvexec::enqueue_cfl(g->plan, g->stream);
+  if (err) return err;
+  FV_HIP(fvk::launch_cfl_init(g->stream, g->d_inst, nullptr, 1));
+  return get_inst(g);
+}
+
+}  // namespace
+
+extern "C" size_t fv_grid_workspace_bytes(const fv_grid_desc* desc, int precision) {
+  (void)precision;
+  HostGrid hg;
+  if (validate_and_copy(desc, hg) != FV_OK) return 0;
+  return layout_of(hg).total;
+}
+
+extern "C" int fv_create_grid(const fv_grid_desc* desc, void* d_workspace, size_t bytes,
+                              void* hip_stream, fv_grid** out) {
+  if (!out) return set_error(FV_E_INVAL, "null output handle");
+  *out = nullptr;
+  fv_grid* g = new (std::nothrow) fv_grid();
+  if (!g) return set_error(FV_E_NOMEM, "host allocation failed");
+  int st = validate_and_copy(desc, g->hg);
+  if (st) {
+    delete g;
+    return st;
+  }
+  g->L = layout_of(g->hg);
+  if (!d_workspace || bytes < g->L.total) {
+    delete g;
+    return set_error(FV_E_NOMEM, "workspace of %zu bytes, need %zu", bytes, g->L.total);
+  }
+  if (((uintptr_t)d_workspace) % kAlign) {
+    delete g;
+    return set_error(FV_E_INVAL, "workspace must be %zu-byte aligned", kAlign);
+  }
+  g->stream = (hipStream_t)hip_stream;
+  g->ws = (char*)d_workspace;
+  g->ws_bytes = bytes;
+  g->d_blocks = (fvk::DevBlock*)(g->ws + g->L.blocks);
+  g->d_inst = (fvk::DevInstance*)(g->ws + g->L.inst);
+  g->d_ntiles = (int*)(g->ws + g->L.ntiles);
+  g->d_tiles = (fvk::DevTile*)(g->ws + g->L.tiles);
+  g->d_part = (double*)(g->ws + g->L.part);
+  g->d_segs = (fvk::GhostSeg*)(g->ws + g->L.segs);
+  for (int s = 0; s < 3; ++s) g->d_u[s] = (double*)(g->ws + g->L.u[s]);
+
+  build_blocks(g->hg, g->ws, g->L, 0, g->hblocks, 0);
+  std::vector<fvk::GhostSeg> segs;
+  build_segs(g->hg, segs);
+  auto fail = [&](int e) {
+    delete g;
+    return e;
+  };
+  if (hipMemcpyAsync(g->d_blocks, g->hblocks.data(), sizeof(fvk::DevBlock) * g->hblocks.size(),
+                     hipMemcpyHostToDevice, g->stream) != hipSuccess ||
+      hipMemcpyAsync(g->d_segs, segs.data(), sizeof(fvk::GhostSeg) * segs.size(),
+                     hipMemcpyHostToDevice, g->stream) != hipSuccess)
+    return fail(set_error(FV_E_DEVICE, "upload of block descriptors failed"));
+  // node coordinates
+  {
+    size_t noff = 0;
+    for (int b = 0; b < g->hg.nblocks; ++b) {
+      if (g->hg.xs[b].empty()) continue;
+      const size_t nn = g->hg.xs[b].size();
+      char* dst = g->ws + g->L.nodes + noff * sizeof(double);
+      if (hipMemcpyAsync(dst, g->hg.xs[b].data(), nn * sizeof(double), hipMemcpyHostToDevice,
+                         g->stream) != hipSuccess ||
+          hipMemcpyAsync(dst + nn * sizeof(double), g->hg.ys[b].data(), nn * sizeof(double),
+                         hipMemcpyHostToDevice, g->stream) != hipSuccess)
+        return fail(set_error(FV_E_DEVICE, "upload of node coordinates failed"));
+      noff += 2 * nn;
+    }
+  }
+  std::memset(&g->hinst, 0, sizeof(g->hinst));
+  fv_params p;
+  fv_default_params(&p);
+  params_to_inst(&p, g->hg.gamma, g->hinst);
+  g->hinst.ndim = g->hg.ndim;
+  g->hinst.nv = g->hg.nv;
+  g->hinst.ncells = g->hg.ncells;
+  g->hinst.part = g->d_part;
+  g->hinst.step_limit = 0;
+  g->hinst.stopped = 1;
+  g->hinst.flags = fvk::FLAG_NONPHYS;  // no state yet
+  // tile shape: autotune table for this size class, else the default
+  TileShape sh = default_shape(g->hg);
+  const char* tp = tune_path(nullptr);
+  TileShape tsh;
+  if (tune_lookup(tp, tune_key(g->hg, FV_FP64), tsh)) sh = tsh;
+  g->shape = sh;
+  st = upload_tiles(g);
+  if (st) return fail(st);
+  st = put_inst(g, true);
+  if (st) return fail(st);
+  if (hipStreamSynchronize(g->stream) != hipSuccess)
+    return fail(set_error(FV_E_DEVICE, "stream synchronisation failed"));
+  *out = g;
+  return FV_OK;
+}
+
+extern "C" int fv_destroy_grid(fv_grid* g) {
+  if (!g) return FV_E_INVAL;
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  g->graphs.clear();
+  delete g;
+  return FV_OK;
+}
+
+extern "C" int fv_set_state(fv_grid* g, const double* U, int on_device) {
+  if (!g || !U) return set_error(FV_E_INVAL, "null argument");
+  FV_HIP(hipMemcpyAsync(g->d_u[0], U, sizeof(double) * g->hg.state_size,
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, g->stream));
+  fvk::DevInstance& I = g->hinst;
+  I.t = I.dt = I.dt_last = I.raw_min = I.norm_first = I.norm = I.drop = 0.0;
+  for (int v = 0; v < 5; ++v) I.norms[v] = I.rnorms[v] = 0.0;
+  I.steps = 0;
+  I.flags = 0;
+  I.stopped = 0;
+  I.have_first = 0;
+  I.last_step = 0;
+  int st = put_inst(g, true);
+  if (st) return st;
+  st = cfl_pass(g);
+  if (st) return st;
+  g->have_state = 1;
+  if (g->hinst.flags & fvk::FLAG_NONPHYS)
+    return set_error(FV_E_NONPHYSICAL, "initial state has a cell with rho <= 0, p <= 0 or a non-finite value");
+  return FV_OK;
+}
+
+extern "C" int fv_get_state(const fv_grid* gc, double* U, int on_device) {
+  fv_grid* g = const_cast<fv_grid*>(gc);
+  if (!g || !U) return set_error(FV_E_INVAL, "null argument");
+  FV_HIP(hipMemcpyAsync(U, g->d_u[0], sizeof(double) * g->hg.state_size,
+                        on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, g->stream));
+  FV_HIP(hipStreamSynchronize(g->stream));
+  return FV_OK;
+}
+
+extern "C" int fv_residual(fv_grid* g, const fv_params* p, double* R, int on_device,
+                           double norms[5]) {
+  if (!g) return set_error(FV_E_INVAL, "null grid");
+  int st = check_params(p);
+  if (st) return st;
+  if (!g->have_state) return set_error(FV_E_INVAL, "no state set");
+  params_to_inst(p, g->hg.gamma, g->hinst);
+  st = put_inst(g, false);
+  if (st) return st;
+  double* dst = (R && on_device) ? R : g->d_u[1];
+  st = fvexec::enqueue_stage(g->plan, 0, p->precision == FV_FP32_FLUX, dst, g->stream);
+  if (st) return st;
+  FV_HIP(fvk::launch_rnorms(g->stream, g->d_inst, nullptr, 1));
+  if (R && !on_device)
+    FV_HIP(hipMemcpyAsync(R, g->d_u[1], sizeof(double) * g->hg.state_size, hipMemcpyDeviceToHost,
+                          g->stream));
+  st = get_inst(g);
+  if (st) return st;
+  if (norms)
+    for (int v = 0; v < 5; ++v) norms[v] = g->hinst.rnorms[v];
+  return FV_OK;
+}
+
+extern "C" size_t fv_ghost_count(const fv_grid* g) { return g ? (size_t)g->L.ghost_doubles : 0; }
+
+extern "C" int fv_ghosts(fv_grid* g, double* G, int on_device) {
+  if (!g || !G) return set_error(FV_E_INVAL, "null argument");
+  if (!g->have_state) return set_error(FV_E_INVAL, "no state set");
+  double* dst = G;
+  if (!on_device) {
+    if (g->L.ghost_doubles > g->hg.state_size)
+      return set_error(FV_E_NOMEM, "ghost dump larger than a state buffer: pass a device buffer");
+    dst = g->d_u[2];
+  }
+  FV_HIP(fvk::launch_ghosts(g->stream, g->d_blocks, g->d_segs, g->L.nseg, g->L.ghost_cells,
+                            g->hg.nv, dst));
+  if (!on_device)
+    FV_HIP(hipMemcpyAsync(G, dst, sizeof(double) * g->L.ghost_doubles, hipMemcpyDeviceToHost,
+                          g->stream));
+  FV_HIP(hipStreamSynchronize(g->stream));
+  return FV_OK;
+}
+
+static int run_steps(fv_grid* g, const fv_params* p, long long nsteps, double drop_tol,
+                     fv_step_info* info) {
+  if (!g) return set_error(FV_E_INVAL, "null grid");
+  int st = check_params(p);
+  if (st) return st;
+  if (!g->have_state) return set_error(FV_E_INVAL, "no state set");
+  if (nsteps < 0) return set_error(FV_E_INVAL, "negative step count");
+  params_to_inst(p, g->hg.gamma, g->hinst);
+  g->hinst.drop_tol = drop_tol;
+  g->hinst.step_limit = g->hinst.steps + nsteps;
+  st = put_inst(g, false);
+  if (st) return st;
+  FV_HIP(fvk::launch_prepare(g->stream, g->d_inst, nullptr, 1));
+  const int fp32 = p->precision == FV_FP32_FLUX;
+  const int chunk = fvexec::graph_chunk();
+  long long left = nsteps;
+  long long since_check = 0;
+  const bool check = drop_tol > 0.0;
+  while (left > 0) {
+    const int c = (int)std::min<long long>(left, chunk);
+    st = fvexec::enqueue_steps(g->plan, fp32, c, g->stream, &g->graphs);
+    if (st) return st;
+    left -= c;
+    since_check += c;
+    if (check && since_check >= 4LL * chunk && left > 0) {
+      since_check = 0;
+      st = get_inst(g);
+      if (st) return st;
+      if (g->hinst.stopped) break;
+    }
+  }
+  st = get_inst(g);
+  if (st) return st;
+  fill_info(g, info);
+  if (g->hinst.flags & fvk::FLAG_NONPHYS)
+    return set_error(FV_E_NONPHYSICAL, "state turned non-physical after %lld steps", g->hinst.steps);
+  return FV_OK;
+}
+
+extern "C" int fv_step(fv_grid* g, const fv_params* p, int nsteps, fv_step_info* info) {
+  return run_steps(g, p, nsteps, 0.0, info);
+}
+
+extern "C" int fv_step_timed(fv_grid* g, const fv_params* p, int nsteps, fv_step_info* info,
+                             double stage_ms[4]) {
+  if (!g || !stage_ms) return set_error(FV_E_INVAL, "null argument");
+  int st = check_params(p);
+  if (st) return st;
+  if (!g->have_state) return set_error(FV_E_INVAL, "no state set");
+  if (nsteps < 0) return set_error(FV_E_INVAL, "negative step count");
+  params_to_inst(p, g->hg.gamma, g->hinst);
+  g->hinst.drop_tol = 0.0;
+  g->hinst.step_limit = g->hinst.steps + nsteps;
+  st = put_inst(g, false);
+  if (st) return st;
+  FV_HIP(fvk::launch_prepare(g->stream, g->d_inst, nullptr, 1));
+  const int fp32 = p->precision == FV_FP32_FLUX;
+  std::vector<hipEvent_t> ev(5 * (size_t)std::max(nsteps, 1));
+  for (auto& e : ev) FV_HIP(hipEventCreate(&e));
+  for (int k = 0; k < nsteps; ++k) {
+    hipEvent_t* E = &ev[5 * (size_t)k];
+    FV_HIP(hipEventRecord(E[0], g->stream));
+    for (int m = 1; m <= 3; ++m) {
+      st = fvexec::enqueue_stage(g->plan, m, fp32, nullptr, g->stream);
+      if (st) break;
+      FV_HIP(hipEventRecord(E[m], g->stream));
+    }
+    if (st) break;
+    FV_HIP(fvk::launch_finalize(g->stream, g->d_inst, nullptr, 1));
+    FV_HIP(hipEventRecord(E[4], g->stream));
+  }
+  if (!st) {
+    FV_HIP(hipStreamSynchronize(g->stream));
+    for (int s = 0; s < 4; ++s) stage_ms[s] = 0.0;
+    for (int k = 0; k < nsteps; ++k)
+      for (int s = 0; s < 4; ++s) {
+        float ms = 0.f;
+        FV_HIP(hipEventElapsedTime(&ms, ev[5 * (size_t)k + s], ev[5 * (size_t)k + s + 1]));
+        stage_ms[s] += ms;
+      }
+    for (int s = 0; s < 4; ++s) g->last_ms[s] = stage_ms[s];
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  if (st) return st;
+  st = get_inst(g);
+  if (st) return st;
+  fill_info(g, info);
+  if (g->hinst.flags & fvk::FLAG_NONPHYS)
+    return set_error(FV_E_NONPHYSICAL, "state turned non-physical after %lld steps", g->hinst.steps);
+  return FV_OK;
+}
+
+extern "C" int fv_solve(fv_grid* g, const fv_params* p, double drop_tol, long long max_steps,
+                        fv_step_info* info) {
+  if (!(drop_tol >= 0.0)) return set_error(FV_E_INVAL, "drop_tol must be >= 0");
+  return run_steps(g, p, max_steps, drop_tol, info);
+}
+
+extern "C" int fv_grid_get_stats(const fv_grid* g, fv_grid_stats* out) {
+  if (!g || !out) return set_error(FV_E_INVAL, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  out->cells = g->hg.ncells;
+  out->tiles = (long long)g->htiles.size();
+  out->tile_rows = g->shape.rows;
+  out->tile_cols = 64;
+  out->tile_ny = g->hg.ndim == 3 ? g->shape.ny : 1;
+  out->launch_blocks = g->plan.sets.empty() ? 0 : fvexec::launch_grid(g->plan.sets[0], 0);
+  out->workspace_bytes = g->L.total;
+  for (int s = 0; s < 4; ++s) out->last_stage_ms[s] = g->last_ms[s];
+  return FV_OK;
+}
+
+// Candidate tile shapes of the grid's size class are timed on the device with
+// the grid's own state (saved on the host and restored afterwards).
+extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
+  if (!g) return set_error(FV_E_INVAL, "null grid");
+  int st = check_params(p);
+  if (st) return st;
+  if (!g->have_state) return set_error(FV_E_INVAL, "no state set");
+  std::vector<double> saved((size_t)g->hg.state_size);
+  st = fv_get_state(g, saved.data(), 0);
+  if (st) return st;
+  const fvk::DevInstance keep = g->hinst;
+  std::vector<TileShape> cands;
+  if (g->hg.ndim == 2) {
+    for (int r : {4, 8, 16, 32, 64}) {
+      TileShape s;
+      s.rows = r;
+      s.ny = 1;
+      cands.push_back(s);
+    }
+  } else {
+    for (int y : {4, 8})
+      for (int r : {8, 16, 32, 64}) {
+        TileShape s;
+        s.rows = r;
+        s.ny = y;
+        cands.push_back(s);
+      }
+  }
+  const int fp32 = p->precision == FV_FP32_FLUX;
+  TileShape best = g->shape;
+  double best_ms = 1e30;
+  hipEvent_t e0, e1;
+  FV_HIP(hipEventCreate(&e0));
+  FV_HIP(hipEventCreate(&e1));
+  for (const TileShape& c : cands) {
+    g->shape = c;
+    st = upload_tiles(g);
+    if (st) break;
+    // same starting state for every candidate
+    g->hinst = keep;
+    params_to_inst(p, g->hg.gamma, g->hinst);
+    g->hinst.step_limit = keep.steps + 1000000;
+    g->hinst.drop_tol = 0.0;
+    g->hinst.stopped = 0;
+    g->hinst.flags = 0;
+    if ((st = put_inst(g, true))) break;
+    if ((st = fvexec::enqueue_steps(g->plan, fp32, 1, g->stream, nullptr))) break;  // warm-up
+    FV_HIP(hipEventRecord(e0, g->stream));
+    const int reps = 3;
+    if ((st = fvexec::enqueue_steps(g->plan, fp32, reps, g->stream, nullptr))) break;
+    FV_HIP(hipEventRecord(e1, g->stream));
+    FV_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    FV_HIP(hipEventElapsedTime(&ms, e0, e1));
+    const double per = ms / reps;
+    if (per < best_ms) {
+      best_ms = per;
+      best = c;
+    }
+    FV_HIP(hipMemcpyAsync(g->d_u[0], saved.data(), sizeof(double) * saved.size(),
+                          hipMemcpyHostToDevice, g->stream));
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st) return st;
+  g->shape = best;
+  st = upload_tiles(g);
+  if (st) return st;
+  FV_HIP(hipMemcpyAsync(g->d_u[0], saved.data(), sizeof(double) * saved.size(),
+                        hipMemcpyHostToDevice, g->stream));
+  g->hinst = keep;
+  st = put_inst(g, true);
+  if (st) return st;
+  // the per-tile spectral minima of the restored state
+  st = cfl_pass(g);
+  if (st) return st;
+  g->hinst.steps = keep.steps;
+  g->hinst.t = keep.t;
+  tune_store(tune_path(cache_path), tune_key(g->hg, p->precision), best, best_ms);
+  return FV_OK;
+}

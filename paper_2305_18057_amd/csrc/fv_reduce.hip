@@ -1,0 +1,203 @@
+// Per-instance bookkeeping kernels: parameters -> time step and stop flags,
+// step-end reductions of the per-tile partials (fixed order: lane l sums
+// tiles l, l+64, ... then a fixed butterfly), and the ghost dump.
+#include "fv_device.h"
+#include "fv_launch.h"
+
+namespace fvk {
+
+namespace {
+
+// time step of the coming step: dt_fixed, or CFL times the spectral minimum
+// of U^n; a positive t_end clamps the step so that t lands on t_end and stops
+// the instance once t has reached it
+__device__ void next_dt(DevInstance& I) {
+  double dt = I.dt_fixed > 0.0 ? I.dt_fixed : I.cfl * I.raw_min;
+  int last = 0;
+  if (I.t_end > 0.0) {
+    if (I.t >= I.t_end) {
+      I.stopped = 1;
+      I.flags |= FLAG_TEND;
+    } else if (dt >= I.t_end - I.t) {
+      dt = I.t_end - I.t;
+      last = 1;
+    }
+  }
+  I.dt = dt;
+  I.last_step = last;
+}
+
+__global__ void k_prepare(DevInstance* insts, const int* active, int n) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  DevInstance& I = insts[active ? active[x] : x];
+  I.flags &= FLAG_NONPHYS;
+  I.stopped = (I.flags & FLAG_NONPHYS) ? 1 : 0;
+  if (I.steps >= I.step_limit) {
+    I.stopped = 1;
+    I.flags |= FLAG_STEPLIMIT;
+  }
+  if (!I.stopped) next_dt(I);
+}
+
+__device__ void reduce_parts(const DevInstance& I, int lane, double (&s)[5], double& mn, int& bad,
+                             bool sums, bool mins) {
+  double a[5] = {0, 0, 0, 0, 0};
+  double m = INFINITY;
+  int b = 0;
+  for (int t = lane; t < I.ntiles; t += kWave) {
+    const double* p = I.part + (long long)t * kPartStride;
+    if (sums) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) a[v] += p[v];
+    }
+    if (mins) {
+      m = fmin(m, p[5]);
+      b |= p[6] != 0.0;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) s[v] = wave_sum(a[v]);
+  mn = wave_min(m);
+  bad = wave_or(b);
+}
+
+__device__ void norms_from_sums(const DevInstance& I, const double (&s)[5], double* norms,
+                                double& comb) {
+  double cs = 0.0;
+  for (int v = 0; v < 5; ++v) {
+    norms[v] = v < I.nv ? sqrt(s[v] / (double)I.ncells) : 0.0;
+    if (v < I.nv) {
+      const double q = I.qref[v] != 0.0 ? I.qref[v] : 1.0;
+      const double r = norms[v] / q;
+      cs += r * r;
+    }
+  }
+  comb = sqrt(cs);
+}
+
+__global__ void k_finalize(DevInstance* insts, const int* active, int n) {
+  const int x = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (x >= n) return;
+  DevInstance& I = insts[active ? active[x] : x];
+  if (I.stopped) return;
+  double s[5], mn;
+  int bad;
+  reduce_parts(I, lane, s, mn, bad, true, true);
+  if (lane != 0) return;
+  double norms[5], comb;
+  norms_from_sums(I, s, norms, comb);
+  for (int v = 0; v < 5; ++v) I.norms[v] = norms[v];
+  I.norm = comb;
+  if (!I.have_first) {
+    I.norm_first = comb;
+    I.have_first = 1;
+  }
+  I.drop = I.norm_first > 0.0 ? comb / I.norm_first : 0.0;
+  I.t = I.last_step ? I.t_end : I.t + I.dt;
+  I.dt_last = I.dt;
+  I.steps += 1;
+  I.raw_min = mn;
+  if (bad) {
+    I.flags |= FLAG_NONPHYS;
+    I.stopped = 1;
+  }
+  if (I.drop_tol > 0.0 && I.drop <= I.drop_tol) {
+    I.flags |= FLAG_CONVERGED;
+    I.stopped = 1;
+  }
+  if (I.steps >= I.step_limit) {
+    I.flags |= FLAG_STEPLIMIT;
+    I.stopped = 1;
+  }
+  if (!I.stopped) next_dt(I);
+}
+
+__global__ void k_cfl_init(DevInstance* insts, const int* active, int n) {
+  const int x = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (x >= n) return;
+  DevInstance& I = insts[active ? active[x] : x];
+  double s[5], mn;
+  int bad;
+  reduce_parts(I, lane, s, mn, bad, false, true);
+  if (lane != 0) return;
+  I.raw_min = mn;
+  I.flags = bad ? FLAG_NONPHYS : 0;
+  I.stopped = bad ? 1 : 0;
+}
+
+__global__ void k_rnorms(DevInstance* insts, const int* active, int n) {
+  const int x = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (x >= n) return;
+  DevInstance& I = insts[active ? active[x] : x];
+  double s[5], mn;
+  int bad;
+  reduce_parts(I, lane, s, mn, bad, true, false);
+  if (lane != 0) return;
+  double comb;
+  norms_from_sums(I, s, I.rnorms, comb);
+}
+
+// One thread per ghost cell.  Segment = (block, face): both layers.
+__global__ void k_ghosts(const DevBlock* __restrict__ blocks, const GhostSeg* __restrict__ segs,
+                         int nseg, long long ncells, int nv, double* __restrict__ out) {
+  const long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= ncells) return;
+  int s = 0;
+  while (s + 1 < nseg && segs[s + 1].cell_off <= x) ++s;
+  const GhostSeg& G = segs[s];
+  const long long loc = x - G.cell_off;
+  const long long per = (long long)G.n1 * G.n2;
+  const int g = 1 + (int)(loc / per);
+  const long long rem = loc % per;
+  const int t2 = (int)(rem / G.n1), t1 = (int)(rem % G.n1);
+  const DevBlock& B = blocks[G.blk];
+  const int d = G.face >> 1, side = G.face & 1;
+  const int n = d == 0 ? B.ni : (d == 1 ? B.nj : B.nk);
+  const int along = side == 0 ? -g : n - 1 + g;
+  int i, j, k;
+  if (d == 0) { i = along; j = t1; k = t2; }
+  else if (d == 1) { i = t1; j = along; k = t2; }
+  else { i = t1; j = t2; k = along; }
+  double q[5];
+  if (nv == 4) resolve_cell<4>(blocks, B, 0, i, j, k, q);
+  else resolve_cell<5>(blocks, B, 0, i, j, k, q);
+  double* o = out + G.out_off + (long long)(g - 1) * nv * per + rem;
+  for (int v = 0; v < nv; ++v) o[(long long)v * per] = q[v];
+}
+
+}  // namespace
+
+hipError_t launch_prepare(hipStream_t s, DevInstance* insts, const int* active, int n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prepare, dim3((n + 63) / 64), dim3(64), 0, s, insts, active, n);
+  return hipGetLastError();
+}
+hipError_t launch_finalize(hipStream_t s, DevInstance* insts, const int* active, int n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3((n + 3) / 4), dim3(256), 0, s, insts, active, n);
+  return hipGetLastError();
+}
+hipError_t launch_cfl_init(hipStream_t s, DevInstance* insts, const int* active, int n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cfl_init, dim3((n + 3) / 4), dim3(256), 0, s, insts, active, n);
+  return hipGetLastError();
+}
+hipError_t launch_rnorms(hipStream_t s, DevInstance* insts, const int* active, int n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rnorms, dim3((n + 3) / 4), dim3(256), 0, s, insts, active, n);
+  return hipGetLastError();
+}
+hipError_t launch_ghosts(hipStream_t s, const DevBlock* blocks, const GhostSeg* segs, int nseg,
+                         long long ncells, int nv, double* out) {
+  if (ncells <= 0) return hipSuccess;
+  const long long nb = (ncells + 255) / 256;
+  hipLaunchKernelGGL(k_ghosts, dim3((unsigned)nb), dim3(256), 0, s, blocks, segs, nseg, ncells, nv,
+                     out);
+  return hipGetLastError();
+}
+
+}  // namespace fvk

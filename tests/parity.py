@@ -1,0 +1,37 @@
+"""Error metrics of the GPU path against the CPU reference.
+
+U: e = max_v max_cells |dU_v| / max_cells |U_v|  (relative per variable, the
+   worst variable).  The paper compares the solutions of its CPU and GPU runs
+   to a relative difference below 1e-12 (Sec. 8); the same bound is used here.
+R: the residual is a sum of face fluxes that largely cancel, so its round-off
+   is relative to the size of those fluxes, not to R itself:
+   e_R = max_v max_cells |dR_v| / max_cells (sum over faces |F_v| ds).
+"""
+import numpy as np
+
+FP64_TOL = 1e-12
+FP32_STEP_TOL = 1e-5
+FP32_RUN_TOL = 1e-4
+
+
+def per_var(flat, case):
+    """Split a flat [block][var][k][j][i] array into nv arrays (all blocks)."""
+    nv = case.nv
+    parts = [[] for _ in range(nv)]
+    o = 0
+    for b in case.blocks:
+        n = b.ncells
+        for v in range(nv):
+            parts[v].append(np.asarray(flat[o:o + n]))
+            o += n
+    return [np.concatenate(p) for p in parts]
+
+
+def state_err(case, Ug, Uo):
+    g, o = per_var(Ug, case), per_var(Uo, case)
+    return max(float(np.max(np.abs(gv - ov)) / np.max(np.abs(ov))) for gv, ov in zip(g, o))
+
+
+def residual_err(case, Rg, Ro, scale):
+    g, o, s = per_var(Rg, case), per_var(Ro, case), per_var(scale, case)
+    return max(float(np.max(np.abs(gv - ov)) / np.max(sv)) for gv, ov, sv in zip(g, o, s))

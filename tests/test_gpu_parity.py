@@ -1,0 +1,383 @@
+"""GPU path (through the C ABI) against the CPU reference, element by element.
+
+FP64: relative error <= 1e-12 (U metric; R on the flux scale, see parity.py).
+FP32-flux: <= 1e-5 for one step from the same FP64 state, <= 1e-4 after N.
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2305_18057_amd import cases as CS
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_2305_18057_amd import fv
+    from oracle import oracle as O
+    fv.lib()
+    O.lib()
+    return fv, O
+
+
+def gpu_run(fv, case, nsteps, params=None):
+    g = fv.Grid(case)
+    g.set_state(case.state_flat())
+    info = g.step(params or case.params, nsteps) if nsteps else None
+    return g, info
+
+
+def check_residual(fv, O, case, params=None, tol=P.FP64_TOL):
+    params = params or case.params
+    g = fv.Grid(case)
+    g.set_state(case.state_flat())
+    Rg, ng = g.residual(params)
+    ref = O.OracleGrid(case)
+    Ro, no, scale = ref.residual(params, with_scale=True)
+    e = P.residual_err(case, Rg, Ro, scale)
+    say(f"  residual {case.name}: e_R = {e:.3e}")
+    assert e <= tol
+    nv = case.nv
+    assert np.allclose(ng[:nv], no[:nv], rtol=1e-11, atol=0)
+    return g
+
+
+def check_steps(fv, O, case, nsteps, params=None, tol=P.FP64_TOL, ref_params=None):
+    params = params or case.params
+    g, info = gpu_run(fv, case, nsteps, params)
+    Ug = g.get_state()
+    ref = O.OracleGrid(case)
+    io = ref.run(ref_params or params, nsteps)
+    Uo = ref.get_state()
+    e = P.state_err(case, Ug, Uo)
+    say(f"  {nsteps} steps {case.name} prec={params.precision}: e_U = {e:.3e}, "
+        f"t gpu {info['t']:.9g} ref {io['t']:.9g}")
+    assert info["steps"] == io["steps"]
+    assert e <= tol
+    assert abs(info["t"] - io["t"]) <= 1e-11 * abs(io["t"])
+    return g, info, io, e
+
+
+# ---------------------------------------------------------------------------
+# 2D uniform periodic vortex (128 x 64, 100 steps)
+# ---------------------------------------------------------------------------
+def test_vortex_residual(env):
+    fv, O = env
+    check_residual(fv, O, CS.vortex_2d())
+
+
+def test_vortex_100_steps(env):
+    fv, O = env
+    case = CS.vortex_2d()
+    g, info, io, e = check_steps(fv, O, case, 100)
+    assert abs(info["norm"] - io["norm"]) <= 1e-10 * io["norm"]
+    assert abs(info["drop"] - io["drop"]) <= 1e-10
+
+
+@pytest.mark.parametrize("limiter", [CS.UNLIMITED, CS.FIRST_ORDER])
+def test_vortex_limiter_variants(env, limiter):
+    fv, O = env
+    case = CS.vortex_2d(limiter=limiter)
+    check_residual(fv, O, case)
+    check_steps(fv, O, case, 20)
+
+
+def test_periodic_conservation_on_gpu(env):
+    fv, O = env
+    case = CS.vortex_2d()
+    g, info = gpu_run(fv, case, 100)
+    vol = case.blocks[0].h[0] * case.blocks[0].h[1]
+    t0 = case.state_flat().reshape(4, -1).sum(axis=1) * vol
+    t1 = g.get_state().reshape(4, -1).sum(axis=1) * vol
+    assert np.all(np.abs(t1 - t0) <= 1e-13 * np.abs(t0) + 1e-12), (t1 - t0)
+
+
+def test_rerun_bitwise(env):
+    fv, O = env
+    case = CS.inlet_case(256, 64, 2)
+    a, _ = gpu_run(fv, case, 30)
+    b, _ = gpu_run(fv, case, 30)
+    assert np.array_equal(a.get_state(), b.get_state())
+
+
+# ---------------------------------------------------------------------------
+# boundary rules
+# ---------------------------------------------------------------------------
+def perturbed(case, seed=9, amp=0.01):
+    rng = np.random.default_rng(seed)
+    U = case.state_flat()
+    U = U * (1 + amp * rng.standard_normal(U.size))
+    case.U0 = case.split_flat(U)
+    return case
+
+
+def test_ghost_values(env):
+    fv, O = env
+    for case in (perturbed(CS.inlet_case(96, 24, 3, angle_deg=5.0)), CS.vortex_2d(40, 24),
+                 perturbed(CS.blobs_case(20, nblobs=2))):
+        g = fv.Grid(case)
+        g.set_state(case.state_flat())
+        Gg = g.ghosts()
+        Go = O.OracleGrid(case).ghosts()
+        assert Gg.shape == Go.shape
+        d = np.max(np.abs(Gg - Go) / (np.abs(Go) + 1e-300))
+        say(f"  ghosts {case.name}: max rel diff {d:.2e}")
+        assert d <= 1e-14
+
+
+def ragged_2d():
+    ni, nj = 100, 37
+    prim = CS.inlet_freestream(2.5, 12.0)
+    X, Y = CS.inlet_mesh(ni, nj)
+    bcs = [CS.BC(CS.INFLOW, prim=prim), CS.BC(CS.EXTRAP), CS.BC(CS.SLIPWALL), CS.BC(CS.EXTRAP),
+           CS.BC(CS.PERIODIC), CS.BC(CS.PERIODIC)]
+    case = CS.uniform_2d(ni, nj, prim, bcs, x=X, y=Y, name="ragged_2d")
+    case.params = CS.Params(qref=CS.qref_of(prim, 2))
+    return perturbed(case, amp=0.02)
+
+
+def test_ragged_2d(env):
+    fv, O = env
+    case = ragged_2d()
+    check_residual(fv, O, case)
+    check_steps(fv, O, case, 25)
+
+
+def test_tiny_grids(env):
+    fv, O = env
+    for ni, nj in [(1, 1), (3, 2), (2, 5), (65, 3)]:
+        case = perturbed(CS.vortex_2d(ni, nj, noise=0.0), seed=ni * 10 + nj, amp=0.05)
+        case.name = f"tiny_{ni}x{nj}"
+        check_residual(fv, O, case)
+        check_steps(fv, O, case, 5)
+
+
+def test_tile_shape_independence(env, tmp_path):
+    fv, O = env
+    case = CS.inlet_case(200, 72, 2)
+    outs = []
+    for rows in (4, 16, 64):
+        path = tmp_path / f"t{rows}.json"
+        hg = CS.inlet_case(200, 72, 2)
+        ncell = hg.ncells
+        cls = int(math.floor(math.log2(ncell)))
+        path.write_text(json.dumps({f"2d_fp64_c{cls}": {"rows": rows, "ny": 1, "ms": 0.0}}))
+        os.environ["FV_AUTOTUNE_CACHE"] = str(path)
+        try:
+            g, _ = gpu_run(fv, case, 12)
+            assert g.stats()["tile_rows"] == rows
+            outs.append(g.get_state())
+        finally:
+            del os.environ["FV_AUTOTUNE_CACHE"]
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+# ---------------------------------------------------------------------------
+# 2D inlet-like multi-block curvilinear mesh
+# ---------------------------------------------------------------------------
+def test_inlet_small_fp64(env):
+    fv, O = env
+    case = perturbed(CS.inlet_case(4 * 64, 32, 4, angle_deg=3.0))
+    check_residual(fv, O, case)
+    check_steps(fv, O, case, 50)
+
+
+def test_inlet_small_fp32_flux(env):
+    fv, O = env
+    case = perturbed(CS.inlet_case(4 * 64, 32, 4, angle_deg=3.0))
+    p32 = CS.Params(**{**case.params.__dict__, "precision": CS.FP32_FLUX})
+    g, info = gpu_run(fv, case, 1, p32)
+    ref = O.OracleGrid(case)
+    ref.run(case.params, 1)
+    e1 = P.state_err(case, g.get_state(), ref.get_state())
+    g.step(p32, 49)
+    ref.run(case.params, 49)
+    eN = P.state_err(case, g.get_state(), ref.get_state())
+    say(f"  fp32-flux inlet small: 1 step {e1:.2e}, 50 steps {eN:.2e}")
+    assert e1 <= P.FP32_STEP_TOL and eN <= P.FP32_RUN_TOL
+    assert e1 > 1e-12  # the arithmetic really ran in FP32
+
+
+def test_inlet_full_residual_and_steps(env):
+    fv, O = env
+    case = CS.inlet_2d()
+    check_residual(fv, O, case)
+    check_steps(fv, O, case, 10)
+
+
+def test_inlet_full_fp32_flux(env):
+    fv, O = env
+    case = CS.inlet_2d()
+    p32 = CS.Params(**{**case.params.__dict__, "precision": CS.FP32_FLUX})
+    g, _ = gpu_run(fv, case, 1, p32)
+    ref = O.OracleGrid(case)
+    ref.run(case.params, 1)
+    e1 = P.state_err(case, g.get_state(), ref.get_state())
+    say(f"  fp32-flux inlet full, 1 step: {e1:.2e}")
+    assert e1 <= P.FP32_STEP_TOL
+
+
+# ---------------------------------------------------------------------------
+# 3D uniform block with density blobs
+# ---------------------------------------------------------------------------
+def ragged_3d():
+    case = CS.blobs_case(24, nblobs=3, seed=5)
+    b = case.blocks[0]
+    ni, nj, nk = 70, 21, 13
+    h = (1.0 / 70, 1.0 / 60, 1.0 / 50)
+    prim = case.meta["prim"]
+    rng = np.random.default_rng(17)
+    rho = prim[0] * (1 + 0.05 * rng.standard_normal((nk, nj, ni)))
+    vel = [np.full_like(rho, prim[1]), 0.1 * prim[1] * rng.standard_normal(rho.shape),
+           np.zeros_like(rho)]
+    U = CS.conserved(rho, vel, np.full_like(rho, prim[4]))
+    bcs = [CS.BC(CS.INFLOW, prim=prim), CS.BC(CS.EXTRAP), CS.BC(CS.SLIPWALL), CS.BC(CS.SLIPWALL),
+           CS.BC(CS.PERIODIC), CS.BC(CS.PERIODIC)]
+    blk = CS.Block(ni, nj, nk, None, None, (0, 0, 0), h, bcs)
+    return CS.Case("ragged_3d", 3, [blk], [U], CS.Params(qref=CS.qref_of(prim, 3)), 1)
+
+
+def two_block_3d():
+    a = ragged_3d()
+    b = ragged_3d()
+    blk0, blk1 = a.blocks[0], b.blocks[0]
+    blk0.bc[1] = CS.BC(CS.BLOCK, 1, CS.IMIN)
+    blk1.bc[0] = CS.BC(CS.BLOCK, 0, CS.IMAX)
+    return CS.Case("two_block_3d", 3, [blk0, blk1], [a.U0[0], b.U0[0] * 1.01], a.params, 1)
+
+
+@pytest.mark.parametrize("maker", [lambda: CS.blobs_case(32, nblobs=4), ragged_3d, two_block_3d])
+def test_3d_small_fp64(env, maker):
+    fv, O = env
+    case = maker()
+    check_residual(fv, O, case)
+    check_steps(fv, O, case, 10)
+
+
+def test_3d_small_fp32_flux(env):
+    fv, O = env
+    case = ragged_3d()
+    p32 = CS.Params(**{**case.params.__dict__, "precision": CS.FP32_FLUX})
+    g, _ = gpu_run(fv, case, 1, p32)
+    ref = O.OracleGrid(case)
+    ref.run(case.params, 1)
+    e1 = P.state_err(case, g.get_state(), ref.get_state())
+    g.step(p32, 19)
+    ref.run(case.params, 19)
+    eN = P.state_err(case, g.get_state(), ref.get_state())
+    say(f"  fp32-flux 3D ragged: 1 step {e1:.2e}, 20 steps {eN:.2e}")
+    assert e1 <= P.FP32_STEP_TOL and eN <= P.FP32_RUN_TOL
+
+
+def test_blobs_full_residual_and_step(env):
+    fv, O = env
+    case = CS.blobs_3d()
+    check_residual(fv, O, case)
+    check_steps(fv, O, case, 1)
+
+
+def test_blobs_full_50_steps_invariants(env):
+    """At full size after the configured 50 steps: with conserved MUSCL + Roe
+    an entropy wave keeps u and p uniform (a property exact at any size)."""
+    fv, O = env
+    case = CS.blobs_3d()
+    for prec in (CS.FP64, CS.FP32_FLUX):
+        prm = CS.Params(**{**case.params.__dict__, "precision": prec})
+        g, info = gpu_run(fv, case, 50, prm)
+        U = g.get_state().reshape(5, -1)
+        prim = case.meta["prim"]
+        u = U[1] / U[0]
+        p = 0.4 * (U[4] - 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0])
+        eu = np.max(np.abs(u - prim[1])) / prim[1]
+        ep = np.max(np.abs(p - prim[4])) / prim[4]
+        say(f"  blobs 256^3 50 steps prec={prec}: u dev {eu:.2e}, p dev {ep:.2e}")
+        tol = 1e-12 if prec == CS.FP64 else 1e-4
+        assert info["steps"] == 50 and eu <= tol and ep <= tol
+
+
+# ---------------------------------------------------------------------------
+# time control and failure handling
+# ---------------------------------------------------------------------------
+def test_sod_t_end(env):
+    fv, O = env
+    case = CS.sod_2d(n=200, nj=4, t_end=0.2)
+    g, info, io, e = check_steps(fv, O, case, 10000)
+    assert info["t"] == 0.2 and info["flags"] & fv.FLAG_T_END
+
+
+def test_solve_stops_at_same_step(env):
+    fv, O = env
+    case = CS.inlet_case(128, 32, 2, angle_deg=6.0)
+    ref = O.OracleGrid(case)
+    drops = []
+    for _ in range(60):
+        ref.run(case.params, 1)
+        drops.append(ref.run(case.params, 0)["drop"])
+    drops = np.array(drops)
+    # a tolerance half-way between two consecutive running minima
+    runmin = np.minimum.accumulate(drops)
+    s = int(np.argmax(runmin < runmin[20]))  # first step below the 21st running minimum
+    assert s > 20
+    tol = 0.5 * (runmin[s] + runmin[s - 1])
+    ref2 = O.OracleGrid(case)
+    io = ref2.run(case.params, 1000, drop_tol=tol)
+    g = fv.Grid(case)
+    g.set_state(case.state_flat())
+    info = g.solve(case.params, drop_tol=tol, max_steps=1000)
+    say(f"  solve: gpu {info['steps']} steps, ref {io['steps']} steps, tol {tol:.4e}")
+    assert info["steps"] == io["steps"] and info["flags"] & fv.FLAG_CONVERGED
+    assert P.state_err(case, g.get_state(), ref2.get_state()) <= P.FP64_TOL
+
+
+def test_nonphysical_initial_state(env):
+    fv, O = env
+    case = CS.vortex_2d(64, 32)
+    U = case.state_flat().copy()
+    U[100] = -1.0
+    g = fv.Grid(case)
+    st = g.set_state(U, check=False)
+    assert st == fv.FV_E_NONPHYSICAL
+    info = g.step(case.params, 3, check=False)
+    assert info["status"] == fv.FV_E_NONPHYSICAL and info["steps"] == 0
+
+
+def test_nonphysical_after_steps(env):
+    """A time step far beyond the CFL limit drives the state non-physical; the
+    GPU stops at the same step as the reference and says so."""
+    fv, O = env
+    case = CS.sod_2d(n=64, nj=4, t_end=0.0)
+    prm = CS.Params(**{**case.params.__dict__, "dt_fixed": 0.2, "t_end": 0.0})
+    g = fv.Grid(case)
+    g.set_state(case.state_flat())
+    info = g.step(prm, 10, check=False)
+    ref = O.OracleGrid(case)
+    io = ref.run(prm, 10)
+    say(f"  nonphysical: gpu steps {info['steps']} status {info['status']}, ref {io['steps']} {io['status']}")
+    assert io["status"] == O.E_NONPHYSICAL
+    assert info["status"] == fv.FV_E_NONPHYSICAL and info["steps"] == io["steps"]
+
+
+def test_restart_bitwise(env):
+    fv, O = env
+    case = CS.inlet_case(128, 48, 2)
+    a, _ = gpu_run(fv, case, 20)
+    mid = a.get_state()
+    a.step(case.params, 20)
+    b = fv.Grid(case)
+    b.set_state(mid)
+    b.step(case.params, 20)
+    # a restart resets t and the first-step norm but not the state arithmetic
+    assert np.array_equal(a.get_state(), b.get_state())
