@@ -60,8 +60,92 @@ struct DevTile {
 };
 
 // --------------------------------------------------------------------------
-// small helpers
+// memory access: the state and node arrays are global memory; their pointers
+// come from descriptors, so the address space is stated explicitly to get
+// global (not flat) loads and stores
 // --------------------------------------------------------------------------
+typedef __attribute__((address_space(1))) const double g_cdouble;
+typedef __attribute__((address_space(1))) double g_double;
+__device__ __forceinline__ double ldg(const double* p) { return *(g_cdouble*)p; }
+__device__ __forceinline__ void stg(double* p, double v) { *(g_double*)p = v; }
+
+// --------------------------------------------------------------------------
+// arithmetic helpers
+// --------------------------------------------------------------------------
+// Reciprocal and square root from the hardware estimates (v_rcp, v_rsq)
+// refined by Newton-Raphson (reciprocal) and Goldschmidt (square root and its
+// reciprocal together) iterations.  In FP64 the result is within a few ulp of
+// the correctly rounded value for the normal-range arguments met here; in FP32
+// the hardware estimates are used directly.
+template <typename T>
+struct M;
+template <>
+struct M<double> {
+  static __device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+  }
+  // s = sqrt(x), h = 1 / (2 sqrt(x))
+  static __device__ __forceinline__ void sqrt2(double x, double& s, double& h) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y;
+    h = 0.5 * y;
+    double r = __builtin_fma(-g, h, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    r = __builtin_fma(-g, h, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    const double d = __builtin_fma(-g, g, x);
+    s = __builtin_fma(d, h, g);
+  }
+};
+template <>
+struct M<float> {
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  static __device__ __forceinline__ void sqrt2(float x, float& s, float& h) {
+    const float y = __builtin_amdgcn_rsqf(x);
+    s = x * y;
+    h = 0.5f * y;
+  }
+};
+
+// wave-wide neighbour shifts (DPP): shr1 gives lane l the value of lane l-1,
+// shl1 the value of lane l+1; the lane without a source keeps its own value
+__device__ __forceinline__ int dpp_shr1(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_shl1(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ double shr1(double x) {
+  int2 v = __builtin_bit_cast(int2, x);
+  v.x = dpp_shr1(v.x);
+  v.y = dpp_shr1(v.y);
+  return __builtin_bit_cast(double, v);
+}
+__device__ __forceinline__ double shl1(double x) {
+  int2 v = __builtin_bit_cast(int2, x);
+  v.x = dpp_shl1(v.x);
+  v.y = dpp_shl1(v.y);
+  return __builtin_bit_cast(double, v);
+}
+__device__ __forceinline__ float shr1(float x) {
+  return __builtin_bit_cast(float, dpp_shr1(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ float shl1(float x) {
+  return __builtin_bit_cast(float, dpp_shl1(__builtin_bit_cast(int, x)));
+}
+// value of a given lane, as a wave-uniform value
+__device__ __forceinline__ double lane_value(double x, int l) {
+  int2 v = __builtin_bit_cast(int2, x);
+  v.x = __builtin_amdgcn_readlane(v.x, l);
+  v.y = __builtin_amdgcn_readlane(v.y, l);
+  return __builtin_bit_cast(double, v);
+}
+__device__ __forceinline__ float lane_value(float x, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+}
+
 template <typename T>
 __device__ __forceinline__ T minmod(T a, T b) {
   const bool same = (a > T(0) && b > T(0)) || (a < T(0) && b < T(0));
@@ -97,6 +181,14 @@ __device__ __forceinline__ void extrap(const Recon<T>& R, T dm, T dp, T& ep, T& 
   }
 }
 
+// constants of the flux
+template <typename T>
+struct FluxK {
+  T gm1;    // gamma - 1
+  T efix;   // Harten delta / c
+  T iefix;  // 1 / efix (0 when the fix is off)
+};
+
 // Roe's numerical flux of the inviscid normal flux (Sec. 2 flux definition),
 // arranged as
 //   F = 1/2 [F(Q_L).n + F(Q_R).n] - 1/2 [ |V_n| dQ + d1 (1, u, H) + d2 (0, n, V_n) ]
@@ -104,69 +196,100 @@ __device__ __forceinline__ void extrap(const Recon<T>& R, T dm, T dp, T& ep, T& 
 // ld = (|V_n+c| - |V_n-c|)/2,
 //   d1 = lbar dp / c^2 + ld rho~ dV_n / c,   d2 = lbar rho~ dV_n + ld dp / c,
 // and Harten's fix on the two acoustic eigenvalues (delta = efix * c).
-// Returns the flux times the face area.  ND = 2 or 3, NV = ND + 2.
-template <typename T, int ND>
+// Returns the flux times the face area.  ND = 2 or 3; AX >= 0: the unit
+// normal is the coordinate axis AX (n unused), AX < 0: general unit normal n.
+template <typename T, int ND, int AX>
 __device__ __forceinline__ void roe_flux(const T* __restrict__ qL, const T* __restrict__ qR,
-                                         const T* __restrict__ n, T area, T gm1, T efix,
+                                         const T* __restrict__ n, T area, const FluxK<T>& K,
                                          T* __restrict__ F) {
   constexpr int E = ND + 1;
   const T half = T(0.5);
-  const T irL = T(1) / qL[0];
-  const T irR = T(1) / qR[0];
+  T sL, hL, sR, hR;
+  M<T>::sqrt2(qL[0], sL, hL);
+  M<T>::sqrt2(qR[0], sR, hR);
+  const T irL = T(4) * hL * hL;  // 1 / rho
+  const T irR = T(4) * hR * hR;
   T uL[ND], uR[ND];
-  T keL = T(0), keR = T(0), VnL = T(0), VnR = T(0);
+  T keL = T(0), keR = T(0);
 #pragma unroll
   for (int a = 0; a < ND; ++a) {
     uL[a] = qL[1 + a] * irL;
     uR[a] = qR[1 + a] * irR;
     keL += uL[a] * qL[1 + a];
     keR += uR[a] * qR[1 + a];
-    VnL += uL[a] * n[a];
-    VnR += uR[a] * n[a];
   }
-  const T pL = gm1 * (qL[E] - half * keL);
-  const T pR = gm1 * (qR[E] - half * keR);
+  T VnL, VnR;
+  if constexpr (AX >= 0) {
+    VnL = uL[AX];
+    VnR = uR[AX];
+  } else {
+    VnL = T(0);
+    VnR = T(0);
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
+      VnL += uL[a] * n[a];
+      VnR += uR[a] * n[a];
+    }
+  }
+  const T pL = K.gm1 * (qL[E] - half * keL);
+  const T pR = K.gm1 * (qR[E] - half * keR);
   const T HL = (qL[E] + pL) * irL;
   const T HR = (qR[E] + pR) * irR;
-  const T sL = sqrt(qL[0]);
-  const T sR = sqrt(qR[0]);
-  const T is = T(1) / (sL + sR);
+  const T is = M<T>::rcp(sL + sR);
   const T wL = sL * is, wR = sR * is;
   T ut[ND];
-  T q2 = T(0), Vn = T(0);
+  T q2 = T(0);
 #pragma unroll
   for (int a = 0; a < ND; ++a) {
     ut[a] = wL * uL[a] + wR * uR[a];
     q2 += ut[a] * ut[a];
-    Vn += ut[a] * n[a];
+  }
+  T Vn;
+  if constexpr (AX >= 0) {
+    Vn = ut[AX];
+  } else {
+    Vn = T(0);
+#pragma unroll
+    for (int a = 0; a < ND; ++a) Vn += ut[a] * n[a];
   }
   const T Ht = wL * HL + wR * HR;
   const T rt = sL * sR;
-  const T c2 = gm1 * (Ht - half * q2);
-  const T c = sqrt(c2);
-  const T ic = T(1) / c;
+  const T c2 = K.gm1 * (Ht - half * q2);
+  T c, hc;
+  M<T>::sqrt2(c2, c, hc);
+  const T ic = T(2) * hc;
   const T dp = pR - pL;
   const T dVn = VnR - VnL;
   const T lc = fabs(Vn);
   T lm = fabs(Vn - c);
   T lp = fabs(Vn + c);
-  const T del = efix * c;
-  if (del > T(0)) {
-    const T idel = T(1) / del;
-    lm = lm < del ? half * (lm * lm * idel + del) : lm;
-    lp = lp < del ? half * (lp * lp * idel + del) : lp;
-  }
+  const T del = K.efix * c;
+  const T idel = K.iefix * ic;
+  lm = lm < del ? half * (lm * lm * idel + del) : lm;
+  lp = lp < del ? half * (lp * lp * idel + del) : lp;
   const T lbar = half * (lp + lm) - lc;
   const T ld = half * (lp - lm);
   const T rdv = rt * dVn;
   const T d1 = (lbar * dp * ic + ld * rdv) * ic;
   const T d2 = lbar * rdv + ld * dp * ic;
   const T ha = half * area;
+  const T pLR = pL + pR;
   F[0] = ha * ((qL[0] * VnL + qR[0] * VnR) - (lc * (qR[0] - qL[0]) + d1));
 #pragma unroll
-  for (int a = 0; a < ND; ++a)
-    F[1 + a] = ha * ((qL[1 + a] * VnL + qR[1 + a] * VnR + (pL + pR) * n[a]) -
-                     (lc * (qR[1 + a] - qL[1 + a]) + d1 * ut[a] + d2 * n[a]));
+  for (int a = 0; a < ND; ++a) {
+    T m = qL[1 + a] * VnL + qR[1 + a] * VnR;
+    T dd = lc * (qR[1 + a] - qL[1 + a]) + d1 * ut[a];
+    if constexpr (AX >= 0) {
+      if (a == AX) {
+        m += pLR;
+        dd += d2;
+      }
+    } else {
+      m += pLR * n[a];
+      dd += d2 * n[a];
+    }
+    F[1 + a] = ha * (m - dd);
+  }
   F[E] = ha * (((qL[E] + pL) * VnL + (qR[E] + pR) * VnR) -
                (lc * (qR[E] - qL[E]) + d1 * Ht + d2 * Vn));
 }
@@ -175,33 +298,36 @@ __device__ __forceinline__ void roe_flux(const T* __restrict__ qL, const T* __re
 // node coordinates (2D curvilinear)
 // --------------------------------------------------------------------------
 __device__ __forceinline__ double nodex(const DevBlock& B, int i, int j) {
-  return B.xn[(long long)j * (B.ni + 1) + i];
+  return ldg(B.xn + (long long)j * (B.ni + 1) + i);
 }
 __device__ __forceinline__ double nodey(const DevBlock& B, int i, int j) {
-  return B.yn[(long long)j * (B.ni + 1) + i];
+  return ldg(B.yn + (long long)j * (B.ni + 1) + i);
 }
 
 // --------------------------------------------------------------------------
 // ghost resolution: value of cell (i, j, k) of block B in state buffer buf,
-// where at most one index lies outside the block, by at most 2 cells.
+// where at most one index lies outside the block, by at most 2 cells.  The
+// boundary rule gives a source cell (same block, a neighbour block, or the
+// inflow state) and, for slip walls, the wall face's area vector about whose
+// normal the momentum is mirrored: m - 2 (m.S)/(S.S) S.
 // --------------------------------------------------------------------------
 template <int NV>
-__device__ __noinline__ void resolve_cell(const DevBlock* __restrict__ blocks, const DevBlock& B,
+__device__ __forceinline__ void load_cell(const DevBlock* __restrict__ blocks, const DevBlock& B,
                                           int buf, int i, int j, int k, double* q) {
   constexpr int ND = NV - 2;
+  if (i >= 0 && i < B.ni && j >= 0 && j < B.nj && k >= 0 && k < B.nk) {
+    const double* s = B.u[buf] + ((long long)k * B.nj + j) * B.ni + i;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q[v] = ldg(s + v * B.ncell);
+    return;
+  }
   int f, g;
   if (i < 0) { f = 0; g = -i; }
   else if (i >= B.ni) { f = 1; g = i - B.ni + 1; }
   else if (j < 0) { f = 2; g = -j; }
   else if (j >= B.nj) { f = 3; g = j - B.nj + 1; }
   else if (k < 0) { f = 4; g = -k; }
-  else if (k >= B.nk) { f = 5; g = k - B.nk + 1; }
-  else {
-    const double* s = B.u[buf] + ((long long)k * B.nj + j) * B.ni + i;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) q[v] = s[v * B.ncell];
-    return;
-  }
+  else { f = 5; g = k - B.nk + 1; }
   const int d = f >> 1, side = f & 1;
   const int kind = B.bc_kind[f];
   if (kind == BC_INFLOW) {
@@ -209,8 +335,7 @@ __device__ __noinline__ void resolve_cell(const DevBlock* __restrict__ blocks, c
     for (int v = 0; v < NV; ++v) q[v] = B.bc_q[f][v];
     return;
   }
-  const DevBlock* S = &B;
-  if (kind == BC_BLOCK) S = &blocks[B.bc_nbr[f]];
+  const DevBlock* S = (kind == BC_BLOCK) ? &blocks[B.bc_nbr[f]] : &B;
   const int n = d == 0 ? S->ni : (d == 1 ? S->nj : S->nk);
   int along;
   if (kind == BC_PERIODIC || kind == BC_BLOCK) along = side == 0 ? n - g : g - 1;
@@ -222,19 +347,21 @@ __device__ __noinline__ void resolve_cell(const DevBlock* __restrict__ blocks, c
   else sk = along;
   const double* s = S->u[buf] + ((long long)sk * S->nj + sj) * S->ni + si;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) q[v] = s[v * S->ncell];
+  for (int v = 0; v < NV; ++v) q[v] = ldg(s + v * S->ncell);
   if (kind == BC_SLIPWALL) {
-    // mirror the momentum about the wall face's normal: m - 2 (m.S)/(S.S) S
     double Sv[3] = {0.0, 0.0, 0.0};
     if (B.xn != nullptr) {
+      const double* X = B.xn;
+      const double* Y = B.yn;
+      const long long w1 = B.ni + 1;
       if (d == 0) {
         const int w = side == 0 ? 0 : B.ni;
-        Sv[0] = nodey(B, w, j + 1) - nodey(B, w, j);
-        Sv[1] = -(nodex(B, w, j + 1) - nodex(B, w, j));
+        Sv[0] = ldg(Y + (long long)(j + 1) * w1 + w) - ldg(Y + (long long)j * w1 + w);
+        Sv[1] = -(ldg(X + (long long)(j + 1) * w1 + w) - ldg(X + (long long)j * w1 + w));
       } else {
         const int w = side == 0 ? 0 : B.nj;
-        Sv[0] = -(nodey(B, i + 1, w) - nodey(B, i, w));
-        Sv[1] = nodex(B, i + 1, w) - nodex(B, i, w);
+        Sv[0] = -(ldg(Y + (long long)w * w1 + i + 1) - ldg(Y + (long long)w * w1 + i));
+        Sv[1] = ldg(X + (long long)w * w1 + i + 1) - ldg(X + (long long)w * w1 + i);
       }
     } else {
       Sv[d] = 1.0;
@@ -249,6 +376,13 @@ __device__ __noinline__ void resolve_cell(const DevBlock* __restrict__ blocks, c
 #pragma unroll
     for (int a = 0; a < ND; ++a) q[1 + a] -= fct * Sv[a];
   }
+}
+
+// kept for the ghost dump (out of the hot path)
+template <int NV>
+__device__ void resolve_cell(const DevBlock* __restrict__ blocks, const DevBlock& B, int buf, int i,
+                             int j, int k, double* q) {
+  load_cell<NV>(blocks, B, buf, i, j, k, q);
 }
 
 // --------------------------------------------------------------------------

@@ -1,21 +1,20 @@
 // 2D stage kernels: MUSCL + Roe residual, SSP-RK3 stage update and the
 // fused reductions, one wavefront per tile.
 //
-// A tile is 64 consecutive columns i (lane = column) by n rows.  The wave
-// marches up the rows.  At row j it
-//   - loads Q(j+1) of its column (the j-stencil needs rows j-2 .. j+1 and
-//     rows j-1, j are carried in registers),
-//   - forms the j-face flux at j-1/2 from the carried extrapolation of cell
-//     j-1 and the one of cell j, and with it completes the residual of row
-//     j-1, which it then updates and stores (coalesced along i),
-//   - forms the i-face flux at i-1/2 of row j: the neighbour values come
-//     from lane shuffles, the three halo cells (i0-2, i0-1, i0+ncol) from
-//     lanes 0..2, and the flux leaving through i+1/2 is the next lane's
-//     i-1/2 flux.  The tile's right-edge fluxes are formed 64 rows at a time
-//     by a batched pre-pass (lane r: row r), so every face flux of the tile
-//     is formed exactly once, except the shared edges between tiles.
-// Ghost cells are never stored; reads outside the block go through the
-// boundary rule (resolve_cell).
+// A tile is 64 consecutive columns i (lane = column; ncol of them active) by
+// n rows.  The wave marches up the rows; at row j it
+//   - forms the j-face flux at j-1/2 from the extrapolation of cell j-1
+//     (carried) and of cell j (rows j-1, j, j+1 of the own column are in
+//     registers; row j+2 is already being fetched for the next step),
+//   - completes the residual of row j-1 with it, applies the RK stage update
+//     and stores the row (coalesced along i), adding the fused reductions,
+//   - forms the i-face flux at i-1/2 of row j.  Neighbour values come from
+//     the lanes next door (DPP wave shifts), the three halo cells i0-2,
+//     i0-1, i0+ncol from lanes 0..2, and the flux through i+1/2 is the next
+//     lane's i-1/2 flux.  The right-edge fluxes of the tile are formed 64 rows
+//     at a time by a pre-pass (lane r: row r) and kept in LDS.
+// Every face flux of the tile is formed once (tile edges aside).  Ghost cells
+// are never stored: reads outside the block follow the boundary rule.
 #include "fv_device.h"
 #include "fv_launch.h"
 
@@ -23,78 +22,56 @@ namespace fvk {
 
 namespace {
 
+constexpr int kWavesPerWG = 4;
+
 template <typename T>
 struct Ctx2D {
   const DevBlock* blocks;
   const DevBlock* B;
-  int buf;  // stage input buffer
+  int buf;
   Recon<T> rc;
-  T gm1, efix;
+  FluxK<T> K;
 };
 
-// load one cell (interior fast path, boundary rule otherwise)
-__device__ __forceinline__ void load2d(const DevBlock* blocks, const DevBlock& B, int buf, int i,
-                                       int j, double (&q)[4]) {
-  if (i >= 0 && i < B.ni && j >= 0 && j < B.nj) {
-    const double* s = B.u[buf] + (long long)j * B.ni + i;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) q[v] = s[v * B.ncell];
-  } else {
-    resolve_cell<4>(blocks, B, buf, i, j, 0, q);
-  }
-}
-
-// area vector of i-face (i, j) and j-face (i, j), from nodes or uniform
-__device__ __forceinline__ void ivec(const DevBlock& B, double xa, double ya, double xb,
-                                     double yb, double (&S)[2]) {
-  // nodes a = (i, j), b = (i, j+1)
-  if (B.xn) {
-    S[0] = yb - ya;
-    S[1] = -(xb - xa);
-  } else {
-    S[0] = B.area[0];
-    S[1] = 0.0;
-  }
-}
-__device__ __forceinline__ void jvec(const DevBlock& B, double xa, double ya, double xb,
-                                     double yb, double (&S)[2]) {
-  // nodes a = (i, j), b = (i+1, j)
-  if (B.xn) {
-    S[0] = -(yb - ya);
-    S[1] = xb - xa;
-  } else {
-    S[0] = 0.0;
-    S[1] = B.area[1];
-  }
-}
-
 template <typename T>
-__device__ __forceinline__ void face_flux2d(const Ctx2D<T>& C, const T (&qL)[4], const T (&qR)[4],
-                                            const double (&S)[2], T (&G)[4]) {
-  T n[2], area;
-  if (C.B->xn) {
-    const double A = sqrt(S[0] * S[0] + S[1] * S[1]);
-    const double iA = 1.0 / A;
-    n[0] = T(S[0] * iA);
-    n[1] = T(S[1] * iA);
-    area = T(A);
-  } else {
-    area = T(S[0] + S[1]);  // one component is zero
-    n[0] = T(S[0] != 0.0 ? 1.0 : 0.0);
-    n[1] = T(S[1] != 0.0 ? 1.0 : 0.0);
-  }
-  roe_flux<T, 2>(qL, qR, n, area, C.gm1, C.efix, G);
+__device__ __forceinline__ void setup(Ctx2D<T>& C, const DevBlock* blocks, const DevBlock& B,
+                                      int buf, const DevInstance& I) {
+  C.blocks = blocks;
+  C.B = &B;
+  C.buf = buf;
+  C.rc.lim = I.limiter;
+  C.rc.heps = T(0.5 * I.eps);
+  C.rc.c1 = T(0.25 * I.eps * (1.0 - I.kappa));
+  C.rc.c2 = T(0.25 * I.eps * (1.0 + I.kappa));
+  C.K.gm1 = T(I.gamma - 1.0);
+  C.K.efix = T(I.efix);
+  C.K.iefix = T(I.efix > 0.0 ? 1.0 / I.efix : 0.0);
 }
 
-// i-face flux at the right edge of the tile for row jr (column ie = i0+ncol)
+// flux across a face of area vector S (curvilinear) or along axis AX (uniform)
+template <typename T, int AX>
+__device__ __forceinline__ void face_flux(const Ctx2D<T>& C, const T (&qL)[4], const T (&qR)[4],
+                                          double Sx, double Sy, T (&G)[4]) {
+  if (C.B->xn) {
+    double A, h;
+    M<double>::sqrt2(Sx * Sx + Sy * Sy, A, h);
+    const double iA = 2.0 * h;
+    const T n[2] = {T(Sx * iA), T(Sy * iA)};
+    roe_flux<T, 2, -1>(qL, qR, n, T(A), C.K, G);
+  } else {
+    roe_flux<T, 2, AX>(qL, qR, nullptr, T(C.B->area[AX]), C.K, G);
+  }
+}
+
+// i-face flux at column ie, row jr from the four cells ie-2 .. ie+1
 template <typename T>
 __device__ void edge_face(const Ctx2D<T>& C, int ie, int jr, T (&G)[4]) {
   const DevBlock& B = *C.B;
   double a[4], b[4], c[4], d[4];
-  load2d(C.blocks, B, C.buf, ie - 2, jr, a);
-  load2d(C.blocks, B, C.buf, ie - 1, jr, b);
-  load2d(C.blocks, B, C.buf, ie, jr, c);
-  load2d(C.blocks, B, C.buf, ie + 1, jr, d);
+  load_cell<4>(C.blocks, B, C.buf, ie - 2, jr, 0, a);
+  load_cell<4>(C.blocks, B, C.buf, ie - 1, jr, 0, b);
+  load_cell<4>(C.blocks, B, C.buf, ie, jr, 0, c);
+  load_cell<4>(C.blocks, B, C.buf, ie + 1, jr, 0, d);
   T qL[4], qR[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -105,127 +82,129 @@ __device__ void edge_face(const Ctx2D<T>& C, int ie, int jr, T (&G)[4]) {
     qL[v] = tb + ep;
     qR[v] = tc - em2;
   }
-  double S[2];
-  if (B.xn)
-    ivec(B, nodex(B, ie, jr), nodey(B, ie, jr), nodex(B, ie, jr + 1), nodey(B, ie, jr + 1), S);
-  else
-    ivec(B, 0, 0, 0, 0, S);
-  face_flux2d(C, qL, qR, S, G);
+  double Sx = 0.0, Sy = 0.0;
+  if (B.xn) {
+    Sx = nodey(B, ie, jr + 1) - nodey(B, ie, jr);
+    Sy = -(nodex(B, ie, jr + 1) - nodex(B, ie, jr));
+  }
+  face_flux<T, 0>(C, qL, qR, Sx, Sy, G);
 }
 
 template <int MODE, typename T>
-__device__ void tile2d(const DevTile& tl, const DevBlock* __restrict__ blocks,
-                       DevInstance& I, double* __restrict__ rout, int lane) {
+__device__ void tile2d(const DevTile& tl, const DevBlock* __restrict__ blocks, DevInstance& I,
+                       double* __restrict__ rout, int lane, T* __restrict__ s_edge) {
   const DevBlock& B = blocks[tl.blk];
   const int ni = B.ni;
   const int i0 = tl.i0, j0 = tl.j0, n = tl.n, nc = tl.ncol;
   const int i = i0 + lane;
   const bool act = lane < nc;
-  const int ic = act ? i : ni - 1;  // safe column for inactive lanes
+  const int ic = act ? i : ni - 1;  // safe column for idle lanes
+  const int last = nc - 1;          // lane owning the tile's right edge
   const int bin = MODE == 0 ? 0 : MODE - 1;
   const int bout = MODE == 1 ? 1 : (MODE == 2 ? 2 : 0);
   const bool curv = B.xn != nullptr;
+  // halo lanes: 0 -> column i0-1, 1 -> i0-2, 2 -> i0+ncol
+  const int hcol = lane == 0 ? i0 - 1 : (lane == 1 ? i0 - 2 : i0 + nc);
+  const bool hlane = lane < 3;
 
   Ctx2D<T> C;
-  C.blocks = blocks;
-  C.B = &B;
-  C.buf = bin;
-  C.rc.lim = I.limiter;
-  C.rc.heps = T(0.5 * I.eps);
-  C.rc.c1 = T(0.25 * I.eps * (1.0 - I.kappa));
-  C.rc.c2 = T(0.25 * I.eps * (1.0 + I.kappa));
-  C.gm1 = T(I.gamma - 1.0);
-  C.efix = T(I.efix);
+  setup(C, blocks, B, bin, I);
   const double gamma = I.gamma;
   const double dt = I.dt;
-
-  const double* __restrict__ Uin = B.u[bin];
   double* __restrict__ Uout = B.u[bout];
   const double* __restrict__ Un = B.u[0];
   const long long ncell = B.ncell;
 
-  // ---- prologue: rows j0-2, j0-1, j0 of the own column
-  double qa_d[4], qb_d[4], q0_d[4];
-  load2d(blocks, B, bin, ic, j0 - 2, qa_d);
-  load2d(blocks, B, bin, ic, j0 - 1, qb_d);
-  load2d(blocks, B, bin, ic, j0, q0_d);
-  T qm1[4], q0[4], epm1[4];
-  double qm1_d[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const T ta = T(qa_d[v]), tb = T(qb_d[v]), tc = T(q0_d[v]);
-    T em;
-    extrap(C.rc, tb - ta, tc - tb, epm1[v], em);
-    qm1[v] = tb;
-    q0[v] = tc;
-    qm1_d[v] = qb_d[v];
-  }
-  // node rows j-1 (m), j (0), j+1 (1): own column and the next one
-  double xm = 0, ym = 0, xmr = 0, ymr = 0, x0 = 0, y0 = 0, x0r = 0, y0r = 0;
+  // ---- prologue: rows j0-2 .. j0+1 of the own column, nodes of row j0
+  double qa[4], qm1[4], q0[4], qn[4];
+  load_cell<4>(blocks, B, bin, ic, j0 - 2, 0, qa);
+  load_cell<4>(blocks, B, bin, ic, j0 - 1, 0, qm1);
+  load_cell<4>(blocks, B, bin, ic, j0, 0, q0);
+  load_cell<4>(blocks, B, bin, ic, j0 + 1, 0, qn);
+  double xm = 0, ym = 0, x0 = 0, y0 = 0, xhm = 0, yhm = 0, xh0 = 0, yh0 = 0;
   if (curv) {
     x0 = nodex(B, ic, j0);
     y0 = nodey(B, ic, j0);
-    x0r = nodex(B, ic + 1, j0);
-    y0r = nodey(B, ic + 1, j0);
+    double hx = 0, hy = 0;
+    if (lane == 2) {
+      hx = nodex(B, i0 + nc, j0);
+      hy = nodey(B, i0 + nc, j0);
+    }
+    xh0 = lane_value(hx, 2);
+    yh0 = lane_value(hy, 2);
+  }
+  T epm1[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    T em;
+    extrap(C.rc, T(qm1[v]) - T(qa[v]), T(q0[v]) - T(qm1[v]), epm1[v], em);
   }
 
-  double ri[4] = {0, 0, 0, 0};  // i-direction part of the residual of the carried row
-  T gbot[4] = {T(0), T(0), T(0), T(0)};
-  T edge[4] = {T(0), T(0), T(0), T(0)};
+  double rg[4] = {0, 0, 0, 0};  // (G_i+1/2 - G_i-1/2) - G_j-1/2 of the carried row
   double nacc[4] = {0, 0, 0, 0};
   double dmin = INFINITY;
   int bad = 0;
 
   for (int r = 0; r <= n; ++r) {
     const int j = j0 + r;
-    if (r < n && (r & 63) == 0) {
-      // right-edge i-faces of rows j .. j+63 of this tile, one per lane
-      const int rr = min(lane, n - r - 1);
-      edge_face(C, i0 + nc, j + rr, edge);
+    const bool more = r < n;
+    // ---- (1) loads for later in this step and for the next step
+    double qnn[4] = {0, 0, 0, 0}, hv[4] = {0, 0, 0, 0}, un[4] = {0, 0, 0, 0};
+    double x1 = 0, y1 = 0, hx1 = 0, hy1 = 0;
+    if (more) {
+      load_cell<4>(blocks, B, bin, ic, j + 2, 0, qnn);
+      if (hlane) load_cell<4>(blocks, B, bin, hcol, j, 0, hv);
+      if (curv) {
+        x1 = nodex(B, ic, j + 1);
+        y1 = nodey(B, ic, j + 1);
+        if (lane == 2) {
+          hx1 = nodex(B, i0 + nc, j + 1);
+          hy1 = nodey(B, i0 + nc, j + 1);
+        }
+      }
     }
-    // ---- Q(j+1) of the own column
-    double qn_d[4];
-    load2d(blocks, B, bin, ic, j + 1, qn_d);
-    T qn[4];
+    if (MODE >= 2 && r >= 1 && act) {
+      const long long idx = (long long)(j - 1) * ni + i;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) qn[v] = T(qn_d[v]);
-    double x1 = 0, y1 = 0, x1r = 0, y1r = 0;
-    if (curv && r < n) {
-      x1 = nodex(B, ic, j + 1);
-      y1 = nodey(B, ic, j + 1);
-      x1r = nodex(B, ic + 1, j + 1);
-      y1r = nodey(B, ic + 1, j + 1);
+      for (int v = 0; v < 4; ++v) un[v] = ldg(Un + v * ncell + idx);
     }
-    // ---- j-face at j-1/2
-    T ep0[4], em0[4], qL[4], qR[4], Gj[4];
+    // ---- (2) right-edge i-face fluxes of the next 64 rows (LDS)
+    if (more && (r & 63) == 0) {
+      const int rr = min(lane, n - r - 1);
+      T ge[4];
+      edge_face(C, i0 + nc, j + rr, ge);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) s_edge[lane * 4 + v] = ge[v];
+      __builtin_amdgcn_wave_barrier();
+    }
+    // ---- (3) j-face at j-1/2
+    T qLj[4], qRj[4], ep0[4], Gj[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      extrap(C.rc, q0[v] - qm1[v], qn[v] - q0[v], ep0[v], em0[v]);
-      qL[v] = qm1[v] + epm1[v];
-      qR[v] = q0[v] - em0[v];
+      const T a = T(qm1[v]), b = T(q0[v]), c = T(qn[v]);
+      T em;
+      extrap(C.rc, b - a, c - b, ep0[v], em);
+      qLj[v] = a + epm1[v];
+      qRj[v] = b - em;
     }
-    {
-      double S[2];
-      jvec(B, x0, y0, x0r, y0r, S);
-      face_flux2d(C, qL, qR, S, Gj);
-    }
-    // ---- complete, update and store row j-1
+    const double x0r = lane == last ? xh0 : shl1(x0);
+    const double y0r = lane == last ? yh0 : shl1(y0);
+    face_flux<T, 1>(C, qLj, qRj, -(y0r - y0), x0r - x0, Gj);
+    // ---- (4) complete, update and store row j-1
+    const double xmr = lane == last ? xhm : shl1(xm);
+    const double ymr = lane == last ? yhm : shl1(ym);
     if (r >= 1 && act) {
       const long long idx = (long long)(j - 1) * ni + i;
       double R[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) R[v] = ri[v] + ((double)Gj[v] - (double)gbot[v]);
-      double vol;
-      if (curv) {
-        vol = 0.5 * ((x0r - xm) * (y0 - ymr) - (x0 - xmr) * (y0r - ym));
-      } else {
-        vol = B.vol;
-      }
+      for (int v = 0; v < 4; ++v) R[v] = rg[v] + (double)Gj[v];
+      const double vol = curv ? 0.5 * ((x0r - xm) * (y0 - ymr) - (x0 - xmr) * (y0r - ym)) : B.vol;
       if (MODE == 0) {
+        const double iv = 1.0 / vol;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          rout[B.out_off + v * ncell + idx] = R[v];
-          const double rv = R[v] / vol;
+          stg(rout + B.out_off + v * ncell + idx, R[v]);
+          const double rv = R[v] * iv;
           nacc[v] += rv * rv;
         }
       } else {
@@ -233,20 +212,17 @@ __device__ void tile2d(const DevTile& tl, const DevBlock* __restrict__ blocks,
         double out[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const double us = qm1_d[v] - f * R[v];
-          if (MODE == 1) {
-            out[v] = us;
-          } else if (MODE == 2) {
-            out[v] = 0.75 * Un[v * ncell + idx] + 0.25 * us;
-          } else {
-            out[v] = (1.0 / 3.0) * Un[v * ncell + idx] + (2.0 / 3.0) * us;
-          }
-          Uout[v * ncell + idx] = out[v];
+          const double us = qm1[v] - f * R[v];
+          if (MODE == 1) out[v] = us;
+          else if (MODE == 2) out[v] = 0.75 * un[v] + 0.25 * us;
+          else out[v] = (1.0 / 3.0) * un[v] + (2.0 / 3.0) * us;
+          stg(Uout + v * ncell + idx, out[v]);
         }
         if (MODE == 1) {
+          const double iv = 1.0 / vol;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const double rv = R[v] / vol;
+            const double rv = R[v] * iv;
             nacc[v] += rv * rv;
           }
         }
@@ -268,56 +244,48 @@ __device__ void tile2d(const DevTile& tl, const DevBlock* __restrict__ blocks,
         }
       }
     }
-    // ---- i-faces of row j
-    if (r < n) {
-      double hv_d[4] = {0, 0, 0, 0};
-      if (lane < 3) {
-        const int hi = lane == 0 ? i0 - 1 : (lane == 1 ? i0 - 2 : i0 + nc);
-        load2d(blocks, B, bin, hi, j, hv_d);
-      }
-      T Gi[4];
+    // ---- (5) i-face at i-1/2 of row j
+    if (more) {
+      const double xh1 = lane_value(hx1, 2), yh1 = lane_value(hy1, 2);
+      T qLi[4], qRi[4], Gi[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const T hv = T(hv_d[v]);
-        const T left = __shfl(q0[v], lane - 1 < 0 ? 0 : lane - 1, kWave);
-        const T right = __shfl(q0[v], lane + 1 > 63 ? 63 : lane + 1, kWave);
-        const T h1 = __shfl(hv, 1, kWave);  // Q(i0-2)
-        const T h2 = __shfl(hv, 2, kWave);  // Q(i0+ncol)
-        const T qim1 = lane == 0 ? hv : left;
-        const T qip1 = lane == nc - 1 ? h2 : right;
+        const T c = T(q0[v]);
+        const T h = T(hv[v]);
+        const T left = shr1(c);
+        const T right = shl1(c);
+        const T hright = lane_value(h, 2);  // Q(i0+ncol)
+        const T hfar = shl1(h);             // lane 0: Q(i0-2) from lane 1
+        const T qim1 = lane == 0 ? h : left;
+        const T qip1 = lane == last ? hright : right;
         T epc, emc;
-        extrap(C.rc, q0[v] - qim1, qip1 - q0[v], epc, emc);
-        // extrapolation of cell i-1 towards i-1/2
-        const T epl = __shfl(epc, lane - 1 < 0 ? 0 : lane - 1, kWave);
+        extrap(C.rc, c - qim1, qip1 - c, epc, emc);
         T ep0l, em0l;
-        extrap(C.rc, hv - h1, q0[v] - hv, ep0l, em0l);  // cell i0-1 (lane 0)
-        const T epi = lane == 0 ? ep0l : epl;
-        qL[v] = qim1 + epi;
-        qR[v] = q0[v] - emc;
+        extrap(C.rc, h - hfar, c - h, ep0l, em0l);  // cell i0-1 (used by lane 0)
+        const T epl = shr1(epc);
+        qLi[v] = qim1 + (lane == 0 ? ep0l : epl);
+        qRi[v] = c - emc;
       }
-      double S[2];
-      ivec(B, x0, y0, x1, y1, S);
-      face_flux2d(C, qL, qR, S, Gi);
+      face_flux<T, 0>(C, qLi, qRi, y1 - y0, -(x1 - x0), Gi);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const T gr = __shfl(Gi[v], lane + 1 > 63 ? 63 : lane + 1, kWave);
-        const T ge = __shfl(edge[v], r & 63, kWave);
-        const T grr = lane == nc - 1 ? ge : gr;
-        ri[v] = (double)grr - (double)Gi[v];
-        gbot[v] = Gj[v];
+        const T ge = s_edge[(r & 63) * 4 + v];
+        const T gr = lane == last ? ge : shl1(Gi[v]);
+        rg[v] = ((double)gr - (double)Gi[v]) - (double)Gj[v];
       }
+      xhm = xh0; yhm = yh0;
+      xh0 = xh1; yh0 = yh1;
     }
-    // ---- shift the carried rows
+    // ---- (6) rotate the carried rows
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       qm1[v] = q0[v];
       q0[v] = qn[v];
+      qn[v] = qnn[v];
       epm1[v] = ep0[v];
-      qm1_d[v] = q0_d[v];
-      q0_d[v] = qn_d[v];
     }
-    xm = x0; ym = y0; xmr = x0r; ymr = y0r;
-    x0 = x1; y0 = y1; x0r = x1r; y0r = y1r;
+    xm = x0; ym = y0;
+    x0 = x1; y0 = y1;
   }
 
   // ---- per-tile partials (fixed-order wave reductions)
@@ -348,15 +316,15 @@ __global__ __launch_bounds__(256) void k_stage2d(const DevTile* __restrict__ til
                                                  const DevBlock* __restrict__ blocks,
                                                  DevInstance* __restrict__ insts,
                                                  double* __restrict__ rout) {
+  __shared__ T s_edge[kWavesPerWG][64 * 4];
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nwv = blockDim.x >> 6;
   const int ntiles = *ntiles_p;
-  for (int t = blockIdx.x * nwv + wid; t < ntiles; t += gridDim.x * nwv) {
+  for (int t = blockIdx.x * kWavesPerWG + wid; t < ntiles; t += gridDim.x * kWavesPerWG) {
     const DevTile tl = tiles[t];
     DevInstance& I = insts[tl.inst];
     if (MODE != 0 && I.stopped) continue;
-    tile2d<MODE, T>(tl, blocks, I, rout, lane);
+    tile2d<MODE, T>(tl, blocks, I, rout, lane, s_edge[wid]);
   }
 }
 
@@ -367,9 +335,8 @@ __global__ __launch_bounds__(256) void k_cfl2d(const DevTile* __restrict__ tiles
                                                DevInstance* __restrict__ insts) {
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int nwv = blockDim.x >> 6;
   const int ntiles = *ntiles_p;
-  for (int t = blockIdx.x * nwv + wid; t < ntiles; t += gridDim.x * nwv) {
+  for (int t = blockIdx.x * kWavesPerWG + wid; t < ntiles; t += gridDim.x * kWavesPerWG) {
     const DevTile tl = tiles[t];
     DevInstance& I = insts[tl.inst];
     const DevBlock& B = blocks[tl.blk];
@@ -383,9 +350,10 @@ __global__ __launch_bounds__(256) void k_cfl2d(const DevTile* __restrict__ tiles
         const long long idx = (long long)j * B.ni + i;
         double q[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) q[v] = B.u[0][v * B.ncell + idx];
+        for (int v = 0; v < 4; ++v) q[v] = ldg(B.u[0] + v * B.ncell + idx);
         double Sb[2][3], vol;
         if (B.xn) {
+          // nodes a = (i, j), b = (i+1, j), c = (i, j+1), d = (i+1, j+1)
           const double xa = nodex(B, i, j), ya = nodey(B, i, j);
           const double xb = nodex(B, i + 1, j), yb = nodey(B, i + 1, j);
           const double xc = nodex(B, i, j + 1), yc = nodey(B, i, j + 1);

@@ -2,17 +2,18 @@
 // update and fused reductions.  One workgroup per tile.
 //
 // A tile is 64 columns i (lane) by ny rows j (one wavefront per row) and
-// marches over n planes k.  The workgroup has ny + 1 waves: waves 0..ny-1
-// own the rows; wave ny owns no cells, it loads the four j-halo rows of each
-// plane and forms the j-face flux at the tile's top edge.  Per plane k:
-//   - each row wave loads Q(k+1) of its column (k-stencil rows k-1, k carried
-//     in registers), forms the k-face flux at k-1/2, completes the residual of
-//     plane k-1 and updates/stores it;
-//   - the plane k is staged in LDS (rows j0-2 .. j0+ny+1), then every row wave
-//     forms its i-face flux (lane shuffles, halo lanes, batched right-edge
-//     pre-pass as in 2D) and its j-face flux at j-1/2 (LDS rows), the j-face
-//     fluxes are exchanged through LDS, and each row keeps the in-plane part
-//     of its residual for the next iteration.
+// marches over n planes k.  The workgroup has NY + 1 waves: waves 0..NY-1 own
+// the rows; wave NY owns no cells: it fetches the four j-halo rows of each
+// plane (one plane ahead) and forms the j-face flux at the tile's top edge.
+// Per plane k:
+//   - each row wave forms the k-face flux at k-1/2 (planes k-1, k, k+1 of its
+//     column in registers, k+2 in flight), completes the residual of plane
+//     k-1, applies the stage update and stores it;
+//   - the plane k is staged in LDS (rows j0-2 .. j0+ny+1); every row wave forms
+//     its j-face flux at j-1/2 from LDS and its i-face flux at i-1/2 (DPP lane
+//     shifts, halo lanes, right-edge pre-pass in LDS as in 2D); the j-face
+//     fluxes are exchanged through LDS and each row keeps the in-plane part
+//     of its residual for the next plane.
 // Every face flux of the tile is formed once (tile edges aside).
 #include "fv_device.h"
 #include "fv_launch.h"
@@ -21,44 +22,25 @@ namespace fvk {
 
 namespace {
 
-__device__ __forceinline__ void load3d(const DevBlock* blocks, const DevBlock& B, int buf, int i,
-                                       int j, int k, double (&q)[5]) {
-  if (i >= 0 && i < B.ni && j >= 0 && j < B.nj && k >= 0 && k < B.nk) {
-    const double* s = B.u[buf] + ((long long)k * B.nj + j) * B.ni + i;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) q[v] = s[v * B.ncell];
-  } else {
-    resolve_cell<5>(blocks, B, buf, i, j, k, q);
-  }
-}
-
-// Roe flux across a face whose unit normal is the coordinate axis AX
-template <typename T, int AX>
-__device__ __forceinline__ void axis_flux(const T (&qL)[5], const T (&qR)[5], T area, T gm1, T efix,
-                                          T (&F)[5]) {
-  const T n[3] = {T(AX == 0 ? 1 : 0), T(AX == 1 ? 1 : 0), T(AX == 2 ? 1 : 0)};
-  roe_flux<T, 3>(qL, qR, n, area, gm1, efix, F);
-}
-
 template <typename T>
 struct Ctx3D {
   const DevBlock* blocks;
   const DevBlock* B;
   int buf;
   Recon<T> rc;
-  T gm1, efix;
-  T ax, ay, az;  // face areas
+  FluxK<T> K;
+  T ax, ay, az;
 };
 
-// i-face at the right edge of the tile for row j, plane kr (column ie)
+// i-face at column ie of row j, plane kr, from the four cells ie-2 .. ie+1
 template <typename T>
 __device__ void edge_face3(const Ctx3D<T>& C, int ie, int j, int kr, T (&G)[5]) {
   const DevBlock& B = *C.B;
   double a[5], b[5], c[5], d[5];
-  load3d(C.blocks, B, C.buf, ie - 2, j, kr, a);
-  load3d(C.blocks, B, C.buf, ie - 1, j, kr, b);
-  load3d(C.blocks, B, C.buf, ie, j, kr, c);
-  load3d(C.blocks, B, C.buf, ie + 1, j, kr, d);
+  load_cell<5>(C.blocks, B, C.buf, ie - 2, j, kr, a);
+  load_cell<5>(C.blocks, B, C.buf, ie - 1, j, kr, b);
+  load_cell<5>(C.blocks, B, C.buf, ie, j, kr, c);
+  load_cell<5>(C.blocks, B, C.buf, ie + 1, j, kr, d);
   T qL[5], qR[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
@@ -69,124 +51,203 @@ __device__ void edge_face3(const Ctx3D<T>& C, int ie, int j, int kr, T (&G)[5]) 
     qL[v] = tb + ep;
     qR[v] = tc - em2;
   }
-  axis_flux<T, 0>(qL, qR, C.ax, C.gm1, C.efix, G);
+  roe_flux<T, 3, 0>(qL, qR, nullptr, C.ax, C.K, G);
 }
 
-template <int MODE, typename T, int NY>
-__device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, DevInstance& I,
-                       double* __restrict__ rout, int lane, int w, T* s_q, T* s_f,
-                       double* s_red) {
-  const DevBlock& B = blocks[tl.blk];
-  const int ni = B.ni, nj = B.nj;
-  const int i0 = tl.i0, j0 = tl.j0, k0 = tl.k0, n = tl.n, nc = tl.ncol, ny = tl.ny;
-  const bool rowwave = w < NY;
-  const bool rowact = w < ny;           // this wave owns a row of cells
-  const int j = j0 + (rowwave ? w : ny);  // ghost wave: the row above the tile
-  const int i = i0 + lane;
-  const bool act = lane < nc;
-  const int ic = act ? i : ni - 1;
-  const int jc = rowact ? j : j0;       // safe row for idle waves
-  const int bin = MODE == 0 ? 0 : MODE - 1;
-  const int bout = MODE == 1 ? 1 : (MODE == 2 ? 2 : 0);
+template <typename T, int NY>
+struct Smem3 {
+  T q[(NY + 4) * 5 * kWave];    // plane k, rows j0-2 .. j0+NY+1
+  T f[(NY + 1) * 5 * kWave];    // j-face fluxes at j-1/2, rows j0 .. j0+NY
+  T edge[NY][kWave * 5];        // right-edge i-face fluxes, per row wave
+  T halo[NY][3][5];             // i-halo cells of plane k: i0-1, i0-2, i0+ncol
+  double red[(NY + 1) * 8];
+};
 
-  Ctx3D<T> C;
+template <typename T>
+__device__ __forceinline__ void setup3(Ctx3D<T>& C, const DevBlock* blocks, const DevBlock& B, int buf,
+                                       const DevInstance& I) {
   C.blocks = blocks;
   C.B = &B;
-  C.buf = bin;
+  C.buf = buf;
   C.rc.lim = I.limiter;
   C.rc.heps = T(0.5 * I.eps);
   C.rc.c1 = T(0.25 * I.eps * (1.0 - I.kappa));
   C.rc.c2 = T(0.25 * I.eps * (1.0 + I.kappa));
-  C.gm1 = T(I.gamma - 1.0);
-  C.efix = T(I.efix);
+  C.K.gm1 = T(I.gamma - 1.0);
+  C.K.efix = T(I.efix);
+  C.K.iefix = T(I.efix > 0.0 ? 1.0 / I.efix : 0.0);
   C.ax = T(B.area[0]);
   C.ay = T(B.area[1]);
   C.az = T(B.area[2]);
+}
+
+// j-face flux at j-1/2 from the LDS rows j-2 .. j+1 (slots s .. s+3), to SF(s)
+template <typename T, int NY>
+__device__ __forceinline__ void jface3(const Ctx3D<T>& C, Smem3<T, NY>& sm, int s, int lane) {
+  T qL[5], qR[5], Gj[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    const T a = sm.q[(s * 5 + v) * kWave + lane], b = sm.q[((s + 1) * 5 + v) * kWave + lane];
+    const T c = sm.q[((s + 2) * 5 + v) * kWave + lane], d = sm.q[((s + 3) * 5 + v) * kWave + lane];
+    T ep, em, ep2, em2;
+    extrap(C.rc, b - a, c - b, ep, em);
+    extrap(C.rc, c - b, d - c, ep2, em2);
+    qL[v] = b + ep;
+    qR[v] = c - em2;
+  }
+  roe_flux<T, 3, 1>(qL, qR, nullptr, C.ay, C.K, Gj);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) sm.f[(s * 5 + v) * kWave + lane] = Gj[v];
+}
+
+// The helper wave: per plane, stage the j-halo rows and the i-halo cells in
+// LDS (fetched one plane ahead) and form the tile's top-edge j-face flux.
+template <int MODE, typename T, int NY>
+__device__ void helper3d(const DevTile& tl, const DevBlock* __restrict__ blocks, const DevInstance& I,
+                         int lane, Smem3<T, NY>& sm) {
+  const DevBlock& B = blocks[tl.blk];
+  const int ni = B.ni;
+  const int i0 = tl.i0, j0 = tl.j0, k0 = tl.k0, n = tl.n, nc = tl.ncol, ny = tl.ny;
+  const int bin = MODE == 0 ? 0 : MODE - 1;
+  const int ic = lane < nc ? i0 + lane : ni - 1;
+  Ctx3D<T> C;
+  setup3(C, blocks, B, bin, I);
+  const int hrows[4] = {j0 - 2, j0 - 1, j0 + ny, j0 + ny + 1};
+  const int hslot[4] = {0, 1, ny + 2, ny + 3};
+  // i-halo lane assignment: lane = 3 * row + which, which 0: i0-1, 1: i0-2, 2: i0+ncol
+  const int hr = lane / 3, hw = lane - 3 * (lane / 3);
+  const bool hlane = hr < ny;
+  const int hcol = hw == 0 ? i0 - 1 : (hw == 1 ? i0 - 2 : i0 + nc);
+  double hrow[4][5], hcell[5] = {0, 0, 0, 0, 0};
+  if (n > 0) {
+#pragma unroll
+    for (int h = 0; h < 4; ++h) load_cell<5>(blocks, B, bin, ic, hrows[h], k0, hrow[h]);
+    if (hlane) load_cell<5>(blocks, B, bin, hcol, j0 + hr, k0, hcell);
+  }
+  for (int r = 0; r < n; ++r) {
+    const int k = k0 + r;
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sm.q[(hslot[h] * 5 + v) * kWave + lane] = T(hrow[h][v]);
+    if (hlane) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sm.halo[hr][hw][v] = T(hcell[v]);
+    }
+    if (r + 1 < n) {
+#pragma unroll
+      for (int h = 0; h < 4; ++h) load_cell<5>(blocks, B, bin, ic, hrows[h], k + 1, hrow[h]);
+      if (hlane) load_cell<5>(blocks, B, bin, hcol, j0 + hr, k + 1, hcell);
+    }
+    __syncthreads();
+    jface3<T, NY>(C, sm, ny, lane);
+    __syncthreads();
+  }
+}
+
+template <int MODE, typename T, int NY>
+__device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, DevInstance& I,
+                       double* __restrict__ rout, int lane, int w, Smem3<T, NY>& sm) {
+  const DevBlock& B = blocks[tl.blk];
+  const int ni = B.ni, nj = B.nj;
+  const int i0 = tl.i0, j0 = tl.j0, k0 = tl.k0, n = tl.n, nc = tl.ncol, ny = tl.ny;
+  const bool rowact = w < ny;
+  const int j = j0 + w;
+  const int i = i0 + lane;
+  const bool act = lane < nc;
+  const int ic = act ? i : ni - 1;
+  const int jc = rowact ? j : j0;
+  const int last = nc - 1;
+  const int bin = MODE == 0 ? 0 : MODE - 1;
+  const int bout = MODE == 1 ? 1 : (MODE == 2 ? 2 : 0);
+
+  Ctx3D<T> C;
+  setup3(C, blocks, B, bin, I);
   const double gamma = I.gamma;
   const double dt = I.dt;
   const double vol = B.vol;
+  const double ivol = 1.0 / vol;
   const long long ncell = B.ncell;
   double* __restrict__ Uout = B.u[bout];
   const double* __restrict__ Un = B.u[0];
 
-  // LDS slots: s_q[(row slot)][v][lane], row slot = j - j0 + 2
-  auto SQ = [&](int slot, int v) -> T& { return s_q[(slot * 5 + v) * kWave + lane]; };
-  auto SF = [&](int slot, int v) -> T& { return s_f[(slot * 5 + v) * kWave + lane]; };
-
-  // ---- prologue (row waves): planes k0-2, k0-1, k0 of the own column
-  T qkm1[5], qk[5], epm1[5];
-  double qkm1_d[5], qk_d[5];
+  // ---- prologue
+  double qm1[5] = {0, 0, 0, 0, 0}, q0[5] = {0, 0, 0, 0, 0}, qn[5] = {0, 0, 0, 0, 0};
+  T epm1[5] = {T(0), T(0), T(0), T(0), T(0)};
   if (rowact) {
-    double a[5], b[5], c[5];
-    load3d(blocks, B, bin, ic, jc, k0 - 2, a);
-    load3d(blocks, B, bin, ic, jc, k0 - 1, b);
-    load3d(blocks, B, bin, ic, jc, k0, c);
+    double qa[5];
+    load_cell<5>(blocks, B, bin, ic, jc, k0 - 2, qa);
+    load_cell<5>(blocks, B, bin, ic, jc, k0 - 1, qm1);
+    load_cell<5>(blocks, B, bin, ic, jc, k0, q0);
+    load_cell<5>(blocks, B, bin, ic, jc, k0 + 1, qn);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      const T ta = T(a[v]), tb = T(b[v]), tc = T(c[v]);
       T em;
-      extrap(C.rc, tb - ta, tc - tb, epm1[v], em);
-      qkm1[v] = tb;
-      qk[v] = tc;
-      qkm1_d[v] = b[v];
-      qk_d[v] = c[v];
+      extrap(C.rc, T(qm1[v]) - T(qa[v]), T(q0[v]) - T(qm1[v]), epm1[v], em);
     }
   }
-  double rij[5] = {0, 0, 0, 0, 0};
-  T gkb[5] = {T(0), T(0), T(0), T(0), T(0)};
-  T edge[5] = {T(0), T(0), T(0), T(0), T(0)};
+
+  double rg[5] = {0, 0, 0, 0, 0};
   double nacc[5] = {0, 0, 0, 0, 0};
   double dmin = INFINITY;
   int bad = 0;
 
   for (int r = 0; r <= n; ++r) {
     const int k = k0 + r;
-    T qn[5], ep0[5];
-    double qn_d[5];
+    const bool more = r < n;
+    T Gk[5], ep0[5];
+    double qnn[5] = {0, 0, 0, 0, 0};
     if (rowact) {
-      if (r < n && (r & 63) == 0) {
+      // ---- (1) the next plane of the own column
+      if (more) load_cell<5>(blocks, B, bin, ic, jc, k + 2, qnn);
+      // ---- (2) right-edge i-face fluxes of the next 64 planes
+      if (more && (r & 63) == 0) {
         const int rr = min(lane, n - r - 1);
-        edge_face3(C, i0 + nc, jc, k + rr, edge);
+        T ge[5];
+        edge_face3(C, i0 + nc, jc, k + rr, ge);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm.edge[w][lane * 5 + v] = ge[v];
+        __builtin_amdgcn_wave_barrier();
       }
-      load3d(blocks, B, bin, ic, jc, k + 1, qn_d);
-      // ---- k-face at k-1/2
-      T em0[5], qL[5], qR[5], Gk[5];
+      // ---- (3) k-face at k-1/2
+      T qL[5], qR[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        qn[v] = T(qn_d[v]);
-        extrap(C.rc, qk[v] - qkm1[v], qn[v] - qk[v], ep0[v], em0[v]);
-        qL[v] = qkm1[v] + epm1[v];
-        qR[v] = qk[v] - em0[v];
+        const T a = T(qm1[v]), b = T(q0[v]), c = T(qn[v]);
+        T em;
+        extrap(C.rc, b - a, c - b, ep0[v], em);
+        qL[v] = a + epm1[v];
+        qR[v] = b - em;
       }
-      axis_flux<T, 2>(qL, qR, C.az, C.gm1, C.efix, Gk);
-      // ---- complete plane k-1
+      roe_flux<T, 3, 2>(qL, qR, nullptr, C.az, C.K, Gk);
+      // ---- (4) complete plane k-1
       if (r >= 1 && act) {
         const long long idx = ((long long)(k - 1) * nj + j) * ni + i;
         double R[5];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) R[v] = rij[v] + ((double)Gk[v] - (double)gkb[v]);
+        for (int v = 0; v < 5; ++v) R[v] = rg[v] + (double)Gk[v];
         if (MODE == 0) {
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            rout[B.out_off + v * ncell + idx] = R[v];
-            const double rv = R[v] / vol;
+            stg(rout + B.out_off + v * ncell + idx, R[v]);
+            const double rv = R[v] * ivol;
             nacc[v] += rv * rv;
           }
         } else {
-          const double f = dt / vol;
+          const double f = dt * ivol;
           double out[5];
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            const double us = qkm1_d[v] - f * R[v];
+            const double us = qm1[v] - f * R[v];
             if (MODE == 1) out[v] = us;
-            else if (MODE == 2) out[v] = 0.75 * Un[v * ncell + idx] + 0.25 * us;
-            else out[v] = (1.0 / 3.0) * Un[v * ncell + idx] + (2.0 / 3.0) * us;
-            Uout[v * ncell + idx] = out[v];
+            else if (MODE == 2) out[v] = 0.75 * ldg(Un + v * ncell + idx) + 0.25 * us;
+            else out[v] = (1.0 / 3.0) * ldg(Un + v * ncell + idx) + (2.0 / 3.0) * us;
+            stg(Uout + v * ncell + idx, out[v]);
           }
           if (MODE == 1) {
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
-              const double rv = R[v] / vol;
+              const double rv = R[v] * ivol;
               nacc[v] += rv * rv;
             }
           }
@@ -197,102 +258,67 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
           }
         }
       }
-#pragma unroll
-      for (int v = 0; v < 5; ++v) gkb[v] = Gk[v];
     }
-    // ---- in-plane faces of plane k
-    if (r < n) {
+    // ---- (5) in-plane faces of plane k
+    if (more) {
       if (rowact) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) SQ(w + 2, v) = qk[v];
-      }
-      if (!rowwave) {
-        // j-halo rows of plane k: j0-2, j0-1, j0+ny, j0+ny+1
-        const int rows[4] = {j0 - 2, j0 - 1, j0 + ny, j0 + ny + 1};
-        const int slots[4] = {0, 1, ny + 2, ny + 3};
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          double q[5];
-          load3d(blocks, B, bin, ic, rows[h], k, q);
-#pragma unroll
-          for (int v = 0; v < 5; ++v) SQ(slots[h], v) = T(q[v]);
-        }
+        for (int v = 0; v < 5; ++v) sm.q[((w + 2) * 5 + v) * kWave + lane] = T(q0[v]);
       }
       __syncthreads();
-      if (rowact || !rowwave) {
-        // j-face at j-1/2: rows j-2 .. j+1 = slots s .. s+3 with s = j - j0
-        const int s = j - j0;
-        T qL[5], qR[5], Gj[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const T a = SQ(s, v), b = SQ(s + 1, v), c = SQ(s + 2, v), d = SQ(s + 3, v);
-          T ep, em, ep2, em2;
-          extrap(C.rc, b - a, c - b, ep, em);
-          extrap(C.rc, c - b, d - c, ep2, em2);
-          qL[v] = b + ep;
-          qR[v] = c - em2;
-        }
-        axis_flux<T, 1>(qL, qR, C.ay, C.gm1, C.efix, Gj);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) SF(s, v) = Gj[v];
-      }
       T Gi[5], Gr[5];
       if (rowact) {
-        // i-face at i-1/2 of row j, plane k
-        double hv_d[5] = {0, 0, 0, 0, 0};
-        if (lane < 3) {
-          const int hi = lane == 0 ? i0 - 1 : (lane == 1 ? i0 - 2 : i0 + nc);
-          load3d(blocks, B, bin, hi, jc, k, hv_d);
-        }
+        jface3<T, NY>(C, sm, w, lane);
         T qL[5], qR[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-          const T hv = T(hv_d[v]);
-          const T left = __shfl(qk[v], lane - 1 < 0 ? 0 : lane - 1, kWave);
-          const T right = __shfl(qk[v], lane + 1 > 63 ? 63 : lane + 1, kWave);
-          const T h1 = __shfl(hv, 1, kWave);
-          const T h2 = __shfl(hv, 2, kWave);
-          const T qim1 = lane == 0 ? hv : left;
-          const T qip1 = lane == nc - 1 ? h2 : right;
+          const T c = T(q0[v]);
+          const T h0 = sm.halo[w][0][v];  // Q(i0-1)
+          const T h1 = sm.halo[w][1][v];  // Q(i0-2)
+          const T h2 = sm.halo[w][2][v];  // Q(i0+ncol)
+          const T left = shr1(c);
+          const T right = shl1(c);
+          const T qim1 = lane == 0 ? h0 : left;
+          const T qip1 = lane == last ? h2 : right;
           T epc, emc;
-          extrap(C.rc, qk[v] - qim1, qip1 - qk[v], epc, emc);
-          const T epl = __shfl(epc, lane - 1 < 0 ? 0 : lane - 1, kWave);
+          extrap(C.rc, c - qim1, qip1 - c, epc, emc);
           T ep0l, em0l;
-          extrap(C.rc, hv - h1, qk[v] - hv, ep0l, em0l);
+          extrap(C.rc, h0 - h1, c - h0, ep0l, em0l);
+          const T epl = shr1(epc);
           qL[v] = qim1 + (lane == 0 ? ep0l : epl);
-          qR[v] = qk[v] - emc;
+          qR[v] = c - emc;
         }
-        axis_flux<T, 0>(qL, qR, C.ax, C.gm1, C.efix, Gi);
+        roe_flux<T, 3, 0>(qL, qR, nullptr, C.ax, C.K, Gi);
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-          const T gr = __shfl(Gi[v], lane + 1 > 63 ? 63 : lane + 1, kWave);
-          const T ge = __shfl(edge[v], r & 63, kWave);
-          Gr[v] = lane == nc - 1 ? ge : gr;
+          const T ge = sm.edge[w][(r & 63) * 5 + v];
+          Gr[v] = lane == last ? ge : shl1(Gi[v]);
         }
       }
       __syncthreads();
       if (rowact) {
-        const int s = j - j0;
 #pragma unroll
         for (int v = 0; v < 5; ++v)
-          rij[v] = ((double)Gr[v] - (double)Gi[v]) + ((double)SF(s + 1, v) - (double)SF(s, v));
+          rg[v] = (((double)Gr[v] - (double)Gi[v]) +
+                   ((double)sm.f[((w + 1) * 5 + v) * kWave + lane] -
+                    (double)sm.f[(w * 5 + v) * kWave + lane])) -
+                  (double)Gk[v];
       }
     }
     if (rowact) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        qkm1[v] = qk[v];
-        qk[v] = qn[v];
+        qm1[v] = q0[v];
+        q0[v] = qn[v];
+        qn[v] = qnn[v];
         epm1[v] = ep0[v];
-        qkm1_d[v] = qk_d[v];
-        qk_d[v] = qn_d[v];
       }
     }
   }
 
-  // ---- per-tile partials: wave reductions, then the row waves in order
+  // ---- per-tile partials of this row wave
   if (MODE == 0 || MODE == 1 || MODE == 3) {
-    double s[5];
+    double s[5] = {0, 0, 0, 0, 0};
     double m = 0.0;
     int b = 0;
     if (MODE == 3) {
@@ -302,36 +328,37 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
 #pragma unroll
       for (int v = 0; v < 5; ++v) s[v] = wave_sum(nacc[v]);
     }
-    if (lane == 0 && rowwave) {
+    if (lane == 0) {
       if (MODE == 3) {
-        s_red[w * 8 + 5] = m;
-        s_red[w * 8 + 6] = (double)b;
+        sm.red[w * 8 + 5] = m;
+        sm.red[w * 8 + 6] = (double)b;
       } else {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) s_red[w * 8 + v] = s[v];
+        for (int v = 0; v < 5; ++v) sm.red[w * 8 + v] = s[v];
       }
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double* part = I.part + (long long)tl.local * kPartStride;
-      if (MODE == 3) {
-        double mm = INFINITY;
-        double bb = 0.0;
-        for (int x = 0; x < ny; ++x) {
-          mm = fmin(mm, s_red[x * 8 + 5]);
-          bb = fmax(bb, s_red[x * 8 + 6]);
-        }
-        part[5] = mm;
-        part[6] = bb;
-      } else {
-        for (int v = 0; v < 5; ++v) {
-          double a = 0.0;
-          for (int x = 0; x < ny; ++x) a += s_red[x * 8 + v];
-          part[v] = a;
-        }
-      }
+  }
+}
+
+// tile partials: the row waves' sums in row order (fixed order)
+template <int MODE, int NY>
+__device__ void tile_partials3d(const DevTile& tl, DevInstance& I, const double* red) {
+  double* part = I.part + (long long)tl.local * kPartStride;
+  if (MODE == 3) {
+    double mm = INFINITY;
+    double bb = 0.0;
+    for (int x = 0; x < tl.ny; ++x) {
+      mm = fmin(mm, red[x * 8 + 5]);
+      bb = fmax(bb, red[x * 8 + 6]);
     }
-    __syncthreads();
+    part[5] = mm;
+    part[6] = bb;
+  } else if (MODE == 0 || MODE == 1) {
+    for (int v = 0; v < 5; ++v) {
+      double a = 0.0;
+      for (int x = 0; x < tl.ny; ++x) a += red[x * 8 + v];
+      part[v] = a;
+    }
   }
 }
 
@@ -341,9 +368,7 @@ __global__ __launch_bounds__(64 * (NY + 1)) void k_stage3d(const DevTile* __rest
                                                            const DevBlock* __restrict__ blocks,
                                                            DevInstance* __restrict__ insts,
                                                            double* __restrict__ rout) {
-  __shared__ T s_q[(NY + 4) * 5 * kWave];
-  __shared__ T s_f[(NY + 1) * 5 * kWave];
-  __shared__ double s_red[(NY + 1) * 8];
+  __shared__ Smem3<T, NY> sm;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ntiles = *ntiles_p;
@@ -351,7 +376,11 @@ __global__ __launch_bounds__(64 * (NY + 1)) void k_stage3d(const DevTile* __rest
     const DevTile tl = tiles[t];
     DevInstance& I = insts[tl.inst];
     if (MODE != 0 && I.stopped) continue;
-    tile3d<MODE, T, NY>(tl, blocks, I, rout, lane, w, s_q, s_f, s_red);
+    // the row waves and the helper wave take the same barriers
+    if (w < NY) tile3d<MODE, T, NY>(tl, blocks, I, rout, lane, w, sm);
+    else helper3d<MODE, T, NY>(tl, blocks, I, lane, sm);
+    __syncthreads();
+    if (threadIdx.x == 0) tile_partials3d<MODE, NY>(tl, I, sm.red);
     __syncthreads();
   }
 }
@@ -379,7 +408,7 @@ __global__ __launch_bounds__(256) void k_cfl3d(const DevTile* __restrict__ tiles
           const long long idx = ((long long)(tl.k0 + r) * B.nj + (tl.j0 + y)) * B.ni + i;
           double q[5];
 #pragma unroll
-          for (int v = 0; v < 5; ++v) q[v] = B.u[0][v * B.ncell + idx];
+          for (int v = 0; v < 5; ++v) q[v] = ldg(B.u[0] + v * B.ncell + idx);
           dmin = fmin(dmin, cell_dt_limit<3>(q, Sb, B.vol, I.gamma, bad));
         }
     }

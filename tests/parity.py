@@ -35,3 +35,18 @@ def state_err(case, Ug, Uo):
 def residual_err(case, Rg, Ro, scale):
     g, o, s = per_var(Rg, case), per_var(Ro, case), per_var(scale, case)
     return max(float(np.max(np.abs(gv - ov)) / np.max(sv)) for gv, ov, sv in zip(g, o, s))
+
+
+def cell_volumes(case):
+    """Cell volumes in the state order of one variable (all blocks)."""
+    out = []
+    for b in case.blocks:
+        if b.x is not None:
+            X, Y = b.x, b.y
+            a = (X[1:, 1:] - X[:-1, :-1]) * (Y[1:, :-1] - Y[:-1, 1:])
+            c = (X[1:, :-1] - X[:-1, 1:]) * (Y[1:, 1:] - Y[:-1, :-1])
+            out.append((0.5 * (a - c)).ravel())
+        else:
+            v = b.h[0] * b.h[1] * (b.h[2] if case.ndim == 3 else 1.0)
+            out.append(np.full(b.ncells, v))
+    return np.concatenate(out)
