@@ -46,17 +46,19 @@ def _compile(src: str, extra) -> str:
     return obj
 
 
-def build(extra=(), jobs: int = 8) -> str:
+def build(extra=(), jobs: int = 8, out: str = LIB, build_dir: str = BUILD) -> str:
+    global BUILD
+    BUILD = build_dir
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, list(extra)), SOURCES))
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -141,6 +141,9 @@ __device__ void tile2d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
   }
 
   double rg[4] = {0, 0, 0, 0};  // (G_i+1/2 - G_i-1/2) - G_j-1/2 of the carried row
+#ifdef FV_EDGE_REGS
+  T edge_r[4] = {T(0), T(0), T(0), T(0)};
+#endif
   double nacc[4] = {0, 0, 0, 0};
   double dmin = INFINITY;
   int bad = 0;
@@ -171,11 +174,15 @@ __device__ void tile2d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
     // ---- (2) right-edge i-face fluxes of the next 64 rows (LDS)
     if (more && (r & 63) == 0) {
       const int rr = min(lane, n - r - 1);
+#ifdef FV_EDGE_REGS
+      edge_face(C, i0 + nc, j + rr, edge_r);
+#else
       T ge[4];
       edge_face(C, i0 + nc, j + rr, ge);
 #pragma unroll
       for (int v = 0; v < 4; ++v) s_edge[lane * 4 + v] = ge[v];
       __builtin_amdgcn_wave_barrier();
+#endif
     }
     // ---- (3) j-face at j-1/2
     T qLj[4], qRj[4], ep0[4], Gj[4];
@@ -187,12 +194,16 @@ __device__ void tile2d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
       qLj[v] = a + epm1[v];
       qRj[v] = b - em;
     }
-    const double x0r = lane == last ? xh0 : shl1(x0);
-    const double y0r = lane == last ? yh0 : shl1(y0);
+    // lane shifts are taken by every lane, then selected (a conditional
+    // expression would run them under a partial EXEC mask)
+    const double x0s = shl1(x0), y0s = shl1(y0);
+    const double x0r = lane == last ? xh0 : x0s;
+    const double y0r = lane == last ? yh0 : y0s;
     face_flux<T, 1>(C, qLj, qRj, -(y0r - y0), x0r - x0, Gj);
     // ---- (4) complete, update and store row j-1
-    const double xmr = lane == last ? xhm : shl1(xm);
-    const double ymr = lane == last ? yhm : shl1(ym);
+    const double xms = shl1(xm), yms = shl1(ym);
+    const double xmr = lane == last ? xhm : xms;
+    const double ymr = lane == last ? yhm : yms;
     if (r >= 1 && act) {
       const long long idx = (long long)(j - 1) * ni + i;
       double R[4];
@@ -269,8 +280,13 @@ __device__ void tile2d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
       face_flux<T, 0>(C, qLi, qRi, y1 - y0, -(x1 - x0), Gi);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
+#ifdef FV_EDGE_REGS
+        const T ge = lane_value(edge_r[v], r & 63);
+#else
         const T ge = s_edge[(r & 63) * 4 + v];
-        const T gr = lane == last ? ge : shl1(Gi[v]);
+#endif
+        const T gs = shl1(Gi[v]);
+        const T gr = lane == last ? ge : gs;
         rg[v] = ((double)gr - (double)Gi[v]) - (double)Gj[v];
       }
       xhm = xh0; yhm = yh0;

@@ -292,7 +292,8 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
           const T ge = sm.edge[w][(r & 63) * 5 + v];
-          Gr[v] = lane == last ? ge : shl1(Gi[v]);
+          const T gs = shl1(Gi[v]);
+          Gr[v] = lane == last ? ge : gs;
         }
       }
       __syncthreads();

@@ -17,7 +17,7 @@ import numpy as np
 from . import cases as _cases
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfv.so")
+LIB_PATH = os.environ.get("FV_LIBRARY") or os.path.join(_HERE, "libfv.so")
 
 FV_OK, FV_PENDING = 0, 1
 FV_E_INVAL, FV_E_NOMEM, FV_E_DEVICE, FV_E_NONPHYSICAL = -1, -2, -3, -4
