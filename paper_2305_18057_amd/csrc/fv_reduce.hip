@@ -40,12 +40,29 @@ __global__ void k_prepare(DevInstance* insts, const int* active, int n) {
   if (!I.stopped) next_dt(I);
 }
 
-__device__ void reduce_parts(const DevInstance& I, int lane, double (&s)[5], double& mn, int& bad,
-                             bool sums, bool mins) {
+// Sums of the per-tile partials of one instance by a workgroup of kRedThreads
+// threads: thread x adds the tiles of its contiguous chunk in order, then a
+// fixed pairwise tree in LDS combines the threads (the result depends only on
+// the tile count, never on timing).  Result valid in thread 0.
+constexpr int kRedThreads = 256;
+
+struct RedOut {
+  double s[5];
+  double mn;
+  int bad;
+};
+
+__device__ void reduce_parts(const DevInstance& I, bool sums, bool mins, RedOut& out) {
+  __shared__ double sh[kRedThreads][6];
+  __shared__ int shb[kRedThreads];
+  const int x = threadIdx.x;
+  const int nt = I.ntiles;
+  const int chunk = (nt + kRedThreads - 1) / kRedThreads;
+  const int t0 = x * chunk, t1 = min(nt, t0 + chunk);
   double a[5] = {0, 0, 0, 0, 0};
   double m = INFINITY;
   int b = 0;
-  for (int t = lane; t < I.ntiles; t += kWave) {
+  for (int t = t0; t < t1; ++t) {
     const double* p = I.part + (long long)t * kPartStride;
     if (sums) {
 #pragma unroll
@@ -57,12 +74,28 @@ __device__ void reduce_parts(const DevInstance& I, int lane, double (&s)[5], dou
     }
   }
 #pragma unroll
-  for (int v = 0; v < 5; ++v) s[v] = wave_sum(a[v]);
-  mn = wave_min(m);
-  bad = wave_or(b);
+  for (int v = 0; v < 5; ++v) sh[x][v] = a[v];
+  sh[x][5] = m;
+  shb[x] = b;
+  __syncthreads();
+  for (int h = kRedThreads / 2; h >= 1; h >>= 1) {
+    if (x < h) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sh[x][v] += sh[x + h][v];
+      sh[x][5] = fmin(sh[x][5], sh[x + h][5]);
+      shb[x] |= shb[x + h];
+    }
+    __syncthreads();
+  }
+  if (x == 0) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out.s[v] = sh[0][v];
+    out.mn = sh[0][5];
+    out.bad = shb[0];
+  }
 }
 
-__device__ void norms_from_sums(const DevInstance& I, const double (&s)[5], double* norms,
+__device__ void norms_from_sums(const DevInstance& I, const double* s, double* norms,
                                 double& comb) {
   double cs = 0.0;
   for (int v = 0; v < 5; ++v) {
@@ -76,18 +109,15 @@ __device__ void norms_from_sums(const DevInstance& I, const double (&s)[5], doub
   comb = sqrt(cs);
 }
 
-__global__ void k_finalize(DevInstance* insts, const int* active, int n) {
-  const int x = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
-  if (x >= n) return;
-  DevInstance& I = insts[active ? active[x] : x];
+__global__ __launch_bounds__(kRedThreads) void k_finalize(DevInstance* insts, const int* active,
+                                                         int n) {
+  DevInstance& I = insts[active ? active[blockIdx.x] : blockIdx.x];
   if (I.stopped) return;
-  double s[5], mn;
-  int bad;
-  reduce_parts(I, lane, s, mn, bad, true, true);
-  if (lane != 0) return;
+  RedOut R;
+  reduce_parts(I, true, true, R);
+  if (threadIdx.x != 0) return;
   double norms[5], comb;
-  norms_from_sums(I, s, norms, comb);
+  norms_from_sums(I, R.s, norms, comb);
   for (int v = 0; v < 5; ++v) I.norms[v] = norms[v];
   I.norm = comb;
   if (!I.have_first) {
@@ -98,8 +128,8 @@ __global__ void k_finalize(DevInstance* insts, const int* active, int n) {
   I.t = I.last_step ? I.t_end : I.t + I.dt;
   I.dt_last = I.dt;
   I.steps += 1;
-  I.raw_min = mn;
-  if (bad) {
+  I.raw_min = R.mn;
+  if (R.bad) {
     I.flags |= FLAG_NONPHYS;
     I.stopped = 1;
   }
@@ -114,31 +144,25 @@ __global__ void k_finalize(DevInstance* insts, const int* active, int n) {
   if (!I.stopped) next_dt(I);
 }
 
-__global__ void k_cfl_init(DevInstance* insts, const int* active, int n) {
-  const int x = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
-  if (x >= n) return;
-  DevInstance& I = insts[active ? active[x] : x];
-  double s[5], mn;
-  int bad;
-  reduce_parts(I, lane, s, mn, bad, false, true);
-  if (lane != 0) return;
-  I.raw_min = mn;
-  I.flags = bad ? FLAG_NONPHYS : 0;
-  I.stopped = bad ? 1 : 0;
+__global__ __launch_bounds__(kRedThreads) void k_cfl_init(DevInstance* insts, const int* active,
+                                                         int n) {
+  DevInstance& I = insts[active ? active[blockIdx.x] : blockIdx.x];
+  RedOut R;
+  reduce_parts(I, false, true, R);
+  if (threadIdx.x != 0) return;
+  I.raw_min = R.mn;
+  I.flags = R.bad ? FLAG_NONPHYS : 0;
+  I.stopped = R.bad ? 1 : 0;
 }
 
-__global__ void k_rnorms(DevInstance* insts, const int* active, int n) {
-  const int x = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
-  if (x >= n) return;
-  DevInstance& I = insts[active ? active[x] : x];
-  double s[5], mn;
-  int bad;
-  reduce_parts(I, lane, s, mn, bad, true, false);
-  if (lane != 0) return;
+__global__ __launch_bounds__(kRedThreads) void k_rnorms(DevInstance* insts, const int* active,
+                                                       int n) {
+  DevInstance& I = insts[active ? active[blockIdx.x] : blockIdx.x];
+  RedOut R;
+  reduce_parts(I, true, false, R);
+  if (threadIdx.x != 0) return;
   double comb;
-  norms_from_sums(I, s, I.rnorms, comb);
+  norms_from_sums(I, R.s, I.rnorms, comb);
 }
 
 // One thread per ghost cell.  Segment = (block, face): both layers.
@@ -178,17 +202,17 @@ hipError_t launch_prepare(hipStream_t s, DevInstance* insts, const int* active, 
 }
 hipError_t launch_finalize(hipStream_t s, DevInstance* insts, const int* active, int n) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3((n + 3) / 4), dim3(256), 0, s, insts, active, n);
+  hipLaunchKernelGGL(k_finalize, dim3(n), dim3(kRedThreads), 0, s, insts, active, n);
   return hipGetLastError();
 }
 hipError_t launch_cfl_init(hipStream_t s, DevInstance* insts, const int* active, int n) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cfl_init, dim3((n + 3) / 4), dim3(256), 0, s, insts, active, n);
+  hipLaunchKernelGGL(k_cfl_init, dim3(n), dim3(kRedThreads), 0, s, insts, active, n);
   return hipGetLastError();
 }
 hipError_t launch_rnorms(hipStream_t s, DevInstance* insts, const int* active, int n) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rnorms, dim3((n + 3) / 4), dim3(256), 0, s, insts, active, n);
+  hipLaunchKernelGGL(k_rnorms, dim3(n), dim3(kRedThreads), 0, s, insts, active, n);
   return hipGetLastError();
 }
 hipError_t launch_ghosts(hipStream_t s, const DevBlock* blocks, const GhostSeg* segs, int nseg,
