@@ -214,14 +214,20 @@ int fv_grid_get_stats(const fv_grid* g, fv_grid_stats* out);
 /* ---------------------------------------------------------------------- */
 /* Batched execution and serving (continuous batching over one arena).     */
 /* ---------------------------------------------------------------------- */
+enum { FV_SERVER_DRYRUN = 1 };  /* fv_server_desc.flags: no device work at all;
+                                   every resident instance "takes" one step per
+                                   step slot and returns its initial state
+                                   (tests the scheduling logic on any host) */
+
 typedef struct fv_server_desc {
   void* d_arena;           /* caller's device memory for resident instances */
   size_t arena_bytes;
   void* hip_stream;        /* stream the server launches on */
-  int max_instances;       /* resident slots */
+  int max_instances;       /* resident slots (1..1024) */
   const char* autotune_cache; /* JSON autotune table or NULL */
   int precision;           /* FV_FP64 or FV_FP32_FLUX for every instance */
   int steps_per_launch;    /* RK steps per batched graph launch (0: 10) */
+  int flags;               /* FV_SERVER_* */
 } fv_server_desc;
 
 typedef struct fv_server fv_server;
@@ -237,6 +243,12 @@ int fv_submit(fv_server* s, const fv_grid_desc* desc, const double* U0, const fv
 int fv_poll(fv_server* s, unsigned long long ticket, double* U_out, size_t cap_doubles,
             fv_step_info* info);
 int fv_cancel(fv_server* s, unsigned long long ticket);
+/* Timestamps (seconds on the server's steady clock) of a request that
+ * fv_poll has not yet collected: submission, admission (resident), and
+ * completion (negative while not reached).  FV_E_NOTFOUND otherwise. */
+int fv_request_times(fv_server* s, unsigned long long ticket, double times[3]);
+/* Seconds on the server's steady clock (the clock of fv_request_times). */
+double fv_server_clock(fv_server* s);
 typedef struct fv_server_stats {
   long long submitted, admitted, completed, cancelled, failed;
   long long launches, cell_steps;

@@ -26,7 +26,8 @@ struct StepPlan {
   fvk::DevBlock* blocks = nullptr;
   fvk::DevInstance* insts = nullptr;
   const int* active = nullptr;  // device list of instance indices (nullptr: 0..ninst-1)
-  int ninst = 0;
+  int ninst = 0;                // finalize grid (the capacity when ninst_dev is set)
+  const int* ninst_dev = nullptr;  // device-resident live instance count
   std::vector<LaunchSet> sets;
 };
 
@@ -49,6 +50,8 @@ int launch_grid(const LaunchSet& s, int fp32);
 int enqueue_stage(const StepPlan& P, int mode, int fp32, double* rout, hipStream_t s);
 int enqueue_cfl(const StepPlan& P, hipStream_t s);
 // nsteps full steps; with a cache, replays (and captures on first use) a graph
-int enqueue_steps(const StepPlan& P, int fp32, int nsteps, hipStream_t s, GraphCache* cache);
+// (variant tells apart plans with different launch sets in one cache)
+int enqueue_steps(const StepPlan& P, int fp32, int nsteps, hipStream_t s, GraphCache* cache,
+                  int variant = 0);
 
 }  // namespace fvexec

@@ -86,13 +86,14 @@ static int enqueue_one_step(const StepPlan& P, int fp32, hipStream_t st) {
     const int e = enqueue_stage(P, m, fp32, nullptr, st);
     if (e) return e;
   }
-  const hipError_t e = fvk::launch_finalize(st, P.insts, P.active, P.ninst);
+  const hipError_t e = fvk::launch_finalize(st, P.insts, P.active, P.ninst, P.ninst_dev);
   if (e != hipSuccess)
     return fvrt::set_error(FV_E_DEVICE, "finalize launch failed: %s", hipGetErrorString(e));
   return FV_OK;
 }
 
-int enqueue_steps(const StepPlan& P, int fp32, int nsteps, hipStream_t st, GraphCache* cache) {
+int enqueue_steps(const StepPlan& P, int fp32, int nsteps, hipStream_t st, GraphCache* cache,
+                  int variant) {
   if (nsteps <= 0) return FV_OK;
   if (!cache || !graphs_enabled()) {
     for (int k = 0; k < nsteps; ++k) {
@@ -101,7 +102,7 @@ int enqueue_steps(const StepPlan& P, int fp32, int nsteps, hipStream_t st, Graph
     }
     return FV_OK;
   }
-  const int key = nsteps * 2 + (fp32 ? 1 : 0);
+  const int key = (variant << 22) | (nsteps << 1) | (fp32 ? 1 : 0);
   hipGraphExec_t ex = cache->get(key);
   if (!ex) {
     hipStream_t cs;

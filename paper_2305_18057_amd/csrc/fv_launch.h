@@ -29,7 +29,8 @@ const void* stage3d_kernel_ptr(int mode, int fp32, int ny);
 //   cfl_init: spectral minimum and physical check after a new state
 //   rnorms:   norms of a residual-only evaluation
 hipError_t launch_prepare(hipStream_t s, DevInstance* insts, const int* active, int n);
-hipError_t launch_finalize(hipStream_t s, DevInstance* insts, const int* active, int n);
+hipError_t launch_finalize(hipStream_t s, DevInstance* insts, const int* active, int n,
+                           const int* n_dev = nullptr);
 hipError_t launch_cfl_init(hipStream_t s, DevInstance* insts, const int* active, int n);
 hipError_t launch_rnorms(hipStream_t s, DevInstance* insts, const int* active, int n);
 

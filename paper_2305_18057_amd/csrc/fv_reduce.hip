@@ -110,7 +110,10 @@ __device__ void norms_from_sums(const DevInstance& I, const double* s, double* n
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_finalize(DevInstance* insts, const int* active,
-                                                         int n) {
+                                                         int n, const int* n_dev) {
+  // with a device-resident count the grid is sized for the capacity and the
+  // workgroups beyond the live count leave at once (graphs stay valid)
+  if (n_dev && (int)blockIdx.x >= *n_dev) return;
   DevInstance& I = insts[active ? active[blockIdx.x] : blockIdx.x];
   if (I.stopped) return;
   RedOut R;
@@ -200,9 +203,10 @@ hipError_t launch_prepare(hipStream_t s, DevInstance* insts, const int* active, 
   hipLaunchKernelGGL(k_prepare, dim3((n + 63) / 64), dim3(64), 0, s, insts, active, n);
   return hipGetLastError();
 }
-hipError_t launch_finalize(hipStream_t s, DevInstance* insts, const int* active, int n) {
+hipError_t launch_finalize(hipStream_t s, DevInstance* insts, const int* active, int n,
+                           const int* n_dev) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3(n), dim3(kRedThreads), 0, s, insts, active, n);
+  hipLaunchKernelGGL(k_finalize, dim3(n), dim3(kRedThreads), 0, s, insts, active, n, n_dev);
   return hipGetLastError();
 }
 hipError_t launch_cfl_init(hipStream_t s, DevInstance* insts, const int* active, int n) {

@@ -70,7 +70,7 @@ class fv_grid_stats(C.Structure):
 class fv_server_desc(C.Structure):
     _fields_ = [("d_arena", C.c_void_p), ("arena_bytes", C.c_size_t), ("hip_stream", C.c_void_p),
                 ("max_instances", C.c_int), ("autotune_cache", C.c_char_p),
-                ("precision", C.c_int), ("steps_per_launch", C.c_int)]
+                ("precision", C.c_int), ("steps_per_launch", C.c_int), ("flags", C.c_int)]
 
 
 class fv_server_stats(C.Structure):
@@ -86,8 +86,8 @@ EXPORTS = [
     "fv_create_grid", "fv_destroy_grid", "fv_set_state", "fv_get_state", "fv_residual",
     "fv_ghost_count", "fv_ghosts", "fv_step", "fv_step_timed", "fv_solve", "fv_tune",
     "fv_grid_get_stats",
-    "fv_server_create", "fv_submit", "fv_poll", "fv_cancel", "fv_server_get_stats",
-    "fv_server_destroy",
+    "fv_server_create", "fv_submit", "fv_poll", "fv_cancel", "fv_request_times",
+    "fv_server_clock", "fv_server_get_stats", "fv_server_destroy",
 ]
 
 _lib = None
@@ -129,6 +129,9 @@ def lib():
                             C.c_longlong, C.POINTER(C.c_ulonglong)]
     L.fv_poll.argtypes = [vp, C.c_ulonglong, dp, C.c_size_t, C.POINTER(fv_step_info)]
     L.fv_cancel.argtypes = [vp, C.c_ulonglong]
+    L.fv_request_times.argtypes = [vp, C.c_ulonglong, dp]
+    L.fv_server_clock.restype = C.c_double
+    L.fv_server_clock.argtypes = [vp]
     L.fv_server_get_stats.argtypes = [vp, C.POINTER(fv_server_stats)]
     L.fv_server_destroy.argtypes = [vp]
     _lib = L
@@ -317,17 +320,29 @@ def workspace_bytes(case) -> int:
 # server
 # ---------------------------------------------------------------------------
 class Server:
-    """Continuous-batching solver service over one torch-allocated arena."""
+    """Continuous-batching solver service over one torch-allocated arena.
+
+    ``dry_run=True`` exercises the scheduler without touching a device (every
+    request takes one step per step slot and returns its initial state)."""
+
+    FLAG_DRYRUN = 1
 
     def __init__(self, arena_bytes: int, max_instances=64, precision=_cases.FP32_FLUX,
-                 steps_per_launch=10, autotune_cache: Optional[str] = None, device="cuda"):
-        torch = _torch()
-        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
-        self.stream = current_stream_handle(self.arena.device)
+                 steps_per_launch=10, autotune_cache: Optional[str] = None, device="cuda",
+                 dry_run=False):
         self._cache = autotune_cache.encode() if autotune_cache else None
-        d = fv_server_desc(C.c_void_p(self.arena.data_ptr()), C.c_size_t(int(arena_bytes)),
-                           C.c_void_p(self.stream), int(max_instances), self._cache,
-                           int(precision), int(steps_per_launch))
+        if dry_run:
+            self.arena = None
+            ptr, stream = None, None
+        else:
+            torch = _torch()
+            self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=device)
+            ptr = self.arena.data_ptr()
+            stream = current_stream_handle(self.arena.device)
+        self.stream = stream
+        d = fv_server_desc(C.c_void_p(ptr), C.c_size_t(int(arena_bytes)), C.c_void_p(stream),
+                           int(max_instances), self._cache, int(precision), int(steps_per_launch),
+                           self.FLAG_DRYRUN if dry_run else 0)
         h = C.c_void_p()
         _check(lib().fv_server_create(C.byref(d), C.byref(h)))
         self._h = h
@@ -343,9 +358,18 @@ class Server:
         self._sizes[t.value] = U.size
         return t.value
 
+    def times(self, ticket: int):
+        """(submitted, admitted, done) on the server clock; negative = not yet."""
+        out = (C.c_double * 3)()
+        _check(lib().fv_request_times(self._h, C.c_ulonglong(ticket), out))
+        return tuple(out[:])
+
+    def clock(self) -> float:
+        return lib().fv_server_clock(self._h)
+
     def poll(self, ticket: int):
         """None while pending, else (status, U, info)."""
-        n = self._sizes[ticket]
+        n = self._sizes.get(ticket, 0)
         U = np.empty(n)
         info = fv_step_info()
         st = lib().fv_poll(self._h, C.c_ulonglong(ticket), U.ctypes.data_as(C.POINTER(C.c_double)),
@@ -354,6 +378,7 @@ class Server:
             return None
         if st not in (FV_OK, FV_E_NONPHYSICAL, FV_E_CANCELLED):
             _check(st)
+        self._sizes.pop(ticket, None)
         return st, U, info_dict(info)
 
     def cancel(self, ticket: int) -> int:

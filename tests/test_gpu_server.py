@@ -1,0 +1,146 @@
+"""Batched execution and the serving loop on the GPU.
+
+Each served instance must give the same state alone and in any mix (bitwise:
+its arithmetic and its reductions use only its own tiles, in a fixed order),
+stop at exactly its own stop step, and match the CPU reference like a grid
+solved on its own.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2305_18057_amd import cases as CS
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_2305_18057_amd import fv
+    from oracle import oracle as O
+    fv.lib()
+    return fv, O
+
+
+def drain(srv, tickets, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        assert time.time() - t0 < timeout, "server did not finish in time"
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        time.sleep(0.0005)
+    return out
+
+
+def mixed_cases():
+    cs = [CS.inlet_case(192, 48, 3, mach=2.5, angle_deg=4.0, name="m0"),
+          CS.inlet_case(64, 64, 1, mach=3.0, name="m1"),
+          CS.blobs_case(24, nblobs=3, seed=11, name="m2"),
+          CS.inlet_case(320, 40, 2, mach=1.8, angle_deg=8.0, name="m3"),
+          CS.vortex_2d(96, 48, seed=3),
+          CS.blobs_case(40, nblobs=2, seed=12, mach=2.5, name="m5")]
+    return cs
+
+
+@pytest.mark.parametrize("prec", [CS.FP64, CS.FP32_FLUX])
+def test_alone_equals_in_mix(env, prec):
+    fv, O = env
+    cs = mixed_cases()
+    steps = [37, 23, 41, 19, 30, 26]  # not multiples of the launch length
+    alone = []
+    for c, n in zip(cs, steps):
+        srv = fv.Server(arena_bytes=256 << 20, max_instances=4, precision=prec, steps_per_launch=7)
+        t = srv.submit(c, drop_tol=0.0, max_steps=n)
+        alone.append(drain(srv, [t])[t])
+        srv.close()
+    srv = fv.Server(arena_bytes=256 << 20, max_instances=3, precision=prec, steps_per_launch=7)
+    ts = [srv.submit(c, drop_tol=0.0, max_steps=n) for c, n in zip(cs, steps)]
+    mix = drain(srv, ts)
+    for k, t in enumerate(ts):
+        st, U, info = mix[t]
+        st0, U0, info0 = alone[k]
+        assert st == fv.FV_OK and st0 == fv.FV_OK
+        assert info["steps"] == steps[k] and info0["steps"] == steps[k]
+        assert np.array_equal(U, U0), f"instance {k} differs alone vs in mix"
+        assert info["t"] == info0["t"] and info["norm"] == info0["norm"]
+    s = srv.stats()
+    assert s["completed"] == len(cs) and s["arena_used"] == 0
+    srv.close()
+
+
+def test_served_equals_grid_and_reference(env):
+    fv, O = env
+    for c in (CS.inlet_case(256, 64, 4, angle_deg=5.0), CS.blobs_case(32, nblobs=4)):
+        srv = fv.Server(arena_bytes=256 << 20, max_instances=2, precision=CS.FP64, steps_per_launch=10)
+        t = srv.submit(c, drop_tol=0.0, max_steps=25)
+        st, U, info = drain(srv, [t])[t]
+        srv.close()
+        g = fv.Grid(c)
+        g.set_state(c.state_flat())
+        gi = g.step(c.params, 25)
+        assert np.array_equal(U, g.get_state())
+        ref = O.OracleGrid(c)
+        io = ref.run(c.params, 25)
+        e = P.state_err(c, U, ref.get_state())
+        assert info["steps"] == io["steps"] == 25 and e <= P.FP64_TOL, e
+
+
+def test_drop_tolerance_stop_matches_solve(env):
+    fv, O = env
+    c = CS.inlet_case(128, 32, 2, angle_deg=6.0)
+    g = fv.Grid(c)
+    g.set_state(c.state_flat())
+    gi = g.step(c.params, 60)
+    # a tolerance the drop crosses inside the run
+    tol = gi["drop"] * 1.000001
+    g2 = fv.Grid(c)
+    g2.set_state(c.state_flat())
+    si = g2.solve(c.params, drop_tol=tol, max_steps=500)
+    srv = fv.Server(arena_bytes=128 << 20, max_instances=2, precision=CS.FP64, steps_per_launch=9)
+    t = srv.submit(c, drop_tol=tol, max_steps=500)
+    st, U, info = drain(srv, [t])[t]
+    srv.close()
+    assert info["steps"] == si["steps"] and info["flags"] & fv.FLAG_CONVERGED
+    assert np.array_equal(U, g2.get_state())
+
+
+def test_failure_isolated(env):
+    fv, O = env
+    good = CS.inlet_case(128, 32, 2)
+    bad = CS.sod_2d(n=64, nj=4, t_end=0.0)
+    bad_p = CS.Params(**{**bad.params.__dict__, "dt_fixed": 0.2})  # far past the CFL limit
+    srv = fv.Server(arena_bytes=128 << 20, max_instances=4, precision=CS.FP64, steps_per_launch=5)
+    tg = srv.submit(good, drop_tol=0.0, max_steps=20)
+    tb = srv.submit(bad, drop_tol=0.0, max_steps=20, params=bad_p)
+    res = drain(srv, [tg, tb])
+    srv.close()
+    assert res[tb][0] == fv.FV_E_NONPHYSICAL and res[tb][2]["steps"] < 20
+    assert res[tg][0] == fv.FV_OK and res[tg][2]["steps"] == 20
+    g = fv.Grid(good)
+    g.set_state(good.state_flat())
+    g.step(good.params, 20)
+    assert np.array_equal(res[tg][1], g.get_state())
+
+
+def test_continuous_admission_under_load(env):
+    """More requests than slots and arena: later ones are admitted as earlier
+    ones retire, while the others keep running."""
+    fv, O = env
+    cs = [CS.inlet_case(64 * (1 + k % 4), 32 + 16 * (k % 3), 1 + k % 3, mach=1.5 + 0.2 * k,
+                        name=f"q{k}") for k in range(12)]
+    srv = fv.Server(arena_bytes=48 << 20, max_instances=4, precision=CS.FP32_FLUX, steps_per_launch=5)
+    ts = [srv.submit(c, drop_tol=0.0, max_steps=15 + 3 * k) for k, c in enumerate(cs)]
+    res = drain(srv, ts)
+    s = srv.stats()
+    srv.close()
+    assert all(res[t][0] == fv.FV_OK for t in ts)
+    assert [res[t][2]["steps"] for t in ts] == [15 + 3 * k for k in range(12)]
+    assert s["admitted"] == 12 and s["launches"] > 0 and s["arena_used"] == 0
