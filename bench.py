@@ -7,19 +7,28 @@ whole grid.  The headline workload is the 2D supersonic-inlet-like
 multi-block grid (4 blocks of 512 x 256 cells, sheared wavy curvilinear mesh,
 Mach 4 inflow of the paper's inflow table, slip walls, extrapolation outflow)
 in FP64.  Inputs are synthetic and already resident in HBM when the timed
-region starts.
+region starts; tile shapes come from the autotuner before timing.
 
 Printed: one JSON line with cell-updates/s, the roofline of the stage kernel
-(algorithmic bytes per launch / average launch time from HIP events) and the
-CPU reference timed on a bounded sample on this host.
+(algorithmic bytes per launch / average launch time from HIP events on the
+launch stream), the CPU reference timed on a bounded sample on this host,
+and (unless --no-extra) the FP32-flux and 3D workloads, the 64-instance
+batch and the serving trace.
+
+``--summarize DIR`` turns rocprofv3 CSV output (kernel trace stats or
+counter collection) into the short text summaries kept under profiles/.
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import math
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -27,13 +36,20 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6   # vector FP64, 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+FP32_PEAK_TFS = 157.3
 METRIC = "cell-updates/s + % HBM roofline; batched p50/p99 solve latency vs plain"
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_2305_18057_amd", "csrc")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# --------------------------------------------------------------------------
+# algorithmic figures per cell
+# --------------------------------------------------------------------------
 def algorithmic_bytes_per_cell_step(case) -> int:
     """Compulsory HBM bytes of one SSP-RK3 step per cell (FP64 state).
 
@@ -49,10 +65,68 @@ def algorithmic_bytes_per_cell_step(case) -> int:
     return b
 
 
-def time_grid(fv, case, params, steps, warmup):
+def algorithmic_flops_per_cell_stage(case) -> int:
+    """FP64 operations of one cell-stage counted from the formulas (add, mul,
+    div, sqrt, abs/min/max each 1; a fused multiply-add 2), averaged over the
+    three stages: ND face fluxes (each face flux is formed once and used by
+    the two cells it separates), the reconstruction of every variable in every
+    direction, the flux divergence, the stage update and the fused norm / CFL
+    reductions.  Newton steps of reciprocals and roots are not counted."""
+    nd = case.ndim
+    curv = any(blk.x is not None for blk in case.blocks)
+    if nd == 2:
+        flux = 140 + (7 if curv else -6)  # general normal (+ |S|, n) or axis-aligned
+        recon = 5 * 4 * 2
+        div = 3 * 4
+        upd = 17 + (11 if curv else 0)    # + volume and face vectors from nodes
+        red = 19
+        return 2 * flux + recon + div + upd + red
+    flux = 155
+    recon = 5 * 5 * 3
+    div = 5 * 5
+    upd = 21
+    red = 19
+    return 3 * flux + recon + div + upd + red
+
+
+# --------------------------------------------------------------------------
+# committed profile summaries (traffic and instruction counts)
+# --------------------------------------------------------------------------
+def kernel_sources_sha(ndim: int) -> str:
+    h = hashlib.sha256()
+    for f in ("fv_device.h", "fv_kernels2d.hip" if ndim == 2 else "fv_kernels3d.hip"):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profile_record(kernel: str, workload: str, ndim: int):
+    """key: value lines of profiles/<kernel>_<workload>_counters.txt, or None
+    when absent or taken from kernel sources other than the current ones."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith((" ", "#", "|")):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("kernel_sources_sha") != kernel_sources_sha(ndim):
+        return None
+    return rec
+
+
+# --------------------------------------------------------------------------
+# single-grid timing
+# --------------------------------------------------------------------------
+def time_grid(fv, case, params, steps, warmup, tune_cache=None):
     import torch
     g = fv.Grid(case)
     g.set_state(case.state_flat())
+    if tune_cache is not None:
+        g.tune(params, tune_cache)
+        g.set_state(case.state_flat())
     if warmup:
         g.step(params, warmup)
     stream = torch.cuda.current_stream()
@@ -65,24 +139,43 @@ def time_grid(fv, case, params, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     dev_ms = e0.elapsed_time(e1)
-    # per-kernel timing pass over the same number of steps
+    # per-kernel timing pass over the same number of steps (HIP events around
+    # every stage launch on the grid's stream)
     _, stage_ms = g.step_timed(params, steps)
     st = g.stats()
     return g, info, wall, dev_ms, stage_ms, st
 
 
-def roofline_of(case, stage_ms, steps):
+def roofline_of(case, stage_ms, steps, workload, fp32=False):
     cells = case.ncells
+    kernel = "k_stage2d" if case.ndim == 2 else "k_stage3d"
     per_step = algorithmic_bytes_per_cell_step(case) * cells
     launches = 3 * steps
     avg_ms = float(sum(stage_ms[:3])) / launches
     bytes_per_launch = per_step / 3.0
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                kernel="k_stage2d" if case.ndim == 2 else "k_stage3d",
+    rec = profile_record(kernel, workload + ("_fp32flux" if fp32 else "_fp64"), case.ndim)
+    traffic = None
+    if rec is not None and "hbm_bytes_per_launch" in rec:
+        traffic = int(float(rec["hbm_bytes_per_launch"]))
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
+                kernel=kernel, bytes_per_cell_step=algorithmic_bytes_per_cell_step(case),
                 bytes_per_launch=int(bytes_per_launch), avg_launch_ms=round(avg_ms, 5),
                 finalize_avg_ms=round(float(stage_ms[3]) / steps, 5))
+    flops = algorithmic_flops_per_cell_stage(case)
+    tfs = flops * cells / (avg_ms * 1e-3) / 1e12
+    peak = FP32_PEAK_TFS if fp32 else FP64_PEAK_TFS
+    alu = dict(flops_per_cell_stage=flops, achieved_tflops=round(tfs, 3), peak_tflops=peak,
+               frac=round(tfs / peak, 4),
+               intensity_flop_per_byte=round(flops / (bytes_per_launch / cells), 2),
+               ridge_flop_per_byte=round(peak * 1e3 / HBM_PEAK_GBS, 2))
+    if rec is not None:
+        for k in ("valu_instr_per_cell_stage", "valu_busy_frac", "wait_frac", "vgprs",
+                  "scratch_bytes_per_lane"):
+            if k in rec:
+                alu[k] = float(rec[k])
+    return roof, alu
 
 
 def cpu_baseline(case, budget_s=12.0):
@@ -101,57 +194,382 @@ def cpu_baseline(case, budget_s=12.0):
                        f"({dt:.1f} s wall, FP64, OpenMP over faces/cells)")
 
 
+# --------------------------------------------------------------------------
+# batched instances and the serving trace
+# --------------------------------------------------------------------------
+def _drain(srv, tickets, timeout=600.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        if time.time() - t0 > timeout:
+            raise RuntimeError("server did not finish in time")
+        for t in tickets:
+            if t not in out:
+                r = srv.poll(t)
+                if r is not None:
+                    out[t] = r
+        time.sleep(0.0005)
+    return out
+
+
+def _plain_solve(fv, case, drop_tol, max_steps, params=None):
+    """One request solved on its own: grid, upload, solve, download (wall)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = fv.Grid(case)
+    g.set_state(case.state_flat())
+    info = g.solve(params or case.params, drop_tol=drop_tol, max_steps=max_steps, check=False)
+    g.get_state()
+    dt = time.perf_counter() - t0
+    g.close()
+    return dt, info
+
+
+def arena_for(fv, cs, slack=1.5):
+    return int(sum(fv.workspace_bytes(c) for c in cs) * slack) + (64 << 20)
+
+
+def bench_batched(fv, cases, steps=100, count=64, spl=10):
+    cs = cases.batch_2d(count, seed=4, nsteps=steps)  # FP32-flux
+    cells = sum(c.ncells for c in cs)
+    log(f"[bench] batched {count} instances, {cells} cells, {steps} steps")
+    # plain: one instance after the other, same precision
+    seq = 0.0
+    for c in cs:
+        dt, info = _plain_solve(fv, c, 0.0, steps)
+        assert info["steps"] == steps
+        seq += dt
+    srv = fv.Server(arena_bytes=arena_for(fv, cs), max_instances=count,
+                    precision=cases.FP32_FLUX, steps_per_launch=spl)
+    # one untimed pass so that graphs and code objects are ready
+    _drain(srv, [srv.submit(cs[0], drop_tol=0.0, max_steps=spl)])
+    ts = [srv.submit(c, drop_tol=0.0, max_steps=steps) for c in cs]
+    res = _drain(srv, ts)
+    tm = [srv.times(t) for t in ts]
+    srv.close()
+    assert all(res[t][0] == fv.FV_OK and res[t][2]["steps"] == steps for t in ts)
+    span = max(x[2] for x in tm) - min(x[0] for x in tm)
+    return dict(instances=count, cells=cells, steps=steps, precision="fp32flux",
+                value=round(cells * steps / span, 1), unit="cell-updates/s",
+                makespan_s=round(span, 4), sequential_s=round(seq, 4),
+                sequential_value=round(cells * steps / seq, 1),
+                speedup=round(seq / span, 3), steps_per_launch=spl)
+
+
+def _serve(fv, cases, reqs, built, arena, max_inst, spl, rate_scale=1.0):
+    srv = fv.Server(arena_bytes=arena, max_instances=max_inst, precision=cases.FP32_FLUX,
+                    steps_per_launch=spl)
+    _drain(srv, [srv.submit(built[0], drop_tol=0.0, max_steps=spl)])  # warm
+    tickets = [None] * len(reqs)
+    start = time.perf_counter()
+    k = 0
+    pending = set()
+    done = {}
+    while len(done) < len(reqs):
+        now = time.perf_counter() - start
+        while k < len(reqs) and reqs[k].arrival * rate_scale <= now:
+            s = reqs[k].spec
+            tickets[k] = srv.submit(built[k], drop_tol=s["drop_tol"], max_steps=s["max_steps"])
+            pending.add(k)
+            k += 1
+        for q in list(pending):
+            r = srv.poll(tickets[q])
+            if r is not None:
+                done[q] = r
+                pending.discard(q)
+        if now > 900:
+            raise RuntimeError("serving trace did not finish")
+        time.sleep(0.0002)
+    tm = [srv.times(t) for t in tickets]
+    srv.close()
+    lat = [x[2] - x[0] for x in tm]
+    span = max(x[2] for x in tm) - min(x[0] for x in tm)
+    work = sum(built[q].ncells * done[q][2]["steps"] for q in range(len(reqs)))
+    ok = sum(1 for q in range(len(reqs)) if done[q][0] == fv.FV_OK)
+    return lat, span, work, ok
+
+
+def _pct(xs, p):
+    s = sorted(xs)
+    i = min(len(s) - 1, max(0, int(math.ceil(p / 100.0 * len(s))) - 1))
+    return s[i]
+
+
+def bench_serving(fv, cases, count=64, max_steps=500, spl=10, max_inst=32):
+    reqs = cases.serving_trace(256, seed=5, max_steps=max_steps)[:count]
+    built = [cases.build_request(r, precision=cases.FP32_FLUX) for r in reqs]
+    arena = min(arena_for(fv, built, 1.2), 48 << 30)
+    log(f"[bench] serving {count} requests (first {count} of the 256-request trace), "
+        f"max_steps {max_steps}, arena {arena >> 20} MiB")
+    lat, span, work, ok = _serve(fv, cases, reqs, built, arena, max_inst, spl)
+    # plain: sequential FP64 solves in arrival order on the same GPU
+    solve_s, steps_plain = [], []
+    for r in reqs:
+        c = cases.build_request(r, precision=cases.FP64)
+        dt, info = _plain_solve(fv, c, r.spec["drop_tol"], r.spec["max_steps"])
+        solve_s.append(dt)
+        steps_plain.append(info["steps"])
+    end = 0.0
+    lat_p = []
+    for r, s in zip(reqs, solve_s):
+        st = max(r.arrival, end)
+        end = st + s
+        lat_p.append(end - r.arrival)
+    span_p = end - reqs[0].arrival
+    work_p = sum(b.ncells * n for b, n in zip(built, steps_plain))
+    out = dict(requests=count, max_steps=max_steps, drop_tol=reqs[0].spec["drop_tol"],
+               arrival_rate_per_s=200.0, completed_ok=ok,
+               batched=dict(precision="fp32flux", p50_s=round(_pct(lat, 50), 4),
+                            p99_s=round(_pct(lat, 99), 4), makespan_s=round(span, 4),
+                            value=round(work / span, 1), unit="cell-updates/s"),
+               plain=dict(precision="fp64", p50_s=round(_pct(lat_p, 50), 4),
+                          p99_s=round(_pct(lat_p, 99), 4), makespan_s=round(span_p, 4),
+                          value=round(work_p / span_p, 1), unit="cell-updates/s"))
+    out["throughput_ratio"] = round(out["batched"]["value"] / out["plain"]["value"], 3)
+    # supplementary: the same requests at about 0.7x the measured capacity
+    cap_rate = count / span
+    scale = (200.0 / (0.7 * cap_rate))
+    lat2, span2, work2, ok2 = _serve(fv, cases, reqs, built, arena, max_inst, spl, rate_scale=scale)
+    out["low_load"] = dict(arrival_rate_per_s=round(200.0 / scale, 2), p50_s=round(_pct(lat2, 50), 4),
+                           p99_s=round(_pct(lat2, 99), 4), value=round(work2 / span2, 1))
+    return out
+
+
+# --------------------------------------------------------------------------
+# rocprofv3 output -> short text summaries
+# --------------------------------------------------------------------------
+def _col(row, *names):
+    low = {k.lower(): v for k, v in row.items()}
+    for n in names:
+        if n.lower() in low:
+            return low[n.lower()]
+    return None
+
+
+def _counter_runs(dirs, kernel_filter):
+    """{kernel: {counter: mean per dispatch, '_dur_ns', '_vgpr', ...}} over the
+    counter-collection CSVs under ``dirs``."""
+    per = {}
+    for d in dirs:
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(path) as fh:
+                for row in csv.DictReader(fh):
+                    name = _col(row, "Kernel_Name").replace("(anonymous namespace)::", "")
+                    if kernel_filter not in name:
+                        continue
+                    name = name.split("(")[0]
+                    key = (name, d, _col(row, "Dispatch_Id"))
+                    e = per.setdefault(key, {})
+                    c = _col(row, "Counter_Name")
+                    e[c] = e.get(c, 0.0) + float(_col(row, "Counter_Value"))
+                    t0, t1 = _col(row, "Start_Timestamp"), _col(row, "End_Timestamp")
+                    if t0 and t1:
+                        e["_dur_ns"] = float(t1) - float(t0)
+                    for k, names in (("_vgpr", ("Arch_VGPR_Count", "VGPR_Count")),
+                                     ("_scratch", ("Scratch_Size",)), ("_grid", ("Grid_Size",))):
+                        v = _col(row, *names)
+                        if v not in (None, ""):
+                            e[k] = float(v)
+    agg = {}
+    for (name, _, _), e in per.items():
+        a = agg.setdefault(name, {"_n": {}})
+        for k, v in e.items():
+            a.setdefault(k, []).append(v)
+    out = {}
+    for name, a in agg.items():
+        out[name] = {k: sum(v) / len(v) for k, v in a.items() if k != "_n"}
+        out[name]["_dispatches"] = max(len(v) for k, v in a.items() if k != "_n")
+    return out
+
+
+def summarize(dirs, kernel_filter, out_path, command, calib=None, workload=None, precision="fp64"):
+    """Kernel-trace stats (``*kernel_stats.csv``) and counter collection
+    (``*counter_collection.csv``) of rocprofv3 runs as a short text file.
+    ``calib`` names the runs of the same counters over a 1 GiB device copy,
+    whose known traffic scales FETCH_SIZE / WRITE_SIZE (KiB) to bytes."""
+    lines = ["# rocprofv3 summary", f"command: {command}", ""]
+    for d in dirs:
+        for path in glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True):
+            lines.append(f"# kernel stats ({os.path.basename(path)})")
+            lines.append("| kernel | calls | total ms | avg us | min us | max us | % |")
+            lines.append("|---|---|---|---|---|---|---|")
+            with open(path) as fh:
+                for row in csv.DictReader(fh):
+                    name = _col(row, "Name").replace("(anonymous namespace)::", "").split("(")[0]
+                    lines.append(f"| {name} | {_col(row, 'Calls')} | "
+                                 f"{float(_col(row, 'TotalDurationNs'))/1e6:.3f} | "
+                                 f"{float(_col(row, 'AverageNs'))/1e3:.2f} | "
+                                 f"{float(_col(row, 'MinNs'))/1e3:.2f} | "
+                                 f"{float(_col(row, 'MaxNs'))/1e3:.2f} | "
+                                 f"{float(_col(row, 'Percentage')):.2f} |")
+            lines.append("")
+    cnt = _counter_runs(dirs, kernel_filter)
+    if cnt:
+        lines.append("# counters, mean per dispatch (FETCH_SIZE / WRITE_SIZE in KiB)")
+        for name, a in sorted(cnt.items()):
+            vals = ", ".join(f"{k}={v:.6g}" for k, v in sorted(a.items()) if not k.startswith("_"))
+            lines.append(f"  {name}: dispatches={a['_dispatches']} dur_us={a.get('_dur_ns', 0)/1e3:.2f} "
+                         f"vgpr={a.get('_vgpr')} scratch={a.get('_scratch')} grid={a.get('_grid')} {vals}")
+        lines.append("")
+    fetch_f = write_f = None
+    if calib:
+        cc = _counter_runs(calib, "copyBuffer")
+        big = [a for a in cc.values() if a.get("_grid", 0) >= 65536] or list(cc.values())
+        f = [a["FETCH_SIZE"] for a in big if "FETCH_SIZE" in a]
+        w = [a["WRITE_SIZE"] for a in big if "WRITE_SIZE" in a]
+        if f:
+            fetch_f = float(1 << 30) / (max(f) * 1024.0)
+        if w:
+            write_f = float(1 << 30) / (max(w) * 1024.0)
+        lines.append(f"# calibration: 1 GiB device copy reads FETCH_SIZE={max(f) if f else None} KiB, "
+                     f"WRITE_SIZE={max(w) if w else None} KiB")
+        lines.append("")
+    if workload and cnt:
+        from paper_2305_18057_amd import cases
+        case = cases.inlet_2d() if workload == "inlet_2d" else cases.blobs_3d()
+        cells = case.ncells
+        st = [a for n, a in cnt.items() if "stage" in n]
+        def mean(k):
+            v = [a[k] for a in st if k in a]
+            return sum(v) / len(v) if v else None
+        lines.append(f"kernel_sources_sha: {kernel_sources_sha(case.ndim)}")
+        lines.append(f"workload: {workload}_{precision}")
+        lines.append(f"cells: {cells}")
+        alg = algorithmic_bytes_per_cell_step(case) * cells / 3.0
+        lines.append(f"algorithmic_bytes_per_launch: {alg:.0f}")
+        fs, ws = mean("FETCH_SIZE"), mean("WRITE_SIZE")
+        if fs is not None and ws is not None and fetch_f and write_f:
+            hbm = fs * 1024.0 * fetch_f + ws * 1024.0 * write_f
+            lines.append(f"fetch_factor: {fetch_f:.4f}")
+            lines.append(f"write_factor: {write_f:.4f}")
+            lines.append(f"hbm_bytes_per_launch: {hbm:.0f}")
+            lines.append(f"traffic_over_algorithmic: {hbm / alg:.3f}")
+        vi = mean("SQ_INSTS_VALU")
+        dur = mean("_dur_ns")
+        if vi is not None:
+            lines.append(f"valu_instr_per_cell_stage: {vi * 64.0 / cells:.1f}")
+            if dur:
+                # a wave64 VALU instruction holds its 16-lane SIMD for 4 cycles
+                lines.append(f"valu_busy_frac: {vi * 4.0 / (dur * 1e-9 * 2.4e9 * 1024):.3f}")
+        wa, wc = mean("SQ_WAIT_ANY"), mean("SQ_WAVE_CYCLES")
+        if wa is not None and wc:
+            lines.append(f"wait_frac: {wa / wc:.3f}")
+        fl = mean("SQ_INSTS_VALU_FLOPS_FP64")
+        if fl is not None:
+            lines.append(f"fp64_flops_per_cell_stage_measured: {fl * 64.0 / cells:.1f}")
+        v = mean("_vgpr")
+        if v is not None:
+            lines.append(f"vgprs: {v:.0f}")
+        sc = mean("_scratch")
+        if sc is not None:
+            lines.append(f"scratch_bytes_per_lane: {sc:.0f}")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+# --------------------------------------------------------------------------
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="inlet_2d", choices=["inlet_2d", "blobs_3d"],
+                    help="headline workload (default: the 2D inlet-like grid)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32flux"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
+    ap.add_argument("--no-tune", action="store_true", help="default tile shapes, no autotuning")
+    ap.add_argument("--tile-cache", help="autotune table (JSON); shapes already in it are reused "
+                                         "without timing (default: a fresh temporary table)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--summarize", metavar="DIRS",
+                    help="comma-separated rocprofv3 CSV output folders to summarize, then exit")
+    ap.add_argument("--calib", metavar="DIRS", help="with --summarize: copy-probe counter runs")
+    ap.add_argument("--kernel", default="k_stage", help="kernel name filter for --summarize")
+    ap.add_argument("--out", help="summary file for --summarize")
+    ap.add_argument("--command", default="", help="profiling command recorded in the summary")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize.split(","), args.kernel, args.out, args.command,
+                  args.calib.split(",") if args.calib else None,
+                  args.workload, args.precision)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} (WORLD_SIZE={world}) is not "
-              "supported: the hot path is measured on a single MI355X and would shard by "
-              "blocks / instances across GPUs (see DESIGN.md).", file=sys.stderr)
+              "supported: the hot path runs on a single MI355X (a large grid would shard by "
+              "blocks, batches and serving by instance).", file=sys.stderr)
         sys.exit(2)
 
     import torch
-    from paper_2305_18057_amd import cases, fv
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        n = 1 << 27  # 128 Mi doubles = 1 GiB
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"copied 3 x {n * 8} bytes", flush=True)
+        return
+    from paper_2305_18057_amd import cases, fv
     fv.lib()
+    tune_cache = None
+    if not args.no_tune:
+        tune_cache = args.tile_cache or os.path.join(tempfile.mkdtemp(prefix="fv_tune_"), "tiles.json")
 
-    # ---- headline: 2D inlet-like 4 x 512 x 256, FP64
-    case = cases.inlet_2d()
-    prm = case.params
-    log(f"[bench] headline {case.name} cells={case.ncells} steps={args.steps} warmup={args.warmup}")
-    g, info, wall, dev_ms, stage_ms, st = time_grid(fv, case, prm, args.steps, args.warmup)
+    # ---- headline
+    prec = cases.FP64 if args.precision == "fp64" else cases.FP32_FLUX
+    case = cases.inlet_2d() if args.workload == "inlet_2d" else cases.blobs_3d()
+    prm = cases.Params(**{**case.params.__dict__, "precision": prec})
+    log(f"[bench] headline {case.name} {args.precision} cells={case.ncells} steps={args.steps} "
+        f"warmup={args.warmup}")
+    g, info, wall, dev_ms, stage_ms, st = time_grid(fv, case, prm, args.steps, args.warmup, tune_cache)
     ms_per_step = dev_ms / args.steps
     value = case.ncells * args.steps / (dev_ms * 1e-3)
-    roof = roofline_of(case, stage_ms, args.steps)
+    roof, alu = roofline_of(case, stage_ms, args.steps, args.workload, prec == cases.FP32_FLUX)
     log(f"[bench] {value/1e9:.3f} G cell-updates/s, {ms_per_step*1e3:.1f} us/step, "
-        f"stage kernel {roof['avg_launch_ms']*1e3:.1f} us -> {roof['achieved']:.0f} GB/s")
+        f"stage kernel {roof['avg_launch_ms']*1e3:.1f} us -> {roof['achieved']:.0f} GB/s "
+        f"({100*roof['frac']:.1f}% HBM), tile rows={st['tile_rows']} ny={st['tile_ny']}")
+    g.close()
     del g
 
     extra = {}
     if not args.no_extra:
-        for name, mk, prec, steps in [
-            ("inlet_2d_fp32flux", cases.inlet_2d, cases.FP32_FLUX, args.steps),
-            ("blobs_3d_fp64", cases.blobs_3d, cases.FP64, 50),
-            ("blobs_3d_fp32flux", cases.blobs_3d, cases.FP32_FLUX, 50),
-        ]:
+        others = [("inlet_2d", cases.inlet_2d, cases.FP64, args.steps),
+                  ("inlet_2d", cases.inlet_2d, cases.FP32_FLUX, args.steps),
+                  ("blobs_3d", cases.blobs_3d, cases.FP64, 50),
+                  ("blobs_3d", cases.blobs_3d, cases.FP32_FLUX, 50)]
+        for wl, mk, pr, steps in others:
+            name = f"{wl}_{'fp64' if pr == cases.FP64 else 'fp32flux'}"
+            if wl == args.workload and pr == prec:
+                continue
             c = mk()
-            p = cases.Params(**{**c.params.__dict__, "precision": prec})
+            p = cases.Params(**{**c.params.__dict__, "precision": pr})
             log(f"[bench] extra {name} cells={c.ncells} steps={steps}")
-            gx, ix, wx, dx, sx, stx = time_grid(fv, c, p, steps, 5)
-            rx = roofline_of(c, sx, steps)
+            gx, ix, wx, dx, sx, stx = time_grid(fv, c, p, steps, 5, tune_cache)
+            rx, ax = roofline_of(c, sx, steps, wl, pr == cases.FP32_FLUX)
             extra[name] = dict(value=round(c.ncells * steps / (dx * 1e-3), 1),
-                               ms_per_step=round(dx / steps, 5), roofline=rx,
+                               ms_per_step=round(dx / steps, 5), roofline=rx, alu=ax,
                                tile=dict(rows=stx["tile_rows"], ny=stx["tile_ny"],
                                          tiles=stx["tiles"], blocks=stx["launch_blocks"]))
             log(f"[bench]   {extra[name]['value']/1e9:.3f} G cell-updates/s, "
-                f"{rx['achieved']:.0f} GB/s ({100*rx['frac']:.1f}% HBM)")
+                f"{rx['achieved']:.0f} GB/s ({100*rx['frac']:.1f}% HBM), "
+                f"rows={stx['tile_rows']} ny={stx['tile_ny']}")
+            gx.close()
             del gx
+        extra["batched_64"] = bench_batched(fv, cases)
+        b = extra["batched_64"]
+        log(f"[bench]   batched {b['value']/1e9:.3f} G cell-updates/s vs sequential "
+            f"{b['sequential_value']/1e9:.3f} G ({b['speedup']}x)")
+        extra["serving"] = bench_serving(fv, cases)
+        s = extra["serving"]
+        log(f"[bench]   serving p50 {s['batched']['p50_s']} s p99 {s['batched']['p99_s']} s, "
+            f"{s['batched']['value']/1e9:.3f} G/s vs plain p50 {s['plain']['p50_s']} s "
+            f"p99 {s['plain']['p99_s']} s {s['plain']['value']/1e9:.3f} G/s")
 
     cpu = None
     if not args.no_cpu:
@@ -159,6 +577,14 @@ def main():
         cpu = cpu_baseline(case)
         log(f"[bench] cpu {cpu['value']/1e6:.2f} M cell-updates/s on {cpu['cores']} threads")
 
+    if args.workload == "inlet_2d":
+        desc = ("inlet_2d: 2D Euler, 4 blocks x 512x256 cells on the sheared wavy inlet-like "
+                "curvilinear mesh, Mach 4 inflow (p=12270 Pa, T=217 K), slip walls, extrapolation "
+                "outflow, MUSCL-minmod + Roe, SSP-RK3, CFL 0.5")
+    else:
+        desc = ("blobs_3d: 3D Euler, one uniform 256^3 block, Mach 2 free stream with 16 seeded "
+                "Gaussian density blobs, supersonic inflow / extrapolation outflow, periodic "
+                "transverse faces, MUSCL-minmod + Roe, SSP-RK3, CFL 0.5")
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -170,21 +596,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if prec == cases.FP64 else "f32-flux/f64-state",
         "data": "synthetic",
         "config": {
-            "workload": "inlet_2d: 2D Euler, 4 blocks x 512x256 cells on the sheared wavy "
-                        "inlet-like curvilinear mesh, Mach 4 inflow (p=12270 Pa, T=217 K), "
-                        "slip walls, extrapolation outflow, MUSCL-minmod + Roe, SSP-RK3, CFL 0.5",
+            "workload": desc,
             "cells": case.ncells,
-            "precision": "fp64",
+            "precision": args.precision,
             "tile_rows": st["tile_rows"],
+            "tile_ny": st["tile_ny"],
             "tiles": st["tiles"],
             "launch_blocks": st["launch_blocks"],
-            "parallelism": "single GPU",
+            "autotuned": tune_cache is not None,
         },
         "ssspnt": round(1e-6 * case.ncells * 3 * args.steps / (dev_ms * 1e-3), 2),
         "roofline": roof,
+        "alu": alu,
         "cpu_baseline": cpu,
         "extra": extra,
         "wall_s_timed": round(wall, 4),

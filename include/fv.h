@@ -196,7 +196,8 @@ int fv_step_timed(fv_grid* g, const fv_params* p, int nsteps, fv_step_info* info
 /* Time the candidate tile shapes of this grid's size class on the device,
  * keep the fastest for this grid and record it in the autotune table
  * (cache_path: JSON file, NULL: environment FV_AUTOTUNE_CACHE or none).
- * The state is saved and restored. */
+ * The state is saved and restored.  When the table already holds a shape for
+ * this size class and precision, that shape is applied without timing. */
 int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path);
 
 typedef struct fv_grid_stats {

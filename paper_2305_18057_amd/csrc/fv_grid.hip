@@ -387,6 +387,19 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
   int st = check_params(p);
   if (st) return st;
   if (!g->have_state) return set_error(FV_E_INVAL, "no state set");
+  {
+    // a shape already recorded for this size class and precision is applied
+    // as is; the state is untouched, only the per-tile minima are redone
+    TileShape rec;
+    if (tune_lookup(tune_path(cache_path), tune_key(g->hg, p->precision), rec)) {
+      if (rec.rows != g->shape.rows || rec.ny != g->shape.ny) {
+        g->shape = rec;
+        if ((st = upload_tiles(g))) return st;
+        if ((st = cfl_pass(g))) return st;
+      }
+      return FV_OK;
+    }
+  }
   std::vector<double> saved((size_t)g->hg.state_size);
   st = fv_get_state(g, saved.data(), 0);
   if (st) return st;
