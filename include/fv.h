@@ -68,7 +68,10 @@ enum {
  *   EXTRAP    ghost = nearest interior cell (zeroth-order extrapolation)
  *   SLIPWALL  ghost layer g = interior cell g-1 from the wall with its
  *             momentum mirrored about the unit normal of that wall face;
- *             rho and rho*e_t copied */
+ *             rho and rho*e_t copied
+ * PERIODIC, BLOCK and SLIPWALL read two distinct cells across the face, so
+ * the source block needs at least 2 cells along that direction
+ * (FV_E_INVAL otherwise). */
 enum { FV_BC_PERIODIC = 0, FV_BC_BLOCK = 1, FV_BC_INFLOW = 2, FV_BC_EXTRAP = 3, FV_BC_SLIPWALL = 4 };
 enum { FV_IMIN = 0, FV_IMAX = 1, FV_JMIN = 2, FV_JMAX = 3, FV_KMIN = 4, FV_KMAX = 5 };
 

@@ -188,8 +188,15 @@ struct Recon {
   T heps, c1, c2;
 };
 
-template <typename T>
+// LIM >= 0 fixes the limiter at compile time; LIM < 0 reads it from R.lim
+template <int LIM = -1, typename T>
 __device__ __forceinline__ void extrap(const Recon<T>& R, T dm, T dp, T& ep, T& em) {
+  if constexpr (LIM == LIM_MINMOD) {
+    const T s = R.heps * minmod(dm, dp);
+    ep = s;
+    em = s;
+    return;
+  }
   if (R.lim == LIM_MINMOD) {
     const T s = R.heps * minmod(dm, dp);
     ep = s;

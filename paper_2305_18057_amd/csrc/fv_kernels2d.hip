@@ -3,18 +3,23 @@
 //
 // A tile is 64 consecutive columns i (lane = column; ncol of them active) by
 // n rows.  The wave marches up the rows; at row j it
-//   - forms the j-face flux at j-1/2 from the extrapolation of cell j-1
-//     (carried) and of cell j (rows j-1, j, j+1 of the own column are in
-//     registers; row j+2 is already being fetched for the next step),
+//   - forms the j-face flux at j-1/2 from the extrapolations of cells j-1
+//     (carried) and j (rows j-1, j, j+1 of the own column are in registers),
 //   - completes the residual of row j-1 with it, applies the RK stage update
 //     and stores the row (coalesced along i), adding the fused reductions,
-//   - forms the i-face flux at i-1/2 of row j.  Neighbour values come from
-//     the lanes next door (DPP wave shifts), the three halo cells i0-2,
-//     i0-1, i0+ncol from lanes 0..2, and the flux through i+1/2 is the next
-//     lane's i-1/2 flux.  The right-edge fluxes of the tile are formed 64 rows
-//     at a time by a pre-pass (lane r: row r) and kept in LDS.
-// Every face flux of the tile is formed once (tile edges aside).  Ghost cells
-// are never stored: reads outside the block follow the boundary rule.
+//   - forms the i-face flux at i-1/2 of row j.  The row, with its three halo
+//     cells i0-2, i0-1 and i0+ncol, goes through a per-wave LDS row buffer,
+//     from which every lane reads its neighbours; the flux through i+1/2 is
+//     the next lane's i-1/2 flux (the tile's right-edge fluxes come from a
+//     pre-pass over the tile's rows, one row per lane).
+// Everything a row needs from memory (the row two ahead, the halo cells, the
+// node row two ahead, U^n) is requested one row ahead, with addresses that are
+// always inside the arrays, so loads overlap a whole row of arithmetic.  Ghost
+// cells are never stored: a cell outside the block is resolved to its source
+// (a cell of this or a neighbour block, the inflow state, or a mirrored cell)
+// before the load and corrected after it.
+#include <type_traits>
+
 #include "fv_device.h"
 #include "fv_launch.h"
 
@@ -23,286 +28,446 @@ namespace fvk {
 namespace {
 
 constexpr int kWavesPerWG = 4;
+constexpr int kSlots = 72;  // LDS row slots: column i0 + c at slot c + 2; slot 71 is scratch
 
 template <typename T>
-struct Ctx2D {
-  const DevBlock* blocks;
-  const DevBlock* B;
-  int buf;
-  Recon<T> rc;
-  FluxK<T> K;
+struct Lds2D {
+  T q[4][kSlots];     // stencil row of the i-faces
+  T g[4][kSlots];     // i-face fluxes of the row
+  T edge[4][kSlots];  // right-edge fluxes of the tile, row r at [v][r]
 };
 
-template <typename T>
-__device__ __forceinline__ void setup(Ctx2D<T>& C, const DevBlock* blocks, const DevBlock& B,
-                                      int buf, const DevInstance& I) {
-  C.blocks = blocks;
-  C.B = &B;
-  C.buf = buf;
-  C.rc.lim = I.limiter;
-  C.rc.heps = T(0.5 * I.eps);
-  C.rc.c1 = T(0.25 * I.eps * (1.0 - I.kappa));
-  C.rc.c2 = T(0.25 * I.eps * (1.0 + I.kappa));
-  C.K.gm1 = T(I.gamma - 1.0);
-  C.K.efix = T(I.efix);
-  C.K.iefix = T(I.efix > 0.0 ? 1.0 / I.efix : 0.0);
+// order LDS accesses of the wave (the wave executes them in program order;
+// this keeps the compiler from moving them across each other)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// flux across a face of area vector S (curvilinear) or along axis AX (uniform)
-template <typename T, int AX>
-__device__ __forceinline__ void face_flux(const Ctx2D<T>& C, const T (&qL)[4], const T (&qR)[4],
-                                          double Sx, double Sy, T (&G)[4]) {
-  if (C.B->xn) {
+// wave-uniform read-only value (scalar load)
+typedef __attribute__((address_space(4))) const double k_cdouble;
+__device__ __forceinline__ double ldk(const double* p) { return *(const k_cdouble*)p; }
+
+// global loads / stores at a wave-uniform base plus a per-lane byte offset
+__device__ __forceinline__ double ldo(const double* base, unsigned off) {
+  return *(g_cdouble*)((const char*)base + off);
+}
+__device__ __forceinline__ void sto(double* base, unsigned off, double v) {
+  *(g_double*)((char*)base + off) = v;
+}
+
+// Where the value of cell (i, j) of block B comes from, without touching
+// memory: a cell of B or of a neighbour block (kind 0), the inflow state of
+// face f (kind 1; p is then some valid cell of B) or a cell mirrored about
+// the wall face f (kind 2).  rs is the row stride of the source block.
+struct Src2 {
+  const double* p;
+  long long vs;
+  int rs, kind, f, t;  // t: index along the wall of the mirrored cell
+};
+
+__device__ __forceinline__ Src2 resolve2(const DevBlock* __restrict__ blocks, const DevBlock& B,
+                                         int buf, int i, int j) {
+  Src2 s;
+  s.kind = 0;
+  s.f = 0;
+  s.t = 0;
+  s.rs = B.ni;
+  s.vs = B.ncell;
+  if (i >= 0 && i < B.ni && j >= 0 && j < B.nj) {
+    s.p = B.u[buf] + (long long)j * B.ni + i;
+    return s;
+  }
+  int f, g;
+  if (i < 0) { f = 0; g = -i; }
+  else if (i >= B.ni) { f = 1; g = i - B.ni + 1; }
+  else if (j < 0) { f = 2; g = -j; }
+  else { f = 3; g = j - B.nj + 1; }
+  const int d = f >> 1, side = f & 1;
+  const int kind = B.bc_kind[f];
+  const DevBlock* S = kind == BC_BLOCK ? &blocks[B.bc_nbr[f]] : &B;
+  const int n = d == 0 ? S->ni : S->nj;
+  int along;
+  if (kind == BC_PERIODIC || kind == BC_BLOCK) along = side == 0 ? n - g : g - 1;
+  else if (kind == BC_EXTRAP) along = side == 0 ? 0 : n - 1;
+  else if (kind == BC_SLIPWALL) along = side == 0 ? g - 1 : n - g;
+  else along = side == 0 ? 0 : n - 1;  // INFLOW: any valid cell, the value is replaced
+  const int si = d == 0 ? along : i;
+  const int sj = d == 1 ? along : j;
+  s.p = S->u[buf] + (long long)sj * S->ni + si;
+  s.rs = S->ni;
+  s.vs = S->ncell;
+  s.kind = kind == BC_INFLOW ? 1 : (kind == BC_SLIPWALL ? 2 : 0);
+  s.f = f;
+  s.t = d == 0 ? j : i;
+  return s;
+}
+
+__device__ __forceinline__ void load2(const Src2& s, double (&q)[4]) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) q[v] = ldg(s.p + v * s.vs);
+}
+
+// inflow state or slip-wall mirror: m - 2 (m.S)/(S.S) S with S the area
+// vector of the wall face next to the ghost cell
+template <bool CURV>
+__device__ __forceinline__ void fix2(const Src2& s, const DevBlock& B, double (&q)[4]) {
+  if (s.kind == 1) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q[v] = B.bc_q[s.f][v];
+  } else if (s.kind == 2) {
+    double Sx, Sy;
+    if (CURV) {
+      const long long w1 = B.ni + 1;
+      if (s.f < 2) {
+        const int w = s.f == 0 ? 0 : B.ni;
+        Sx = ldg(B.yn + (long long)(s.t + 1) * w1 + w) - ldg(B.yn + (long long)s.t * w1 + w);
+        Sy = -(ldg(B.xn + (long long)(s.t + 1) * w1 + w) - ldg(B.xn + (long long)s.t * w1 + w));
+      } else {
+        const long long w = s.f == 2 ? 0 : B.nj;
+        Sx = -(ldg(B.yn + w * w1 + s.t + 1) - ldg(B.yn + w * w1 + s.t));
+        Sy = ldg(B.xn + w * w1 + s.t + 1) - ldg(B.xn + w * w1 + s.t);
+      }
+    } else {
+      Sx = s.f < 2 ? 1.0 : 0.0;
+      Sy = s.f < 2 ? 0.0 : 1.0;
+    }
+    const double ms = q[1] * Sx + q[2] * Sy;
+    const double ss = Sx * Sx + Sy * Sy;
+    const double fct = 2.0 * ms / ss;
+    q[1] -= fct * Sx;
+    q[2] -= fct * Sy;
+  }
+}
+
+// flux across a face of area vector (Sx, Sy) (curvilinear) or of the
+// uniform area `area` along axis AX
+template <typename T, int AX, bool CURV>
+__device__ __forceinline__ void face_flux(const FluxK<T>& K, const T (&qL)[4], const T (&qR)[4],
+                                          double Sx, double Sy, double area, T (&G)[4]) {
+  if constexpr (CURV) {
     double A, h;
     M<double>::sqrt2(Sx * Sx + Sy * Sy, A, h);
     const double iA = 2.0 * h;
     const T n[2] = {T(Sx * iA), T(Sy * iA)};
-    roe_flux<T, 2, -1>(qL, qR, n, T(A), C.K, G);
+    roe_flux<T, 2, -1>(qL, qR, n, T(A), K, G);
   } else {
-    roe_flux<T, 2, AX>(qL, qR, nullptr, T(C.B->area[AX]), C.K, G);
+    roe_flux<T, 2, AX>(qL, qR, nullptr, T(area), K, G);
   }
 }
 
-// i-face flux at column ie, row jr from the four cells ie-2 .. ie+1
-template <typename T>
-__device__ void edge_face(const Ctx2D<T>& C, int ie, int jr, T (&G)[4]) {
-  const DevBlock& B = *C.B;
-  double a[4], b[4], c[4], d[4];
-  load_cell<4>(C.blocks, B, C.buf, ie - 2, jr, 0, a);
-  load_cell<4>(C.blocks, B, C.buf, ie - 1, jr, 0, b);
-  load_cell<4>(C.blocks, B, C.buf, ie, jr, 0, c);
-  load_cell<4>(C.blocks, B, C.buf, ie + 1, jr, 0, d);
-  T qL[4], qR[4];
-#pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const T ta = T(a[v]), tb = T(b[v]), tc = T(c[v]), td = T(d[v]);
-    T ep, em, ep2, em2;
-    extrap(C.rc, tb - ta, tc - tb, ep, em);    // cell ie-1
-    extrap(C.rc, tc - tb, td - tc, ep2, em2);  // cell ie
-    qL[v] = tb + ep;
-    qR[v] = tc - em2;
-  }
-  double Sx = 0.0, Sy = 0.0;
-  if (B.xn) {
-    Sx = nodey(B, ie, jr + 1) - nodey(B, ie, jr);
-    Sy = -(nodex(B, ie, jr + 1) - nodex(B, ie, jr));
-  }
-  face_flux<T, 0>(C, qL, qR, Sx, Sy, G);
-}
-
-template <int MODE, typename T>
+template <int MODE, typename T, bool CURV, int LIM>
 __device__ void tile2d(const DevTile& tl, const DevBlock* __restrict__ blocks, DevInstance& I,
-                       double* __restrict__ rout, int lane, T* __restrict__ s_edge) {
+                       double* __restrict__ rout, int lane, Lds2D<T>& L) {
   const DevBlock& B = blocks[tl.blk];
-  const int ni = B.ni;
+  const int ni = B.ni, nj = B.nj;
   const int i0 = tl.i0, j0 = tl.j0, n = tl.n, nc = tl.ncol;
-  const int i = i0 + lane;
   const bool act = lane < nc;
-  const int ic = act ? i : ni - 1;  // safe column for idle lanes
-  const int last = nc - 1;          // lane owning the tile's right edge
-  const int bin = MODE == 0 ? 0 : MODE - 1;
-  const int bout = MODE == 1 ? 1 : (MODE == 2 ? 2 : 0);
-  const bool curv = B.xn != nullptr;
-  // halo lanes: 0 -> column i0-1, 1 -> i0-2, 2 -> i0+ncol
-  const int hcol = lane == 0 ? i0 - 1 : (lane == 1 ? i0 - 2 : i0 + nc);
-  const bool hlane = lane < 3;
+  const int ic = act ? i0 + lane : ni - 1;  // safe column for idle lanes
+  const int last = nc - 1;                  // lane owning the tile's right edge
+  constexpr int bin = MODE == 0 ? 0 : MODE - 1;
+  constexpr int bout = MODE == 1 ? 1 : (MODE == 2 ? 2 : 0);
+  const long long ncell = B.ncell;
+  const double* __restrict__ Q = B.u[bin];
+  const double* __restrict__ Un = B.u[0];
+  double* __restrict__ Uout = B.u[bout];
+  const double* __restrict__ X = B.xn;
+  const double* __restrict__ Y = B.yn;
+  const long long nrow = ni + 1;           // node row length
+  const unsigned cb = (unsigned)ic * 8u;   // own column, bytes
+  const int ir = i0 + nc;                  // node column right of the tile
 
-  Ctx2D<T> C;
-  setup(C, blocks, B, bin, I);
+  Recon<T> rc;
+  rc.lim = I.limiter;
+  rc.heps = T(0.5 * I.eps);
+  rc.c1 = T(0.25 * I.eps * (1.0 - I.kappa));
+  rc.c2 = T(0.25 * I.eps * (1.0 + I.kappa));
+  FluxK<T> K;
+  K.gm1 = T(I.gamma - 1.0);
+  K.efix = T(I.efix);
+  K.iefix = T(I.efix > 0.0 ? 1.0 / I.efix : 0.0);
   const double gamma = I.gamma;
   const double dt = I.dt;
-  double* __restrict__ Uout = B.u[bout];
-  const double* __restrict__ Un = B.u[0];
-  const long long ncell = B.ncell;
+  const double areaI = B.area[0], areaJ = B.area[1], uvol = B.vol;
 
-  // ---- prologue: rows j0-2 .. j0+1 of the own column, nodes of row j0
-  double qa[4], qm1[4], q0[4], qn[4];
-  load_cell<4>(blocks, B, bin, ic, j0 - 2, 0, qa);
-  load_cell<4>(blocks, B, bin, ic, j0 - 1, 0, qm1);
-  load_cell<4>(blocks, B, bin, ic, j0, 0, q0);
-  load_cell<4>(blocks, B, bin, ic, j0 + 1, 0, qn);
-  double xm = 0, ym = 0, x0 = 0, y0 = 0, xhm = 0, yhm = 0, xh0 = 0, yh0 = 0;
-  if (curv) {
-    x0 = nodex(B, ic, j0);
-    y0 = nodey(B, ic, j0);
-    double hx = 0, hy = 0;
-    if (lane == 2) {
-      hx = nodex(B, i0 + nc, j0);
-      hy = nodey(B, i0 + nc, j0);
+  // ---- halo lanes: 0 -> column i0-1, 1 -> i0-2, 2 -> i0+ncol (others: own column)
+  const int hcol = lane == 0 ? i0 - 1 : (lane == 1 ? i0 - 2 : (lane == 2 ? ir : ic));
+  const Src2 hs = resolve2(blocks, B, bin, hcol, 0);  // row j: hs.p + j * hs.rs
+  const bool hfix = __builtin_amdgcn_ballot_w64(hs.kind != 0) != 0;
+  const int hslot = lane == 0 ? 1 : (lane == 1 ? 0 : (lane == 2 ? nc + 2 : kSlots - 1));
+  auto halo_load = [&](int j, double (&h)[4]) {
+    const int jc = min(j, nj - 1);
+    const double* p = hs.p + (long long)jc * hs.rs;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) h[v] = ldg(p + v * hs.vs);
+  };
+  auto halo_fix = [&](int j, double (&h)[4]) {
+    if (hfix) {
+      Src2 s = hs;
+      s.t = j;
+      fix2<CURV>(s, B, h);
     }
-    xh0 = lane_value(hx, 2);
-    yh0 = lane_value(hy, 2);
+  };
+  // own column, row j (inside the block)
+  auto row_load = [&](const double* base, int j, double (&q)[4]) {
+    const double* p = base + (long long)j * ni;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q[v] = ldo(p + v * ncell, cb);
+  };
+
+  // ---- prologue: rows j0-2 .. j0+1, halo of row j0, node rows j0, j0+1,
+  //      and everything the right-edge pre-pass reads (issued together)
+  double qa[4], qm1[4], q0[4], qn[4], hv[4], un[4] = {0, 0, 0, 0};
+  const Src2 sa = resolve2(blocks, B, bin, ic, j0 - 2);
+  const Src2 sb = resolve2(blocks, B, bin, ic, j0 - 1);
+  const Src2 sd = resolve2(blocks, B, bin, ic, j0 + 1);
+  load2(sa, qa);
+  load2(sb, qm1);
+  row_load(Q, j0, q0);
+  load2(sd, qn);
+  halo_load(j0, hv);
+  double x0 = 0, y0 = 0, x1 = 0, y1 = 0, xR0 = 0, yR0 = 0, xR1 = 0, yR1 = 0;
+  if constexpr (CURV) {
+    const double* xr = X + j0 * nrow;
+    const double* yr = Y + j0 * nrow;
+    x0 = ldo(xr, cb);
+    y0 = ldo(yr, cb);
+    x1 = ldo(xr + nrow, cb);
+    y1 = ldo(yr + nrow, cb);
+    xR0 = ldk(xr + ir);
+    yR0 = ldk(yr + ir);
+    xR1 = ldk(xr + nrow + ir);
+    yR1 = ldk(yr + nrow + ir);
   }
-  T epm1[4];
+  // pre-pass: i-face flux through the tile's right edge for row j0 + lane
+  const int er = j0 + min(lane, n - 1);
+  Src2 se[4];
+  double ce[4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    se[c] = resolve2(blocks, B, bin, ir - 2 + c, er);
+    load2(se[c], ce[c]);
+  }
+  double ex0 = 0, ey0 = 0, ex1 = 0, ey1 = 0;
+  if constexpr (CURV) {
+    ex0 = ldg(X + er * nrow + ir);
+    ey0 = ldg(Y + er * nrow + ir);
+    ex1 = ldg(X + (er + 1) * nrow + ir);
+    ey1 = ldg(Y + (er + 1) * nrow + ir);
+  }
+  // ghost corrections of the prologue cells
+  fix2<CURV>(sa, B, qa);
+  fix2<CURV>(sb, B, qm1);
+  fix2<CURV>(sd, B, qn);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) fix2<CURV>(se[c], B, ce[c]);
+  {
+    T qL[4], qR[4], G[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const T a = T(ce[0][v]), b = T(ce[1][v]), c = T(ce[2][v]), d = T(ce[3][v]);
+      T ep, em, ep2, em2;
+      extrap<LIM>(rc, b - a, c - b, ep, em);    // cell ir-1
+      extrap<LIM>(rc, c - b, d - c, ep2, em2);  // cell ir
+      qL[v] = b + ep;
+      qR[v] = c - em2;
+    }
+    face_flux<T, 0, CURV>(K, qL, qR, ey1 - ey0, -(ex1 - ex0), areaI, G);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) L.edge[v][lane] = G[v];
+  }
+  T epm1[4];  // + side extrapolation of cell j-1
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     T em;
-    extrap(C.rc, T(qm1[v]) - T(qa[v]), T(q0[v]) - T(qm1[v]), epm1[v], em);
+    extrap<LIM>(rc, T(qm1[v]) - T(qa[v]), T(q0[v]) - T(qm1[v]), epm1[v], em);
   }
-
-  double rg[4] = {0, 0, 0, 0};  // (G_i+1/2 - G_i-1/2) - G_j-1/2 of the carried row
-#ifdef FV_EDGE_REGS
-  T edge_r[4] = {T(0), T(0), T(0), T(0)};
-#endif
+  // right neighbour's node of row j0 (the last lane takes the node right of the tile)
+  double x0r = 0, y0r = 0;
+  if constexpr (CURV) {
+    const double xs = shl1(x0), ys = shl1(y0);
+    x0r = lane == last ? xR0 : xs;
+    y0r = lane == last ? yR0 : ys;
+  }
+  double xm = 0, ym = 0, xmr = 0, ymr = 0;  // node row j-1 (own, right neighbour)
+  double rg[4] = {0, 0, 0, 0};  // (G_i+1/2 - G_i-1/2) - G_j-1/2 of the pending row j-1
   double nacc[4] = {0, 0, 0, 0};
   double dmin = INFINITY;
   int bad = 0;
+  // LDS addresses of this lane
+  T* const qs_own = &L.q[0][lane + 2];
+  T* const qs_halo = &L.q[0][hslot];
+  T* const gs_own = &L.g[0][lane];
 
-  for (int r = 0; r <= n; ++r) {
+  // one row of the march; FIRST: no pending row below, LASTR: the row above the tile
+  auto step = [&](auto first_t, auto last_t, int r) {
+    constexpr bool FIRST = decltype(first_t)::value;
+    constexpr bool LASTR = decltype(last_t)::value;
     const int j = j0 + r;
-    const bool more = r < n;
-    // ---- (1) loads for later in this step and for the next step
-    double qnn[4] = {0, 0, 0, 0}, hv[4] = {0, 0, 0, 0}, un[4] = {0, 0, 0, 0};
-    double x1 = 0, y1 = 0, hx1 = 0, hy1 = 0;
-    if (more) {
-      load_cell<4>(blocks, B, bin, ic, j + 2, 0, qnn);
-      if (hlane) load_cell<4>(blocks, B, bin, hcol, j, 0, hv);
-      if (curv) {
-        x1 = nodex(B, ic, j + 1);
-        y1 = nodey(B, ic, j + 1);
-        if (lane == 2) {
-          hx1 = nodex(B, i0 + nc, j + 1);
-          hy1 = nodey(B, i0 + nc, j + 1);
-        }
+    // ---- (1) requests for the next row
+    double q2[4];
+    double x2 = 0, y2 = 0, xR2 = 0, yR2 = 0;
+    Src2 s2;
+    if constexpr (!LASTR) {
+      if (j + 2 < nj) {
+        s2.p = Q + (long long)(j + 2) * ni + ic;
+        s2.vs = ncell;
+        s2.rs = ni;
+        s2.kind = 0;
+        s2.f = 0;
+        s2.t = 0;
+      } else {
+        s2 = resolve2(blocks, B, bin, ic, j + 2);
+      }
+      load2(s2, q2);
+      if constexpr (CURV) {
+        const long long jr = min(j + 2, nj);
+        x2 = ldo(X + jr * nrow, cb);
+        y2 = ldo(Y + jr * nrow, cb);
+        xR2 = ldk(X + jr * nrow + ir);
+        yR2 = ldk(Y + jr * nrow + ir);
       }
     }
-    if (MODE >= 2 && r >= 1 && act) {
-      const long long idx = (long long)(j - 1) * ni + i;
+    // ---- (2) j-face at j-1/2
+    T ep0[4], Gj[4];
+    {
+      T qL[4], qR[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) un[v] = ldg(Un + v * ncell + idx);
+      for (int v = 0; v < 4; ++v) {
+        const T a = T(qm1[v]), b = T(q0[v]), c = T(qn[v]);
+        T em;
+        extrap<LIM>(rc, b - a, c - b, ep0[v], em);
+        qL[v] = a + epm1[v];
+        qR[v] = b - em;
+      }
+      face_flux<T, 1, CURV>(K, qL, qR, -(y0r - y0), x0r - x0, areaJ, Gj);
     }
-    // ---- (2) right-edge i-face fluxes of the next 64 rows (LDS)
-    if (more && (r & 63) == 0) {
-      const int rr = min(lane, n - r - 1);
-#ifdef FV_EDGE_REGS
-      edge_face(C, i0 + nc, j + rr, edge_r);
-#else
-      T ge[4];
-      edge_face(C, i0 + nc, j + rr, ge);
+    // ---- (3) complete, update and store row j-1
+    if constexpr (!FIRST) {
+      if (act) {
+        const long long ro = (long long)(j - 1) * ni;
+        double R[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) s_edge[lane * 4 + v] = ge[v];
-      __builtin_amdgcn_wave_barrier();
-#endif
-    }
-    // ---- (3) j-face at j-1/2
-    T qLj[4], qRj[4], ep0[4], Gj[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const T a = T(qm1[v]), b = T(q0[v]), c = T(qn[v]);
-      T em;
-      extrap(C.rc, b - a, c - b, ep0[v], em);
-      qLj[v] = a + epm1[v];
-      qRj[v] = b - em;
-    }
-    // lane shifts are taken by every lane, then selected (a conditional
-    // expression would run them under a partial EXEC mask)
-    const double x0s = shl1(x0), y0s = shl1(y0);
-    const double x0r = lane == last ? xh0 : x0s;
-    const double y0r = lane == last ? yh0 : y0s;
-    face_flux<T, 1>(C, qLj, qRj, -(y0r - y0), x0r - x0, Gj);
-    // ---- (4) complete, update and store row j-1
-    const double xms = shl1(xm), yms = shl1(ym);
-    const double xmr = lane == last ? xhm : xms;
-    const double ymr = lane == last ? yhm : yms;
-    if (r >= 1 && act) {
-      const long long idx = (long long)(j - 1) * ni + i;
-      double R[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) R[v] = rg[v] + (double)Gj[v];
-      const double vol = curv ? 0.5 * ((x0r - xm) * (y0 - ymr) - (x0 - xmr) * (y0r - ym)) : B.vol;
-      if (MODE == 0) {
-        const double iv = 1.0 / vol;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          stg(rout + B.out_off + v * ncell + idx, R[v]);
-          const double rv = R[v] * iv;
-          nacc[v] += rv * rv;
-        }
-      } else {
-        const double f = dt / vol;
-        double out[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const double us = qm1[v] - f * R[v];
-          if (MODE == 1) out[v] = us;
-          else if (MODE == 2) out[v] = 0.75 * un[v] + 0.25 * us;
-          else out[v] = (1.0 / 3.0) * un[v] + (2.0 / 3.0) * us;
-          stg(Uout + v * ncell + idx, out[v]);
-        }
-        if (MODE == 1) {
-          const double iv = 1.0 / vol;
+        for (int v = 0; v < 4; ++v) R[v] = rg[v] + (double)Gj[v];
+        double vol = uvol;
+        if constexpr (CURV) vol = 0.5 * ((x0r - xm) * (y0 - ymr) - (x0 - xmr) * (y0r - ym));
+        const double iv = M<double>::rcp(vol);
+        if (MODE == 0) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
+            sto(rout + B.out_off + v * ncell + ro, cb, R[v]);
             const double rv = R[v] * iv;
             nacc[v] += rv * rv;
           }
-        }
-        if (MODE == 3) {
-          double Sb[2][3];
-          if (curv) {
-            Sb[0][0] = 0.5 * ((y0 - ym) + (y0r - ymr));
-            Sb[0][1] = -0.5 * ((x0 - xm) + (x0r - xmr));
-            Sb[1][0] = -0.5 * ((ymr - ym) + (y0r - y0));
-            Sb[1][1] = 0.5 * ((xmr - xm) + (x0r - x0));
-          } else {
-            Sb[0][0] = B.area[0];
-            Sb[0][1] = 0.0;
-            Sb[1][0] = 0.0;
-            Sb[1][1] = B.area[1];
+        } else {
+          const double f = dt * iv;
+          double out[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const double us = qm1[v] - f * R[v];
+            if (MODE == 1) out[v] = us;
+            else if (MODE == 2) out[v] = 0.75 * un[v] + 0.25 * us;
+            else out[v] = (1.0 / 3.0) * un[v] + (2.0 / 3.0) * us;
+            sto(Uout + v * ncell + ro, cb, out[v]);
           }
-          Sb[0][2] = Sb[1][2] = 0.0;
-          dmin = fmin(dmin, cell_dt_limit<2>(out, Sb, vol, gamma, bad));
+          if (MODE == 1) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const double rv = R[v] * iv;
+              nacc[v] += rv * rv;
+            }
+          }
+          if (MODE == 3) {
+            double Sb[2][3];
+            if constexpr (CURV) {
+              Sb[0][0] = 0.5 * ((y0 - ym) + (y0r - ymr));
+              Sb[0][1] = -0.5 * ((x0 - xm) + (x0r - xmr));
+              Sb[1][0] = -0.5 * ((ymr - ym) + (y0r - y0));
+              Sb[1][1] = 0.5 * ((xmr - xm) + (x0r - x0));
+            } else {
+              Sb[0][0] = areaI;
+              Sb[0][1] = 0.0;
+              Sb[1][0] = 0.0;
+              Sb[1][1] = areaJ;
+            }
+            Sb[0][2] = Sb[1][2] = 0.0;
+            dmin = fmin(dmin, cell_dt_limit<2>(out, Sb, vol, gamma, bad));
+          }
         }
       }
     }
-    // ---- (5) i-face at i-1/2 of row j
-    if (more) {
-      const double xh1 = lane_value(hx1, 2), yh1 = lane_value(hy1, 2);
-      T qLi[4], qRi[4], Gi[4];
+    // U^n of row j, for the update at the next row
+    if constexpr (!LASTR) {
+      if (MODE >= 2) row_load(Un, j, un);
+    }
+    // ---- (4) i-face at i-1/2 of row j, through the LDS row buffer
+    if constexpr (!LASTR) {
+      halo_fix(j, hv);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qs_own[v * kSlots] = T(q0[v]);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qs_halo[v * kSlots] = T(hv[v]);
+      wave_lds_sync();
+      halo_load(j + 1, hv);  // halo of the next row
+      T qL[4], qR[4], Gi[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const T c = T(q0[v]);
-        const T h = T(hv[v]);
-        const T left = shr1(c);
-        const T right = shl1(c);
-        const T hright = lane_value(h, 2);  // Q(i0+ncol)
-        const T hfar = shl1(h);             // lane 0: Q(i0-2) from lane 1
-        const T qim1 = lane == 0 ? h : left;
-        const T qip1 = lane == last ? hright : right;
-        T epc, emc;
-        extrap(C.rc, c - qim1, qip1 - c, epc, emc);
-        T ep0l, em0l;
-        extrap(C.rc, h - hfar, c - h, ep0l, em0l);  // cell i0-1 (used by lane 0)
-        const T epl = shr1(epc);
-        qLi[v] = qim1 + (lane == 0 ? ep0l : epl);
-        qRi[v] = c - emc;
+        const T qim2 = qs_own[v * kSlots - 2];
+        const T qim1 = qs_own[v * kSlots - 1];
+        const T qip1 = qs_own[v * kSlots + 1];
+        T epl, eml, epc, emc;
+        extrap<LIM>(rc, qim1 - qim2, c - qim1, epl, eml);  // cell i-1
+        extrap<LIM>(rc, c - qim1, qip1 - c, epc, emc);     // cell i
+        qL[v] = qim1 + epl;
+        qR[v] = c - emc;
       }
-      face_flux<T, 0>(C, qLi, qRi, y1 - y0, -(x1 - x0), Gi);
+      face_flux<T, 0, CURV>(K, qL, qR, y1 - y0, -(x1 - x0), areaI, Gi);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) gs_own[v * kSlots] = Gi[v];
+      wave_lds_sync();
+      const T* gsrc = lane == last ? &L.edge[0][r] : &L.g[0][lane + 1];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-#ifdef FV_EDGE_REGS
-        const T ge = lane_value(edge_r[v], r & 63);
-#else
-        const T ge = s_edge[(r & 63) * 4 + v];
-#endif
-        const T gs = shl1(Gi[v]);
-        const T gr = lane == last ? ge : gs;
+        const T gr = gsrc[v * kSlots];
         rg[v] = ((double)gr - (double)Gi[v]) - (double)Gj[v];
       }
-      xhm = xh0; yhm = yh0;
-      xh0 = xh1; yh0 = yh1;
+      wave_lds_sync();
     }
-    // ---- (6) rotate the carried rows
+    // ---- (5) rotate the carried rows
+    if constexpr (!LASTR) {
+      if (j + 2 >= nj) fix2<CURV>(s2, B, q2);
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      qm1[v] = q0[v];
-      q0[v] = qn[v];
-      qn[v] = qnn[v];
-      epm1[v] = ep0[v];
+      for (int v = 0; v < 4; ++v) {
+        qm1[v] = q0[v];
+        q0[v] = qn[v];
+        qn[v] = q2[v];
+        epm1[v] = ep0[v];
+      }
+      if constexpr (CURV) {
+        xm = x0;
+        ym = y0;
+        xmr = x0r;
+        ymr = y0r;
+        const double xs = shl1(x1), ys = shl1(y1);
+        x0r = lane == last ? xR1 : xs;
+        y0r = lane == last ? yR1 : ys;
+        x0 = x1;
+        y0 = y1;
+        x1 = x2;
+        y1 = y2;
+        xR1 = xR2;
+        yR1 = yR2;
+      }
     }
-    xm = x0; ym = y0;
-    x0 = x1; y0 = y1;
-  }
+  };
+
+  using F = std::integral_constant<bool, false>;
+  using Tr = std::integral_constant<bool, true>;
+  step(Tr(), F(), 0);
+  for (int r = 1; r < n; ++r) step(F(), F(), r);
+  step(F(), Tr(), n);
 
   // ---- per-tile partials (fixed-order wave reductions)
   double* part = I.part + (long long)tl.local * kPartStride;
@@ -326,13 +491,14 @@ __device__ void tile2d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
   }
 }
 
+// at most 256 VGPRs: two waves per SIMD
 template <int MODE, typename T>
-__global__ __launch_bounds__(256) void k_stage2d(const DevTile* __restrict__ tiles,
+__global__ __launch_bounds__(256, 2) void k_stage2d(const DevTile* __restrict__ tiles,
                                                  const int* __restrict__ ntiles_p,
                                                  const DevBlock* __restrict__ blocks,
                                                  DevInstance* __restrict__ insts,
                                                  double* __restrict__ rout) {
-  __shared__ T s_edge[kWavesPerWG][64 * 4];
+  __shared__ Lds2D<T> s_lds[kWavesPerWG];
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ntiles = *ntiles_p;
@@ -340,7 +506,15 @@ __global__ __launch_bounds__(256) void k_stage2d(const DevTile* __restrict__ til
     const DevTile tl = tiles[t];
     DevInstance& I = insts[tl.inst];
     if (MODE != 0 && I.stopped) continue;
-    tile2d<MODE, T>(tl, blocks, I, rout, lane, s_edge[wid]);
+    // the common configuration (minmod) is compiled with the limiter fixed
+    const bool curv = blocks[tl.blk].xn != nullptr;
+    if (I.limiter == LIM_MINMOD) {
+      if (curv) tile2d<MODE, T, true, LIM_MINMOD>(tl, blocks, I, rout, lane, s_lds[wid]);
+      else tile2d<MODE, T, false, LIM_MINMOD>(tl, blocks, I, rout, lane, s_lds[wid]);
+    } else {
+      if (curv) tile2d<MODE, T, true, -1>(tl, blocks, I, rout, lane, s_lds[wid]);
+      else tile2d<MODE, T, false, -1>(tl, blocks, I, rout, lane, s_lds[wid]);
+    }
   }
 }
 

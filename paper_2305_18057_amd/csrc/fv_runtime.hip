@@ -92,6 +92,12 @@ int validate_and_copy(const fv_grid_desc* d, HostGrid& g) {
         if (n1 != m1 || n2 != m2)
           return set_error(FV_E_INVAL, "block %d face %d: transverse size %dx%d != neighbour's %dx%d", b, f, n1, n2, m1, m2);
       }
+      // the two ghost layers of these rules are two distinct cells of the source block
+      if (bc.kind == FV_BC_PERIODIC || bc.kind == FV_BC_SLIPWALL || bc.kind == FV_BC_BLOCK) {
+        const fv_block_desc& S = bc.kind == FV_BC_BLOCK ? g.blocks[bc.nbr_block] : B;
+        if (face_ext(S, f / 2) < 2)
+          return set_error(FV_E_INVAL, "block %d face %d: this rule needs at least 2 cells across the face", b, f);
+      }
       if (bc.kind == FV_BC_INFLOW) {
         if (!(bc.prim_in[0] > 0.0) || !(bc.prim_in[4] > 0.0))
           return set_error(FV_E_INVAL, "block %d face %d: inflow needs rho > 0 and p > 0", b, f);
@@ -234,7 +240,8 @@ void build_tiles(const HostGrid& g, const TileShape& sh, int inst_index, int bof
   for (int b = 0; b < g.nblocks; ++b) {
     const fv_block_desc& B = g.blocks[b];
     if (g.ndim == 2) {
-      const int R = std::max(kMinRows2D, sh.rows);
+      // at most 64 rows: the right-edge fluxes of a tile are formed one row per lane
+      const int R = std::min(64, std::max(kMinRows2D, sh.rows));
       for (int j0 = 0; j0 < B.nj; j0 += R)
         for (int i0 = 0; i0 < B.ni; i0 += 64) {
           fvk::DevTile t;

@@ -65,6 +65,11 @@ def test_workspace_bytes_and_validation(fvb):
     c2.blocks[1] = CS.Block(64, 16, 1, None, None, (0, 0, 0), (1, 1, 1), c2.blocks[1].bc)
     gd = fvb.GridDesc(c2)
     assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) == 0
+    # a periodic direction one cell deep has no second ghost source
+    c1 = CS.vortex_2d(1, 4, noise=0.0)
+    gd = fvb.GridDesc(c1)
+    assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) == 0
+    assert b"at least 2 cells" in L.fv_last_error()
     # 3D curvilinear is not provided
     c3 = CS.blobs_case(8, nblobs=1)
     c3.blocks[0].x = np.zeros((9, 9))
