@@ -246,7 +246,7 @@ def bench_batched(fv, cases, steps=100, count=64, spl=10):
     _drain(srv, [srv.submit(cs[0], drop_tol=0.0, max_steps=spl)])
     ts = [srv.submit(c, drop_tol=0.0, max_steps=steps) for c in cs]
     res = _drain(srv, ts)
-    tm = [srv.times(t) for t in ts]
+    tm = [res[t][2]["times"] for t in ts]
     srv.close()
     assert all(res[t][0] == fv.FV_OK and res[t][2]["steps"] == steps for t in ts)
     span = max(x[2] for x in tm) - min(x[0] for x in tm)
@@ -281,7 +281,7 @@ def _serve(fv, cases, reqs, built, arena, max_inst, spl, rate_scale=1.0):
         if now > 900:
             raise RuntimeError("serving trace did not finish")
         time.sleep(0.0002)
-    tm = [srv.times(t) for t in tickets]
+    tm = [done[q][2]["times"] for q in range(len(reqs))]
     srv.close()
     lat = [x[2] - x[0] for x in tm]
     span = max(x[2] for x in tm) - min(x[0] for x in tm)

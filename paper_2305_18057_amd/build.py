@@ -23,7 +23,9 @@ ARCH = os.environ.get("FV_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["fv_runtime.hip", "fv_exec.hip", "fv_grid.hip", "fv_server.hip",
            "fv_kernels2d.hip", "fv_kernels3d.hip", "fv_reduce.hip"]
 
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+# -ffp-contract=off: no automatic fused multiply-adds; the kernels write the
+# fused forms explicitly, so every inlined copy of a formula rounds alike
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          "-I", INC, "-I", CSRC]

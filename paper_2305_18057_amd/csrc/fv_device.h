@@ -168,6 +168,13 @@ __device__ __forceinline__ float lane_value(float x, int l) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
 }
 
+// a * b + c rounded once.  The library is compiled without automatic
+// contraction, so every inlined copy of a formula rounds the same way (a face
+// flux formed by two different tiles is bitwise the same); the fused forms
+// are written out where they belong.
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 template <typename T>
 __device__ __forceinline__ T minmod(T a, T b) {
   const bool same = (a > T(0) && b > T(0)) || (a < T(0) && b < T(0));
@@ -202,8 +209,8 @@ __device__ __forceinline__ void extrap(const Recon<T>& R, T dm, T dp, T& ep, T& 
     ep = s;
     em = s;
   } else if (R.lim == LIM_NONE) {
-    ep = R.c1 * dm + R.c2 * dp;
-    em = R.c2 * dm + R.c1 * dp;
+    ep = fmad(R.c1, dm, R.c2 * dp);
+    em = fmad(R.c2, dm, R.c1 * dp);
   } else {
     ep = T(0);
     em = T(0);
@@ -239,51 +246,53 @@ __device__ __forceinline__ void roe_flux(const T* __restrict__ qL, const T* __re
   const T irL = T(4) * hL * hL;  // 1 / rho
   const T irR = T(4) * hR * hR;
   T uL[ND], uR[ND];
-  T keL = T(0), keR = T(0);
 #pragma unroll
   for (int a = 0; a < ND; ++a) {
     uL[a] = qL[1 + a] * irL;
     uR[a] = qR[1 + a] * irR;
-    keL += uL[a] * qL[1 + a];
-    keR += uR[a] * qR[1 + a];
+  }
+  T keL = uL[0] * qL[1], keR = uR[0] * qR[1];
+#pragma unroll
+  for (int a = 1; a < ND; ++a) {
+    keL = fmad(uL[a], qL[1 + a], keL);
+    keR = fmad(uR[a], qR[1 + a], keR);
   }
   T VnL, VnR;
   if constexpr (AX >= 0) {
     VnL = uL[AX];
     VnR = uR[AX];
   } else {
-    VnL = T(0);
-    VnR = T(0);
+    VnL = uL[0] * n[0];
+    VnR = uR[0] * n[0];
 #pragma unroll
-    for (int a = 0; a < ND; ++a) {
-      VnL += uL[a] * n[a];
-      VnR += uR[a] * n[a];
+    for (int a = 1; a < ND; ++a) {
+      VnL = fmad(uL[a], n[a], VnL);
+      VnR = fmad(uR[a], n[a], VnR);
     }
   }
-  const T pL = K.gm1 * (qL[E] - half * keL);
-  const T pR = K.gm1 * (qR[E] - half * keR);
+  const T pL = K.gm1 * fmad(-half, keL, qL[E]);
+  const T pR = K.gm1 * fmad(-half, keR, qR[E]);
   const T HL = (qL[E] + pL) * irL;
   const T HR = (qR[E] + pR) * irR;
   const T is = M<T>::rcp(sL + sR);
   const T wL = sL * is, wR = sR * is;
   T ut[ND];
-  T q2 = T(0);
 #pragma unroll
-  for (int a = 0; a < ND; ++a) {
-    ut[a] = wL * uL[a] + wR * uR[a];
-    q2 += ut[a] * ut[a];
-  }
+  for (int a = 0; a < ND; ++a) ut[a] = fmad(wL, uL[a], wR * uR[a]);
+  T q2 = ut[0] * ut[0];
+#pragma unroll
+  for (int a = 1; a < ND; ++a) q2 = fmad(ut[a], ut[a], q2);
   T Vn;
   if constexpr (AX >= 0) {
     Vn = ut[AX];
   } else {
-    Vn = T(0);
+    Vn = ut[0] * n[0];
 #pragma unroll
-    for (int a = 0; a < ND; ++a) Vn += ut[a] * n[a];
+    for (int a = 1; a < ND; ++a) Vn = fmad(ut[a], n[a], Vn);
   }
-  const T Ht = wL * HL + wR * HR;
+  const T Ht = fmad(wL, HL, wR * HR);
   const T rt = sL * sR;
-  const T c2 = K.gm1 * (Ht - half * q2);
+  const T c2 = K.gm1 * fmad(-half, q2, Ht);
   T c, hc;
   M<T>::sqrt2(c2, c, hc);
   const T ic = T(2) * hc;
@@ -294,33 +303,34 @@ __device__ __forceinline__ void roe_flux(const T* __restrict__ qL, const T* __re
   T lp = fabs(Vn + c);
   const T del = K.efix * c;
   const T idel = K.iefix * ic;
-  lm = lm < del ? half * (lm * lm * idel + del) : lm;
-  lp = lp < del ? half * (lp * lp * idel + del) : lp;
-  const T lbar = half * (lp + lm) - lc;
+  lm = lm < del ? half * fmad(lm * lm, idel, del) : lm;
+  lp = lp < del ? half * fmad(lp * lp, idel, del) : lp;
+  const T lbar = fmad(half, lp + lm, -lc);
   const T ld = half * (lp - lm);
   const T rdv = rt * dVn;
-  const T d1 = (lbar * dp * ic + ld * rdv) * ic;
-  const T d2 = lbar * rdv + ld * dp * ic;
+  const T dpc = dp * ic;
+  const T d1 = fmad(lbar, dpc, ld * rdv) * ic;
+  const T d2 = fmad(lbar, rdv, ld * dpc);
   const T ha = half * area;
   const T pLR = pL + pR;
-  F[0] = ha * ((qL[0] * VnL + qR[0] * VnR) - (lc * (qR[0] - qL[0]) + d1));
+  F[0] = ha * (fmad(qL[0], VnL, qR[0] * VnR) - fmad(lc, qR[0] - qL[0], d1));
 #pragma unroll
   for (int a = 0; a < ND; ++a) {
-    T m = qL[1 + a] * VnL + qR[1 + a] * VnR;
-    T dd = lc * (qR[1 + a] - qL[1 + a]) + d1 * ut[a];
+    T m = fmad(qL[1 + a], VnL, qR[1 + a] * VnR);
+    T dd = fmad(lc, qR[1 + a] - qL[1 + a], d1 * ut[a]);
     if constexpr (AX >= 0) {
       if (a == AX) {
         m += pLR;
         dd += d2;
       }
     } else {
-      m += pLR * n[a];
-      dd += d2 * n[a];
+      m = fmad(pLR, n[a], m);
+      dd = fmad(d2, n[a], dd);
     }
     F[1 + a] = ha * (m - dd);
   }
-  F[E] = ha * (((qL[E] + pL) * VnL + (qR[E] + pR) * VnR) -
-               (lc * (qR[E] - qL[E]) + d1 * Ht + d2 * Vn));
+  F[E] = ha * (fmad(qL[E] + pL, VnL, (qR[E] + pR) * VnR) -
+               fmad(lc, qR[E] - qL[E], fmad(d1, Ht, d2 * Vn)));
 }
 
 // --------------------------------------------------------------------------
@@ -445,13 +455,12 @@ __device__ __forceinline__ double cell_dt_limit(const double* q, const double (*
   const double rho = q[0];
   const double ir = 1.0 / rho;
   double u[3] = {0.0, 0.0, 0.0};
-  double ke = 0.0;
 #pragma unroll
-  for (int a = 0; a < ND; ++a) {
-    u[a] = q[1 + a] * ir;
-    ke += u[a] * q[1 + a];
-  }
-  const double p = (gamma - 1.0) * (q[E] - 0.5 * ke);
+  for (int a = 0; a < ND; ++a) u[a] = q[1 + a] * ir;
+  double ke = u[0] * q[1];
+#pragma unroll
+  for (int a = 1; a < ND; ++a) ke = fmad(u[a], q[1 + a], ke);
+  const double p = (gamma - 1.0) * fmad(-0.5, ke, q[E]);
   ok = ok && rho > 0.0 && p > 0.0;
   if (!ok) {
     bad = 1;
@@ -461,13 +470,13 @@ __device__ __forceinline__ double cell_dt_limit(const double* q, const double (*
   double lam = 0.0;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    double us = 0.0, ss = 0.0;
+    double us = u[0] * Sb[d][0], ss = Sb[d][0] * Sb[d][0];
 #pragma unroll
-    for (int a = 0; a < ND; ++a) {
-      us += u[a] * Sb[d][a];
-      ss += Sb[d][a] * Sb[d][a];
+    for (int a = 1; a < ND; ++a) {
+      us = fmad(u[a], Sb[d][a], us);
+      ss = fmad(Sb[d][a], Sb[d][a], ss);
     }
-    lam += fabs(us) + c * sqrt(ss);
+    lam += fmad(c, sqrt(ss), fabs(us));
   }
   return vol / lam;
 }

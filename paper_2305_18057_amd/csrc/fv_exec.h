@@ -12,7 +12,8 @@
 
 namespace fvexec {
 
-enum { kSet2D = 0, kSet3D4 = 1, kSet3D8 = 2 };
+// tile sets: 2D, 3D with 3 j-rows per tile (4-wave workgroups), 3D with 7 (8 waves)
+enum { kSet2D = 0, kSet3D3 = 1, kSet3D7 = 2 };
 
 struct LaunchSet {
   fvk::DevTile* tiles = nullptr;

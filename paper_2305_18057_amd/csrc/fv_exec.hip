@@ -41,7 +41,7 @@ int launch_grid(const LaunchSet& s, int fp32) {
     const int need = (s.ntiles + 3) / 4;
     cap = std::min(cap, need);
   } else {
-    const int ny = s.kind == kSet3D8 ? 8 : 4;
+    const int ny = s.kind == kSet3D7 ? 7 : 3;
     cap = fvrt::occupancy_blocks(fvk::stage3d_kernel_ptr(1, fp32, ny), 64 * (ny + 1));
     cap = std::min(cap, s.ntiles);
   }
@@ -57,7 +57,7 @@ int enqueue_stage(const StepPlan& P, int mode, int fp32, double* rout, hipStream
     if (s.kind == kSet2D)
       e = fvk::launch_stage2d(mode, fp32, grid, 256, st, s.tiles, s.ntiles_dev, P.blocks, P.insts, rout);
     else
-      e = fvk::launch_stage3d(mode, fp32, s.kind == kSet3D8 ? 8 : 4, grid, st, s.tiles, s.ntiles_dev,
+      e = fvk::launch_stage3d(mode, fp32, s.kind == kSet3D7 ? 7 : 3, grid, st, s.tiles, s.ntiles_dev,
                               P.blocks, P.insts, rout);
     if (e != hipSuccess)
       return fvrt::set_error(FV_E_DEVICE, "stage launch failed: %s", hipGetErrorString(e));

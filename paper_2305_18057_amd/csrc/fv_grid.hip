@@ -51,7 +51,7 @@ int upload_tiles(fv_grid* g) {
   ls.tiles = g->d_tiles;
   ls.ntiles_dev = g->d_ntiles;
   ls.ntiles = nt;
-  ls.kind = g->hg.ndim == 2 ? fvexec::kSet2D : (g->shape.ny == 8 ? fvexec::kSet3D8 : fvexec::kSet3D4);
+  ls.kind = g->hg.ndim == 2 ? fvexec::kSet2D : (g->shape.ny >= 7 ? fvexec::kSet3D7 : fvexec::kSet3D3);
   g->plan.sets.push_back(ls);
   g->graphs.clear();
   // the tile list and the instance's tile count must be on the device before
@@ -413,7 +413,7 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
       cands.push_back(s);
     }
   } else {
-    for (int y : {4, 8})
+    for (int y : {3, 7})
       for (int r : {8, 16, 32, 64}) {
         TileShape s;
         s.rows = r;

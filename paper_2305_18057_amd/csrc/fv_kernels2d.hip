@@ -148,7 +148,7 @@ __device__ __forceinline__ void face_flux(const FluxK<T>& K, const T (&qL)[4], c
                                           double Sx, double Sy, double area, T (&G)[4]) {
   if constexpr (CURV) {
     double A, h;
-    M<double>::sqrt2(Sx * Sx + Sy * Sy, A, h);
+    M<double>::sqrt2(fmad(Sx, Sx, Sy * Sy), A, h);
     const double iA = 2.0 * h;
     const T n[2] = {T(Sx * iA), T(Sy * iA)};
     roe_flux<T, 2, -1>(qL, qR, n, T(A), K, G);
@@ -158,7 +158,7 @@ __device__ __forceinline__ void face_flux(const FluxK<T>& K, const T (&qL)[4], c
 }
 
 template <int MODE, typename T, bool CURV, int LIM>
-__device__ void tile2d(const DevTile& tl, const DevBlock* __restrict__ blocks, DevInstance& I,
+__device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __restrict__ blocks, DevInstance& I,
                        double* __restrict__ rout, int lane, Lds2D<T>& L) {
   const DevBlock& B = blocks[tl.blk];
   const int ni = B.ni, nj = B.nj;
@@ -351,31 +351,31 @@ __device__ void tile2d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
 #pragma unroll
         for (int v = 0; v < 4; ++v) R[v] = rg[v] + (double)Gj[v];
         double vol = uvol;
-        if constexpr (CURV) vol = 0.5 * ((x0r - xm) * (y0 - ymr) - (x0 - xmr) * (y0r - ym));
+        if constexpr (CURV) vol = 0.5 * fmad(x0r - xm, y0 - ymr, -((x0 - xmr) * (y0r - ym)));
         const double iv = M<double>::rcp(vol);
         if (MODE == 0) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             sto(rout + B.out_off + v * ncell + ro, cb, R[v]);
             const double rv = R[v] * iv;
-            nacc[v] += rv * rv;
+            nacc[v] = fmad(rv, rv, nacc[v]);
           }
         } else {
           const double f = dt * iv;
           double out[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const double us = qm1[v] - f * R[v];
+            const double us = fmad(-f, R[v], qm1[v]);
             if (MODE == 1) out[v] = us;
-            else if (MODE == 2) out[v] = 0.75 * un[v] + 0.25 * us;
-            else out[v] = (1.0 / 3.0) * un[v] + (2.0 / 3.0) * us;
+            else if (MODE == 2) out[v] = fmad(0.75, un[v], 0.25 * us);
+            else out[v] = fmad(1.0 / 3.0, un[v], (2.0 / 3.0) * us);
             sto(Uout + v * ncell + ro, cb, out[v]);
           }
           if (MODE == 1) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const double rv = R[v] * iv;
-              nacc[v] += rv * rv;
+              nacc[v] = fmad(rv, rv, nacc[v]);
             }
           }
           if (MODE == 3) {
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(256) void k_cfl2d(const DevTile* __restrict__ tiles
           const double xb = nodex(B, i + 1, j), yb = nodey(B, i + 1, j);
           const double xc = nodex(B, i, j + 1), yc = nodey(B, i, j + 1);
           const double xd = nodex(B, i + 1, j + 1), yd = nodey(B, i + 1, j + 1);
-          vol = 0.5 * ((xd - xa) * (yc - yb) - (xc - xb) * (yd - ya));
+          vol = 0.5 * fmad(xd - xa, yc - yb, -((xc - xb) * (yd - ya)));
           Sb[0][0] = 0.5 * ((yc - ya) + (yd - yb));
           Sb[0][1] = -0.5 * ((xc - xa) + (xd - xb));
           Sb[1][0] = -0.5 * ((yb - ya) + (yd - yc));

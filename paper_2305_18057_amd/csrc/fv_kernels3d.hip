@@ -1,20 +1,26 @@
 // 3D stage kernels (uniform grids): MUSCL + Roe residual, SSP-RK3 stage
 // update and fused reductions.  One workgroup per tile.
 //
-// A tile is 64 columns i (lane) by ny rows j (one wavefront per row) and
-// marches over n planes k.  The workgroup has NY + 1 waves: waves 0..NY-1 own
-// the rows; wave NY owns no cells: it fetches the four j-halo rows of each
-// plane (one plane ahead) and forms the j-face flux at the tile's top edge.
-// Per plane k:
+// A tile is 64 columns i (lane) by ny <= NY rows j (one wavefront per row)
+// and marches over n <= 64 planes k.  The workgroup has NY + 1 waves: waves
+// 0..NY-1 own the rows; wave NY (the helper) owns no cells: one plane ahead it
+// fetches the four j-halo rows and the i-halo cells of the tile, stages them
+// in LDS, and forms the j-face flux through the tile's top edge.  Per plane k:
 //   - each row wave forms the k-face flux at k-1/2 (planes k-1, k, k+1 of its
 //     column in registers, k+2 in flight), completes the residual of plane
 //     k-1, applies the stage update and stores it;
-//   - the plane k is staged in LDS (rows j0-2 .. j0+ny+1); every row wave forms
-//     its j-face flux at j-1/2 from LDS and its i-face flux at i-1/2 (DPP lane
-//     shifts, halo lanes, right-edge pre-pass in LDS as in 2D); the j-face
-//     fluxes are exchanged through LDS and each row keeps the in-plane part
-//     of its residual for the next plane.
-// Every face flux of the tile is formed once (tile edges aside).
+//   - the plane is staged in LDS (rows j0-2 .. j0+ny+1, each row with the
+//     i-halo slots i0-2, i0-1, i0+ncol); every row wave forms its j-face flux
+//     at j-1/2 and its i-face flux at i-1/2 from LDS; the fluxes are exchanged
+//     through LDS and each row keeps the in-plane part of its residual for
+//     the next plane.  The right-edge i-face fluxes of a row come from a
+//     pre-pass over the tile's planes (one plane per lane).
+// Two workgroup barriers per plane; every face flux of the tile is formed
+// once (tile edges aside).  Loads for the next plane are issued one plane
+// ahead at addresses inside the arrays; ghost cells are resolved to their
+// source before the load and corrected after it.
+#include <type_traits>
+
 #include "fv_device.h"
 #include "fv_launch.h"
 
@@ -22,233 +28,323 @@ namespace fvk {
 
 namespace {
 
-template <typename T>
-struct Ctx3D {
-  const DevBlock* blocks;
-  const DevBlock* B;
-  int buf;
-  Recon<T> rc;
-  FluxK<T> K;
-  T ax, ay, az;
-};
-
-// i-face at column ie of row j, plane kr, from the four cells ie-2 .. ie+1
-template <typename T>
-__device__ void edge_face3(const Ctx3D<T>& C, int ie, int j, int kr, T (&G)[5]) {
-  const DevBlock& B = *C.B;
-  double a[5], b[5], c[5], d[5];
-  load_cell<5>(C.blocks, B, C.buf, ie - 2, j, kr, a);
-  load_cell<5>(C.blocks, B, C.buf, ie - 1, j, kr, b);
-  load_cell<5>(C.blocks, B, C.buf, ie, j, kr, c);
-  load_cell<5>(C.blocks, B, C.buf, ie + 1, j, kr, d);
-  T qL[5], qR[5];
-#pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    const T ta = T(a[v]), tb = T(b[v]), tc = T(c[v]), td = T(d[v]);
-    T ep, em, ep2, em2;
-    extrap(C.rc, tb - ta, tc - tb, ep, em);
-    extrap(C.rc, tc - tb, td - tc, ep2, em2);
-    qL[v] = tb + ep;
-    qR[v] = tc - em2;
-  }
-  roe_flux<T, 3, 0>(qL, qR, nullptr, C.ax, C.K, G);
-}
+constexpr int kS3 = 72;  // LDS row slots: column i0 + c at slot c + 2; slot 71 is scratch
 
 template <typename T, int NY>
 struct Smem3 {
-  T q[(NY + 4) * 5 * kWave];    // plane k, rows j0-2 .. j0+NY+1
-  T f[(NY + 1) * 5 * kWave];    // j-face fluxes at j-1/2, rows j0 .. j0+NY
-  T edge[NY][kWave * 5];        // right-edge i-face fluxes, per row wave
-  T halo[NY][3][5];             // i-halo cells of plane k: i0-1, i0-2, i0+ncol
+  T q[NY + 4][5][kS3];   // plane k: rows j0-2 .. j0+NY+1
+  T f[NY + 1][5][64];    // j-face fluxes at j-1/2, rows j0 .. j0+NY
+  T g[NY][5][kS3];       // i-face fluxes of each row
+  T edge[NY][5][64];     // right-edge i-face fluxes, per row, plane r at [r]
   double red[(NY + 1) * 8];
 };
 
-template <typename T>
-__device__ __forceinline__ void setup3(Ctx3D<T>& C, const DevBlock* blocks, const DevBlock& B, int buf,
-                                       const DevInstance& I) {
-  C.blocks = blocks;
-  C.B = &B;
-  C.buf = buf;
-  C.rc.lim = I.limiter;
-  C.rc.heps = T(0.5 * I.eps);
-  C.rc.c1 = T(0.25 * I.eps * (1.0 - I.kappa));
-  C.rc.c2 = T(0.25 * I.eps * (1.0 + I.kappa));
-  C.K.gm1 = T(I.gamma - 1.0);
-  C.K.efix = T(I.efix);
-  C.K.iefix = T(I.efix > 0.0 ? 1.0 / I.efix : 0.0);
-  C.ax = T(B.area[0]);
-  C.ay = T(B.area[1]);
-  C.az = T(B.area[2]);
+// where cell (i, j, k) of block B comes from, without touching memory (as in
+// 2D): kind 0 a cell of B or a neighbour block, 1 the inflow state of face f,
+// 2 the cell mirrored about the wall face f.  ps: plane stride of the source.
+struct Src3 {
+  const double* p;
+  long long vs, ps;
+  int kind, f;
+};
+
+__device__ __forceinline__ Src3 resolve3(const DevBlock* __restrict__ blocks, const DevBlock& B,
+                                         int buf, int i, int j, int k) {
+  Src3 s;
+  s.kind = 0;
+  s.f = 0;
+  s.vs = B.ncell;
+  s.ps = (long long)B.ni * B.nj;
+  if (i >= 0 && i < B.ni && j >= 0 && j < B.nj && k >= 0 && k < B.nk) {
+    s.p = B.u[buf] + ((long long)k * B.nj + j) * B.ni + i;
+    return s;
+  }
+  int f, g;
+  if (i < 0) { f = 0; g = -i; }
+  else if (i >= B.ni) { f = 1; g = i - B.ni + 1; }
+  else if (j < 0) { f = 2; g = -j; }
+  else if (j >= B.nj) { f = 3; g = j - B.nj + 1; }
+  else if (k < 0) { f = 4; g = -k; }
+  else { f = 5; g = k - B.nk + 1; }
+  const int d = f >> 1, side = f & 1;
+  const int kind = B.bc_kind[f];
+  const DevBlock* S = kind == BC_BLOCK ? &blocks[B.bc_nbr[f]] : &B;
+  const int n = d == 0 ? S->ni : (d == 1 ? S->nj : S->nk);
+  int along;
+  if (kind == BC_PERIODIC || kind == BC_BLOCK) along = side == 0 ? n - g : g - 1;
+  else if (kind == BC_EXTRAP) along = side == 0 ? 0 : n - 1;
+  else if (kind == BC_SLIPWALL) along = side == 0 ? g - 1 : n - g;
+  else along = side == 0 ? 0 : n - 1;  // INFLOW: any valid cell, the value is replaced
+  const int si = d == 0 ? along : i;
+  const int sj = d == 1 ? along : j;
+  const int sk = d == 2 ? along : k;
+  s.p = S->u[buf] + ((long long)sk * S->nj + sj) * S->ni + si;
+  s.vs = S->ncell;
+  s.ps = (long long)S->ni * S->nj;
+  s.kind = kind == BC_INFLOW ? 1 : (kind == BC_SLIPWALL ? 2 : 0);
+  s.f = f;
+  return s;
 }
 
-// j-face flux at j-1/2 from the LDS rows j-2 .. j+1 (slots s .. s+3), to SF(s)
-template <typename T, int NY>
-__device__ __forceinline__ void jface3(const Ctx3D<T>& C, Smem3<T, NY>& sm, int s, int lane) {
-  T qL[5], qR[5], Gj[5];
+__device__ __forceinline__ void load3(const double* p, long long vs, double (&q)[5]) {
 #pragma unroll
-  for (int v = 0; v < 5; ++v) {
-    const T a = sm.q[(s * 5 + v) * kWave + lane], b = sm.q[((s + 1) * 5 + v) * kWave + lane];
-    const T c = sm.q[((s + 2) * 5 + v) * kWave + lane], d = sm.q[((s + 3) * 5 + v) * kWave + lane];
-    T ep, em, ep2, em2;
-    extrap(C.rc, b - a, c - b, ep, em);
-    extrap(C.rc, c - b, d - c, ep2, em2);
-    qL[v] = b + ep;
-    qR[v] = c - em2;
+  for (int v = 0; v < 5; ++v) q[v] = ldg(p + v * vs);
+}
+
+// inflow state, or the uniform-grid slip-wall mirror (normal momentum negated)
+__device__ __forceinline__ void fix3(int kind, int f, const DevBlock& B, double (&q)[5]) {
+  if (kind == 1) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) q[v] = B.bc_q[f][v];
+  } else if (kind == 2) {
+    // m - 2 (m.S)/(S.S) S with S along axis f/2: the normal component flips
+    // (selected per component: a run-time index would put q in scratch memory)
+    const int d = f >> 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) q[1 + a] -= a == d ? 2.0 * q[1 + a] : 0.0;
   }
-  roe_flux<T, 3, 1>(qL, qR, nullptr, C.ay, C.K, Gj);
-#pragma unroll
-  for (int v = 0; v < 5; ++v) sm.f[(s * 5 + v) * kWave + lane] = Gj[v];
+}
+
+__device__ __forceinline__ double ldo3(const double* base, unsigned off) {
+  return *(g_cdouble*)((const char*)base + off);
+}
+__device__ __forceinline__ void sto3(double* base, unsigned off, double v) {
+  *(g_double*)((char*)base + off) = v;
+}
+
+template <int LIM, typename T>
+__device__ __forceinline__ void face_states(const Recon<T>& rc, T a, T b, T c, T d, T& qL, T& qR) {
+  T ep, em, ep2, em2;
+  extrap<LIM>(rc, b - a, c - b, ep, em);    // cell of b
+  extrap<LIM>(rc, c - b, d - c, ep2, em2);  // cell of c
+  qL = b + ep;
+  qR = c - em2;
+}
+
+template <typename T>
+__device__ __forceinline__ void setup_consts(const DevInstance& I, Recon<T>& rc, FluxK<T>& K) {
+  rc.lim = I.limiter;
+  rc.heps = T(0.5 * I.eps);
+  rc.c1 = T(0.25 * I.eps * (1.0 - I.kappa));
+  rc.c2 = T(0.25 * I.eps * (1.0 + I.kappa));
+  K.gm1 = T(I.gamma - 1.0);
+  K.efix = T(I.efix);
+  K.iefix = T(I.efix > 0.0 ? 1.0 / I.efix : 0.0);
 }
 
 // The helper wave: per plane, stage the j-halo rows and the i-halo cells in
 // LDS (fetched one plane ahead) and form the tile's top-edge j-face flux.
-template <int MODE, typename T, int NY>
+template <int MODE, typename T, int NY, int LIM>
 __device__ void helper3d(const DevTile& tl, const DevBlock* __restrict__ blocks, const DevInstance& I,
                          int lane, Smem3<T, NY>& sm) {
   const DevBlock& B = blocks[tl.blk];
   const int ni = B.ni;
   const int i0 = tl.i0, j0 = tl.j0, k0 = tl.k0, n = tl.n, nc = tl.ncol, ny = tl.ny;
-  const int bin = MODE == 0 ? 0 : MODE - 1;
+  constexpr int bin = MODE == 0 ? 0 : MODE - 1;
   const int ic = lane < nc ? i0 + lane : ni - 1;
-  Ctx3D<T> C;
-  setup3(C, blocks, B, bin, I);
-  const int hrows[4] = {j0 - 2, j0 - 1, j0 + ny, j0 + ny + 1};
-  const int hslot[4] = {0, 1, ny + 2, ny + 3};
-  // i-halo lane assignment: lane = 3 * row + which, which 0: i0-1, 1: i0-2, 2: i0+ncol
+  Recon<T> rc;
+  FluxK<T> K;
+  setup_consts(I, rc, K);
+  const T ay = T(B.area[1]);
+  // j-halo rows of the own column: j0-2, j0-1, j0+ny, j0+ny+1
+  const int hrow[4] = {j0 - 2, j0 - 1, j0 + ny, j0 + ny + 1};
+  Src3 hs[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) hs[h] = resolve3(blocks, B, bin, ic, hrow[h], 0);
+  // i-halo cells: lane = 3 * row + which; which 0: i0-1, 1: i0-2, 2: i0+ncol
   const int hr = lane / 3, hw = lane - 3 * (lane / 3);
   const bool hlane = hr < ny;
-  const int hcol = hw == 0 ? i0 - 1 : (hw == 1 ? i0 - 2 : i0 + nc);
-  double hrow[4][5], hcell[5] = {0, 0, 0, 0, 0};
-  if (n > 0) {
+  const int hcol = !hlane ? ic : (hw == 0 ? i0 - 1 : (hw == 1 ? i0 - 2 : i0 + nc));
+  const Src3 cs = resolve3(blocks, B, bin, hcol, hlane ? j0 + hr : j0, 0);
+  const int cslot = hw == 0 ? 1 : (hw == 1 ? 0 : nc + 2);
+  const int crow = hlane ? hr + 2 : 0;
+  const bool fixrows = __builtin_amdgcn_ballot_w64(hs[0].kind != 0 || hs[1].kind != 0 ||
+                                                    hs[2].kind != 0 || hs[3].kind != 0) != 0;
+  const bool fixcells = __builtin_amdgcn_ballot_w64(hlane && cs.kind != 0) != 0;
+  double hv[4][5], cv[5];
 #pragma unroll
-    for (int h = 0; h < 4; ++h) load_cell<5>(blocks, B, bin, ic, hrows[h], k0, hrow[h]);
-    if (hlane) load_cell<5>(blocks, B, bin, hcol, j0 + hr, k0, hcell);
-  }
+  for (int h = 0; h < 4; ++h) load3(hs[h].p + (long long)k0 * hs[h].ps, hs[h].vs, hv[h]);
+  load3(cs.p + (long long)k0 * cs.ps, cs.vs, cv);
   for (int r = 0; r < n; ++r) {
-    const int k = k0 + r;
+    if (fixrows) {
 #pragma unroll
-    for (int h = 0; h < 4; ++h)
+      for (int h = 0; h < 4; ++h) fix3(hs[h].kind, hs[h].f, B, hv[h]);
+    }
+    if (fixcells && hlane) fix3(cs.kind, cs.f, B, cv);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sm.q[(hslot[h] * 5 + v) * kWave + lane] = T(hrow[h][v]);
+    for (int v = 0; v < 5; ++v) {
+      sm.q[0][v][lane + 2] = T(hv[0][v]);
+      sm.q[1][v][lane + 2] = T(hv[1][v]);
+      sm.q[ny + 2][v][lane + 2] = T(hv[2][v]);
+      sm.q[ny + 3][v][lane + 2] = T(hv[3][v]);
+    }
     if (hlane) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sm.halo[hr][hw][v] = T(hcell[v]);
+      for (int v = 0; v < 5; ++v) sm.q[crow][v][cslot] = T(cv[v]);
     }
-    if (r + 1 < n) {
+    // the next plane (clamped inside the tile; the last one is not used)
+    const long long kn = k0 + min(r + 1, n - 1);
 #pragma unroll
-      for (int h = 0; h < 4; ++h) load_cell<5>(blocks, B, bin, ic, hrows[h], k + 1, hrow[h]);
-      if (hlane) load_cell<5>(blocks, B, bin, hcol, j0 + hr, k + 1, hcell);
-    }
+    for (int h = 0; h < 4; ++h) load3(hs[h].p + kn * hs[h].ps, hs[h].vs, hv[h]);
+    load3(cs.p + kn * cs.ps, cs.vs, cv);
     __syncthreads();
-    jface3<T, NY>(C, sm, ny, lane);
+    // top-edge j-face at j0+ny-1/2 from rows ny .. ny+3 (slots)
+    {
+      T qL[5], qR[5], G[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        face_states<LIM>(rc, sm.q[ny][v][lane + 2], sm.q[ny + 1][v][lane + 2], sm.q[ny + 2][v][lane + 2],
+                         sm.q[ny + 3][v][lane + 2], qL[v], qR[v]);
+      roe_flux<T, 3, 1>(qL, qR, nullptr, ay, K, G);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sm.f[ny][v][lane] = G[v];
+    }
     __syncthreads();
   }
 }
 
-template <int MODE, typename T, int NY>
+template <int MODE, typename T, int NY, int LIM>
 __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, DevInstance& I,
                        double* __restrict__ rout, int lane, int w, Smem3<T, NY>& sm) {
   const DevBlock& B = blocks[tl.blk];
-  const int ni = B.ni, nj = B.nj;
+  const int ni = B.ni, nj = B.nj, nk = B.nk;
   const int i0 = tl.i0, j0 = tl.j0, k0 = tl.k0, n = tl.n, nc = tl.ncol, ny = tl.ny;
   const bool rowact = w < ny;
-  const int j = j0 + w;
-  const int i = i0 + lane;
+  const int jc = rowact ? j0 + w : j0;
   const bool act = lane < nc;
-  const int ic = act ? i : ni - 1;
-  const int jc = rowact ? j : j0;
+  const int ic = act ? i0 + lane : ni - 1;
   const int last = nc - 1;
-  const int bin = MODE == 0 ? 0 : MODE - 1;
-  const int bout = MODE == 1 ? 1 : (MODE == 2 ? 2 : 0);
-
-  Ctx3D<T> C;
-  setup3(C, blocks, B, bin, I);
+  const int ir = i0 + nc;
+  constexpr int bin = MODE == 0 ? 0 : MODE - 1;
+  constexpr int bout = MODE == 1 ? 1 : (MODE == 2 ? 2 : 0);
+  Recon<T> rc;
+  FluxK<T> K;
+  setup_consts(I, rc, K);
+  const T ax = T(B.area[0]), ay = T(B.area[1]), az = T(B.area[2]);
   const double gamma = I.gamma;
   const double dt = I.dt;
   const double vol = B.vol;
   const double ivol = 1.0 / vol;
   const long long ncell = B.ncell;
-  double* __restrict__ Uout = B.u[bout];
+  const long long pstr = (long long)ni * nj;
+  const double* __restrict__ Q = B.u[bin];
   const double* __restrict__ Un = B.u[0];
+  double* __restrict__ Uout = B.u[bout];
+  // own column at row jc: element (k) at Q + k * pstr + jc * ni + ic
+  const unsigned cb = (unsigned)(jc * ni + ic) * 8u;
 
-  // ---- prologue
-  double qm1[5] = {0, 0, 0, 0, 0}, q0[5] = {0, 0, 0, 0, 0}, qn[5] = {0, 0, 0, 0, 0};
-  T epm1[5] = {T(0), T(0), T(0), T(0), T(0)};
-  if (rowact) {
-    double qa[5];
-    load_cell<5>(blocks, B, bin, ic, jc, k0 - 2, qa);
-    load_cell<5>(blocks, B, bin, ic, jc, k0 - 1, qm1);
-    load_cell<5>(blocks, B, bin, ic, jc, k0, q0);
-    load_cell<5>(blocks, B, bin, ic, jc, k0 + 1, qn);
+  auto col_load = [&](const double* base, int k, double (&q)[5]) {
+    const double* p = base + (long long)k * pstr;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      T em;
-      extrap(C.rc, T(qm1[v]) - T(qa[v]), T(q0[v]) - T(qm1[v]), epm1[v], em);
-    }
-  }
+    for (int v = 0; v < 5; ++v) q[v] = ldo3(p + v * ncell, cb);
+  };
 
+  // ---- prologue: planes k0-2 .. k0+1 of the own column, and the right-edge
+  //      pre-pass (i-face through i0+ncol-1/2 of this row, plane k0 + lane)
+  double qa[5], qm1[5], q0[5], qn[5], un[5] = {0, 0, 0, 0, 0};
+  const Src3 sa = resolve3(blocks, B, bin, ic, jc, k0 - 2);
+  const Src3 sb = resolve3(blocks, B, bin, ic, jc, k0 - 1);
+  const Src3 sd = resolve3(blocks, B, bin, ic, jc, k0 + 1);
+  load3(sa.p, sa.vs, qa);
+  load3(sb.p, sb.vs, qm1);
+  col_load(Q, k0, q0);
+  load3(sd.p, sd.vs, qn);
+  const int ek = k0 + min(lane, n - 1);
+  Src3 se[4];
+  double ce[4][5];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    se[c] = resolve3(blocks, B, bin, ir - 2 + c, jc, ek);
+    load3(se[c].p, se[c].vs, ce[c]);
+  }
+  fix3(sa.kind, sa.f, B, qa);
+  fix3(sb.kind, sb.f, B, qm1);
+  fix3(sd.kind, sd.f, B, qn);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) fix3(se[c].kind, se[c].f, B, ce[c]);
+  if (rowact) {
+    T qL[5], qR[5], G[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+      face_states<LIM>(rc, T(ce[0][v]), T(ce[1][v]), T(ce[2][v]), T(ce[3][v]), qL[v], qR[v]);
+    roe_flux<T, 3, 0>(qL, qR, nullptr, ax, K, G);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sm.edge[w][v][lane] = G[v];
+  }
+  T epm1[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    T em;
+    extrap<LIM>(rc, T(qm1[v]) - T(qa[v]), T(q0[v]) - T(qm1[v]), epm1[v], em);
+  }
   double rg[5] = {0, 0, 0, 0, 0};
   double nacc[5] = {0, 0, 0, 0, 0};
   double dmin = INFINITY;
   int bad = 0;
+  T* const qrow = &sm.q[rowact ? w + 2 : 0][0][0];
 
-  for (int r = 0; r <= n; ++r) {
+  auto step = [&](auto first_t, auto last_t, int r) {
+    constexpr bool FIRST = decltype(first_t)::value;
+    constexpr bool LASTP = decltype(last_t)::value;
     const int k = k0 + r;
-    const bool more = r < n;
-    T Gk[5], ep0[5];
-    double qnn[5] = {0, 0, 0, 0, 0};
-    if (rowact) {
-      // ---- (1) the next plane of the own column
-      if (more) load_cell<5>(blocks, B, bin, ic, jc, k + 2, qnn);
-      // ---- (2) right-edge i-face fluxes of the next 64 planes
-      if (more && (r & 63) == 0) {
-        const int rr = min(lane, n - r - 1);
-        T ge[5];
-        edge_face3(C, i0 + nc, jc, k + rr, ge);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) sm.edge[w][lane * 5 + v] = ge[v];
-        __builtin_amdgcn_wave_barrier();
+    // ---- (1) the plane k+2 of the own column
+    double q2[5];
+    Src3 s2;
+    if constexpr (!LASTP) {
+      if (k + 2 < nk) {
+        col_load(Q, k + 2, q2);
+        s2.kind = 0;
+        s2.f = 0;
+      } else {
+        s2 = resolve3(blocks, B, bin, ic, jc, k + 2);
+        load3(s2.p, s2.vs, q2);
       }
-      // ---- (3) k-face at k-1/2
+    }
+    // ---- (2) k-face at k-1/2
+    T Gk[5], ep0[5];
+    {
       T qL[5], qR[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const T a = T(qm1[v]), b = T(q0[v]), c = T(qn[v]);
         T em;
-        extrap(C.rc, b - a, c - b, ep0[v], em);
+        extrap<LIM>(rc, b - a, c - b, ep0[v], em);
         qL[v] = a + epm1[v];
         qR[v] = b - em;
       }
-      roe_flux<T, 3, 2>(qL, qR, nullptr, C.az, C.K, Gk);
-      // ---- (4) complete plane k-1
-      if (r >= 1 && act) {
-        const long long idx = ((long long)(k - 1) * nj + j) * ni + i;
+      roe_flux<T, 3, 2>(qL, qR, nullptr, az, K, Gk);
+    }
+    // ---- (3) complete plane k-1
+    if constexpr (!FIRST) {
+      if (rowact && act) {
+        double* const orow = Uout + (long long)(k - 1) * pstr;
         double R[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) R[v] = rg[v] + (double)Gk[v];
         if (MODE == 0) {
+          double* const rrow = rout + B.out_off + (long long)(k - 1) * pstr;
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            stg(rout + B.out_off + v * ncell + idx, R[v]);
+            sto3(rrow + v * ncell, cb, R[v]);
             const double rv = R[v] * ivol;
-            nacc[v] += rv * rv;
+            nacc[v] = fmad(rv, rv, nacc[v]);
           }
         } else {
-          const double f = dt * ivol;
+          const double fct = dt * ivol;
           double out[5];
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            const double us = qm1[v] - f * R[v];
+            const double us = fmad(-fct, R[v], qm1[v]);
             if (MODE == 1) out[v] = us;
-            else if (MODE == 2) out[v] = 0.75 * ldg(Un + v * ncell + idx) + 0.25 * us;
-            else out[v] = (1.0 / 3.0) * ldg(Un + v * ncell + idx) + (2.0 / 3.0) * us;
-            stg(Uout + v * ncell + idx, out[v]);
+            else if (MODE == 2) out[v] = fmad(0.75, un[v], 0.25 * us);
+            else out[v] = fmad(1.0 / 3.0, un[v], (2.0 / 3.0) * us);
+            sto3(orow + v * ncell, cb, out[v]);
           }
           if (MODE == 1) {
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
               const double rv = R[v] * ivol;
-              nacc[v] += rv * rv;
+              nacc[v] = fmad(rv, rv, nacc[v]);
             }
           }
           if (MODE == 3) {
@@ -259,63 +355,62 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
         }
       }
     }
-    // ---- (5) in-plane faces of plane k
-    if (more) {
-      if (rowact) {
+    if constexpr (!LASTP) {
+      // U^n of plane k for the next update
+      if (MODE >= 2) col_load(Un, k, un);
+      // ---- (4) stage plane k in LDS; in-plane faces
+      if (rowact && act) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sm.q[((w + 2) * 5 + v) * kWave + lane] = T(q0[v]);
+        for (int v = 0; v < 5; ++v) qrow[v * kS3 + lane + 2] = T(q0[v]);
       }
       __syncthreads();
-      T Gi[5], Gr[5];
+      T Gi[5];
       if (rowact) {
-        jface3<T, NY>(C, sm, w, lane);
-        T qL[5], qR[5];
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const T c = T(q0[v]);
-          const T h0 = sm.halo[w][0][v];  // Q(i0-1)
-          const T h1 = sm.halo[w][1][v];  // Q(i0-2)
-          const T h2 = sm.halo[w][2][v];  // Q(i0+ncol)
-          const T left = shr1(c);
-          const T right = shl1(c);
-          const T qim1 = lane == 0 ? h0 : left;
-          const T qip1 = lane == last ? h2 : right;
-          T epc, emc;
-          extrap(C.rc, c - qim1, qip1 - c, epc, emc);
-          T ep0l, em0l;
-          extrap(C.rc, h0 - h1, c - h0, ep0l, em0l);
-          const T epl = shr1(epc);
-          qL[v] = qim1 + (lane == 0 ? ep0l : epl);
-          qR[v] = c - emc;
-        }
-        roe_flux<T, 3, 0>(qL, qR, nullptr, C.ax, C.K, Gi);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          const T ge = sm.edge[w][(r & 63) * 5 + v];
-          const T gs = shl1(Gi[v]);
-          Gr[v] = lane == last ? ge : gs;
-        }
-      }
-      __syncthreads();
-      if (rowact) {
+        T qL[5], qR[5], Gj[5];
+        // j-face at j-1/2 from rows w .. w+3 (slots), own column
 #pragma unroll
         for (int v = 0; v < 5; ++v)
-          rg[v] = (((double)Gr[v] - (double)Gi[v]) +
-                   ((double)sm.f[((w + 1) * 5 + v) * kWave + lane] -
-                    (double)sm.f[(w * 5 + v) * kWave + lane])) -
+          face_states<LIM>(rc, sm.q[w][v][lane + 2], sm.q[w + 1][v][lane + 2], sm.q[w + 2][v][lane + 2],
+                           sm.q[w + 3][v][lane + 2], qL[v], qR[v]);
+        roe_flux<T, 3, 1>(qL, qR, nullptr, ay, K, Gj);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm.f[w][v][lane] = Gj[v];
+        // i-face at i-1/2 from the row's slots lane .. lane+3
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          face_states<LIM>(rc, qrow[v * kS3 + lane], qrow[v * kS3 + lane + 1], T(q0[v]),
+                           qrow[v * kS3 + lane + 3], qL[v], qR[v]);
+        roe_flux<T, 3, 0>(qL, qR, nullptr, ax, K, Gi);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm.g[w][v][lane] = Gi[v];
+      }
+      __syncthreads();
+      if (rowact) {
+        const T* gsrc = lane == last ? &sm.edge[w][0][r] : &sm.g[w][0][lane + 1];
+        const int gstr = lane == last ? 64 : kS3;
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          rg[v] = (((double)gsrc[v * gstr] - (double)Gi[v]) +
+                   ((double)sm.f[w + 1][v][lane] - (double)sm.f[w][v][lane])) -
                   (double)Gk[v];
       }
-    }
-    if (rowact) {
+      // ---- (5) rotate
+      if (k + 2 >= nk) fix3(s2.kind, s2.f, B, q2);
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         qm1[v] = q0[v];
         q0[v] = qn[v];
-        qn[v] = qnn[v];
+        qn[v] = q2[v];
         epm1[v] = ep0[v];
       }
     }
-  }
+  };
+
+  using F = std::integral_constant<bool, false>;
+  using Tr = std::integral_constant<bool, true>;
+  step(Tr(), F(), 0);
+  for (int r = 1; r < n; ++r) step(F(), F(), r);
+  step(F(), Tr(), n);
 
   // ---- per-tile partials of this row wave
   if (MODE == 0 || MODE == 1 || MODE == 3) {
@@ -342,7 +437,7 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
 }
 
 // tile partials: the row waves' sums in row order (fixed order)
-template <int MODE, int NY>
+template <int MODE>
 __device__ void tile_partials3d(const DevTile& tl, DevInstance& I, const double* red) {
   double* part = I.part + (long long)tl.local * kPartStride;
   if (MODE == 3) {
@@ -363,12 +458,22 @@ __device__ void tile_partials3d(const DevTile& tl, DevInstance& I, const double*
   }
 }
 
+template <int MODE, typename T, int NY, int LIM>
+__device__ __forceinline__ void run_tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks,
+                                           DevInstance& I, double* __restrict__ rout, int lane, int w,
+                                           Smem3<T, NY>& sm) {
+  // the row waves and the helper wave take the same barriers
+  if (w < NY) tile3d<MODE, T, NY, LIM>(tl, blocks, I, rout, lane, w, sm);
+  else helper3d<MODE, T, NY, LIM>(tl, blocks, I, lane, sm);
+}
+
+// at most 256 VGPRs: two waves per SIMD
 template <int MODE, typename T, int NY>
-__global__ __launch_bounds__(64 * (NY + 1)) void k_stage3d(const DevTile* __restrict__ tiles,
-                                                           const int* __restrict__ ntiles_p,
-                                                           const DevBlock* __restrict__ blocks,
-                                                           DevInstance* __restrict__ insts,
-                                                           double* __restrict__ rout) {
+__global__ __launch_bounds__(64 * (NY + 1), 2) void k_stage3d(const DevTile* __restrict__ tiles,
+                                                              const int* __restrict__ ntiles_p,
+                                                              const DevBlock* __restrict__ blocks,
+                                                              DevInstance* __restrict__ insts,
+                                                              double* __restrict__ rout) {
   __shared__ Smem3<T, NY> sm;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -377,11 +482,10 @@ __global__ __launch_bounds__(64 * (NY + 1)) void k_stage3d(const DevTile* __rest
     const DevTile tl = tiles[t];
     DevInstance& I = insts[tl.inst];
     if (MODE != 0 && I.stopped) continue;
-    // the row waves and the helper wave take the same barriers
-    if (w < NY) tile3d<MODE, T, NY>(tl, blocks, I, rout, lane, w, sm);
-    else helper3d<MODE, T, NY>(tl, blocks, I, lane, sm);
+    if (I.limiter == LIM_MINMOD) run_tile3d<MODE, T, NY, LIM_MINMOD>(tl, blocks, I, rout, lane, w, sm);
+    else run_tile3d<MODE, T, NY, -1>(tl, blocks, I, rout, lane, w, sm);
     __syncthreads();
-    if (threadIdx.x == 0) tile_partials3d<MODE, NY>(tl, I, sm.red);
+    if (threadIdx.x == 0) tile_partials3d<MODE>(tl, I, sm.red);
     __syncthreads();
   }
 }
@@ -438,7 +542,7 @@ hipError_t launch_stage3d(int mode, int fp32, int ny, int grid, hipStream_t s, c
   hipLaunchKernelGGL((k_stage3d<M, T, N>), dim3(grid), dim3(64 * (N + 1)), 0, s, tiles, ntiles, \
                      blocks, insts, rout)
 #define FV_L3N(M, T) \
-  if (ny == 8) FV_L3(M, T, 8); else FV_L3(M, T, 4)
+  if (ny >= 7) FV_L3(M, T, 7); else FV_L3(M, T, 3)
   if (fp32) {
     switch (mode) {
       case 0: FV_L3N(0, float); break;
@@ -467,7 +571,7 @@ hipError_t launch_cfl3d(int grid, int block, hipStream_t s, const DevTile* tiles
 }
 
 const void* stage3d_kernel_ptr(int mode, int fp32, int ny) {
-#define FV_P3(M, T) (ny == 8 ? (const void*)&k_stage3d<M, T, 8> : (const void*)&k_stage3d<M, T, 4>)
+#define FV_P3(M, T) (ny >= 7 ? (const void*)&k_stage3d<M, T, 7> : (const void*)&k_stage3d<M, T, 3>)
   if (fp32) {
     switch (mode) {
       case 0: return FV_P3(0, float);

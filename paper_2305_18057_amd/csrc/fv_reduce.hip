@@ -41,10 +41,13 @@ __global__ void k_prepare(DevInstance* insts, const int* active, int n) {
 }
 
 // Sums of the per-tile partials of one instance by a workgroup of kRedThreads
-// threads: thread x adds the tiles of its contiguous chunk in order, then a
-// fixed pairwise tree in LDS combines the threads (the result depends only on
-// the tile count, never on timing).  Result valid in thread 0.
+// threads.  Thread x takes the tiles x, x + kRedThreads, ... in that order
+// (the loads of four tiles are in flight together), each wavefront combines
+// its lanes by a fixed butterfly, and thread 0 adds the wavefront results in
+// wavefront order: the result depends only on the tile count, never on
+// timing.  Result valid in thread 0.
 constexpr int kRedThreads = 256;
+constexpr int kRedWaves = kRedThreads / 64;
 
 struct RedOut {
   double s[5];
@@ -53,45 +56,66 @@ struct RedOut {
 };
 
 __device__ void reduce_parts(const DevInstance& I, bool sums, bool mins, RedOut& out) {
-  __shared__ double sh[kRedThreads][6];
-  __shared__ int shb[kRedThreads];
+  __shared__ double sh[kRedWaves][6];
+  __shared__ int shb[kRedWaves];
   const int x = threadIdx.x;
+  const int lane = x & 63, w = x >> 6;
   const int nt = I.ntiles;
-  const int chunk = (nt + kRedThreads - 1) / kRedThreads;
-  const int t0 = x * chunk, t1 = min(nt, t0 + chunk);
+  const double* __restrict__ part = I.part;
   double a[5] = {0, 0, 0, 0, 0};
   double m = INFINITY;
   int b = 0;
-  for (int t = t0; t < t1; ++t) {
-    const double* p = I.part + (long long)t * kPartStride;
-    if (sums) {
+  for (int t0 = x; t0 < nt; t0 += 4 * kRedThreads) {
+    double p[4][7];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) a[v] += p[v];
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u * kRedThreads;
+      const double* q = part + (long long)min(t, nt - 1) * kPartStride;
+#pragma unroll
+      for (int v = 0; v < 7; ++v) p[u][v] = q[v];
     }
-    if (mins) {
-      m = fmin(m, p[5]);
-      b |= p[6] != 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (t0 + u * kRedThreads < nt) {
+        if (sums) {
+#pragma unroll
+          for (int v = 0; v < 5; ++v) a[v] += p[u][v];
+        }
+        if (mins) {
+          m = fmin(m, p[u][5]);
+          b |= p[u][6] != 0.0;
+        }
+      }
     }
   }
 #pragma unroll
-  for (int v = 0; v < 5; ++v) sh[x][v] = a[v];
-  sh[x][5] = m;
-  shb[x] = b;
+  for (int v = 0; v < 5; ++v) a[v] = wave_sum(a[v]);
+  m = wave_min(m);
+  b = wave_or(b);
+  if (lane == 0) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sh[w][v] = a[v];
+    sh[w][5] = m;
+    shb[w] = b;
+  }
   __syncthreads();
-  for (int h = kRedThreads / 2; h >= 1; h >>= 1) {
-    if (x < h) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) sh[x][v] += sh[x + h][v];
-      sh[x][5] = fmin(sh[x][5], sh[x + h][5]);
-      shb[x] |= shb[x + h];
-    }
-    __syncthreads();
-  }
   if (x == 0) {
+    double s[6];
+    int bb = 0;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) out.s[v] = sh[0][v];
-    out.mn = sh[0][5];
-    out.bad = shb[0];
+    for (int v = 0; v < 5; ++v) s[v] = sh[0][v];
+    s[5] = sh[0][5];
+    bb = shb[0];
+    for (int y = 1; y < kRedWaves; ++y) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) s[v] += sh[y][v];
+      s[5] = fmin(s[5], sh[y][5]);
+      bb |= shb[y];
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out.s[v] = s[v];
+    out.mn = s[5];
+    out.bad = bb;
   }
 }
 

@@ -28,7 +28,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 // tile shape of an instance: 2D rows per tile; 3D ny rows and planes per tile
 struct TileShape {
   int rows = 8;   // 2D: rows per tile; 3D: planes per tile
-  int ny = 4;     // 3D only: j-rows per tile (4 or 8)
+  int ny = 7;     // 3D only: j-rows per tile (3 or 7)
   bool operator<(const TileShape& o) const { return rows < o.rows || (rows == o.rows && ny < o.ny); }
 };
 

@@ -108,7 +108,7 @@ int validate_and_copy(const fv_grid_desc* d, HostGrid& g) {
   return FV_OK;
 }
 
-static const int kMinRows2D = 4, kMinPlanes3D = 4, kMinNy3D = 4;
+static const int kMinRows2D = 4, kMinPlanes3D = 4, kMinNy3D = 3;
 
 long long max_tiles_of(const HostGrid& g) {
   long long t = 0;
@@ -227,7 +227,7 @@ TileShape default_shape(const HostGrid& g) {
     s.rows = rows;
     s.ny = 1;
   } else {
-    s.ny = 4;
+    s.ny = 7;
     s.rows = 32;
   }
   return s;
@@ -258,8 +258,9 @@ void build_tiles(const HostGrid& g, const TileShape& sh, int inst_index, int bof
           out.push_back(t);
         }
     } else {
-      const int P = std::max(kMinPlanes3D, sh.rows);
-      const int NY = sh.ny == 8 ? 8 : 4;
+      // at most 64 planes: the right-edge fluxes of a row are formed one plane per lane
+      const int P = std::min(64, std::max(kMinPlanes3D, sh.rows));
+      const int NY = sh.ny >= 7 ? 7 : 3;
       for (int k0 = 0; k0 < B.nk; k0 += P)
         for (int j0 = 0; j0 < B.nj; j0 += NY)
           for (int i0 = 0; i0 < B.ni; i0 += 64) {

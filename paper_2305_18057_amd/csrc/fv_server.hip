@@ -154,7 +154,7 @@ namespace {
 
 int kind_of(const HostGrid& g, const TileShape& sh) {
   if (g.ndim == 2) return fvexec::kSet2D;
-  return sh.ny == 8 ? fvexec::kSet3D8 : fvexec::kSet3D4;
+  return sh.ny >= 7 ? fvexec::kSet3D7 : fvexec::kSet3D3;
 }
 
 // arena footprint of one instance: reduction partials, node coordinates and

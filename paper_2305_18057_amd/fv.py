@@ -368,8 +368,12 @@ class Server:
         return lib().fv_server_clock(self._h)
 
     def poll(self, ticket: int):
-        """None while pending, else (status, U, info)."""
+        """None while pending, else (status, U, info); info["times"] holds the
+        request's (submitted, admitted, done) server-clock times."""
         n = self._sizes.get(ticket, 0)
+        tm = (C.c_double * 3)()
+        if lib().fv_request_times(self._h, C.c_ulonglong(ticket), tm) == FV_OK and tm[2] < 0:
+            return None
         U = np.empty(n)
         info = fv_step_info()
         st = lib().fv_poll(self._h, C.c_ulonglong(ticket), U.ctypes.data_as(C.POINTER(C.c_double)),
@@ -379,7 +383,9 @@ class Server:
         if st not in (FV_OK, FV_E_NONPHYSICAL, FV_E_CANCELLED):
             _check(st)
         self._sizes.pop(ticket, None)
-        return st, U, info_dict(info)
+        d = info_dict(info)
+        d["times"] = tuple(tm[:])
+        return st, U, d
 
     def cancel(self, ticket: int) -> int:
         return lib().fv_cancel(self._h, C.c_ulonglong(ticket))
