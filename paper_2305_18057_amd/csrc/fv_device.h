@@ -196,10 +196,18 @@ struct Recon {
 };
 
 // LIM >= 0 fixes the limiter at compile time; LIM < 0 reads it from R.lim
+// eps/2 minmod(a, b) by sign injection: (copysign(eps/4, a) + copysign(eps/4, b))
+// is eps/2, -eps/2 or 0 exactly, times min(|a|, |b|): the same value as the
+// select form (bitwise, up to the sign of a zero result), with no compares
+template <typename T>
+__device__ __forceinline__ T half_eps_minmod(T qeps, T a, T b) {
+  return (copysign(qeps, a) + copysign(qeps, b)) * fmin(fabs(a), fabs(b));
+}
+
 template <int LIM = -1, typename T>
 __device__ __forceinline__ void extrap(const Recon<T>& R, T dm, T dp, T& ep, T& em) {
   if constexpr (LIM == LIM_MINMOD) {
-    const T s = R.heps * minmod(dm, dp);
+    const T s = half_eps_minmod(T(0.5) * R.heps, dm, dp);
     ep = s;
     em = s;
     return;

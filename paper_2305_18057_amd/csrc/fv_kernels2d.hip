@@ -329,8 +329,26 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
         yR2 = ldk(Y + jr * nrow + ir);
       }
     }
-    // ---- (2) j-face at j-1/2
-    T ep0[4], Gj[4];
+    // ---- (2) row j through the LDS row buffer: i-neighbours and halo cells
+    T qim2[4], qim1[4], qip1[4];
+    if constexpr (!LASTR) {
+      halo_fix(j, hv);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qs_own[v * kSlots] = T(q0[v]);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qs_halo[v * kSlots] = T(hv[v]);
+      wave_lds_sync();
+      halo_load(j + 1, hv);  // halo of the next row
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        qim2[v] = qs_own[v * kSlots - 2];
+        qim1[v] = qs_own[v * kSlots - 1];
+        qip1[v] = qs_own[v * kSlots + 1];
+      }
+    }
+    // ---- (3) j-face at j-1/2 and i-face at i-1/2 (independent: their
+    //      arithmetic interleaves in one scheduling region)
+    T ep0[4], Gj[4], Gi[4];
     {
       T qL[4], qR[4];
 #pragma unroll
@@ -343,7 +361,20 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
       }
       face_flux<T, 1, CURV>(K, qL, qR, -(y0r - y0), x0r - x0, areaJ, Gj);
     }
-    // ---- (3) complete, update and store row j-1
+    if constexpr (!LASTR) {
+      T qL[4], qR[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T c = T(q0[v]);
+        T epl, eml, epc, emc;
+        extrap<LIM>(rc, qim1[v] - qim2[v], c - qim1[v], epl, eml);  // cell i-1
+        extrap<LIM>(rc, c - qim1[v], qip1[v] - c, epc, emc);        // cell i
+        qL[v] = qim1[v] + epl;
+        qR[v] = c - emc;
+      }
+      face_flux<T, 0, CURV>(K, qL, qR, y1 - y0, -(x1 - x0), areaI, Gi);
+    }
+    // ---- (4) complete, update and store row j-1
     if constexpr (!FIRST) {
       if (act) {
         const long long ro = (long long)(j - 1) * ni;
@@ -401,29 +432,8 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
     if constexpr (!LASTR) {
       if (MODE >= 2) row_load(Un, j, un);
     }
-    // ---- (4) i-face at i-1/2 of row j, through the LDS row buffer
+    // ---- (5) the right neighbours' i-face fluxes: pending part of row j
     if constexpr (!LASTR) {
-      halo_fix(j, hv);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) qs_own[v * kSlots] = T(q0[v]);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) qs_halo[v * kSlots] = T(hv[v]);
-      wave_lds_sync();
-      halo_load(j + 1, hv);  // halo of the next row
-      T qL[4], qR[4], Gi[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const T c = T(q0[v]);
-        const T qim2 = qs_own[v * kSlots - 2];
-        const T qim1 = qs_own[v * kSlots - 1];
-        const T qip1 = qs_own[v * kSlots + 1];
-        T epl, eml, epc, emc;
-        extrap<LIM>(rc, qim1 - qim2, c - qim1, epl, eml);  // cell i-1
-        extrap<LIM>(rc, c - qim1, qip1 - c, epc, emc);     // cell i
-        qL[v] = qim1 + epl;
-        qR[v] = c - emc;
-      }
-      face_flux<T, 0, CURV>(K, qL, qR, y1 - y0, -(x1 - x0), areaI, Gi);
 #pragma unroll
       for (int v = 0; v < 4; ++v) gs_own[v * kSlots] = Gi[v];
       wave_lds_sync();
@@ -435,7 +445,7 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
       }
       wave_lds_sync();
     }
-    // ---- (5) rotate the carried rows
+    // ---- (6) rotate the carried rows
     if constexpr (!LASTR) {
       if (j + 2 >= nj) fix2<CURV>(s2, B, q2);
 #pragma unroll

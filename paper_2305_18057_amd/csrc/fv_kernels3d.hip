@@ -300,21 +300,50 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
         load3(s2.p, s2.vs, q2);
       }
     }
-    // ---- (2) k-face at k-1/2
-    T Gk[5], ep0[5];
-    {
-      T qL[5], qR[5];
+    // ---- (2) stage plane k in LDS
+    T Gk[5] = {T(0), T(0), T(0), T(0), T(0)}, ep0[5] = {T(0), T(0), T(0), T(0), T(0)};
+    T Gi[5];
+    if constexpr (!LASTP) {
+      if (rowact && act) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const T a = T(qm1[v]), b = T(q0[v]), c = T(qn[v]);
-        T em;
-        extrap<LIM>(rc, b - a, c - b, ep0[v], em);
-        qL[v] = a + epm1[v];
-        qR[v] = b - em;
+        for (int v = 0; v < 5; ++v) qrow[v * kS3 + lane + 2] = T(q0[v]);
       }
-      roe_flux<T, 3, 2>(qL, qR, nullptr, az, K, Gk);
+      __syncthreads();
     }
-    // ---- (3) complete plane k-1
+    // ---- (3) k-face at k-1/2, and (in-plane) j-face at j-1/2 and i-face at
+    //      i-1/2 from LDS: independent, their arithmetic interleaves
+    if (rowact) {
+      {
+        T qL[5], qR[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          const T a = T(qm1[v]), b = T(q0[v]), c = T(qn[v]);
+          T em;
+          extrap<LIM>(rc, b - a, c - b, ep0[v], em);
+          qL[v] = a + epm1[v];
+          qR[v] = b - em;
+        }
+        roe_flux<T, 3, 2>(qL, qR, nullptr, az, K, Gk);
+      }
+      if constexpr (!LASTP) {
+        T qL[5], qR[5], Gj[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          face_states<LIM>(rc, sm.q[w][v][lane + 2], sm.q[w + 1][v][lane + 2], sm.q[w + 2][v][lane + 2],
+                           sm.q[w + 3][v][lane + 2], qL[v], qR[v]);
+        roe_flux<T, 3, 1>(qL, qR, nullptr, ay, K, Gj);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm.f[w][v][lane] = Gj[v];
+#pragma unroll
+        for (int v = 0; v < 5; ++v)
+          face_states<LIM>(rc, qrow[v * kS3 + lane], qrow[v * kS3 + lane + 1], T(q0[v]),
+                           qrow[v * kS3 + lane + 3], qL[v], qR[v]);
+        roe_flux<T, 3, 0>(qL, qR, nullptr, ax, K, Gi);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm.g[w][v][lane] = Gi[v];
+      }
+    }
+    // ---- (4) complete plane k-1
     if constexpr (!FIRST) {
       if (rowact && act) {
         double* const orow = Uout + (long long)(k - 1) * pstr;
@@ -358,33 +387,8 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
     if constexpr (!LASTP) {
       // U^n of plane k for the next update
       if (MODE >= 2) col_load(Un, k, un);
-      // ---- (4) stage plane k in LDS; in-plane faces
-      if (rowact && act) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) qrow[v * kS3 + lane + 2] = T(q0[v]);
-      }
       __syncthreads();
-      T Gi[5];
-      if (rowact) {
-        T qL[5], qR[5], Gj[5];
-        // j-face at j-1/2 from rows w .. w+3 (slots), own column
-#pragma unroll
-        for (int v = 0; v < 5; ++v)
-          face_states<LIM>(rc, sm.q[w][v][lane + 2], sm.q[w + 1][v][lane + 2], sm.q[w + 2][v][lane + 2],
-                           sm.q[w + 3][v][lane + 2], qL[v], qR[v]);
-        roe_flux<T, 3, 1>(qL, qR, nullptr, ay, K, Gj);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) sm.f[w][v][lane] = Gj[v];
-        // i-face at i-1/2 from the row's slots lane .. lane+3
-#pragma unroll
-        for (int v = 0; v < 5; ++v)
-          face_states<LIM>(rc, qrow[v * kS3 + lane], qrow[v * kS3 + lane + 1], T(q0[v]),
-                           qrow[v * kS3 + lane + 3], qL[v], qR[v]);
-        roe_flux<T, 3, 0>(qL, qR, nullptr, ax, K, Gi);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) sm.g[w][v][lane] = Gi[v];
-      }
-      __syncthreads();
+      // ---- (5) the pending in-plane part of plane k
       if (rowact) {
         const T* gsrc = lane == last ? &sm.edge[w][0][r] : &sm.g[w][0][lane + 1];
         const int gstr = lane == last ? 64 : kS3;
@@ -394,7 +398,7 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
                    ((double)sm.f[w + 1][v][lane] - (double)sm.f[w][v][lane])) -
                   (double)Gk[v];
       }
-      // ---- (5) rotate
+      // ---- (6) rotate
       if (k + 2 >= nk) fix3(s2.kind, s2.f, B, q2);
 #pragma unroll
       for (int v = 0; v < 5; ++v) {

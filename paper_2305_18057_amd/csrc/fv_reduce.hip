@@ -42,11 +42,11 @@ __global__ void k_prepare(DevInstance* insts, const int* active, int n) {
 
 // Sums of the per-tile partials of one instance by a workgroup of kRedThreads
 // threads.  Thread x takes the tiles x, x + kRedThreads, ... in that order
-// (the loads of four tiles are in flight together), each wavefront combines
+// (the loads of two tiles are in flight together), each wavefront combines
 // its lanes by a fixed butterfly, and thread 0 adds the wavefront results in
 // wavefront order: the result depends only on the tile count, never on
 // timing.  Result valid in thread 0.
-constexpr int kRedThreads = 256;
+constexpr int kRedThreads = 1024;
 constexpr int kRedWaves = kRedThreads / 64;
 
 struct RedOut {
@@ -65,17 +65,17 @@ __device__ void reduce_parts(const DevInstance& I, bool sums, bool mins, RedOut&
   double a[5] = {0, 0, 0, 0, 0};
   double m = INFINITY;
   int b = 0;
-  for (int t0 = x; t0 < nt; t0 += 4 * kRedThreads) {
-    double p[4][7];
+  for (int t0 = x; t0 < nt; t0 += 2 * kRedThreads) {
+    double p[2][7];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 2; ++u) {
       const int t = t0 + u * kRedThreads;
       const double* q = part + (long long)min(t, nt - 1) * kPartStride;
 #pragma unroll
       for (int v = 0; v < 7; ++v) p[u][v] = q[v];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 2; ++u) {
       if (t0 + u * kRedThreads < nt) {
         if (sums) {
 #pragma unroll

@@ -18,3 +18,18 @@ def orc():
     from oracle import oracle
     oracle.lib()
     return oracle
+
+
+def pytest_sessionfinish(session, exitstatus):
+    """GPU runs: every parity error the tests measured, with its case, goes to
+    gpurun_out/parity_report.txt (the tests also print them)."""
+    try:
+        from tests import parity
+    except Exception:
+        return
+    if not parity.REPORT:
+        return
+    out = os.path.join(ROOT, "gpurun_out")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, "parity_report.txt"), "w") as fh:
+        fh.write("\n".join(parity.REPORT) + "\n")

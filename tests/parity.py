@@ -64,3 +64,11 @@ def cell_volumes(case):
             v = b.h[0] * b.h[1] * (b.h[2] if case.ndim == 3 else 1.0)
             out.append(np.full(b.ncells, v))
     return np.concatenate(out)
+
+
+# every measured error of the GPU tests, written out at the end of the session
+REPORT = []
+
+
+def report(test, msg):
+    REPORT.append(f"{test}: {msg}")

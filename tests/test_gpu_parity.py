@@ -20,6 +20,7 @@ pytestmark = pytest.mark.gpu
 def say(msg):
     print(msg, flush=True)
     sys.stdout.flush()
+    P.report(os.environ.get("PYTEST_CURRENT_TEST", "?").split(" ")[0], msg.strip())
 
 
 @pytest.fixture(scope="module")

@@ -90,6 +90,7 @@ def test_served_equals_grid_and_reference(env):
         ref = O.OracleGrid(c)
         io = ref.run(c.params, 25)
         e = P.state_err(c, U, ref.get_state())
+        P.report("test_served_equals_grid_and_reference", f"served {c.name} 25 steps: e_U = {e:.3e}")
         assert info["steps"] == io["steps"] == 25 and e <= P.FP64_TOL, e
 
 
