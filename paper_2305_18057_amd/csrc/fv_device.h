@@ -433,22 +433,75 @@ __device__ void resolve_cell(const DevBlock* __restrict__ blocks, const DevBlock
 }
 
 // --------------------------------------------------------------------------
+// XCD-aware assignment of tiles to persistent workgroups.  Workgroups are
+// dealt to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8).  Each
+// XCD walks one contiguous eighth of the tile list, so tiles that are
+// neighbours in the grid (and read each other's halo rows) are processed by
+// one XCD at about the same time, through its L2.  Every tile is taken by
+// exactly one (workgroup, slot); the order does not change any result.
+// --------------------------------------------------------------------------
+constexpr int kXcds = 8;
+
+struct TileWalk {
+  int t, end, stride;
+};
+
+__device__ __forceinline__ TileWalk xcd_walk(int ntiles, int slots_per_wg, int slot) {
+  const int G = gridDim.x;
+  TileWalk w;
+  if (G % kXcds != 0) {  // plain grid-stride order
+    w.t = blockIdx.x * slots_per_wg + slot;
+    w.end = ntiles;
+    w.stride = G * slots_per_wg;
+    return w;
+  }
+  const int x = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
+  const int chunk = (ntiles + kXcds - 1) / kXcds;
+  const int beg = x * chunk;
+  w.t = beg + k * slots_per_wg + slot;
+  w.end = min(ntiles, beg + chunk);
+  w.stride = (G / kXcds) * slots_per_wg;
+  return w;
+}
+
+// --------------------------------------------------------------------------
 // wave-wide deterministic reductions (fixed butterfly order)
 // --------------------------------------------------------------------------
+// DPP lane permutations of a double (both halves moved alike): quad_perm,
+// row_half_mirror and row_mirror keep every lane's source inside its row
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  int2 v = __builtin_bit_cast(int2, x);
+  v.x = __builtin_amdgcn_update_dpp(v.x, v.x, CTRL, 0xf, 0xf, false);
+  v.y = __builtin_amdgcn_update_dpp(v.y, v.y, CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, v);
+}
+// sum over the wave in a fixed order: within each row of 16 lanes by four
+// DPP exchange steps (every lane of a row ends with the row sum, combined in
+// the same pattern on every lane), then the four row sums in row order
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  const double r0 = lane_value(v, 0), r1 = lane_value(v, 16);
+  const double r2 = lane_value(v, 32), r3 = lane_value(v, 48);
+  return ((r0 + r1) + r2) + r3;
 }
 __device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
-  return v;
+  v = fmin(v, dpp_d<0xB1>(v));
+  v = fmin(v, dpp_d<0x4E>(v));
+  v = fmin(v, dpp_d<0x141>(v));
+  v = fmin(v, dpp_d<0x140>(v));
+  return fmin(fmin(lane_value(v, 0), lane_value(v, 16)), fmin(lane_value(v, 32), lane_value(v, 48)));
 }
 __device__ __forceinline__ int wave_or(int v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v |= __shfl_xor(v, o, kWave);
-  return v;
+  v |= __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xf, 0xf, false);
+  v |= __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xf, 0xf, false);
+  v |= __builtin_amdgcn_update_dpp(v, v, 0x141, 0xf, 0xf, false);
+  v |= __builtin_amdgcn_update_dpp(v, v, 0x140, 0xf, 0xf, false);
+  return __builtin_amdgcn_readlane(v, 0) | __builtin_amdgcn_readlane(v, 16) |
+         __builtin_amdgcn_readlane(v, 32) | __builtin_amdgcn_readlane(v, 48);
 }
 
 // local time-step limit |Omega| / sum_d(|u.Sbar_d| + c|Sbar_d|) of a cell and

@@ -46,6 +46,9 @@ int launch_grid(const LaunchSet& s, int fp32) {
     cap = std::min(cap, s.ntiles);
   }
   if (s.max_grid > 0) cap = std::min(cap, s.max_grid);
+  // a multiple of the XCD count, so that every XCD walks its own part of the
+  // tile list (see xcd_walk)
+  if (cap >= fvk::kXcds) cap -= cap % fvk::kXcds;
   return std::max(cap, 1);
 }
 

@@ -262,21 +262,6 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
   fix2<CURV>(sd, B, qn);
 #pragma unroll
   for (int c = 0; c < 4; ++c) fix2<CURV>(se[c], B, ce[c]);
-  {
-    T qL[4], qR[4], G[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const T a = T(ce[0][v]), b = T(ce[1][v]), c = T(ce[2][v]), d = T(ce[3][v]);
-      T ep, em, ep2, em2;
-      extrap<LIM>(rc, b - a, c - b, ep, em);    // cell ir-1
-      extrap<LIM>(rc, c - b, d - c, ep2, em2);  // cell ir
-      qL[v] = b + ep;
-      qR[v] = c - em2;
-    }
-    face_flux<T, 0, CURV>(K, qL, qR, ey1 - ey0, -(ex1 - ex0), areaI, G);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) L.edge[v][lane] = G[v];
-  }
   T epm1[4];  // + side extrapolation of cell j-1
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -373,6 +358,23 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
         qR[v] = c - emc;
       }
       face_flux<T, 0, CURV>(K, qL, qR, y1 - y0, -(x1 - x0), areaI, Gi);
+    }
+    if constexpr (FIRST) {
+      // the pre-pass: i-face flux through the tile's right edge for row j0 + lane
+      // (independent of the row's two fluxes; formed alongside them)
+      T qL[4], qR[4], G[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const T a = T(ce[0][v]), b = T(ce[1][v]), c = T(ce[2][v]), d = T(ce[3][v]);
+        T ep, em, ep2, em2;
+        extrap<LIM>(rc, b - a, c - b, ep, em);    // cell ir-1
+        extrap<LIM>(rc, c - b, d - c, ep2, em2);  // cell ir
+        qL[v] = b + ep;
+        qR[v] = c - em2;
+      }
+      face_flux<T, 0, CURV>(K, qL, qR, ey1 - ey0, -(ex1 - ex0), areaI, G);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) L.edge[v][lane] = G[v];
     }
     // ---- (4) complete, update and store row j-1
     if constexpr (!FIRST) {
@@ -512,8 +514,8 @@ __global__ __launch_bounds__(256, 2) void k_stage2d(const DevTile* __restrict__ 
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ntiles = *ntiles_p;
-  for (int t = blockIdx.x * kWavesPerWG + wid; t < ntiles; t += gridDim.x * kWavesPerWG) {
-    const DevTile tl = tiles[t];
+  for (TileWalk tw = xcd_walk(ntiles, kWavesPerWG, wid); tw.t < tw.end; tw.t += tw.stride) {
+    const DevTile tl = tiles[tw.t];
     DevInstance& I = insts[tl.inst];
     if (MODE != 0 && I.stopped) continue;
     // the common configuration (minmod) is compiled with the limiter fixed

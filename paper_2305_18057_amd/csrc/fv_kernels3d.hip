@@ -482,8 +482,8 @@ __global__ __launch_bounds__(64 * (NY + 1), 2) void k_stage3d(const DevTile* __r
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ntiles = *ntiles_p;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const DevTile tl = tiles[t];
+  for (TileWalk tw = xcd_walk(ntiles, 1, 0); tw.t < tw.end; tw.t += tw.stride) {
+    const DevTile tl = tiles[tw.t];
     DevInstance& I = insts[tl.inst];
     if (MODE != 0 && I.stopped) continue;
     if (I.limiter == LIM_MINMOD) run_tile3d<MODE, T, NY, LIM_MINMOD>(tl, blocks, I, rout, lane, w, sm);
