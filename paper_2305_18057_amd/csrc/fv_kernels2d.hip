@@ -67,41 +67,99 @@ struct Src2 {
   int rs, kind, f, t;  // t: index along the wall of the mirrored cell
 };
 
-__device__ __forceinline__ Src2 resolve2(const DevBlock* __restrict__ blocks, const DevBlock& B,
-                                         int buf, int i, int j) {
-  Src2 s;
-  s.kind = 0;
-  s.f = 0;
-  s.t = 0;
-  s.rs = B.ni;
-  s.vs = B.ncell;
-  if (i >= 0 && i < B.ni && j >= 0 && j < B.nj) {
-    s.p = B.u[buf] + (long long)j * B.ni + i;
-    return s;
-  }
-  int f, g;
-  if (i < 0) { f = 0; g = -i; }
-  else if (i >= B.ni) { f = 1; g = i - B.ni + 1; }
-  else if (j < 0) { f = 2; g = -j; }
-  else { f = 3; g = j - B.nj + 1; }
+// The ghost layer g (1 or 2) beyond face f of block B is a copy of one line
+// of cells of a source block (a column for i-faces, a row for j-faces), or the
+// inflow state.  With f and g the same for the whole wavefront, this is
+// scalar work (no per-lane memory reads).
+struct GLine {
+  const double* u;  // source state buffer
+  long long vs;     // its variable stride
+  int rs;           // its row stride
+  int along;        // source column (i-faces) or row (j-faces)
+  int kind;         // 0 copy, 1 inflow state, 2 mirrored copy
+};
+
+__device__ __forceinline__ GLine ghost_line(const DevBlock* __restrict__ blocks, const DevBlock& B,
+                                            int buf, int f, int g) {
   const int d = f >> 1, side = f & 1;
   const int kind = B.bc_kind[f];
   const DevBlock* S = kind == BC_BLOCK ? &blocks[B.bc_nbr[f]] : &B;
   const int n = d == 0 ? S->ni : S->nj;
   int along;
   if (kind == BC_PERIODIC || kind == BC_BLOCK) along = side == 0 ? n - g : g - 1;
-  else if (kind == BC_EXTRAP) along = side == 0 ? 0 : n - 1;
   else if (kind == BC_SLIPWALL) along = side == 0 ? g - 1 : n - g;
-  else along = side == 0 ? 0 : n - 1;  // INFLOW: any valid cell, the value is replaced
-  const int si = d == 0 ? along : i;
-  const int sj = d == 1 ? along : j;
-  s.p = S->u[buf] + (long long)sj * S->ni + si;
-  s.rs = S->ni;
-  s.vs = S->ncell;
-  s.kind = kind == BC_INFLOW ? 1 : (kind == BC_SLIPWALL ? 2 : 0);
+  else along = side == 0 ? 0 : n - 1;  // EXTRAP, or INFLOW (any valid line)
+  GLine L;
+  L.u = S->u[buf];
+  L.vs = S->ncell;
+  L.rs = S->ni;
+  L.along = along;
+  L.kind = kind == BC_INFLOW ? 1 : (kind == BC_SLIPWALL ? 2 : 0);
+  return L;
+}
+
+// cell (col, jr) of the own column with jr wave-uniform (inside the block, or
+// up to two rows beyond a j-face)
+__device__ __forceinline__ Src2 col_src(const DevBlock* __restrict__ blocks, const DevBlock& B, int buf,
+                                        int col, int jr) {
+  Src2 s;
+  s.f = 0;
+  s.t = col;
+  if (jr >= 0 && jr < B.nj) {
+    s.p = B.u[buf] + (long long)jr * B.ni + col;
+    s.vs = B.ncell;
+    s.rs = B.ni;
+    s.kind = 0;
+    return s;
+  }
+  const int f = jr < 0 ? 2 : 3;
+  const GLine L = ghost_line(blocks, B, buf, f, jr < 0 ? -jr : jr - B.nj + 1);
+  s.p = L.u + (long long)L.along * L.rs + col;
+  s.vs = L.vs;
+  s.rs = L.rs;
+  s.kind = L.kind;
   s.f = f;
-  s.t = d == 0 ? j : i;
   return s;
+}
+
+// cell (ic_, row) with the column ic_ wave-uniform (inside the block, or up to
+// two columns beyond an i-face) and the row inside the block
+__device__ __forceinline__ Src2 row_src(const DevBlock* __restrict__ blocks, const DevBlock& B, int buf,
+                                        int icol, int row) {
+  Src2 s;
+  s.f = 0;
+  s.t = row;
+  if (icol >= 0 && icol < B.ni) {
+    s.p = B.u[buf] + (long long)row * B.ni + icol;
+    s.vs = B.ncell;
+    s.rs = B.ni;
+    s.kind = 0;
+    return s;
+  }
+  const int f = icol < 0 ? 0 : 1;
+  const GLine L = ghost_line(blocks, B, buf, f, icol < 0 ? -icol : icol - B.ni + 1);
+  s.p = L.u + (long long)row * L.rs + L.along;
+  s.vs = L.vs;
+  s.rs = L.rs;
+  s.kind = L.kind;
+  s.f = f;
+  return s;
+}
+
+// inflow state, or the mirror m - 2 (m.S)/(S.S) S about a wall face of area
+// vector (sx, sy) given by the caller
+__device__ __forceinline__ void fix_with(const Src2& s, const DevBlock& B, double sx, double sy,
+                                         double (&q)[4]) {
+  if (s.kind == 1) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) q[v] = B.bc_q[s.f][v];
+  } else if (s.kind == 2) {
+    const double ms = q[1] * sx + q[2] * sy;
+    const double ss = sx * sx + sy * sy;
+    const double fct = 2.0 * ms / ss;
+    q[1] -= fct * sx;
+    q[2] -= fct * sy;
+  }
 }
 
 __device__ __forceinline__ void load2(const Src2& s, double (&q)[4]) {
@@ -192,8 +250,11 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
   const double areaI = B.area[0], areaJ = B.area[1], uvol = B.vol;
 
   // ---- halo lanes: 0 -> column i0-1, 1 -> i0-2, 2 -> i0+ncol (others: own column)
-  const int hcol = lane == 0 ? i0 - 1 : (lane == 1 ? i0 - 2 : (lane == 2 ? ir : ic));
-  const Src2 hs = resolve2(blocks, B, bin, hcol, 0);  // row j: hs.p + j * hs.rs
+  const Src2 h0 = row_src(blocks, B, bin, i0 - 1, 0);
+  const Src2 h1 = row_src(blocks, B, bin, i0 - 2, 0);
+  const Src2 h2 = row_src(blocks, B, bin, ir, 0);
+  const Src2 hown = row_src(blocks, B, bin, ic, 0);
+  const Src2 hs = lane == 0 ? h0 : (lane == 1 ? h1 : (lane == 2 ? h2 : hown));  // row j: hs.p + j * hs.rs
   const bool hfix = __builtin_amdgcn_ballot_w64(hs.kind != 0) != 0;
   const int hslot = lane == 0 ? 1 : (lane == 1 ? 0 : (lane == 2 ? nc + 2 : kSlots - 1));
   auto halo_load = [&](int j, double (&h)[4]) {
@@ -219,9 +280,26 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
   // ---- prologue: rows j0-2 .. j0+1, halo of row j0, node rows j0, j0+1,
   //      and everything the right-edge pre-pass reads (issued together)
   double qa[4], qm1[4], q0[4], qn[4], hv[4], un[4] = {0, 0, 0, 0};
-  const Src2 sa = resolve2(blocks, B, bin, ic, j0 - 2);
-  const Src2 sb = resolve2(blocks, B, bin, ic, j0 - 1);
-  const Src2 sd = resolve2(blocks, B, bin, ic, j0 + 1);
+  const Src2 sa = col_src(blocks, B, bin, ic, j0 - 2);
+  const Src2 sb = col_src(blocks, B, bin, ic, j0 - 1);
+  const Src2 sd = col_src(blocks, B, bin, ic, j0 + 1);
+  // area vectors of the bottom / top wall faces of the own column, for the
+  // slip-wall ghosts of this tile (read with the prologue)
+  double bwx = 0, bwy = 1, twx = 0, twy = 1;
+  const bool bwall = j0 < 2 && B.bc_kind[2] == BC_SLIPWALL;
+  const bool twall = j0 + n + 2 > nj && B.bc_kind[3] == BC_SLIPWALL;
+  if constexpr (CURV) {
+    if (bwall) {
+      bwx = -(ldo(Y + 1, cb) - ldo(Y, cb));
+      bwy = ldo(X + 1, cb) - ldo(X, cb);
+    }
+    if (twall) {
+      const double* xw = X + (long long)nj * nrow;
+      const double* yw = Y + (long long)nj * nrow;
+      twx = -(ldo(yw + 1, cb) - ldo(yw, cb));
+      twy = ldo(xw + 1, cb) - ldo(xw, cb);
+    }
+  }
   load2(sa, qa);
   load2(sb, qm1);
   row_load(Q, j0, q0);
@@ -246,7 +324,7 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
   double ce[4][4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    se[c] = resolve2(blocks, B, bin, ir - 2 + c, er);
+    se[c] = row_src(blocks, B, bin, ir - 2 + c, er);
     load2(se[c], ce[c]);
   }
   double ex0 = 0, ey0 = 0, ex1 = 0, ey1 = 0;
@@ -257,9 +335,9 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
     ey1 = ldg(Y + (er + 1) * nrow + ir);
   }
   // ghost corrections of the prologue cells
-  fix2<CURV>(sa, B, qa);
-  fix2<CURV>(sb, B, qm1);
-  fix2<CURV>(sd, B, qn);
+  fix_with(sa, B, bwx, bwy, qa);
+  fix_with(sb, B, bwx, bwy, qm1);
+  fix_with(sd, B, twx, twy, qn);
 #pragma unroll
   for (int c = 0; c < 4; ++c) fix2<CURV>(se[c], B, ce[c]);
   T epm1[4];  // + side extrapolation of cell j-1
@@ -295,16 +373,7 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
     double x2 = 0, y2 = 0, xR2 = 0, yR2 = 0;
     Src2 s2;
     if constexpr (!LASTR) {
-      if (j + 2 < nj) {
-        s2.p = Q + (long long)(j + 2) * ni + ic;
-        s2.vs = ncell;
-        s2.rs = ni;
-        s2.kind = 0;
-        s2.f = 0;
-        s2.t = 0;
-      } else {
-        s2 = resolve2(blocks, B, bin, ic, j + 2);
-      }
+      s2 = col_src(blocks, B, bin, ic, j + 2);
       load2(s2, q2);
       if constexpr (CURV) {
         const long long jr = min(j + 2, nj);
@@ -449,7 +518,7 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
     }
     // ---- (6) rotate the carried rows
     if constexpr (!LASTR) {
-      if (j + 2 >= nj) fix2<CURV>(s2, B, q2);
+      if (j + 2 >= nj) fix_with(s2, B, twx, twy, q2);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         qm1[v] = q0[v];
