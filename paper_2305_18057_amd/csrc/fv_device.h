@@ -13,7 +13,9 @@
 namespace fvk {
 
 constexpr int kWave = 64;
-constexpr int kPartStride = 8;  // per-tile partials: 5 norm sums, spectral min, flag, spare
+// per-tile partials: 5 norm sums, spectral minimum, flag (and a spare slot),
+// stored value-major: value v of tile t at part[v * ntiles + t]
+constexpr int kPartStride = 8;
 
 enum { BC_PERIODIC = 0, BC_BLOCK = 1, BC_INFLOW = 2, BC_EXTRAP = 3, BC_SLIPWALL = 4 };
 enum { LIM_MINMOD = 0, LIM_NONE = 1, LIM_FIRST = 2 };

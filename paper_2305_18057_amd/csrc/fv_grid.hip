@@ -41,7 +41,11 @@ int upload_tiles(fv_grid* g) {
   FV_HIP(hipMemcpyAsync(g->d_tiles, g->htiles.data(), sizeof(fvk::DevTile) * nt,
                         hipMemcpyHostToDevice, g->stream));
   FV_HIP(hipMemcpyAsync(g->d_ntiles, &nt, sizeof(int), hipMemcpyHostToDevice, g->stream));
+  // the instance's tile count sizes its partials (value-major) and their
+  // reductions: it follows the tile list at once, on the host and the device
   g->hinst.ntiles = nt;
+  FV_HIP(hipMemcpyAsync((char*)g->d_inst + offsetof(fvk::DevInstance, ntiles), &g->hinst.ntiles,
+                        sizeof(int), hipMemcpyHostToDevice, g->stream));
   g->plan = fvexec::StepPlan();
   g->plan.blocks = g->d_blocks;
   g->plan.insts = g->d_inst;
@@ -431,8 +435,9 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
     g->shape = c;
     st = upload_tiles(g);
     if (st) break;
-    // same starting state for every candidate
+    // same starting state for every candidate (with this candidate's tiles)
     g->hinst = keep;
+    g->hinst.ntiles = (int)g->htiles.size();
     params_to_inst(p, g->hg.gamma, g->hinst);
     g->hinst.step_limit = keep.steps + 1000000;
     g->hinst.drop_tol = 0.0;
@@ -464,6 +469,7 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
   FV_HIP(hipMemcpyAsync(g->d_u[0], saved.data(), sizeof(double) * saved.size(),
                         hipMemcpyHostToDevice, g->stream));
   g->hinst = keep;
+  g->hinst.ntiles = (int)g->htiles.size();
   st = put_inst(g, true);
   if (st) return st;
   // the per-tile spectral minima of the restored state

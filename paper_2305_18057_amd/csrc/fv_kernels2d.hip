@@ -551,23 +551,24 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
   step(F(), Tr(), n);
 
   // ---- per-tile partials (fixed-order wave reductions)
-  double* part = I.part + (long long)tl.local * kPartStride;
+  double* part = I.part + tl.local;
+  const long long ps = I.ntiles;
   if (MODE == 0 || MODE == 1) {
     double s[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) s[v] = wave_sum(nacc[v]);
     if (lane == 0) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) part[v] = s[v];
-      part[4] = 0.0;
+      for (int v = 0; v < 4; ++v) part[v * ps] = s[v];
+      part[4 * ps] = 0.0;
     }
   }
   if (MODE == 3) {
     const double m = wave_min(dmin);
     const int b = wave_or(bad);
     if (lane == 0) {
-      part[5] = m;
-      part[6] = (double)b;
+      part[5 * ps] = m;
+      part[6 * ps] = (double)b;
     }
   }
 }
@@ -648,9 +649,10 @@ __global__ __launch_bounds__(256) void k_cfl2d(const DevTile* __restrict__ tiles
     const double m = wave_min(dmin);
     const int b = wave_or(bad);
     if (lane == 0) {
-      double* part = I.part + (long long)tl.local * kPartStride;
-      part[5] = m;
-      part[6] = (double)b;
+      double* part = I.part + tl.local;
+      const long long ps = I.ntiles;
+      part[5 * ps] = m;
+      part[6 * ps] = (double)b;
     }
   }
 }

@@ -443,7 +443,8 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
 // tile partials: the row waves' sums in row order (fixed order)
 template <int MODE>
 __device__ void tile_partials3d(const DevTile& tl, DevInstance& I, const double* red) {
-  double* part = I.part + (long long)tl.local * kPartStride;
+  double* part = I.part + tl.local;
+  const long long ps = I.ntiles;
   if (MODE == 3) {
     double mm = INFINITY;
     double bb = 0.0;
@@ -451,13 +452,13 @@ __device__ void tile_partials3d(const DevTile& tl, DevInstance& I, const double*
       mm = fmin(mm, red[x * 8 + 5]);
       bb = fmax(bb, red[x * 8 + 6]);
     }
-    part[5] = mm;
-    part[6] = bb;
+    part[5 * ps] = mm;
+    part[6 * ps] = bb;
   } else if (MODE == 0 || MODE == 1) {
     for (int v = 0; v < 5; ++v) {
       double a = 0.0;
       for (int x = 0; x < tl.ny; ++x) a += red[x * 8 + v];
-      part[v] = a;
+      part[v * ps] = a;
     }
   }
 }
@@ -529,9 +530,10 @@ __global__ __launch_bounds__(256) void k_cfl3d(const DevTile* __restrict__ tiles
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-      double* part = I.part + (long long)tl.local * kPartStride;
-      part[5] = fmin(fmin(s_m[0], s_m[1]), fmin(s_m[2], s_m[3]));
-      part[6] = (double)(s_b[0] | s_b[1] | s_b[2] | s_b[3]);
+      double* part = I.part + tl.local;
+      const long long ps = I.ntiles;
+      part[5 * ps] = fmin(fmin(s_m[0], s_m[1]), fmin(s_m[2], s_m[3]));
+      part[6 * ps] = (double)(s_b[0] | s_b[1] | s_b[2] | s_b[3]);
     }
     __syncthreads();
   }

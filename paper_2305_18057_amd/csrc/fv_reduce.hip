@@ -11,7 +11,7 @@ namespace {
 // time step of the coming step: dt_fixed, or CFL times the spectral minimum
 // of U^n; a positive t_end clamps the step so that t lands on t_end and stops
 // the instance once t has reached it
-__device__ void next_dt(DevInstance& I) {
+__device__ __forceinline__ void next_dt(DevInstance& I) {
   double dt = I.dt_fixed > 0.0 ? I.dt_fixed : I.cfl * I.raw_min;
   int last = 0;
   if (I.t_end > 0.0) {
@@ -43,9 +43,9 @@ __global__ void k_prepare(DevInstance* insts, const int* active, int n) {
 // Sums of the per-tile partials of one instance by a workgroup of kRedThreads
 // threads.  Thread x takes the tiles x, x + kRedThreads, ... in that order
 // (the loads of two tiles are in flight together), each wavefront combines
-// its lanes by a fixed butterfly, and thread 0 adds the wavefront results in
-// wavefront order: the result depends only on the tile count, never on
-// timing.  Result valid in thread 0.
+// its lanes by a fixed butterfly, and wavefront 0 combines the wavefront
+// results by the same butterfly: the result depends only on the tile count,
+// never on timing.  Result valid in wavefront 0.
 constexpr int kRedThreads = 1024;
 constexpr int kRedWaves = kRedThreads / 64;
 
@@ -55,13 +55,12 @@ struct RedOut {
   int bad;
 };
 
-__device__ void reduce_parts(const DevInstance& I, bool sums, bool mins, RedOut& out) {
+__device__ __forceinline__ void reduce_parts(int nt, const double* __restrict__ part, bool sums,
+                                             bool mins, RedOut& out) {
   __shared__ double sh[kRedWaves][6];
   __shared__ int shb[kRedWaves];
   const int x = threadIdx.x;
   const int lane = x & 63, w = x >> 6;
-  const int nt = I.ntiles;
-  const double* __restrict__ part = I.part;
   double a[5] = {0, 0, 0, 0, 0};
   double m = INFINITY;
   int b = 0;
@@ -70,9 +69,9 @@ __device__ void reduce_parts(const DevInstance& I, bool sums, bool mins, RedOut&
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int t = t0 + u * kRedThreads;
-      const double* q = part + (long long)min(t, nt - 1) * kPartStride;
+      const double* q = part + min(t, nt - 1);
 #pragma unroll
-      for (int v = 0; v < 7; ++v) p[u][v] = q[v];
+      for (int v = 0; v < 7; ++v) p[u][v] = ldg(q + (long long)v * nt);
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
@@ -99,33 +98,25 @@ __device__ void reduce_parts(const DevInstance& I, bool sums, bool mins, RedOut&
     shb[w] = b;
   }
   __syncthreads();
-  if (x == 0) {
-    double s[6];
-    int bb = 0;
+  if (w == 0) {
+    // wavefront 0 combines the wavefront results by the same butterfly
+    const bool has = lane < kRedWaves;
+    const int y = has ? lane : 0;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) s[v] = sh[0][v];
-    s[5] = sh[0][5];
-    bb = shb[0];
-    for (int y = 1; y < kRedWaves; ++y) {
-#pragma unroll
-      for (int v = 0; v < 5; ++v) s[v] += sh[y][v];
-      s[5] = fmin(s[5], sh[y][5]);
-      bb |= shb[y];
-    }
-#pragma unroll
-    for (int v = 0; v < 5; ++v) out.s[v] = s[v];
-    out.mn = s[5];
-    out.bad = bb;
+    for (int v = 0; v < 5; ++v) out.s[v] = wave_sum(has ? sh[y][v] : 0.0);
+    out.mn = wave_min(has ? sh[y][5] : INFINITY);
+    out.bad = wave_or(has ? shb[y] : 0);
   }
 }
 
-__device__ void norms_from_sums(const DevInstance& I, const double* s, double* norms,
-                                double& comb) {
+__device__ __forceinline__ void norms_from_sums(int nv, long long ncells, const double* qref,
+                                                const double* s, double* norms, double& comb) {
   double cs = 0.0;
+#pragma unroll
   for (int v = 0; v < 5; ++v) {
-    norms[v] = v < I.nv ? sqrt(s[v] / (double)I.ncells) : 0.0;
-    if (v < I.nv) {
-      const double q = I.qref[v] != 0.0 ? I.qref[v] : 1.0;
+    norms[v] = v < nv ? sqrt(s[v] / (double)ncells) : 0.0;
+    if (v < nv) {
+      const double q = qref[v] != 0.0 ? qref[v] : 1.0;
       const double r = norms[v] / q;
       cs += r * r;
     }
@@ -139,43 +130,81 @@ __global__ __launch_bounds__(kRedThreads) void k_finalize(DevInstance* insts, co
   // workgroups beyond the live count leave at once (graphs stay valid)
   if (n_dev && (int)blockIdx.x >= *n_dev) return;
   DevInstance& I = insts[active ? active[blockIdx.x] : blockIdx.x];
-  if (I.stopped) return;
+  // every field the step end reads is fetched here, in one batch with the
+  // partials' addresses; the bookkeeping then runs in registers and writes
+  // the marching state back once
+  const int stopped0 = I.stopped, nt = I.ntiles, nv = I.nv;
+  const double* part = I.part;
+  const long long ncells = I.ncells, step_limit = I.step_limit;
+  double qref[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) qref[v] = I.qref[v];
+  const double cfl = I.cfl, dt_fixed = I.dt_fixed, t_end = I.t_end, drop_tol = I.drop_tol;
+  double t = I.t, dt = I.dt, norm_first = I.norm_first;
+  long long steps = I.steps;
+  int flags = I.flags, have_first = I.have_first, last_step = I.last_step;
+  if (stopped0) return;
   RedOut R;
-  reduce_parts(I, true, true, R);
+  reduce_parts(nt, part, true, true, R);
   if (threadIdx.x != 0) return;
-  double norms[5], comb;
-  norms_from_sums(I, R.s, norms, comb);
-  for (int v = 0; v < 5; ++v) I.norms[v] = norms[v];
-  I.norm = comb;
-  if (!I.have_first) {
-    I.norm_first = comb;
-    I.have_first = 1;
+  double comb, nrm[5];
+  norms_from_sums(nv, ncells, qref, R.s, nrm, comb);
+  if (!have_first) {
+    norm_first = comb;
+    have_first = 1;
   }
-  I.drop = I.norm_first > 0.0 ? comb / I.norm_first : 0.0;
-  I.t = I.last_step ? I.t_end : I.t + I.dt;
-  I.dt_last = I.dt;
-  I.steps += 1;
-  I.raw_min = R.mn;
+  const double drop = norm_first > 0.0 ? comb / norm_first : 0.0;
+  t = last_step ? t_end : t + dt;
+  const double dt_last = dt;
+  steps += 1;
+  int stopped = 0;
   if (R.bad) {
-    I.flags |= FLAG_NONPHYS;
-    I.stopped = 1;
+    flags |= FLAG_NONPHYS;
+    stopped = 1;
   }
-  if (I.drop_tol > 0.0 && I.drop <= I.drop_tol) {
-    I.flags |= FLAG_CONVERGED;
-    I.stopped = 1;
+  if (drop_tol > 0.0 && drop <= drop_tol) {
+    flags |= FLAG_CONVERGED;
+    stopped = 1;
   }
-  if (I.steps >= I.step_limit) {
-    I.flags |= FLAG_STEPLIMIT;
-    I.stopped = 1;
+  if (steps >= step_limit) {
+    flags |= FLAG_STEPLIMIT;
+    stopped = 1;
   }
-  if (!I.stopped) next_dt(I);
+  // next time step (the rule of next_dt)
+  if (!stopped) {
+    dt = dt_fixed > 0.0 ? dt_fixed : cfl * R.mn;
+    last_step = 0;
+    if (t_end > 0.0) {
+      if (t >= t_end) {
+        stopped = 1;
+        flags |= FLAG_TEND;
+      } else if (dt >= t_end - t) {
+        dt = t_end - t;
+        last_step = 1;
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) I.norms[v] = nrm[v];
+  I.norm = comb;
+  I.norm_first = norm_first;
+  I.have_first = have_first;
+  I.drop = drop;
+  I.t = t;
+  I.dt_last = dt_last;
+  I.steps = steps;
+  I.raw_min = R.mn;
+  I.flags = flags;
+  I.stopped = stopped;
+  I.dt = dt;
+  I.last_step = last_step;
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_cfl_init(DevInstance* insts, const int* active,
                                                          int n) {
   DevInstance& I = insts[active ? active[blockIdx.x] : blockIdx.x];
   RedOut R;
-  reduce_parts(I, false, true, R);
+  reduce_parts(I.ntiles, I.part, false, true, R);
   if (threadIdx.x != 0) return;
   I.raw_min = R.mn;
   I.flags = R.bad ? FLAG_NONPHYS : 0;
@@ -185,11 +214,18 @@ __global__ __launch_bounds__(kRedThreads) void k_cfl_init(DevInstance* insts, co
 __global__ __launch_bounds__(kRedThreads) void k_rnorms(DevInstance* insts, const int* active,
                                                        int n) {
   DevInstance& I = insts[active ? active[blockIdx.x] : blockIdx.x];
+  const int nv = I.nv;
+  const long long ncells = I.ncells;
+  double qref[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) qref[v] = I.qref[v];
   RedOut R;
-  reduce_parts(I, true, false, R);
+  reduce_parts(I.ntiles, I.part, true, false, R);
   if (threadIdx.x != 0) return;
-  double comb;
-  norms_from_sums(I, R.s, I.rnorms, comb);
+  double comb, rn[5];
+  norms_from_sums(nv, ncells, qref, R.s, rn, comb);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) I.rnorms[v] = rn[v];
 }
 
 // One thread per ghost cell.  Segment = (block, face): both layers.

@@ -196,6 +196,41 @@ def test_tile_shape_independence(env, tmp_path):
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
+def _tune_cls(case, dim):
+    return f"{dim}d_fp64_c{int(math.floor(math.log2(case.ncells)))}"
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_tune_keeps_results(env, tmp_path, dim):
+    """fv_tune, timed (empty table) and recorded (a shape other than the
+    grid's), leaves a grid whose steps give the untuned solution: the same
+    state bit for bit, the same time, norms to rounding."""
+    fv, O = env
+    make = (lambda: CS.inlet_case(200, 72, 2)) if dim == 2 else (lambda: CS.blobs_case(32, nblobs=4))
+    case = make()
+    ref, iref = gpu_run(fv, case, 8)
+    Uref = ref.get_state()
+    shape0 = ref.stats()
+    timed = str(tmp_path / "timed.json")
+    recorded = tmp_path / "recorded.json"
+    other = {"rows": 16 if shape0["tile_rows"] != 16 else 8,
+             "ny": 1 if dim == 2 else (3 if shape0["tile_ny"] != 3 else 7), "ms": 0.0}
+    recorded.write_text(json.dumps({_tune_cls(case, dim): other}))
+    for path in (timed, str(recorded)):
+        g = fv.Grid(case)
+        g.set_state(case.state_flat())
+        st = g.tune(case.params, path)
+        if path != timed:
+            assert (st["tile_rows"], st["tile_ny"]) == (other["rows"], other["ny"])
+        info = g.step(case.params, 8)
+        say(f"  tuned ({'timed' if path == timed else 'recorded'}) shape rows={st['tile_rows']} "
+            f"ny={st['tile_ny']} tiles={st['tiles']}")
+        assert np.array_equal(g.get_state(), Uref)
+        assert info["steps"] == iref["steps"] and info["t"] == iref["t"]
+        nv = case.nv
+        assert np.allclose(info["norms"][:nv], iref["norms"][:nv], rtol=1e-12, atol=0.0)
+
+
 # ---------------------------------------------------------------------------
 # 2D inlet-like multi-block curvilinear mesh
 # ---------------------------------------------------------------------------
