@@ -372,9 +372,15 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
     double q2[4];
     double x2 = 0, y2 = 0, xR2 = 0, yR2 = 0;
     Src2 s2;
+    s2.kind = 0;
+    s2.f = 0;
     if constexpr (!LASTR) {
-      s2 = col_src(blocks, B, bin, ic, j + 2);
-      load2(s2, q2);
+      if (j + 2 < nj) {
+        row_load(Q, j + 2, q2);
+      } else {  // a ghost row beyond the top face
+        s2 = col_src(blocks, B, bin, ic, j + 2);
+        load2(s2, q2);
+      }
       if constexpr (CURV) {
         const long long jr = min(j + 2, nj);
         x2 = ldo(X + jr * nrow, cb);
