@@ -334,6 +334,26 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
     ex1 = ldg(X + (er + 1) * nrow + ir);
     ey1 = ldg(Y + (er + 1) * nrow + ir);
   }
+  // the first row step's next row (j0 + 2), issued last in the prologue batch
+  // so that it has arrived by the end of that step
+  double q2p[4];
+  Src2 s2p;
+  s2p.kind = 0;
+  s2p.f = 0;
+  if (j0 + 2 < nj) {
+    row_load(Q, j0 + 2, q2p);
+  } else {
+    s2p = col_src(blocks, B, bin, ic, j0 + 2);
+    load2(s2p, q2p);
+  }
+  double x2p = 0, y2p = 0, xR2p = 0, yR2p = 0;
+  if constexpr (CURV) {
+    const long long jr = min(j0 + 2, nj);
+    x2p = ldo(X + jr * nrow, cb);
+    y2p = ldo(Y + jr * nrow, cb);
+    xR2p = ldk(X + jr * nrow + ir);
+    yR2p = ldk(Y + jr * nrow + ir);
+  }
   // ghost corrections of the prologue cells
   fix_with(sa, B, bwx, bwy, qa);
   fix_with(sb, B, bwx, bwy, qm1);
@@ -374,7 +394,15 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
     Src2 s2;
     s2.kind = 0;
     s2.f = 0;
-    if constexpr (!LASTR) {
+    if constexpr (FIRST) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) q2[v] = q2p[v];
+      s2 = s2p;
+      x2 = x2p;
+      y2 = y2p;
+      xR2 = xR2p;
+      yR2 = yR2p;
+    } else if constexpr (!LASTR) {
       if (j + 2 < nj) {
         row_load(Q, j + 2, q2);
       } else {  // a ghost row beyond the top face
