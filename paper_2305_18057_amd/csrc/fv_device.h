@@ -43,7 +43,7 @@ struct DevInstance {
   long long step_limit;
   long long ncells;
   int limiter, ndim, nv, ntiles;
-  double* part;             // [ntiles][kPartStride]
+  double* part;             // [kPartStride][ntiles], value-major
   // marching state (device)
   double t, dt, dt_last, raw_min, norm_first, norm, drop;
   double norms[5];
@@ -463,6 +463,28 @@ __device__ __forceinline__ TileWalk xcd_walk(int ntiles, int slots_per_wg, int s
   w.t = beg + k * slots_per_wg + slot;
   w.end = min(ntiles, beg + chunk);
   w.stride = (G / kXcds) * slots_per_wg;
+  return w;
+}
+
+// As xcd_walk, but each workgroup of an XCD takes a contiguous share of that
+// XCD's range (shares differ by at most one tile).  Consecutive tiles of one
+// workgroup then lie side by side in memory, so a new tile finds its address
+// translations and much of its data already cached.  One tile slot per
+// workgroup.
+__device__ __forceinline__ TileWalk xcd_walk_blocked(int ntiles) {
+  const int G = gridDim.x;
+  TileWalk w;
+  w.stride = 1;
+  if (G % kXcds != 0) {
+    w.t = (int)(((long long)blockIdx.x * ntiles) / G);
+    w.end = (int)(((long long)(blockIdx.x + 1) * ntiles) / G);
+    return w;
+  }
+  const int x = blockIdx.x % kXcds, k = blockIdx.x / kXcds, per = G / kXcds;
+  const int chunk = (ntiles + kXcds - 1) / kXcds;
+  const int beg = min(ntiles, x * chunk), len = min(ntiles, beg + chunk) - beg;
+  w.t = beg + (int)(((long long)k * len) / per);
+  w.end = beg + (int)(((long long)(k + 1) * len) / per);
   return w;
 }
 

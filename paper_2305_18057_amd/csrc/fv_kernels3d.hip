@@ -39,52 +39,100 @@ struct Smem3 {
   double red[(NY + 1) * 8];
 };
 
-// where cell (i, j, k) of block B comes from, without touching memory (as in
-// 2D): kind 0 a cell of B or a neighbour block, 1 the inflow state of face f,
-// 2 the cell mirrored about the wall face f.  ps: plane stride of the source.
+// Where a cell of block B comes from, without touching memory (as in 2D):
+// kind 0 a cell of B or a neighbour block, 1 the inflow state of face f, 2 the
+// cell mirrored about the wall face f.  p points at the cell (or, for the
+// column forms below, at its plane 0); vs, ps, rs: variable, plane and row
+// strides of the source block.
 struct Src3 {
   const double* p;
   long long vs, ps;
-  int kind, f;
+  int rs, kind, f;
 };
 
-__device__ __forceinline__ Src3 resolve3(const DevBlock* __restrict__ blocks, const DevBlock& B,
-                                         int buf, int i, int j, int k) {
-  Src3 s;
-  s.kind = 0;
-  s.f = 0;
-  s.vs = B.ncell;
-  s.ps = (long long)B.ni * B.nj;
-  if (i >= 0 && i < B.ni && j >= 0 && j < B.nj && k >= 0 && k < B.nk) {
-    s.p = B.u[buf] + ((long long)k * B.nj + j) * B.ni + i;
-    return s;
-  }
-  int f, g;
-  if (i < 0) { f = 0; g = -i; }
-  else if (i >= B.ni) { f = 1; g = i - B.ni + 1; }
-  else if (j < 0) { f = 2; g = -j; }
-  else if (j >= B.nj) { f = 3; g = j - B.nj + 1; }
-  else if (k < 0) { f = 4; g = -k; }
-  else { f = 5; g = k - B.nk + 1; }
+// The ghost layer g (1 or 2) beyond face f of block B copies the plane of
+// index `along` (along the face normal) of a source block, or takes the inflow
+// state.  f and g are the same for the whole wavefront: scalar work.
+struct GPlane3 {
+  const double* u;
+  long long vs;
+  int ni, nj, along, kind;
+};
+
+__device__ __forceinline__ GPlane3 ghost_plane3(const DevBlock* __restrict__ blocks,
+                                                const DevBlock& B, int buf, int f, int g) {
   const int d = f >> 1, side = f & 1;
   const int kind = B.bc_kind[f];
   const DevBlock* S = kind == BC_BLOCK ? &blocks[B.bc_nbr[f]] : &B;
   const int n = d == 0 ? S->ni : (d == 1 ? S->nj : S->nk);
   int along;
   if (kind == BC_PERIODIC || kind == BC_BLOCK) along = side == 0 ? n - g : g - 1;
-  else if (kind == BC_EXTRAP) along = side == 0 ? 0 : n - 1;
   else if (kind == BC_SLIPWALL) along = side == 0 ? g - 1 : n - g;
-  else along = side == 0 ? 0 : n - 1;  // INFLOW: any valid cell, the value is replaced
-  const int si = d == 0 ? along : i;
-  const int sj = d == 1 ? along : j;
-  const int sk = d == 2 ? along : k;
-  s.p = S->u[buf] + ((long long)sk * S->nj + sj) * S->ni + si;
-  s.vs = S->ncell;
-  s.ps = (long long)S->ni * S->nj;
-  s.kind = kind == BC_INFLOW ? 1 : (kind == BC_SLIPWALL ? 2 : 0);
+  else along = side == 0 ? 0 : n - 1;  // EXTRAP, or INFLOW (any valid plane)
+  GPlane3 G;
+  G.u = S->u[buf];
+  G.vs = S->ncell;
+  G.ni = S->ni;
+  G.nj = S->nj;
+  G.along = along;
+  G.kind = kind == BC_INFLOW ? 1 : (kind == BC_SLIPWALL ? 2 : 0);
+  return G;
+}
+
+__device__ __forceinline__ Src3 own3(const DevBlock& B, int buf, long long off) {
+  Src3 s;
+  s.p = B.u[buf] + off;
+  s.vs = B.ncell;
+  s.ps = (long long)B.ni * B.nj;
+  s.rs = B.ni;
+  s.kind = 0;
+  s.f = 0;
+  return s;
+}
+
+__device__ __forceinline__ Src3 from_ghost3(const GPlane3& G, int f, long long off) {
+  Src3 s;
+  s.p = G.u + off;
+  s.vs = G.vs;
+  s.ps = (long long)G.ni * G.nj;
+  s.rs = G.ni;
+  s.kind = G.kind;
   s.f = f;
   return s;
 }
+
+// cell (i, j, k) with k wave-uniform, i and j inside the block
+__device__ __forceinline__ Src3 src3_k(const DevBlock* __restrict__ blocks, const DevBlock& B, int buf,
+                                       int i, int j, int k) {
+  if (k >= 0 && k < B.nk) return own3(B, buf, ((long long)k * B.nj + j) * B.ni + i);
+  const int f = k < 0 ? 4 : 5;
+  const GPlane3 G = ghost_plane3(blocks, B, buf, f, k < 0 ? -k : k - B.nk + 1);
+  return from_ghost3(G, f, ((long long)G.along * G.nj + j) * G.ni + i);
+}
+
+// column (i, j) with i wave-uniform (inside the block or up to two cells past
+// an i-face) and j inside the block; p is its plane 0 (add k * ps)
+__device__ __forceinline__ Src3 src3_i(const DevBlock* __restrict__ blocks, const DevBlock& B, int buf,
+                                       int i, int j) {
+  if (i >= 0 && i < B.ni) return own3(B, buf, (long long)j * B.ni + i);
+  const int f = i < 0 ? 0 : 1;
+  const GPlane3 G = ghost_plane3(blocks, B, buf, f, i < 0 ? -i : i - B.ni + 1);
+  return from_ghost3(G, f, (long long)j * G.ni + G.along);
+}
+
+// column (i, j) with j wave-uniform (inside the block or up to two cells past
+// a j-face) and i inside the block; p is its plane 0
+__device__ __forceinline__ Src3 src3_j(const DevBlock* __restrict__ blocks, const DevBlock& B, int buf,
+                                       int i, int j) {
+  if (j >= 0 && j < B.nj) return own3(B, buf, (long long)j * B.ni + i);
+  const int f = j < 0 ? 2 : 3;
+  const GPlane3 G = ghost_plane3(blocks, B, buf, f, j < 0 ? -j : j - B.nj + 1);
+  return from_ghost3(G, f, (long long)G.along * G.ni + i);
+}
+
+// two adjacent doubles as one 16-byte global load
+typedef double dv2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const dv2 g_cdv2;
 
 __device__ __forceinline__ void load3(const double* p, long long vs, double (&q)[5]) {
 #pragma unroll
@@ -150,12 +198,17 @@ __device__ void helper3d(const DevTile& tl, const DevBlock* __restrict__ blocks,
   const int hrow[4] = {j0 - 2, j0 - 1, j0 + ny, j0 + ny + 1};
   Src3 hs[4];
 #pragma unroll
-  for (int h = 0; h < 4; ++h) hs[h] = resolve3(blocks, B, bin, ic, hrow[h], 0);
+  for (int h = 0; h < 4; ++h) hs[h] = src3_j(blocks, B, bin, ic, hrow[h]);
   // i-halo cells: lane = 3 * row + which; which 0: i0-1, 1: i0-2, 2: i0+ncol
+  // (three wave-uniform columns, the row per lane)
   const int hr = lane / 3, hw = lane - 3 * (lane / 3);
   const bool hlane = hr < ny;
-  const int hcol = !hlane ? ic : (hw == 0 ? i0 - 1 : (hw == 1 ? i0 - 2 : i0 + nc));
-  const Src3 cs = resolve3(blocks, B, bin, hcol, hlane ? j0 + hr : j0, 0);
+  const Src3 c0 = src3_i(blocks, B, bin, i0 - 1, 0);
+  const Src3 c1 = src3_i(blocks, B, bin, i0 - 2, 0);
+  const Src3 c2 = src3_i(blocks, B, bin, i0 + nc, 0);
+  const Src3 cown = own3(B, bin, (long long)j0 * ni + ic);
+  Src3 cs = !hlane ? cown : (hw == 0 ? c0 : (hw == 1 ? c1 : c2));
+  if (hlane) cs.p += (long long)(j0 + hr) * cs.rs;
   const int cslot = hw == 0 ? 1 : (hw == 1 ? 0 : nc + 2);
   const int crow = hlane ? hr + 2 : 0;
   const bool fixrows = __builtin_amdgcn_ballot_w64(hs[0].kind != 0 || hs[1].kind != 0 ||
@@ -242,9 +295,9 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
   // ---- prologue: planes k0-2 .. k0+1 of the own column, and the right-edge
   //      pre-pass (i-face through i0+ncol-1/2 of this row, plane k0 + lane)
   double qa[5], qm1[5], q0[5], qn[5], un[5] = {0, 0, 0, 0, 0};
-  const Src3 sa = resolve3(blocks, B, bin, ic, jc, k0 - 2);
-  const Src3 sb = resolve3(blocks, B, bin, ic, jc, k0 - 1);
-  const Src3 sd = resolve3(blocks, B, bin, ic, jc, k0 + 1);
+  const Src3 sa = src3_k(blocks, B, bin, ic, jc, k0 - 2);
+  const Src3 sb = src3_k(blocks, B, bin, ic, jc, k0 - 1);
+  const Src3 sd = src3_k(blocks, B, bin, ic, jc, k0 + 1);
   load3(sa.p, sa.vs, qa);
   load3(sb.p, sb.vs, qm1);
   col_load(Q, k0, q0);
@@ -253,9 +306,25 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
   Src3 se[4];
   double ce[4][5];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    se[c] = resolve3(blocks, B, bin, ir - 2 + c, jc, ek);
-    load3(se[c].p, se[c].vs, ce[c]);
+  for (int c = 0; c < 4; ++c) se[c] = src3_i(blocks, B, bin, ir - 2 + c, jc);
+  if (ir - 2 >= 0 && ir + 1 < ni && (ni & 1) == 0 && ((uintptr_t)Q & 15) == 0) {
+    // all four inside the block: per variable, four adjacent cells of one row
+    // read as two 16-byte loads (each cache line fetched once, not once per
+    // cell).  With ni even and a full tile (ir - 2 = i0 + 62), every offset
+    // here is a multiple of 16 bytes.
+    const double* pe = Q + (long long)ek * pstr + (long long)jc * ni + (ir - 2);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      const dv2 a = *(g_cdv2*)(pe + v * ncell);
+      const dv2 b = *(g_cdv2*)(pe + v * ncell + 2);
+      ce[0][v] = a.x;
+      ce[1][v] = a.y;
+      ce[2][v] = b.x;
+      ce[3][v] = b.y;
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) load3(se[c].p + (long long)ek * se[c].ps, se[c].vs, ce[c]);
   }
   fix3(sa.kind, sa.f, B, qa);
   fix3(sb.kind, sb.f, B, qm1);
@@ -296,7 +365,7 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
         s2.kind = 0;
         s2.f = 0;
       } else {
-        s2 = resolve3(blocks, B, bin, ic, jc, k + 2);
+        s2 = src3_k(blocks, B, bin, ic, jc, k + 2);
         load3(s2.p, s2.vs, q2);
       }
     }
@@ -483,7 +552,7 @@ __global__ __launch_bounds__(64 * (NY + 1), 2) void k_stage3d(const DevTile* __r
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ntiles = *ntiles_p;
-  for (TileWalk tw = xcd_walk(ntiles, 1, 0); tw.t < tw.end; tw.t += tw.stride) {
+  for (TileWalk tw = xcd_walk_blocked(ntiles); tw.t < tw.end; tw.t += tw.stride) {
     const DevTile tl = tiles[tw.t];
     DevInstance& I = insts[tl.inst];
     if (MODE != 0 && I.stopped) continue;
