@@ -410,7 +410,7 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
   const fvk::DevInstance keep = g->hinst;
   std::vector<TileShape> cands;
   if (g->hg.ndim == 2) {
-    for (int r : {4, 8, 16, 32, 64}) {
+    for (int r : {2, 3, 4, 5, 6, 8, 12, 16, 32, 64}) {
       TileShape s;
       s.rows = r;
       s.ny = 1;
@@ -418,7 +418,7 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
     }
   } else {
     for (int y : {3, 7})
-      for (int r : {8, 16, 32, 64}) {
+      for (int r : {8, 12, 16, 20, 24, 28, 32, 40, 48, 52, 56, 64}) {
         TileShape s;
         s.rows = r;
         s.ny = y;

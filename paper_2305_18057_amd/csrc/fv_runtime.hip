@@ -108,7 +108,7 @@ int validate_and_copy(const fv_grid_desc* d, HostGrid& g) {
   return FV_OK;
 }
 
-static const int kMinRows2D = 4, kMinPlanes3D = 4, kMinNy3D = 3;
+static const int kMinRows2D = 2, kMinPlanes3D = 4, kMinNy3D = 3;
 
 long long max_tiles_of(const HostGrid& g) {
   long long t = 0;
