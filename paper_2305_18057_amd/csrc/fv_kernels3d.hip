@@ -5,16 +5,16 @@
 // and marches over n <= 64 planes k.  The workgroup has NY + 1 waves: waves
 // 0..NY-1 own the rows; wave NY (the helper) owns no cells: one plane ahead it
 // fetches the four j-halo rows and the i-halo cells of the tile, stages them
-// in LDS, and forms the j-face flux through the tile's top edge.  Per plane k:
+// in LDS, and forms the j-face flux through the tile's top edge and the i-face
+// fluxes through its right edge (one row per lane).  Per plane k:
 //   - each row wave forms the k-face flux at k-1/2 (planes k-1, k, k+1 of its
 //     column in registers, k+2 in flight), completes the residual of plane
 //     k-1, applies the stage update and stores it;
 //   - the plane is staged in LDS (rows j0-2 .. j0+ny+1, each row with the
-//     i-halo slots i0-2, i0-1, i0+ncol); every row wave forms its j-face flux
-//     at j-1/2 and its i-face flux at i-1/2 from LDS; the fluxes are exchanged
-//     through LDS and each row keeps the in-plane part of its residual for
-//     the next plane.  The right-edge i-face fluxes of a row come from a
-//     pre-pass over the tile's planes (one plane per lane).
+//     i-halo slots i0-2, i0-1, i0+ncol, i0+ncol+1); every row wave forms its
+//     j-face flux at j-1/2 and its i-face flux at i-1/2 from LDS; the fluxes
+//     are exchanged through LDS and each row keeps the in-plane part of its
+//     residual for the next plane.
 // Two workgroup barriers per plane; every face flux of the tile is formed
 // once (tile edges aside).  Loads for the next plane are issued one plane
 // ahead at addresses inside the arrays; ghost cells are resolved to their
@@ -101,6 +101,18 @@ __device__ __forceinline__ Src3 from_ghost3(const GPlane3& G, int f, long long o
   return s;
 }
 
+// per-field select (a select of whole structs can end up in scratch memory)
+__device__ __forceinline__ Src3 sel3(bool c, const Src3& a, const Src3& b) {
+  Src3 s;
+  s.p = c ? a.p : b.p;
+  s.vs = c ? a.vs : b.vs;
+  s.ps = c ? a.ps : b.ps;
+  s.rs = c ? a.rs : b.rs;
+  s.kind = c ? a.kind : b.kind;
+  s.f = c ? a.f : b.f;
+  return s;
+}
+
 // cell (i, j, k) with k wave-uniform, i and j inside the block
 __device__ __forceinline__ Src3 src3_k(const DevBlock* __restrict__ blocks, const DevBlock& B, int buf,
                                        int i, int j, int k) {
@@ -129,10 +141,6 @@ __device__ __forceinline__ Src3 src3_j(const DevBlock* __restrict__ blocks, cons
   const GPlane3 G = ghost_plane3(blocks, B, buf, f, j < 0 ? -j : j - B.nj + 1);
   return from_ghost3(G, f, (long long)G.along * G.ni + i);
 }
-
-// two adjacent doubles as one 16-byte global load
-typedef double dv2 __attribute__((ext_vector_type(2)));
-typedef __attribute__((address_space(1))) const dv2 g_cdv2;
 
 __device__ __forceinline__ void load3(const double* p, long long vs, double (&q)[5]) {
 #pragma unroll
@@ -181,7 +189,8 @@ __device__ __forceinline__ void setup_consts(const DevInstance& I, Recon<T>& rc,
 }
 
 // The helper wave: per plane, stage the j-halo rows and the i-halo cells in
-// LDS (fetched one plane ahead) and form the tile's top-edge j-face flux.
+// LDS (fetched one plane ahead) and form the tile's top-edge j-face flux and
+// right-edge i-face fluxes.
 template <int MODE, typename T, int NY, int LIM>
 __device__ void helper3d(const DevTile& tl, const DevBlock* __restrict__ blocks, const DevInstance& I,
                          int lane, Smem3<T, NY>& sm) {
@@ -193,23 +202,24 @@ __device__ void helper3d(const DevTile& tl, const DevBlock* __restrict__ blocks,
   Recon<T> rc;
   FluxK<T> K;
   setup_consts(I, rc, K);
-  const T ay = T(B.area[1]);
+  const T ax = T(B.area[0]), ay = T(B.area[1]);
   // j-halo rows of the own column: j0-2, j0-1, j0+ny, j0+ny+1
   const int hrow[4] = {j0 - 2, j0 - 1, j0 + ny, j0 + ny + 1};
   Src3 hs[4];
 #pragma unroll
   for (int h = 0; h < 4; ++h) hs[h] = src3_j(blocks, B, bin, ic, hrow[h]);
-  // i-halo cells: lane = 3 * row + which; which 0: i0-1, 1: i0-2, 2: i0+ncol
-  // (three wave-uniform columns, the row per lane)
-  const int hr = lane / 3, hw = lane - 3 * (lane / 3);
+  // i-halo cells: lane = 4 * row + which; which 0: i0-1, 1: i0-2, 2: i0+ncol,
+  // 3: i0+ncol+1 (four wave-uniform columns, the row per lane)
+  const int hr = lane >> 2, hw = lane & 3;
   const bool hlane = hr < ny;
   const Src3 c0 = src3_i(blocks, B, bin, i0 - 1, 0);
   const Src3 c1 = src3_i(blocks, B, bin, i0 - 2, 0);
   const Src3 c2 = src3_i(blocks, B, bin, i0 + nc, 0);
+  const Src3 c3 = src3_i(blocks, B, bin, i0 + nc + 1, 0);
   const Src3 cown = own3(B, bin, (long long)j0 * ni + ic);
-  Src3 cs = !hlane ? cown : (hw == 0 ? c0 : (hw == 1 ? c1 : c2));
+  Src3 cs = sel3(!hlane, cown, sel3(hw == 0, c0, sel3(hw == 1, c1, sel3(hw == 2, c2, c3))));
   if (hlane) cs.p += (long long)(j0 + hr) * cs.rs;
-  const int cslot = hw == 0 ? 1 : (hw == 1 ? 0 : nc + 2);
+  const int cslot = hw == 0 ? 1 : (hw == 1 ? 0 : (hw == 2 ? nc + 2 : nc + 3));
   const int crow = hlane ? hr + 2 : 0;
   const bool fixrows = __builtin_amdgcn_ballot_w64(hs[0].kind != 0 || hs[1].kind != 0 ||
                                                     hs[2].kind != 0 || hs[3].kind != 0) != 0;
@@ -252,6 +262,21 @@ __device__ void helper3d(const DevTile& tl, const DevBlock* __restrict__ blocks,
 #pragma unroll
       for (int v = 0; v < 5; ++v) sm.f[ny][v][lane] = G[v];
     }
+    // right-edge i-face at i0+ncol-1/2 of every row (lane = row) from slots
+    // ncol .. ncol+3
+    {
+      const int er = lane < ny ? lane : 0;
+      T qL[5], qR[5], G[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v)
+        face_states<LIM>(rc, sm.q[er + 2][v][nc], sm.q[er + 2][v][nc + 1], sm.q[er + 2][v][nc + 2],
+                         sm.q[er + 2][v][nc + 3], qL[v], qR[v]);
+      roe_flux<T, 3, 0>(qL, qR, nullptr, ax, K, G);
+      if (lane < ny) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm.edge[lane][v][r] = G[v];
+      }
+    }
     __syncthreads();
   }
 }
@@ -267,7 +292,6 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
   const bool act = lane < nc;
   const int ic = act ? i0 + lane : ni - 1;
   const int last = nc - 1;
-  const int ir = i0 + nc;
   constexpr int bin = MODE == 0 ? 0 : MODE - 1;
   constexpr int bout = MODE == 1 ? 1 : (MODE == 2 ? 2 : 0);
   Recon<T> rc;
@@ -292,8 +316,8 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
     for (int v = 0; v < 5; ++v) q[v] = ldo3(p + v * ncell, cb);
   };
 
-  // ---- prologue: planes k0-2 .. k0+1 of the own column, and the right-edge
-  //      pre-pass (i-face through i0+ncol-1/2 of this row, plane k0 + lane)
+  // ---- prologue: planes k0-2 .. k0+1 of the own column (the right-edge
+  //      i-face of each plane comes from the helper wave)
   double qa[5], qm1[5], q0[5], qn[5], un[5] = {0, 0, 0, 0, 0};
   const Src3 sa = src3_k(blocks, B, bin, ic, jc, k0 - 2);
   const Src3 sb = src3_k(blocks, B, bin, ic, jc, k0 - 1);
@@ -302,44 +326,9 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
   load3(sb.p, sb.vs, qm1);
   col_load(Q, k0, q0);
   load3(sd.p, sd.vs, qn);
-  const int ek = k0 + min(lane, n - 1);
-  Src3 se[4];
-  double ce[4][5];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) se[c] = src3_i(blocks, B, bin, ir - 2 + c, jc);
-  if (ir - 2 >= 0 && ir + 1 < ni && (ni & 1) == 0 && ((uintptr_t)Q & 15) == 0) {
-    // all four inside the block: per variable, four adjacent cells of one row
-    // read as two 16-byte loads (each cache line fetched once, not once per
-    // cell).  With ni even and a full tile (ir - 2 = i0 + 62), every offset
-    // here is a multiple of 16 bytes.
-    const double* pe = Q + (long long)ek * pstr + (long long)jc * ni + (ir - 2);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      const dv2 a = *(g_cdv2*)(pe + v * ncell);
-      const dv2 b = *(g_cdv2*)(pe + v * ncell + 2);
-      ce[0][v] = a.x;
-      ce[1][v] = a.y;
-      ce[2][v] = b.x;
-      ce[3][v] = b.y;
-    }
-  } else {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) load3(se[c].p + (long long)ek * se[c].ps, se[c].vs, ce[c]);
-  }
   fix3(sa.kind, sa.f, B, qa);
   fix3(sb.kind, sb.f, B, qm1);
   fix3(sd.kind, sd.f, B, qn);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) fix3(se[c].kind, se[c].f, B, ce[c]);
-  if (rowact) {
-    T qL[5], qR[5], G[5];
-#pragma unroll
-    for (int v = 0; v < 5; ++v)
-      face_states<LIM>(rc, T(ce[0][v]), T(ce[1][v]), T(ce[2][v]), T(ce[3][v]), qL[v], qR[v]);
-    roe_flux<T, 3, 0>(qL, qR, nullptr, ax, K, G);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) sm.edge[w][v][lane] = G[v];
-  }
   T epm1[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
