@@ -1,6 +1,7 @@
 /*
  * Plain FP64 CPU reference of the explicit finite-volume Euler residual and
- * the SSP-RK3 time update on structured multi-block grids.
+ * the explicit RK time update (SSP-RK3, and the paper's 2- and 4-stage
+ * second-order schemes) on structured multi-block grids.
  *
  * TEST INFRASTRUCTURE ONLY.  The test-suite, the package smoke check and the
  * benchmark's CPU-baseline leg load it; the product path never does.  It
@@ -20,7 +21,8 @@
  *   ghost cells refreshed before every RK substep .. Sec. 4 (workflow) and Sec. 5 (ghost extrapolation)
  *   cell-update counting (ssspnt) ................... Sec. 7, Eq. (ssspnt)
  * Readings where the paper is silent (named at each function): Roe's flux with
- * Harten's entropy fix, minmod limiter, SSP-RK3 in Shu-Osher form, a global
+ * Harten's entropy fix, minmod limiter, SSP-RK3 in Shu-Osher form and the
+ * coefficients of the 2- and 4-stage second-order schemes, a global
  * CFL time step from U^n, the ghost rules per boundary kind, an RMS residual
  * norm.
  */
@@ -570,6 +572,116 @@ static void rk3_step(orc_grid* G, const orc_params* P, double dt) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* Explicit RK in the Butcher form of Sec. 3.2, Eq. (runge_kutta), with R  */
+/* per unit volume (Eq. spatial_residual):                                  */
+/*   U^i     = U^n - dt sum_{j<i} a_ij R(U^j)/|Omega|,   i = 1..s          */
+/*   U^{n+1} = U^n - dt sum_i   b_i  R(U^i)/|Omega|.                        */
+/* The paper uses second-order 2-stage and 4-stage schemes and leaves the   */
+/* coefficients to a reference.  Taken here (a reading):                    */
+/*   2 stages: a21 = 1/2,                     b = (0, 1)                    */
+/*   4 stages: a21 = 1/4, a32 = 1/3, a43 = 1/2, b = (0, 0, 0, 1)            */
+/* Every stage residual R(U^i) is kept, as the form is written; ghosts are  */
+/* refreshed before each residual.  Norms come from R(U^1) = R(U^n).        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int s;
+  double a[4][4];
+  double b[4];
+} tableau_t;
+
+static int tableau_of(int rk, tableau_t* T) {
+  memset(T, 0, sizeof(*T));
+  if (rk == 2) {
+    T->s = 2;
+    T->a[1][0] = 0.5;
+    T->b[1] = 1.0;
+    return 1;
+  }
+  if (rk == 4) {
+    T->s = 4;
+    T->a[1][0] = 0.25;
+    T->a[2][1] = 1.0 / 3.0;
+    T->a[3][2] = 0.5;
+    T->b[3] = 1.0;
+    return 1;
+  }
+  if (rk == 103) {
+    /* SSP-RK3 written in this form (a check of the form against the
+     * Shu-Osher arrangement above; selected by tests only) */
+    T->s = 3;
+    T->a[1][0] = 1.0;
+    T->a[2][0] = 0.25;
+    T->a[2][1] = 0.25;
+    T->b[0] = 1.0 / 6.0;
+    T->b[1] = 1.0 / 6.0;
+    T->b[2] = 2.0 / 3.0;
+    return 1;
+  }
+  return 0;
+}
+
+static int butcher_step(orc_grid* G, const orc_params* P, double dt, const tableau_t* T) {
+  const int nd = G->ndim, nv = G->nv, s = T->s;
+  double** rs = (double**)calloc((size_t)G->nblocks * (size_t)s, sizeof(double*));
+  if (!rs) return ORC_E_NOMEM;
+  int st = ORC_OK;
+  for (int bi = 0; bi < G->nblocks && st == ORC_OK; ++bi) {
+    blk_t* b = &G->b[bi];
+    memcpy(b->qn, b->q, sizeof(double) * (size_t)nv * (size_t)b->npad);
+    for (int i = 0; i < s; ++i) {
+      rs[bi * s + i] = (double*)malloc(sizeof(double) * (size_t)nv * (size_t)b->ncell);
+      if (!rs[bi * s + i]) st = ORC_E_NOMEM;
+    }
+  }
+  for (int i = 0; i < s && st == ORC_OK; ++i) {
+    /* stage state U^i (U^1 = U^n, already in q) */
+    if (i > 0) {
+      for (int bi = 0; bi < G->nblocks; ++bi) {
+        blk_t* b = &G->b[bi];
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int k = 0; k < b->nk; ++k)
+          for (int j = 0; j < b->nj; ++j)
+            for (int ii = 0; ii < b->ni; ++ii) {
+              double vol = cell_vol(b, nd, ii, j, k);
+              i64 c = cidx(b, ii, j, k), p = pidx(b, ii, j, k);
+              for (int v = 0; v < nv; ++v) {
+                double acc = 0.0;
+                for (int jj = 0; jj < i; ++jj) acc += T->a[i][jj] * rs[bi * s + jj][v * b->ncell + c];
+                b->q[v * b->npad + p] = b->qn[v * b->npad + p] - dt * acc / vol;
+              }
+            }
+      }
+    }
+    residual_all(G, P, NULL);
+    if (i == 0) norms_of_residual(G, P, G->norms, &G->norm);
+    for (int bi = 0; bi < G->nblocks; ++bi) {
+      blk_t* b = &G->b[bi];
+      memcpy(rs[bi * s + i], b->res, sizeof(double) * (size_t)nv * (size_t)b->ncell);
+    }
+  }
+  if (st == ORC_OK) {
+    for (int bi = 0; bi < G->nblocks; ++bi) {
+      blk_t* b = &G->b[bi];
+#pragma omp parallel for collapse(2) schedule(static)
+      for (int k = 0; k < b->nk; ++k)
+        for (int j = 0; j < b->nj; ++j)
+          for (int ii = 0; ii < b->ni; ++ii) {
+            double vol = cell_vol(b, nd, ii, j, k);
+            i64 c = cidx(b, ii, j, k), p = pidx(b, ii, j, k);
+            for (int v = 0; v < nv; ++v) {
+              double acc = 0.0;
+              for (int jj = 0; jj < s; ++jj) acc += T->b[jj] * rs[bi * s + jj][v * b->ncell + c];
+              b->q[v * b->npad + p] = b->qn[v * b->npad + p] - dt * acc / vol;
+            }
+          }
+    }
+  }
+  for (int i = 0; i < G->nblocks * s; ++i) free(rs[i]);
+  free(rs);
+  return st;
+}
+
+/* ------------------------------------------------------------------------ */
 /* public entry points                                                      */
 /* ------------------------------------------------------------------------ */
 orc_grid* orc_create(int ndim, int nblocks, const orc_block_desc* desc, double gamma) {
@@ -725,6 +837,7 @@ void orc_get_info(const orc_grid* G, orc_info* info) {
  * residual norm (from R(U^n)) is at most drop_tol times the first step's. */
 int orc_run(orc_grid* G, const orc_params* P, long long nsteps, double drop_tol, orc_info* info,
             double* dt_hist) {
+  if (P->rk != 0 && P->rk != 2 && P->rk != 3 && P->rk != 4 && P->rk != 103) return ORC_E_INVAL;
   int status = G->physical ? ORC_OK : ORC_E_NONPHYSICAL;
   for (long long s = 0; s < nsteps && status == ORC_OK; ++s) {
     double dt = P->dt_fixed > 0.0 ? P->dt_fixed : P->cfl * G->raw_min;
@@ -736,7 +849,17 @@ int orc_run(orc_grid* G, const orc_params* P, long long nsteps, double drop_tol,
         last = 1;
       }
     }
-    rk3_step(G, P, dt);
+    if (P->rk == 2 || P->rk == 4 || P->rk == 103) {
+      tableau_t T;
+      tableau_of(P->rk, &T);
+      const int e = butcher_step(G, P, dt, &T);
+      if (e != ORC_OK) {
+        status = e;
+        break;
+      }
+    } else {
+      rk3_step(G, P, dt);
+    }
     G->t = last ? P->t_end : G->t + dt;
     G->dt_last = dt;
     if (dt_hist) dt_hist[s] = dt;

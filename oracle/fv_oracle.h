@@ -36,6 +36,9 @@ typedef struct {
   int limiter;
   double eps, kappa, entropy_fix;
   double qref[5];
+  int rk;                /* 3 (or 0): SSP-RK3; 2, 4: the 2- and 4-stage second-order
+                            schemes of Sec. 3.2 in Butcher form; 103: SSP-RK3 in
+                            Butcher form (tests) */
 } orc_params;
 
 typedef struct {

@@ -45,7 +45,7 @@ class _Block(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("cfl", C.c_double), ("dt_fixed", C.c_double), ("t_end", C.c_double),
                 ("limiter", C.c_int), ("eps", C.c_double), ("kappa", C.c_double),
-                ("entropy_fix", C.c_double), ("qref", C.c_double * 5)]
+                ("entropy_fix", C.c_double), ("qref", C.c_double * 5), ("rk", C.c_int)]
 
 
 class _Info(C.Structure):
@@ -92,7 +92,7 @@ def _ptr(a: np.ndarray):
 def make_params(p) -> _Params:
     q = list(p.qref) + [1.0] * (5 - len(p.qref))
     return _Params(p.cfl, p.dt_fixed, p.t_end, p.limiter, p.eps, p.kappa, p.entropy_fix,
-                   (C.c_double * 5)(*q[:5]))
+                   (C.c_double * 5)(*q[:5]), getattr(p, "rk", 3))
 
 
 def num_threads() -> int:

@@ -83,6 +83,7 @@ class Params:
     kappa: float = -1.0
     entropy_fix: float = 0.1
     qref: Sequence[float] = (1.0, 1.0, 1.0, 1.0, 1.0)
+    rk: int = 3  # 3: SSP-RK3; 2, 4: the 2- and 4-stage second-order schemes
 
 
 @dataclass

@@ -350,6 +350,75 @@ def test_rk3_amplification_entropy_wave(orc, limiter, kappa):
     assert np.max(np.abs(p - p0)) <= 1e-13
 
 
+# The paper's 2- and 4-stage second-order schemes (Sec. 3.2, Eq. runge_kutta,
+# coefficients a reading): on the same linear special case one step
+# multiplies a mode by 1 + z + z^2/2 (2 stages) and by
+# 1 + z + z^2/2 + z^3/6 + z^4/24 (4 stages: a21 = 1/4, a32 = 1/3, a43 = 1/2).
+@pytest.mark.parametrize("rk", [2, 4])
+@pytest.mark.parametrize("limiter,kappa", [(C.FIRST_ORDER, -1.0), (C.UNLIMITED, -1.0)])
+def test_rk_2_4_amplification_entropy_wave(orc, rk, limiter, kappa):
+    N, k = 32, 3
+    h = 1.0 / N
+    u0, p0, amp = 0.7, 1.0, 1e-2
+    xi = np.arange(N)
+    rho = 1.0 + amp * np.cos(2 * math.pi * k * xi / N)
+    U = C.conserved(rho[None, :], [np.full((1, N), u0), np.zeros((1, N))], np.full((1, N), p0))[:, None]
+    bc = [C.BC(C.PERIODIC)] * 6
+    blk = C.Block(N, 1, 1, None, None, (0, 0, 0), (h, h, 1.0), bc)
+    nu = 0.4
+    dt = nu * h / u0
+    prm = C.Params(dt_fixed=dt, limiter=limiter, kappa=kappa, rk=rk)
+    case = C.Case("wave", 2, [blk], [U], prm, 1)
+    g = orc.OracleGrid(case)
+    g.run(prm, 1)
+    out = g.get_state().reshape(4, N)
+    th = 2 * math.pi * k / N
+    e = np.exp(-1j * th)
+    s = 1.0 if limiter == C.FIRST_ORDER else 1.0 + 0.25 * ((1 - kappa) * (1 - e) + (1 + kappa) * (1 / e - 1))
+    z = -nu * s * (1 - e)
+    Gz = 1 + z + z * z / 2 if rk == 2 else 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+    expect = 1.0 + amp * np.real(Gz * np.exp(1j * th * xi))
+    assert np.max(np.abs(out[0] - expect)) <= 1e-14
+
+
+def test_butcher_form_matches_shu_osher(orc):
+    """SSP-RK3 written in the Butcher form of Eq. (runge_kutta) (a21 = 1,
+    a31 = a32 = 1/4, b = (1/6, 1/6, 2/3)) and in the Shu-Osher form agree to
+    rounding: a check of the general-form stepping the 2- and 4-stage
+    schemes use, with off-diagonal and multi-term sums."""
+    case = C.vortex_2d(32, 16)
+    a = orc.OracleGrid(case)
+    ia = a.run(case.params, 5)
+    b = orc.OracleGrid(case)
+    pb = C.Params(**{**case.params.__dict__, "rk": 103})
+    ib = b.run(pb, 5)
+    Ua, Ub = a.get_state(), b.get_state()
+    # the CFL steps follow the states, so t agrees to rounding too
+    assert ia["steps"] == ib["steps"] == 5 and abs(ia["t"] - ib["t"]) <= 1e-14 * ia["t"]
+    assert np.max(np.abs(Ua - Ub)) <= 1e-13 * np.max(np.abs(Ua))
+
+
+def test_rk_schemes_converge_to_the_same_solution(orc):
+    """The 2-, 3- and 4-stage schemes are consistent discretisations in time:
+    at a fixed final time their states differ by O(dt^2), so halving dt cuts
+    the difference to the SSP-RK3 state by about four."""
+    diffs = {2: [], 4: []}
+    for n in (20, 40):
+        base = C.vortex_2d(32, 16, noise=0.0)
+        dt = 0.5 / n
+        out = {}
+        for rk in (2, 3, 4):
+            prm = C.Params(**{**base.params.__dict__, "dt_fixed": dt, "rk": rk, "limiter": C.UNLIMITED})
+            g = orc.OracleGrid(base)
+            g.run(prm, n)
+            out[rk] = g.get_state()
+        for rk in (2, 4):
+            diffs[rk].append(np.max(np.abs(out[rk] - out[3])))
+    for rk in (2, 4):
+        ratio = diffs[rk][0] / diffs[rk][1]
+        assert 3.0 <= ratio <= 5.5, (rk, diffs[rk])
+
+
 def test_entropy_wave_3d_invariance(orc):
     case = C.blobs_case(16, nblobs=3, seed=7, mach=2.0, nsteps=5)
     g = orc.OracleGrid(case)
