@@ -120,7 +120,7 @@ def profile_record(kernel: str, workload: str, ndim: int):
 # --------------------------------------------------------------------------
 # single-grid timing
 # --------------------------------------------------------------------------
-def time_grid(fv, case, params, steps, warmup, tune_cache=None):
+def time_grid(fv, case, params, steps, warmup, tune_cache=None, stage_times=True):
     import torch
     g = fv.Grid(case)
     g.set_state(case.state_flat())
@@ -140,10 +140,36 @@ def time_grid(fv, case, params, steps, warmup, tune_cache=None):
     wall = time.perf_counter() - t0
     dev_ms = e0.elapsed_time(e1)
     # per-kernel timing pass over the same number of steps (HIP events around
-    # every stage launch on the grid's stream)
-    _, stage_ms = g.step_timed(params, steps)
+    # every stage launch on the grid's stream; SSP-RK3 only)
+    stage_ms = g.step_timed(params, steps)[1] if stage_times else None
     st = g.stats()
     return g, info, wall, dev_ms, stage_ms, st
+
+
+def bench_rk_schemes(fv, cases, tune_cache, steps2d):
+    """The paper's 2- and 4-stage second-order schemes beside SSP-RK3 on the
+    2D inlet and 3D blobs grids (FP64): per-step time, cell-updates/s and
+    ssspnt with the substeps counted (Sec. 7, Eq. ssspnt), the measure by
+    which the paper compares its RK2 and RK4 runs."""
+    out = {}
+    for wl, mk, steps in (("inlet_2d", cases.inlet_2d, steps2d), ("blobs_3d", cases.blobs_3d, 20)):
+        c = mk()
+        rows = {}
+        for rk, nst in ((2, 2), (3, 3), (4, 4)):
+            p = cases.Params(**{**c.params.__dict__, "precision": cases.FP64, "rk": rk})
+            gx, ix, wx, dx, _, stx = time_grid(fv, c, p, steps, 5, tune_cache, stage_times=False)
+            rows[f"rk{rk}"] = dict(stages=nst, ms_per_step=round(dx / steps, 5),
+                                   cell_updates_per_s=round(c.ncells * steps / (dx * 1e-3), 1),
+                                   ssspnt=round(1e-6 * c.ncells * nst * steps / (dx * 1e-3), 2))
+            gx.close()
+            del gx
+        base = rows["rk3"]["ssspnt"]
+        for r in rows.values():
+            r["ssspnt_vs_rk3"] = round(r["ssspnt"] / base, 4)
+        out[wl] = dict(cells=c.ncells, steps=steps, **rows)
+        log(f"[bench] rk schemes {wl}: " + ", ".join(
+            f"{k} {v['ms_per_step']*1e3:.1f} us/step ssspnt {v['ssspnt']:.0f}" for k, v in rows.items()))
+    return out
 
 
 def roofline_of(case, stage_ms, steps, workload, fp32=False):
@@ -561,6 +587,7 @@ def main():
                 f"rows={stx['tile_rows']} ny={stx['tile_ny']}")
             gx.close()
             del gx
+        extra["rk_schemes"] = bench_rk_schemes(fv, cases, tune_cache, args.steps)
         extra["batched_64"] = bench_batched(fv, cases)
         b = extra["batched_64"]
         log(f"[bench]   batched {b['value']/1e9:.3f} G cell-updates/s vs sequential "

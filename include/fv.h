@@ -123,7 +123,14 @@ typedef struct fv_params {
   int limiter;         /* FV_LIM_MINMOD, FV_LIM_NONE, FV_FIRST_ORDER */
   double eps, kappa;   /* MUSCL parameters of Eq. (flux) */
   double entropy_fix;  /* Harten's delta / c on the acoustic waves (0: off) */
-  int rk;              /* 3: SSP-RK3 (the only scheme provided) */
+  int rk;              /* explicit RK of Sec. 3.2, Eq. (runge_kutta):
+                          3 (or 0): SSP-RK3 in Shu-Osher form;
+                          2: the 2-stage second-order scheme, a21 = 1/2, b = (0, 1);
+                          4: the 4-stage second-order scheme, a21 = 1/4, a32 = 1/3,
+                             a43 = 1/2, b = (0, 0, 0, 1)
+                          (the coefficients are a reading: the paper cites them).
+                          Other values: FV_E_UNSUPPORTED.  The server and
+                          fv_step_timed take 3 only. */
   double qref[5];      /* reference magnitudes of the combined residual norm
                           (0 entries count as 1) */
 } fv_params;
@@ -189,10 +196,11 @@ int fv_step(fv_grid* g, const fv_params* p, int nsteps, fv_step_info* info);
 int fv_solve(fv_grid* g, const fv_params* p, double drop_tol, long long max_steps,
              fv_step_info* info);
 
-/* Measurement variant of fv_step: the same kernels launched one by one (no
- * graph) with HIP events around each launch on the grid's stream.
- * stage_ms[0..2] receives the summed device time of the three RK stage
- * kernels and stage_ms[3] that of the step-end reductions, over the call. */
+/* Measurement variant of fv_step (SSP-RK3 only): the same kernels launched
+ * one by one (no graph) with HIP events around each launch on the grid's
+ * stream.  stage_ms[0..2] receives the summed device time of the three RK
+ * stage kernels and stage_ms[3] that of the step-end reductions, over the
+ * call. */
 int fv_step_timed(fv_grid* g, const fv_params* p, int nsteps, fv_step_info* info,
                   double stage_ms[4]);
 
@@ -239,7 +247,9 @@ typedef struct fv_server fv_server;
 int fv_server_create(const fv_server_desc* desc, fv_server** out);
 /* Queue a solve (thread-safe): grid, initial state (host), parameters,
  * stop rule (drop <= drop_tol or max_steps steps).  The descriptor and U0
- * are copied.  FV_E_NOMEM if the request can never fit the arena. */
+ * are copied.  FV_E_NOMEM if the request can never fit the arena;
+ * FV_E_UNSUPPORTED for rk other than 3 (resident instances share one stage
+ * sequence). */
 int fv_submit(fv_server* s, const fv_grid_desc* desc, const double* U0, const fv_params* p,
               double drop_tol, long long max_steps, unsigned long long* ticket);
 /* FV_PENDING until done; then the final state (host, cap_doubles >= state

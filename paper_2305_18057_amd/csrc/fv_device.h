@@ -43,6 +43,8 @@ struct DevInstance {
   long long step_limit;
   long long ncells;
   int limiter, ndim, nv, ntiles;
+  int rk, rk_pad;
+  double rk_c[4];           // stage coefficients (see StageKind)
   double* part;             // [kPartStride][ntiles], value-major
   // marching state (device)
   double t, dt, dt_last, raw_min, norm_first, norm, drop;
@@ -60,6 +62,41 @@ struct DevTile {
   int i0, j0, k0, n;
   int ny, pad0, pad1, pad2;
 };
+
+// --------------------------------------------------------------------------
+// Stage kinds of the stage kernels (template MODE):
+//   0  residual only
+//   SSP-RK3 in Shu-Osher form (Sec. 3.2; a reading):
+//   1  U^n -> a:  a = U^n + c0 dt L(U^n)        (c0 = 1)
+//   2  a -> b:    b = 3/4 U^n + 1/4 (a + dt L(a))
+//   3  b -> U^n:  U^{n+1} = 1/3 U^n + 2/3 (b + dt L(b))
+//   The 2- and 4-stage second-order schemes (Sec. 3.2, Eq. runge_kutta with
+//   one nonzero a per row and b = e_s), stage k writing U^n + c_k dt L(input):
+//   1  U^n -> a   (c0: 1/2 or 1/4)
+//   4  a -> b     (c1 = 1/3)
+//   5  b -> a     (c2 = 1/2)
+//   6  a -> U^n   (c3 = 1, last)
+// with L(U) = -R(U)/|Omega|.  Stage 1 also sums the residual norms of U^n;
+// the last stage (3 or 6) forms the per-cell CFL limits of U^{n+1}.
+// --------------------------------------------------------------------------
+template <int MODE>
+struct StageKind {
+  static constexpr int bin = MODE <= 1 ? 0 : (MODE == 2 || MODE == 4 || MODE == 6 ? 1 : 2);
+  static constexpr int bout = MODE == 1 || MODE == 5 ? 1 : (MODE == 2 || MODE == 4 ? 2 : 0);
+  static constexpr bool reads_un = MODE >= 2;        // U^n read pointwise
+  static constexpr bool norms = MODE <= 1;           // residual norms of U^n
+  static constexpr bool cfl = MODE == 3 || MODE == 6;
+  static constexpr bool low = MODE >= 4;             // U^n + c dt L(input)
+  static constexpr int coef = MODE == 1 ? 0 : (MODE == 4 ? 1 : (MODE == 5 ? 2 : (MODE == 6 ? 3 : -1)));
+};
+
+// dt times the stage coefficient (exactly dt where the coefficient is 1)
+template <int MODE>
+__device__ __forceinline__ double stage_dt(const DevInstance& I) {
+  constexpr int c = StageKind<MODE>::coef;
+  if constexpr (c < 0) return I.dt;
+  else return I.dt * I.rk_c[c];
+}
 
 // --------------------------------------------------------------------------
 // memory access: the state and node arrays are global memory; their pointers

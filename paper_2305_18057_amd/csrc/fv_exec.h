@@ -29,6 +29,7 @@ struct StepPlan {
   const int* active = nullptr;  // device list of instance indices (nullptr: 0..ninst-1)
   int ninst = 0;                // finalize grid (the capacity when ninst_dev is set)
   const int* ninst_dev = nullptr;  // device-resident live instance count
+  int rk = 3;                   // 3: SSP-RK3; 2, 4: the 2- and 4-stage second-order schemes
   std::vector<LaunchSet> sets;
 };
 
@@ -36,14 +37,14 @@ class GraphCache {
  public:
   ~GraphCache() { clear(); }
   void clear();
-  hipGraphExec_t get(int key) const {
+  hipGraphExec_t get(long long key) const {
     auto it = m_.find(key);
     return it == m_.end() ? nullptr : it->second;
   }
-  void put(int key, hipGraphExec_t e) { m_[key] = e; }
+  void put(long long key, hipGraphExec_t e) { m_[key] = e; }
 
  private:
-  std::map<int, hipGraphExec_t> m_;
+  std::map<long long, hipGraphExec_t> m_;
 };
 
 int graph_chunk();                       // steps per captured graph

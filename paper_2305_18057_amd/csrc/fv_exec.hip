@@ -84,9 +84,16 @@ int enqueue_cfl(const StepPlan& P, hipStream_t st) {
   return FV_OK;
 }
 
+// stage kinds of one step of each scheme (StageKind in fv_device.h)
+static const int kStages3[] = {1, 2, 3};
+static const int kStages2[] = {1, 6};
+static const int kStages4[] = {1, 4, 5, 6};
+
 static int enqueue_one_step(const StepPlan& P, int fp32, hipStream_t st) {
-  for (int m = 1; m <= 3; ++m) {
-    const int e = enqueue_stage(P, m, fp32, nullptr, st);
+  const int* modes = P.rk == 2 ? kStages2 : (P.rk == 4 ? kStages4 : kStages3);
+  const int ns = P.rk == 2 ? 2 : (P.rk == 4 ? 4 : 3);
+  for (int m = 0; m < ns; ++m) {
+    const int e = enqueue_stage(P, modes[m], fp32, nullptr, st);
     if (e) return e;
   }
   const hipError_t e = fvk::launch_finalize(st, P.insts, P.active, P.ninst, P.ninst_dev);
@@ -105,7 +112,10 @@ int enqueue_steps(const StepPlan& P, int fp32, int nsteps, hipStream_t st, Graph
     }
     return FV_OK;
   }
-  const int key = (variant << 22) | (nsteps << 1) | (fp32 ? 1 : 0);
+  // a captured graph depends on the step count, the precision, the scheme
+  // and the caller's variant
+  const long long key = ((long long)(unsigned)variant << 32) | ((long long)P.rk << 28) |
+                        ((long long)nsteps << 1) | (fp32 ? 1 : 0);
   hipGraphExec_t ex = cache->get(key);
   if (!ex) {
     hipStream_t cs;

@@ -224,8 +224,9 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
   const bool act = lane < nc;
   const int ic = act ? i0 + lane : ni - 1;  // safe column for idle lanes
   const int last = nc - 1;                  // lane owning the tile's right edge
-  constexpr int bin = MODE == 0 ? 0 : MODE - 1;
-  constexpr int bout = MODE == 1 ? 1 : (MODE == 2 ? 2 : 0);
+  using SK = StageKind<MODE>;
+  constexpr int bin = SK::bin;
+  constexpr int bout = SK::bout;
   const long long ncell = B.ncell;
   const double* __restrict__ Q = B.u[bin];
   const double* __restrict__ Un = B.u[0];
@@ -246,7 +247,7 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
   K.efix = T(I.efix);
   K.iefix = T(I.efix > 0.0 ? 1.0 / I.efix : 0.0);
   const double gamma = I.gamma;
-  const double dt = I.dt;
+  const double dt = stage_dt<MODE>(I);
   const double areaI = B.area[0], areaJ = B.area[1], uvol = B.vol;
 
   // ---- halo lanes: 0 -> column i0-1, 1 -> i0-2, 2 -> i0+ncol (others: own column)
@@ -501,10 +502,14 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
           double out[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const double us = fmad(-f, R[v], qm1[v]);
-            if (MODE == 1) out[v] = us;
-            else if (MODE == 2) out[v] = fmad(0.75, un[v], 0.25 * us);
-            else out[v] = fmad(1.0 / 3.0, un[v], (2.0 / 3.0) * us);
+            if constexpr (SK::low) {
+              out[v] = fmad(-f, R[v], un[v]);
+            } else {
+              const double us = fmad(-f, R[v], qm1[v]);
+              if (MODE == 1) out[v] = us;
+              else if (MODE == 2) out[v] = fmad(0.75, un[v], 0.25 * us);
+              else out[v] = fmad(1.0 / 3.0, un[v], (2.0 / 3.0) * us);
+            }
             sto(Uout + v * ncell + ro, cb, out[v]);
           }
           if (MODE == 1) {
@@ -514,7 +519,7 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
               nacc[v] = fmad(rv, rv, nacc[v]);
             }
           }
-          if (MODE == 3) {
+          if constexpr (SK::cfl) {
             double Sb[2][3];
             if constexpr (CURV) {
               Sb[0][0] = 0.5 * ((y0 - ym) + (y0r - ymr));
@@ -535,7 +540,7 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
     }
     // U^n of row j, for the update at the next row
     if constexpr (!LASTR) {
-      if (MODE >= 2) row_load(Un, j, un);
+      if constexpr (SK::reads_un) row_load(Un, j, un);
     }
     // ---- (5) the right neighbours' i-face fluxes: pending part of row j
     if constexpr (!LASTR) {
@@ -597,7 +602,7 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
       part[4 * ps] = 0.0;
     }
   }
-  if (MODE == 3) {
+  if (SK::cfl) {
     const double m = wave_min(dmin);
     const int b = wave_or(bad);
     if (lane == 0) {
@@ -699,47 +704,43 @@ __global__ __launch_bounds__(256) void k_cfl2d(const DevTile* __restrict__ tiles
 hipError_t launch_stage2d(int mode, int fp32, int grid, int block, hipStream_t s, const DevTile* tiles,
                           const int* ntiles, const DevBlock* blocks, DevInstance* insts,
                           double* rout) {
+  if (mode < 0 || mode > 6) return hipErrorInvalidValue;
 #define FV_L2(M, T) hipLaunchKernelGGL((k_stage2d<M, T>), dim3(grid), dim3(block), 0, s, tiles, ntiles, blocks, insts, rout)
-  if (fp32) {
-    switch (mode) {
-      case 0: FV_L2(0, float); break;
-      case 1: FV_L2(1, float); break;
-      case 2: FV_L2(2, float); break;
-      default: FV_L2(3, float); break;
-    }
-  } else {
-    switch (mode) {
-      case 0: FV_L2(0, double); break;
-      case 1: FV_L2(1, double); break;
-      case 2: FV_L2(2, double); break;
-      default: FV_L2(3, double); break;
-    }
+#define FV_L2_ALL(T)              \
+  switch (mode) {                 \
+    case 0: FV_L2(0, T); break;   \
+    case 1: FV_L2(1, T); break;   \
+    case 2: FV_L2(2, T); break;   \
+    case 3: FV_L2(3, T); break;   \
+    case 4: FV_L2(4, T); break;   \
+    case 5: FV_L2(5, T); break;   \
+    default: FV_L2(6, T); break;  \
   }
+  if (fp32) {
+    FV_L2_ALL(float)
+  } else {
+    FV_L2_ALL(double)
+  }
+#undef FV_L2_ALL
 #undef FV_L2
   return hipGetLastError();
 }
-
 hipError_t launch_cfl2d(int grid, int block, hipStream_t s, const DevTile* tiles, const int* ntiles,
                         const DevBlock* blocks, DevInstance* insts) {
   hipLaunchKernelGGL(k_cfl2d, dim3(grid), dim3(block), 0, s, tiles, ntiles, blocks, insts);
   return hipGetLastError();
 }
-
 const void* stage2d_kernel_ptr(int mode, int fp32) {
-  if (fp32) {
-    switch (mode) {
-      case 0: return (const void*)&k_stage2d<0, float>;
-      case 1: return (const void*)&k_stage2d<1, float>;
-      case 2: return (const void*)&k_stage2d<2, float>;
-      default: return (const void*)&k_stage2d<3, float>;
-    }
-  }
-  switch (mode) {
-    case 0: return (const void*)&k_stage2d<0, double>;
-    case 1: return (const void*)&k_stage2d<1, double>;
-    case 2: return (const void*)&k_stage2d<2, double>;
-    default: return (const void*)&k_stage2d<3, double>;
-  }
+  static const void* const kf[7] = {(const void*)&k_stage2d<0, float>, (const void*)&k_stage2d<1, float>,
+                                    (const void*)&k_stage2d<2, float>, (const void*)&k_stage2d<3, float>,
+                                    (const void*)&k_stage2d<4, float>, (const void*)&k_stage2d<5, float>,
+                                    (const void*)&k_stage2d<6, float>};
+  static const void* const kd[7] = {(const void*)&k_stage2d<0, double>, (const void*)&k_stage2d<1, double>,
+                                    (const void*)&k_stage2d<2, double>, (const void*)&k_stage2d<3, double>,
+                                    (const void*)&k_stage2d<4, double>, (const void*)&k_stage2d<5, double>,
+                                    (const void*)&k_stage2d<6, double>};
+  const int m = mode < 0 ? 0 : (mode > 6 ? 6 : mode);
+  return fp32 ? kf[m] : kd[m];
 }
 
 }  // namespace fvk

@@ -197,7 +197,7 @@ __device__ void helper3d(const DevTile& tl, const DevBlock* __restrict__ blocks,
   const DevBlock& B = blocks[tl.blk];
   const int ni = B.ni;
   const int i0 = tl.i0, j0 = tl.j0, k0 = tl.k0, n = tl.n, nc = tl.ncol, ny = tl.ny;
-  constexpr int bin = MODE == 0 ? 0 : MODE - 1;
+  constexpr int bin = StageKind<MODE>::bin;
   const int ic = lane < nc ? i0 + lane : ni - 1;
   Recon<T> rc;
   FluxK<T> K;
@@ -292,14 +292,15 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
   const bool act = lane < nc;
   const int ic = act ? i0 + lane : ni - 1;
   const int last = nc - 1;
-  constexpr int bin = MODE == 0 ? 0 : MODE - 1;
-  constexpr int bout = MODE == 1 ? 1 : (MODE == 2 ? 2 : 0);
+  using SK = StageKind<MODE>;
+  constexpr int bin = SK::bin;
+  constexpr int bout = SK::bout;
   Recon<T> rc;
   FluxK<T> K;
   setup_consts(I, rc, K);
   const T ax = T(B.area[0]), ay = T(B.area[1]), az = T(B.area[2]);
   const double gamma = I.gamma;
-  const double dt = I.dt;
+  const double dt = stage_dt<MODE>(I);
   const double vol = B.vol;
   const double ivol = 1.0 / vol;
   const long long ncell = B.ncell;
@@ -421,10 +422,14 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
           double out[5];
 #pragma unroll
           for (int v = 0; v < 5; ++v) {
-            const double us = fmad(-fct, R[v], qm1[v]);
-            if (MODE == 1) out[v] = us;
-            else if (MODE == 2) out[v] = fmad(0.75, un[v], 0.25 * us);
-            else out[v] = fmad(1.0 / 3.0, un[v], (2.0 / 3.0) * us);
+            if constexpr (SK::low) {
+              out[v] = fmad(-fct, R[v], un[v]);
+            } else {
+              const double us = fmad(-fct, R[v], qm1[v]);
+              if (MODE == 1) out[v] = us;
+              else if (MODE == 2) out[v] = fmad(0.75, un[v], 0.25 * us);
+              else out[v] = fmad(1.0 / 3.0, un[v], (2.0 / 3.0) * us);
+            }
             sto3(orow + v * ncell, cb, out[v]);
           }
           if (MODE == 1) {
@@ -434,7 +439,7 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
               nacc[v] = fmad(rv, rv, nacc[v]);
             }
           }
-          if (MODE == 3) {
+          if constexpr (SK::cfl) {
             const double Sb[3][3] = {{B.area[0], 0.0, 0.0}, {0.0, B.area[1], 0.0},
                                      {0.0, 0.0, B.area[2]}};
             dmin = fmin(dmin, cell_dt_limit<3>(out, Sb, vol, gamma, bad));
@@ -444,7 +449,7 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
     }
     if constexpr (!LASTP) {
       // U^n of plane k for the next update
-      if (MODE >= 2) col_load(Un, k, un);
+      if constexpr (SK::reads_un) col_load(Un, k, un);
       __syncthreads();
       // ---- (5) the pending in-plane part of plane k
       if (rowact) {
@@ -475,11 +480,11 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
   step(F(), Tr(), n);
 
   // ---- per-tile partials of this row wave
-  if (MODE == 0 || MODE == 1 || MODE == 3) {
+  if (SK::norms || SK::cfl) {
     double s[5] = {0, 0, 0, 0, 0};
     double m = 0.0;
     int b = 0;
-    if (MODE == 3) {
+    if (SK::cfl) {
       m = wave_min(dmin);
       b = wave_or(bad);
     } else {
@@ -487,7 +492,7 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
       for (int v = 0; v < 5; ++v) s[v] = wave_sum(nacc[v]);
     }
     if (lane == 0) {
-      if (MODE == 3) {
+      if (SK::cfl) {
         sm.red[w * 8 + 5] = m;
         sm.red[w * 8 + 6] = (double)b;
       } else {
@@ -503,7 +508,7 @@ template <int MODE>
 __device__ void tile_partials3d(const DevTile& tl, DevInstance& I, const double* red) {
   double* part = I.part + tl.local;
   const long long ps = I.ntiles;
-  if (MODE == 3) {
+  if (StageKind<MODE>::cfl) {
     double mm = INFINITY;
     double bb = 0.0;
     for (int x = 0; x < tl.ny; ++x) {
@@ -602,53 +607,60 @@ __global__ __launch_bounds__(256) void k_cfl3d(const DevTile* __restrict__ tiles
 hipError_t launch_stage3d(int mode, int fp32, int ny, int grid, hipStream_t s, const DevTile* tiles,
                           const int* ntiles, const DevBlock* blocks, DevInstance* insts,
                           double* rout) {
+  if (mode < 0 || mode > 6) return hipErrorInvalidValue;
 #define FV_L3(M, T, N)                                                                          \
   hipLaunchKernelGGL((k_stage3d<M, T, N>), dim3(grid), dim3(64 * (N + 1)), 0, s, tiles, ntiles, \
                      blocks, insts, rout)
 #define FV_L3N(M, T) \
   if (ny >= 7) FV_L3(M, T, 7); else FV_L3(M, T, 3)
-  if (fp32) {
-    switch (mode) {
-      case 0: FV_L3N(0, float); break;
-      case 1: FV_L3N(1, float); break;
-      case 2: FV_L3N(2, float); break;
-      default: FV_L3N(3, float); break;
-    }
-  } else {
-    switch (mode) {
-      case 0: FV_L3N(0, double); break;
-      case 1: FV_L3N(1, double); break;
-      case 2: FV_L3N(2, double); break;
-      default: FV_L3N(3, double); break;
-    }
+#define FV_L3_ALL(T)               \
+  switch (mode) {                  \
+    case 0: FV_L3N(0, T); break;   \
+    case 1: FV_L3N(1, T); break;   \
+    case 2: FV_L3N(2, T); break;   \
+    case 3: FV_L3N(3, T); break;   \
+    case 4: FV_L3N(4, T); break;   \
+    case 5: FV_L3N(5, T); break;   \
+    default: FV_L3N(6, T); break;  \
   }
+  if (fp32) {
+    FV_L3_ALL(float)
+  } else {
+    FV_L3_ALL(double)
+  }
+#undef FV_L3_ALL
 #undef FV_L3N
 #undef FV_L3
   return hipGetLastError();
 }
-
 hipError_t launch_cfl3d(int grid, int block, hipStream_t s, const DevTile* tiles, const int* ntiles,
                         const DevBlock* blocks, DevInstance* insts) {
   (void)block;
   hipLaunchKernelGGL(k_cfl3d, dim3(grid), dim3(256), 0, s, tiles, ntiles, blocks, insts);
   return hipGetLastError();
 }
-
 const void* stage3d_kernel_ptr(int mode, int fp32, int ny) {
 #define FV_P3(M, T) (ny >= 7 ? (const void*)&k_stage3d<M, T, 7> : (const void*)&k_stage3d<M, T, 3>)
+  const int m = mode < 0 ? 0 : (mode > 6 ? 6 : mode);
   if (fp32) {
-    switch (mode) {
+    switch (m) {
       case 0: return FV_P3(0, float);
       case 1: return FV_P3(1, float);
       case 2: return FV_P3(2, float);
-      default: return FV_P3(3, float);
+      case 3: return FV_P3(3, float);
+      case 4: return FV_P3(4, float);
+      case 5: return FV_P3(5, float);
+      default: return FV_P3(6, float);
     }
   }
-  switch (mode) {
+  switch (m) {
     case 0: return FV_P3(0, double);
     case 1: return FV_P3(1, double);
     case 2: return FV_P3(2, double);
-    default: return FV_P3(3, double);
+    case 3: return FV_P3(3, double);
+    case 4: return FV_P3(4, double);
+    case 5: return FV_P3(5, double);
+    default: return FV_P3(6, double);
   }
 #undef FV_P3
 }

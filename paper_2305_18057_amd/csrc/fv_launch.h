@@ -6,7 +6,8 @@
 
 namespace fvk {
 
-// 2D: mode 0 = residual only (writes rout), 1..3 = SSP-RK3 stage
+// 2D: mode 0 = residual only (writes rout), 1..6 = RK stage kinds (StageKind
+// in fv_device.h: 1..3 SSP-RK3; 1, 4, 5, 6 the 2- and 4-stage schemes)
 hipError_t launch_stage2d(int mode, int fp32, int grid, int block, hipStream_t s,
                           const DevTile* tiles, const int* ntiles, const DevBlock* blocks,
                           DevInstance* insts, double* rout);

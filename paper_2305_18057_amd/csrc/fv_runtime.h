@@ -71,6 +71,7 @@ const char* tune_path(const char* given);
 
 void params_to_inst(const fv_params* p, double gamma, fvk::DevInstance& I);
 int check_params(const fv_params* p);
+int rk_of(const fv_params* p);  // the scheme: 2, 3 or 4 (rk = 0 means 3)
 int device_cu_count();
 int occupancy_blocks(const void* kernel, int block_threads);
 

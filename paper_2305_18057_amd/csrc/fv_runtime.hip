@@ -375,13 +375,16 @@ void tune_store(const char* path, const std::string& key, const TileShape& sh, d
   rename(tmp.c_str(), path);
 }
 
+int rk_of(const fv_params* p) { return p->rk == 0 ? 3 : p->rk; }
+
 int check_params(const fv_params* p) {
   if (!p) return set_error(FV_E_INVAL, "null params");
   if (p->precision != FV_FP64 && p->precision != FV_FP32_FLUX)
     return set_error(FV_E_INVAL, "unknown precision %d", p->precision);
   if (p->limiter < FV_LIM_MINMOD || p->limiter > FV_FIRST_ORDER)
     return set_error(FV_E_INVAL, "unknown limiter %d", p->limiter);
-  if (p->rk != 0 && p->rk != 3) return set_error(FV_E_UNSUPPORTED, "only SSP-RK3 (rk = 3) is provided");
+  if (p->rk != 0 && p->rk != 2 && p->rk != 3 && p->rk != 4)
+    return set_error(FV_E_UNSUPPORTED, "rk %d: the schemes are 3 (SSP-RK3), 2 and 4", p->rk);
   if (!(p->dt_fixed > 0.0) && !(p->cfl > 0.0)) return set_error(FV_E_INVAL, "need cfl > 0 or dt_fixed > 0");
   if (!std::isfinite(p->cfl) || !std::isfinite(p->dt_fixed) || !std::isfinite(p->t_end) ||
       !std::isfinite(p->eps) || !std::isfinite(p->kappa) || !(p->entropy_fix >= 0.0))
@@ -399,6 +402,14 @@ void params_to_inst(const fv_params* p, double gamma, fvk::DevInstance& I) {
   I.gamma = gamma;
   for (int v = 0; v < 5; ++v) I.qref[v] = p->qref[v];
   I.limiter = p->limiter;
+  // stage coefficients of the scheme (the StageKind table): SSP-RK3 uses
+  // c0 = 1 for its first stage; the 2- and 4-stage second-order schemes
+  // write U^n + c_k dt L at stage k, with c3 the last stage's
+  I.rk = rk_of(p);
+  I.rk_c[0] = I.rk == 2 ? 0.5 : (I.rk == 4 ? 0.25 : 1.0);
+  I.rk_c[1] = 1.0 / 3.0;
+  I.rk_c[2] = 0.5;
+  I.rk_c[3] = 1.0;
 }
 
 int device_cu_count() {

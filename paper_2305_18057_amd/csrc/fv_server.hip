@@ -527,6 +527,8 @@ extern "C" int fv_submit(fv_server* S, const fv_grid_desc* desc, const double* U
   if (!S || !U0 || !ticket) return set_error(FV_E_INVAL, "null argument");
   int st = check_params(p);
   if (st) return st;
+  // resident instances share graph replays of one stage sequence
+  if (rk_of(p) != 3) return set_error(FV_E_UNSUPPORTED, "the server runs SSP-RK3 (rk = 3) only");
   if (max_steps < 1) return set_error(FV_E_INVAL, "max_steps must be >= 1");
   if (!(drop_tol >= 0.0)) return set_error(FV_E_INVAL, "drop_tol must be >= 0");
   Request* r = new (std::nothrow) Request();

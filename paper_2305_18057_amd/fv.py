@@ -179,7 +179,7 @@ class GridDesc:
 def make_params(p: "_cases.Params") -> fv_params:
     q = list(p.qref) + [1.0] * (5 - len(p.qref))
     return fv_params(p.cfl, p.dt_fixed, p.t_end, p.precision, p.limiter, p.eps, p.kappa,
-                     p.entropy_fix, 3, (C.c_double * 5)(*q[:5]))
+                     p.entropy_fix, getattr(p, "rk", 3), (C.c_double * 5)(*q[:5]))
 
 
 def info_dict(info: fv_step_info) -> dict:

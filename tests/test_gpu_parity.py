@@ -257,6 +257,75 @@ def test_inlet_small_fp32_flux(env):
     assert e1 > 1e-12  # the arithmetic really ran in FP32
 
 
+# ---------------------------------------------------------------------------
+# The paper's 2- and 4-stage second-order schemes (Sec. 3.2), against the
+# oracle's Butcher-form stepping
+# ---------------------------------------------------------------------------
+def with_rk(params, rk, **kw):
+    return CS.Params(**{**params.__dict__, "rk": rk, **kw})
+
+
+@pytest.mark.parametrize("rk", [2, 4])
+def test_rk_2_4_vortex(env, rk):
+    fv, O = env
+    case = CS.vortex_2d(128, 64)
+    check_steps(fv, O, case, 20, params=with_rk(case.params, rk))
+
+
+@pytest.mark.parametrize("rk", [2, 4])
+def test_rk_2_4_inlet_small(env, rk):
+    fv, O = env
+    case = perturbed(CS.inlet_case(200, 72, 2, angle_deg=3.0))
+    check_steps(fv, O, case, 12, params=with_rk(case.params, rk))
+
+
+@pytest.mark.parametrize("rk", [2, 4])
+def test_rk_2_4_3d_small(env, rk):
+    fv, O = env
+    case = CS.blobs_case(32, nblobs=4)
+    check_steps(fv, O, case, 6, params=with_rk(case.params, rk))
+
+
+def test_rk_4_fp32_flux(env):
+    fv, O = env
+    case = perturbed(CS.inlet_case(4 * 64, 32, 4, angle_deg=3.0))
+    p64 = with_rk(case.params, 4)
+    p32 = with_rk(case.params, 4, precision=CS.FP32_FLUX)
+    g, info = gpu_run(fv, case, 1, p32)
+    ref = O.OracleGrid(case)
+    ref.run(p64, 1)
+    e1 = P.state_err(case, g.get_state(), ref.get_state())
+    g.step(p32, 29)
+    ref.run(p64, 29)
+    eN = P.state_err(case, g.get_state(), ref.get_state())
+    say(f"  fp32-flux rk4 inlet small: 1 step {e1:.2e}, 30 steps {eN:.2e}")
+    assert e1 <= P.FP32_STEP_TOL and eN <= P.FP32_RUN_TOL
+    assert e1 > 1e-12
+
+
+def test_rk_4_solve_stops_at_same_step(env):
+    fv, O = env
+    case = CS.inlet_case(128, 32, 2, angle_deg=6.0)
+    prm = with_rk(case.params, 4)
+    ref = O.OracleGrid(case)
+    drops = []
+    for _ in range(40):
+        ref.run(prm, 1)
+        drops.append(ref.run(prm, 0)["drop"])
+    runmin = np.minimum.accumulate(np.array(drops))
+    s = int(np.argmax(runmin < runmin[15]))
+    assert s > 15
+    tol = 0.5 * (runmin[s] + runmin[s - 1])  # half-way between two running minima
+    ref2 = O.OracleGrid(case)
+    io = ref2.run(prm, 1000, drop_tol=tol)
+    g = fv.Grid(case)
+    g.set_state(case.state_flat())
+    info = g.solve(prm, drop_tol=tol, max_steps=1000)
+    say(f"  rk4 solve: gpu {info['steps']} steps, oracle {io['steps']} steps, tol {tol:.4e}")
+    assert info["steps"] == io["steps"] and info["flags"] & fv.FLAG_CONVERGED
+    assert P.state_err(case, g.get_state(), ref2.get_state()) <= P.FP64_TOL
+
+
 def test_inlet_full_residual_and_steps(env):
     fv, O = env
     case = CS.inlet_2d()

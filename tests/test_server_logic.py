@@ -85,6 +85,23 @@ def test_oversize_request_rejected(fvb):
     srv.close()
 
 
+def test_server_takes_ssp_rk3_only(fvb):
+    """Resident instances share one stage sequence: the 2- and 4-stage
+    schemes are for grids, and the server says so."""
+    srv = fvb.Server(arena_bytes=32 << 20, max_instances=4, dry_run=True)
+    case = CS.inlet_case(64, 64, 1)
+    for rk in (2, 4):
+        prm = CS.Params(**{**case.params.__dict__, "rk": rk})
+        with pytest.raises(fvb.FVError) as e:
+            srv.submit(case, params=prm, max_steps=10)
+        assert e.value.status == fvb.FV_E_UNSUPPORTED
+    prm = CS.Params(**{**case.params.__dict__, "rk": 5})
+    with pytest.raises(fvb.FVError) as e:
+        srv.submit(case, params=prm, max_steps=10)
+    assert e.value.status == fvb.FV_E_UNSUPPORTED
+    srv.close()
+
+
 def test_cancel_queued_and_resident(fvb):
     srv = fvb.Server(arena_bytes=64 << 20, max_instances=1, steps_per_launch=1, dry_run=True)
     c = CS.inlet_case(128, 64, 2)
