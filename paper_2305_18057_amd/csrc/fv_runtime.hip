@@ -258,7 +258,7 @@ void build_tiles(const HostGrid& g, const TileShape& sh, int inst_index, int bof
           out.push_back(t);
         }
     } else {
-      // at most 64 planes: the right-edge fluxes of a row are formed one plane per lane
+      // at most 64 planes: the kernel keeps a row's right-edge fluxes in 64 LDS slots, one per plane
       const int P = std::min(64, std::max(kMinPlanes3D, sh.rows));
       const int NY = sh.ny >= 7 ? 7 : 3;
       for (int k0 = 0; k0 < B.nk; k0 += P)
