@@ -345,6 +345,27 @@ def test_inlet_full_fp32_flux(env):
     assert e1 <= P.FP32_STEP_TOL
 
 
+def test_inlet_full_500_steps(env):
+    """The inlet configuration as measured (4 x 512 x 256 cells, 500 steps):
+    FP64 against the oracle at the C-19 bar, and FP32-flux after the same
+    500 steps at the after-N bar."""
+    fv, O = env
+    case = CS.inlet_2d()
+    ref = O.OracleGrid(case)
+    io = ref.run(case.params, 500)
+    Uo = ref.get_state()
+    g, info = gpu_run(fv, case, 500)
+    e64 = P.state_err(case, g.get_state(), Uo)
+    p32 = CS.Params(**{**case.params.__dict__, "precision": CS.FP32_FLUX})
+    g32, info32 = gpu_run(fv, case, 500, p32)
+    e32 = P.state_err(case, g32.get_state(), Uo)
+    say(f"  inlet full 500 steps: fp64 e_U = {e64:.3e}, fp32-flux e_U = {e32:.3e}, "
+        f"t gpu {info['t']:.9g} ref {io['t']:.9g}")
+    assert info["steps"] == io["steps"] == 500
+    assert e64 <= P.FP64_TOL and abs(info["t"] - io["t"]) <= 1e-11 * io["t"]
+    assert e32 <= P.FP32_RUN_TOL
+
+
 # ---------------------------------------------------------------------------
 # 3D uniform block with density blobs
 # ---------------------------------------------------------------------------
