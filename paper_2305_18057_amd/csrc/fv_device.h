@@ -525,6 +525,21 @@ __device__ __forceinline__ TileWalk xcd_walk_blocked(int ntiles) {
   return w;
 }
 
+// Issue priority of a wavefront from its progress through a 2D tile.  Two
+// tiles share each SIMD; with equal priorities the older wavefront is issued
+// first, runs ahead, and the younger one ends its tile alone with nothing to
+// hide its latencies.  A wavefront that has finished more rows steps down, so
+// the one behind is preferred and the two end their tiles together.  Only
+// the order of issue changes, never a result.
+__device__ __forceinline__ void prio_by_progress(int rows_done) {
+#ifndef FV_NO_PRIO
+  if (rows_done <= 0) __builtin_amdgcn_s_setprio(3);
+  else if (rows_done == 1) __builtin_amdgcn_s_setprio(2);
+  else if (rows_done == 2) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+#endif
+}
+
 // --------------------------------------------------------------------------
 // wave-wide deterministic reductions (fixed butterfly order)
 // --------------------------------------------------------------------------

@@ -218,6 +218,7 @@ __device__ __forceinline__ void face_flux(const FluxK<T>& K, const T (&qL)[4], c
 template <int MODE, typename T, bool CURV, int LIM>
 __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __restrict__ blocks, DevInstance& I,
                        double* __restrict__ rout, int lane, Lds2D<T>& L) {
+  prio_by_progress(0);
   const DevBlock& B = blocks[tl.blk];
   const int ni = B.ni, nj = B.nj;
   const int i0 = tl.i0, j0 = tl.j0, n = tl.n, nc = tl.ncol;
@@ -586,7 +587,11 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
   using F = std::integral_constant<bool, false>;
   using Tr = std::integral_constant<bool, true>;
   step(Tr(), F(), 0);
-  for (int r = 1; r < n; ++r) step(F(), F(), r);
+  prio_by_progress(1);
+  for (int r = 1; r < n; ++r) {
+    step(F(), F(), r);
+    prio_by_progress(r + 1);
+  }
   step(F(), Tr(), n);
 
   // ---- per-tile partials (fixed-order wave reductions)
