@@ -19,6 +19,7 @@ struct LaunchSet {
   fvk::DevTile* tiles = nullptr;
   int* ntiles_dev = nullptr;  // device-resident count (graphs read it at run time)
   int ntiles = 0;             // host view, sizes the persistent grid
+  bool count_fixed = false;   // ntiles is the exact count for as long as the plan is used
   int kind = kSet2D;
   int max_grid = 0;           // 0: as many workgroups as co-reside on the device
 };

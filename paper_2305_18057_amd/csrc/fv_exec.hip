@@ -56,12 +56,14 @@ int enqueue_stage(const StepPlan& P, int mode, int fp32, double* rout, hipStream
   for (const LaunchSet& s : P.sets) {
     if (s.ntiles <= 0) continue;
     const int grid = launch_grid(s, fp32);
+    const int nfix = s.count_fixed ? s.ntiles : -1;
     hipError_t e;
     if (s.kind == kSet2D)
-      e = fvk::launch_stage2d(mode, fp32, grid, 256, st, s.tiles, s.ntiles_dev, P.blocks, P.insts, rout);
+      e = fvk::launch_stage2d(mode, fp32, grid, 256, st, s.tiles, s.ntiles_dev, nfix, P.blocks, P.insts,
+                              rout);
     else
       e = fvk::launch_stage3d(mode, fp32, s.kind == kSet3D7 ? 7 : 3, grid, st, s.tiles, s.ntiles_dev,
-                              P.blocks, P.insts, rout);
+                              nfix, P.blocks, P.insts, rout);
     if (e != hipSuccess)
       return fvrt::set_error(FV_E_DEVICE, "stage launch failed: %s", hipGetErrorString(e));
   }

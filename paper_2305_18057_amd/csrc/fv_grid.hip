@@ -55,6 +55,8 @@ int upload_tiles(fv_grid* g) {
   ls.tiles = g->d_tiles;
   ls.ntiles_dev = g->d_ntiles;
   ls.ntiles = nt;
+  // graphs are captured again after every change of the tile list (below)
+  ls.count_fixed = true;
   ls.kind = g->hg.ndim == 2 ? fvexec::kSet2D : (g->shape.ny >= 7 ? fvexec::kSet3D7 : fvexec::kSet3D3);
   g->plan.sets.push_back(ls);
   g->graphs.clear();

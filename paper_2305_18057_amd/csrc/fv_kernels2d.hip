@@ -620,14 +620,15 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
 // at most 256 VGPRs: two waves per SIMD
 template <int MODE, typename T>
 __global__ __launch_bounds__(256, 2) void k_stage2d(const DevTile* __restrict__ tiles,
-                                                 const int* __restrict__ ntiles_p,
+                                                 const int* __restrict__ ntiles_p, int nfix,
                                                  const DevBlock* __restrict__ blocks,
                                                  DevInstance* __restrict__ insts,
                                                  double* __restrict__ rout) {
   __shared__ Lds2D<T> s_lds[kWavesPerWG];
   const int lane = threadIdx.x & 63;
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int ntiles = *ntiles_p;
+  // a count fixed at launch saves one dependent load before the first tile
+  const int ntiles = nfix >= 0 ? nfix : *ntiles_p;
   for (TileWalk tw = xcd_walk(ntiles, kWavesPerWG, wid); tw.t < tw.end; tw.t += tw.stride) {
     const DevTile tl = tiles[tw.t];
     DevInstance& I = insts[tl.inst];
@@ -707,10 +708,10 @@ __global__ __launch_bounds__(256) void k_cfl2d(const DevTile* __restrict__ tiles
 // launch wrappers
 // ---------------------------------------------------------------------------
 hipError_t launch_stage2d(int mode, int fp32, int grid, int block, hipStream_t s, const DevTile* tiles,
-                          const int* ntiles, const DevBlock* blocks, DevInstance* insts,
+                          const int* ntiles, int ntiles_fixed, const DevBlock* blocks, DevInstance* insts,
                           double* rout) {
   if (mode < 0 || mode > 6) return hipErrorInvalidValue;
-#define FV_L2(M, T) hipLaunchKernelGGL((k_stage2d<M, T>), dim3(grid), dim3(block), 0, s, tiles, ntiles, blocks, insts, rout)
+#define FV_L2(M, T) hipLaunchKernelGGL((k_stage2d<M, T>), dim3(grid), dim3(block), 0, s, tiles, ntiles, ntiles_fixed, blocks, insts, rout)
 #define FV_L2_ALL(T)              \
   switch (mode) {                 \
     case 0: FV_L2(0, T); break;   \

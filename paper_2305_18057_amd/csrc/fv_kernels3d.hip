@@ -538,14 +538,15 @@ __device__ __forceinline__ void run_tile3d(const DevTile& tl, const DevBlock* __
 // at most 256 VGPRs: two waves per SIMD
 template <int MODE, typename T, int NY>
 __global__ __launch_bounds__(64 * (NY + 1), 2) void k_stage3d(const DevTile* __restrict__ tiles,
-                                                              const int* __restrict__ ntiles_p,
+                                                              const int* __restrict__ ntiles_p, int nfix,
                                                               const DevBlock* __restrict__ blocks,
                                                               DevInstance* __restrict__ insts,
                                                               double* __restrict__ rout) {
   __shared__ Smem3<T, NY> sm;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int ntiles = *ntiles_p;
+  // a count fixed at launch saves one dependent load before the first tile
+  const int ntiles = nfix >= 0 ? nfix : *ntiles_p;
   for (TileWalk tw = xcd_walk_blocked(ntiles); tw.t < tw.end; tw.t += tw.stride) {
     const DevTile tl = tiles[tw.t];
     DevInstance& I = insts[tl.inst];
@@ -605,12 +606,12 @@ __global__ __launch_bounds__(256) void k_cfl3d(const DevTile* __restrict__ tiles
 }  // namespace
 
 hipError_t launch_stage3d(int mode, int fp32, int ny, int grid, hipStream_t s, const DevTile* tiles,
-                          const int* ntiles, const DevBlock* blocks, DevInstance* insts,
+                          const int* ntiles, int ntiles_fixed, const DevBlock* blocks, DevInstance* insts,
                           double* rout) {
   if (mode < 0 || mode > 6) return hipErrorInvalidValue;
 #define FV_L3(M, T, N)                                                                          \
   hipLaunchKernelGGL((k_stage3d<M, T, N>), dim3(grid), dim3(64 * (N + 1)), 0, s, tiles, ntiles, \
-                     blocks, insts, rout)
+                     ntiles_fixed, blocks, insts, rout)
 #define FV_L3N(M, T) \
   if (ny >= 7) FV_L3(M, T, 7); else FV_L3(M, T, 3)
 #define FV_L3_ALL(T)               \
