@@ -31,11 +31,14 @@ import sys
 import tempfile
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+RAMP_S = 0.25          # untimed load before each timed run (clock ramp)
 FP64_PEAK_TFS = 78.6   # vector FP64, 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 FP32_PEAK_TFS = 157.3
 METRIC = "cell-updates/s + % HBM roofline; batched p50/p99 solve latency vs plain"
@@ -120,13 +123,27 @@ def profile_record(kernel: str, workload: str, ndim: int):
 # --------------------------------------------------------------------------
 # single-grid timing
 # --------------------------------------------------------------------------
+def ramp_clocks(g, params, U0, seconds=RAMP_S):
+    """Untimed steps for `seconds`, then the initial state back: the GPU's
+    clocks rise over tens of milliseconds of load, and a short timed window
+    started from idle would measure the ramp rather than the solver."""
+    import torch
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        g.step(params, 50)
+    torch.cuda.synchronize()
+    g.set_state(U0)
+
+
 def time_grid(fv, case, params, steps, warmup, tune_cache=None, stage_times=True):
     import torch
     g = fv.Grid(case)
-    g.set_state(case.state_flat())
+    U0 = case.state_flat()
+    g.set_state(U0)
     if tune_cache is not None:
         g.tune(params, tune_cache)
-        g.set_state(case.state_flat())
+        g.set_state(U0)
+    ramp_clocks(g, params, U0)
     if warmup:
         g.step(params, warmup)
     stream = torch.cuda.current_stream()
@@ -144,6 +161,58 @@ def time_grid(fv, case, params, steps, warmup, tune_cache=None, stage_times=True
     stage_ms = g.step_timed(params, steps)[1] if stage_times else None
     st = g.stats()
     return g, info, wall, dev_ms, stage_ms, st
+
+
+def repeat_timing(fv, case, params, steps, reps=5, tune_cache=None):
+    """Median of `reps` timed runs of `steps` steps, each from the initial
+    state restored from a device copy (clock ramp and 5 warm-up steps
+    first)."""
+    import torch
+    g = fv.Grid(case)
+    U0 = torch.from_numpy(case.state_flat()).to("cuda")
+    g.set_state(U0)
+    if tune_cache is not None:
+        g.tune(params, tune_cache)
+        g.set_state(U0)
+    ramp_clocks(g, params, U0)
+    g.step(params, 5)
+    stream = torch.cuda.current_stream()
+    per = []
+    for _ in range(reps):
+        g.set_state(U0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.step(params, steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        per.append(e0.elapsed_time(e1) / steps)
+    g.close()
+    med = float(np.median(per))
+    return dict(reps=reps, steps=steps, ms_per_step=[round(x, 5) for x in per],
+                median_ms_per_step=round(med, 5),
+                median_cell_updates_per_s=round(case.ncells / (med * 1e-3), 1))
+
+
+def copy_bandwidth():
+    """Achievable device bandwidth: best of 5 timed 1 GiB device-to-device
+    copies, counting the bytes read and written."""
+    import torch
+    n = 1 << 27
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return round(2 * n * 8 / (best * 1e-3) / 1e9, 1)
 
 
 def bench_rk_schemes(fv, cases, tune_cache, steps2d):
@@ -218,6 +287,27 @@ def cpu_baseline(case, budget_s=12.0):
                 cores=O.num_threads(), kind="oracle",
                 sample=f"{case.name}: {n} SSP-RK3 steps of the full {case.ncells}-cell grid "
                        f"({dt:.1f} s wall, FP64, OpenMP over faces/cells)")
+
+
+def cpu_single_core(case, budget_s=5.0):
+    """The oracle on one host core, on a bounded sample of the same grid."""
+    from oracle import oracle as O
+    keep = O.num_threads()
+    O.set_threads(1)
+    try:
+        ref = O.OracleGrid(case)
+        t0 = time.perf_counter()
+        ref.run(case.params, 1)
+        t1 = time.perf_counter() - t0
+        n = max(1, min(50, int(budget_s / max(t1, 1e-6))))
+        t0 = time.perf_counter()
+        ref.run(case.params, n)
+        dt = time.perf_counter() - t0
+    finally:
+        O.set_threads(keep)
+    return dict(value=round(case.ncells * n / dt, 1), unit="cell-updates/s", cores=1,
+                kind="oracle", sample=f"{case.name}: {n} SSP-RK3 steps of the full grid "
+                                      f"({dt:.1f} s wall, FP64, one thread)")
 
 
 # --------------------------------------------------------------------------
@@ -562,8 +652,13 @@ def main():
         f"({100*roof['frac']:.1f}% HBM), tile rows={st['tile_rows']} ny={st['tile_ny']}")
     g.close()
     del g
+    roof["achievable_copy_gbs"] = copy_bandwidth()
 
     extra = {}
+    rep = repeat_timing(fv, case, prm, args.steps, 5, tune_cache)
+    extra["repeats"] = rep
+    log(f"[bench] median of {rep['reps']} runs from the restored initial state: "
+        f"{rep['median_ms_per_step']*1e3:.1f} us/step")
     if not args.no_extra:
         others = [("inlet_2d", cases.inlet_2d, cases.FP64, args.steps),
                   ("inlet_2d", cases.inlet_2d, cases.FP32_FLUX, args.steps),
@@ -603,6 +698,8 @@ def main():
         log("[bench] CPU reference on a bounded sample")
         cpu = cpu_baseline(case)
         log(f"[bench] cpu {cpu['value']/1e6:.2f} M cell-updates/s on {cpu['cores']} threads")
+        extra["cpu_single_core"] = cpu_single_core(case)
+        log(f"[bench] cpu one core {extra['cpu_single_core']['value']/1e6:.2f} M cell-updates/s")
 
     if args.workload == "inlet_2d":
         desc = ("inlet_2d: 2D Euler, 4 blocks x 512x256 cells on the sheared wavy inlet-like "
@@ -635,6 +732,7 @@ def main():
             "launch_blocks": st["launch_blocks"],
             "autotuned": tune_cache is not None,
         },
+        "cell_stage_updates_per_s": round(3 * value, 1),
         "ssspnt": round(1e-6 * case.ncells * 3 * args.steps / (dev_ms * 1e-3), 2),
         "roofline": roof,
         "alu": alu,

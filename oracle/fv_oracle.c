@@ -938,3 +938,12 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+
+/* threads of the following runs (timing only: results do not depend on it) */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

@@ -81,6 +81,7 @@ def lib():
         L.orc_roe.argtypes = [dp, dp, dp, C.c_int, C.c_double, C.c_double, C.c_int, dp]
         L.orc_reconstruct.argtypes = [dp, C.c_int, C.c_double, C.c_double, dp, dp]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -97,6 +98,11 @@ def make_params(p) -> _Params:
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of the following oracle runs (timing only)."""
+    lib().orc_set_threads(int(n))
 
 
 # ---------------------------------------------------------------------------
