@@ -60,7 +60,9 @@ struct DevInstance {
 struct DevTile {
   int blk, inst, local, ncol;
   int i0, j0, k0, n;
-  int ny, pad0, pad1, pad2;
+  int ny;
+  int curv;  // 2D: the block has node coordinates (curvilinear)
+  int pad1, pad2;
 };
 
 // --------------------------------------------------------------------------

@@ -31,6 +31,7 @@ struct StepPlan {
   int ninst = 0;                // finalize grid (the capacity when ninst_dev is set)
   const int* ninst_dev = nullptr;  // device-resident live instance count
   int rk = 3;                   // 3: SSP-RK3; 2, 4: the 2- and 4-stage second-order schemes
+  int lim = -1;                 // >= 0: the limiter of every instance; -1: each instance's own
   std::vector<LaunchSet> sets;
 };
 

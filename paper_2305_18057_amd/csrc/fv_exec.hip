@@ -59,8 +59,8 @@ int enqueue_stage(const StepPlan& P, int mode, int fp32, double* rout, hipStream
     const int nfix = s.count_fixed ? s.ntiles : -1;
     hipError_t e;
     if (s.kind == kSet2D)
-      e = fvk::launch_stage2d(mode, fp32, grid, 256, st, s.tiles, s.ntiles_dev, nfix, P.blocks, P.insts,
-                              rout);
+      e = fvk::launch_stage2d(mode, fp32, grid, 256, st, s.tiles, s.ntiles_dev, nfix, P.lim, P.blocks,
+                              P.insts, rout);
     else
       e = fvk::launch_stage3d(mode, fp32, s.kind == kSet3D7 ? 7 : 3, grid, st, s.tiles, s.ntiles_dev,
                               nfix, P.blocks, P.insts, rout);
@@ -114,10 +114,10 @@ int enqueue_steps(const StepPlan& P, int fp32, int nsteps, hipStream_t st, Graph
     }
     return FV_OK;
   }
-  // a captured graph depends on the step count, the precision, the scheme
-  // and the caller's variant
-  const long long key = ((long long)(unsigned)variant << 32) | ((long long)P.rk << 28) |
-                        ((long long)nsteps << 1) | (fp32 ? 1 : 0);
+  // a captured graph depends on the step count, the precision, the scheme,
+  // the limiter given at launch and the caller's variant
+  const long long key = ((long long)(unsigned)variant << 40) | ((long long)(P.lim + 1) << 36) |
+                        ((long long)P.rk << 32) | ((long long)nsteps << 1) | (fp32 ? 1 : 0);
   hipGraphExec_t ex = cache->get(key);
   if (!ex) {
     hipStream_t cs;

@@ -241,6 +241,7 @@ extern "C" int fv_residual(fv_grid* g, const fv_params* p, double* R, int on_dev
   st = put_inst(g, false);
   if (st) return st;
   double* dst = (R && on_device) ? R : g->d_u[1];
+  g->plan.lim = p->limiter;
   st = fvexec::enqueue_stage(g->plan, 0, p->precision == FV_FP32_FLUX, dst, g->stream);
   if (st) return st;
   FV_HIP(fvk::launch_rnorms(g->stream, g->d_inst, nullptr, 1));
@@ -289,6 +290,7 @@ static int run_steps(fv_grid* g, const fv_params* p, long long nsteps, double dr
   FV_HIP(fvk::launch_prepare(g->stream, g->d_inst, nullptr, 1));
   const int fp32 = p->precision == FV_FP32_FLUX;
   g->plan.rk = fvrt::rk_of(p);
+  g->plan.lim = p->limiter;
   const int chunk = fvexec::graph_chunk();
   long long left = nsteps;
   long long since_check = 0;
@@ -325,6 +327,7 @@ extern "C" int fv_step_timed(fv_grid* g, const fv_params* p, int nsteps, fv_step
   if (st) return st;
   if (fvrt::rk_of(p) != 3) return set_error(FV_E_UNSUPPORTED, "per-stage timing is for SSP-RK3 (rk = 3)");
   g->plan.rk = 3;
+  g->plan.lim = p->limiter;
   if (!g->have_state) return set_error(FV_E_INVAL, "no state set");
   if (nsteps < 0) return set_error(FV_E_INVAL, "negative step count");
   params_to_inst(p, g->hg.gamma, g->hinst);
@@ -454,6 +457,7 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
     g->hinst.stopped = 0;
     g->hinst.flags = 0;
     g->plan.rk = rk;
+    g->plan.lim = p->limiter;
     if ((e = put_inst(g, true))) return e;
     if ((e = fvexec::enqueue_steps(g->plan, fp32, reps, g->stream, &g->graphs))) return e;
     per = 1e30;

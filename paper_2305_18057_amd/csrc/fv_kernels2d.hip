@@ -356,6 +356,9 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
     xR2p = ldk(X + jr * nrow + ir);
     yR2p = ldk(Y + jr * nrow + ir);
   }
+  // a stopped instance's tiles leave here, before any store: the check waits
+  // on a load issued together with the descriptors, not ahead of them
+  if (MODE != 0 && I.stopped) return;
   // ghost corrections of the prologue cells
   fix_with(sa, B, bwx, bwy, qa);
   fix_with(sb, B, bwx, bwy, qm1);
@@ -620,7 +623,7 @@ __device__ __forceinline__ void tile2d(const DevTile& tl, const DevBlock* __rest
 // at most 256 VGPRs: two waves per SIMD
 template <int MODE, typename T>
 __global__ __launch_bounds__(256, 2) void k_stage2d(const DevTile* __restrict__ tiles,
-                                                 const int* __restrict__ ntiles_p, int nfix,
+                                                 const int* __restrict__ ntiles_p, int nfix, int lim_fixed,
                                                  const DevBlock* __restrict__ blocks,
                                                  DevInstance* __restrict__ insts,
                                                  double* __restrict__ rout) {
@@ -632,14 +635,17 @@ __global__ __launch_bounds__(256, 2) void k_stage2d(const DevTile* __restrict__ 
   for (TileWalk tw = xcd_walk(ntiles, kWavesPerWG, wid); tw.t < tw.end; tw.t += tw.stride) {
     const DevTile tl = tiles[tw.t];
     DevInstance& I = insts[tl.inst];
-    if (MODE != 0 && I.stopped) continue;
-    // the common configuration (minmod) is compiled with the limiter fixed
-    const bool curv = blocks[tl.blk].xn != nullptr;
-    if (I.limiter == LIM_MINMOD) {
-      if (curv) tile2d<MODE, T, true, LIM_MINMOD>(tl, blocks, I, rout, lane, s_lds[wid]);
+    // the common configuration (minmod) is compiled with the limiter fixed.
+    // With the limiter given at launch and the block kind in the tile, the
+    // choice needs no descriptor read: the tile routine reads the instance
+    // and block descriptors in one batch (and checks for a stopped instance
+    // there).
+    const int lim = lim_fixed >= 0 ? lim_fixed : I.limiter;
+    if (lim == LIM_MINMOD) {
+      if (tl.curv) tile2d<MODE, T, true, LIM_MINMOD>(tl, blocks, I, rout, lane, s_lds[wid]);
       else tile2d<MODE, T, false, LIM_MINMOD>(tl, blocks, I, rout, lane, s_lds[wid]);
     } else {
-      if (curv) tile2d<MODE, T, true, -1>(tl, blocks, I, rout, lane, s_lds[wid]);
+      if (tl.curv) tile2d<MODE, T, true, -1>(tl, blocks, I, rout, lane, s_lds[wid]);
       else tile2d<MODE, T, false, -1>(tl, blocks, I, rout, lane, s_lds[wid]);
     }
   }
@@ -708,10 +714,10 @@ __global__ __launch_bounds__(256) void k_cfl2d(const DevTile* __restrict__ tiles
 // launch wrappers
 // ---------------------------------------------------------------------------
 hipError_t launch_stage2d(int mode, int fp32, int grid, int block, hipStream_t s, const DevTile* tiles,
-                          const int* ntiles, int ntiles_fixed, const DevBlock* blocks, DevInstance* insts,
-                          double* rout) {
+                          const int* ntiles, int ntiles_fixed, int lim_fixed, const DevBlock* blocks,
+                          DevInstance* insts, double* rout) {
   if (mode < 0 || mode > 6) return hipErrorInvalidValue;
-#define FV_L2(M, T) hipLaunchKernelGGL((k_stage2d<M, T>), dim3(grid), dim3(block), 0, s, tiles, ntiles, ntiles_fixed, blocks, insts, rout)
+#define FV_L2(M, T) hipLaunchKernelGGL((k_stage2d<M, T>), dim3(grid), dim3(block), 0, s, tiles, ntiles, ntiles_fixed, lim_fixed, blocks, insts, rout)
 #define FV_L2_ALL(T)              \
   switch (mode) {                 \
     case 0: FV_L2(0, T); break;   \

@@ -9,9 +9,11 @@ namespace fvk {
 // 2D: mode 0 = residual only (writes rout), 1..6 = RK stage kinds (StageKind
 // in fv_device.h: 1..3 SSP-RK3; 1, 4, 5, 6 the 2- and 4-stage schemes)
 // ntiles_fixed >= 0: the tile count, known when the launch is recorded (the
-// kernels then skip the read of *ntiles); -1: the count is read at run time
+// kernels then skip the read of *ntiles); -1: the count is read at run time.
+// lim_fixed >= 0: the limiter of every instance in the launch; -1: each
+// instance's own
 hipError_t launch_stage2d(int mode, int fp32, int grid, int block, hipStream_t s,
-                          const DevTile* tiles, const int* ntiles, int ntiles_fixed,
+                          const DevTile* tiles, const int* ntiles, int ntiles_fixed, int lim_fixed,
                           const DevBlock* blocks, DevInstance* insts, double* rout);
 hipError_t launch_cfl2d(int grid, int block, hipStream_t s, const DevTile* tiles,
                         const int* ntiles, const DevBlock* blocks, DevInstance* insts);

@@ -255,6 +255,7 @@ void build_tiles(const HostGrid& g, const TileShape& sh, int inst_index, int bof
           t.k0 = 0;
           t.n = std::min(R, B.nj - j0);
           t.ny = 1;
+          t.curv = B.x != nullptr ? 1 : 0;
           out.push_back(t);
         }
     } else {
