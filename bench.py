@@ -258,6 +258,12 @@ def roofline_of(case, stage_ms, steps, workload, fp32=False):
                 kernel=kernel, bytes_per_cell_step=algorithmic_bytes_per_cell_step(case),
                 bytes_per_launch=int(bytes_per_launch), avg_launch_ms=round(avg_ms, 5),
                 finalize_avg_ms=round(float(stage_ms[3]) / steps, 5))
+    if rec is not None and "trace_avg_us_per_launch" in rec:
+        # the profile's execution time per launch, beside the event time above
+        # (which also holds each launch's dispatch and completion)
+        tr = float(rec["trace_avg_us_per_launch"]) * 1e-3
+        roof["trace_avg_launch_ms"] = round(tr, 5)
+        roof["trace_achieved"] = round(bytes_per_launch / (tr * 1e-3) / 1e9, 1)
     flops = algorithmic_flops_per_cell_stage(case)
     tfs = flops * cells / (avg_ms * 1e-3) / 1e12
     peak = FP32_PEAK_TFS if fp32 else FP64_PEAK_TFS
@@ -505,6 +511,7 @@ def summarize(dirs, kernel_filter, out_path, command, calib=None, workload=None,
     ``calib`` names the runs of the same counters over a 1 GiB device copy,
     whose known traffic scales FETCH_SIZE / WRITE_SIZE (KiB) to bytes."""
     lines = ["# rocprofv3 summary", f"command: {command}", ""]
+    trace_calls = trace_ns = 0.0
     for d in dirs:
         for path in glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True):
             lines.append(f"# kernel stats ({os.path.basename(path)})")
@@ -513,6 +520,9 @@ def summarize(dirs, kernel_filter, out_path, command, calib=None, workload=None,
             with open(path) as fh:
                 for row in csv.DictReader(fh):
                     name = _col(row, "Name").replace("(anonymous namespace)::", "").split("(")[0]
+                    if kernel_filter in name:
+                        trace_calls += float(_col(row, "Calls"))
+                        trace_ns += float(_col(row, "TotalDurationNs"))
                     lines.append(f"| {name} | {_col(row, 'Calls')} | "
                                  f"{float(_col(row, 'TotalDurationNs'))/1e6:.3f} | "
                                  f"{float(_col(row, 'AverageNs'))/1e3:.2f} | "
@@ -554,6 +564,10 @@ def summarize(dirs, kernel_filter, out_path, command, calib=None, workload=None,
         lines.append(f"cells: {cells}")
         alg = algorithmic_bytes_per_cell_step(case) * cells / 3.0
         lines.append(f"algorithmic_bytes_per_launch: {alg:.0f}")
+        if trace_calls:
+            # kernel execution time (first wave's start to last wave's end),
+            # over every stage launch of the traced run
+            lines.append(f"trace_avg_us_per_launch: {trace_ns / trace_calls / 1e3:.2f}")
         fs, ws = mean("FETCH_SIZE"), mean("WRITE_SIZE")
         if fs is not None and ws is not None and fetch_f and write_f:
             hbm = fs * 1024.0 * fetch_f + ws * 1024.0 * write_f

@@ -101,6 +101,24 @@ def test_vortex_limiter_variants(env, limiter):
     check_steps(fv, O, case, 20)
 
 
+def test_limiter_switch_on_one_grid(env):
+    """Steps with minmod, then without a limiter, then first order, then
+    minmod again, on one grid object: every call must run its own limiter
+    (the captured step graphs are told apart by the limiter)."""
+    fv, O = env
+    case = perturbed(CS.inlet_case(4 * 64, 32, 4, angle_deg=3.0))
+    g = fv.Grid(case)
+    g.set_state(case.state_flat())
+    ref = O.OracleGrid(case)
+    for lim, n in ((CS.MINMOD, 7), (CS.UNLIMITED, 5), (CS.FIRST_ORDER, 6), (CS.MINMOD, 4)):
+        p = CS.Params(**{**case.params.__dict__, "limiter": lim})
+        g.step(p, n)
+        ref.run(p, n)
+        e = P.state_err(case, g.get_state(), ref.get_state())
+        say(f"  limiter {lim} x {n} steps: e_U = {e:.3e}")
+        assert e <= P.FP64_TOL
+
+
 def test_periodic_conservation_on_gpu(env):
     fv, O = env
     case = CS.vortex_2d()
