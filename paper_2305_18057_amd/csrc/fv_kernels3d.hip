@@ -30,12 +30,16 @@ namespace {
 
 constexpr int kS3 = 72;  // LDS row slots: column i0 + c at slot c + 2; slot 71 is scratch
 
+// q and f are double-buffered by plane parity: plane r of a tile is staged
+// in q[r & 1] and its j-face fluxes go to f[r & 1], so the waves of a
+// workgroup meet once per plane (they write plane r + 1 while others may
+// still read plane r).  g is read and written by its own row wave only.
 template <typename T, int NY>
 struct Smem3 {
-  T q[NY + 4][5][kS3];   // plane k: rows j0-2 .. j0+NY+1
-  T f[NY + 1][5][64];    // j-face fluxes at j-1/2, rows j0 .. j0+NY
-  T g[NY][5][kS3];       // i-face fluxes of each row
-  T edge[NY][5][64];     // right-edge i-face fluxes, per row, plane r at [r]
+  T q[2][NY + 4][5][kS3];  // plane k: rows j0-2 .. j0+NY+1
+  T f[2][NY + 1][5][64];   // j-face fluxes at j-1/2, rows j0 .. j0+NY
+  T g[NY][5][kS3];         // i-face fluxes of each row
+  T edge[NY][5][64];       // right-edge i-face fluxes, per row, plane r at [r]
   double red[(NY + 1) * 8];
 };
 
@@ -228,7 +232,9 @@ __device__ void helper3d(const DevTile& tl, const DevBlock* __restrict__ blocks,
 #pragma unroll
   for (int h = 0; h < 4; ++h) load3(hs[h].p + (long long)k0 * hs[h].ps, hs[h].vs, hv[h]);
   load3(cs.p + (long long)k0 * cs.ps, cs.vs, cv);
-  for (int r = 0; r < n; ++r) {
+  // the halo of plane r into buffer b, then the loads of plane r + 1
+  // (clamped inside the tile; the last one is not used)
+  auto stage = [&](int r, int b) {
     if (fixrows) {
 #pragma unroll
       for (int h = 0; h < 4; ++h) fix3(hs[h].kind, hs[h].f, B, hv[h]);
@@ -236,31 +242,34 @@ __device__ void helper3d(const DevTile& tl, const DevBlock* __restrict__ blocks,
     if (fixcells && hlane) fix3(cs.kind, cs.f, B, cv);
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      sm.q[0][v][lane + 2] = T(hv[0][v]);
-      sm.q[1][v][lane + 2] = T(hv[1][v]);
-      sm.q[ny + 2][v][lane + 2] = T(hv[2][v]);
-      sm.q[ny + 3][v][lane + 2] = T(hv[3][v]);
+      sm.q[b][0][v][lane + 2] = T(hv[0][v]);
+      sm.q[b][1][v][lane + 2] = T(hv[1][v]);
+      sm.q[b][ny + 2][v][lane + 2] = T(hv[2][v]);
+      sm.q[b][ny + 3][v][lane + 2] = T(hv[3][v]);
     }
     if (hlane) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sm.q[crow][v][cslot] = T(cv[v]);
+      for (int v = 0; v < 5; ++v) sm.q[b][crow][v][cslot] = T(cv[v]);
     }
-    // the next plane (clamped inside the tile; the last one is not used)
     const long long kn = k0 + min(r + 1, n - 1);
 #pragma unroll
     for (int h = 0; h < 4; ++h) load3(hs[h].p + kn * hs[h].ps, hs[h].vs, hv[h]);
     load3(cs.p + kn * cs.ps, cs.vs, cv);
-    __syncthreads();
+  };
+  stage(0, 0);
+  __syncthreads();
+  for (int r = 0; r < n; ++r) {
+    const int b = r & 1;
     // top-edge j-face at j0+ny-1/2 from rows ny .. ny+3 (slots)
     {
       T qL[5], qR[5], G[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v)
-        face_states<LIM>(rc, sm.q[ny][v][lane + 2], sm.q[ny + 1][v][lane + 2], sm.q[ny + 2][v][lane + 2],
-                         sm.q[ny + 3][v][lane + 2], qL[v], qR[v]);
+        face_states<LIM>(rc, sm.q[b][ny][v][lane + 2], sm.q[b][ny + 1][v][lane + 2],
+                         sm.q[b][ny + 2][v][lane + 2], sm.q[b][ny + 3][v][lane + 2], qL[v], qR[v]);
       roe_flux<T, 3, 1>(qL, qR, nullptr, ay, K, G);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) sm.f[ny][v][lane] = G[v];
+      for (int v = 0; v < 5; ++v) sm.f[b][ny][v][lane] = G[v];
     }
     // right-edge i-face at i0+ncol-1/2 of every row (lane = row) from slots
     // ncol .. ncol+3
@@ -269,14 +278,15 @@ __device__ void helper3d(const DevTile& tl, const DevBlock* __restrict__ blocks,
       T qL[5], qR[5], G[5];
 #pragma unroll
       for (int v = 0; v < 5; ++v)
-        face_states<LIM>(rc, sm.q[er + 2][v][nc], sm.q[er + 2][v][nc + 1], sm.q[er + 2][v][nc + 2],
-                         sm.q[er + 2][v][nc + 3], qL[v], qR[v]);
+        face_states<LIM>(rc, sm.q[b][er + 2][v][nc], sm.q[b][er + 2][v][nc + 1], sm.q[b][er + 2][v][nc + 2],
+                         sm.q[b][er + 2][v][nc + 3], qL[v], qR[v]);
       roe_flux<T, 3, 0>(qL, qR, nullptr, ax, K, G);
       if (lane < ny) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) sm.edge[lane][v][r] = G[v];
       }
     }
+    if (r + 1 < n) stage(r + 1, b ^ 1);
     __syncthreads();
   }
 }
@@ -340,12 +350,20 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
   double nacc[5] = {0, 0, 0, 0, 0};
   double dmin = INFINITY;
   int bad = 0;
-  T* const qrow = &sm.q[rowact ? w + 2 : 0][0][0];
+  const int qr = rowact ? w + 2 : 0;  // own row in the LDS planes
+  // plane k0 into buffer 0 (the helper stages its halo alongside)
+  if (rowact && act) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sm.q[0][qr][v][lane + 2] = T(q0[v]);
+  }
+  __syncthreads();
 
   auto step = [&](auto first_t, auto last_t, int r) {
     constexpr bool FIRST = decltype(first_t)::value;
     constexpr bool LASTP = decltype(last_t)::value;
     const int k = k0 + r;
+    const int b = r & 1;
+    T* const qrow = &sm.q[b][qr][0][0];
     // ---- (1) the plane k+2 of the own column
     double q2[5];
     Src3 s2;
@@ -359,16 +377,9 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
         load3(s2.p, s2.vs, q2);
       }
     }
-    // ---- (2) stage plane k in LDS
+    // ---- (2) plane k is in LDS buffer b (staged one plane ahead)
     T Gk[5] = {T(0), T(0), T(0), T(0), T(0)}, ep0[5] = {T(0), T(0), T(0), T(0), T(0)};
     T Gi[5];
-    if constexpr (!LASTP) {
-      if (rowact && act) {
-#pragma unroll
-        for (int v = 0; v < 5; ++v) qrow[v * kS3 + lane + 2] = T(q0[v]);
-      }
-      __syncthreads();
-    }
     // ---- (3) k-face at k-1/2, and (in-plane) j-face at j-1/2 and i-face at
     //      i-1/2 from LDS: independent, their arithmetic interleaves
     if (rowact) {
@@ -388,11 +399,11 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
         T qL[5], qR[5], Gj[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v)
-          face_states<LIM>(rc, sm.q[w][v][lane + 2], sm.q[w + 1][v][lane + 2], sm.q[w + 2][v][lane + 2],
-                           sm.q[w + 3][v][lane + 2], qL[v], qR[v]);
+          face_states<LIM>(rc, sm.q[b][w][v][lane + 2], sm.q[b][w + 1][v][lane + 2],
+                           sm.q[b][w + 2][v][lane + 2], sm.q[b][w + 3][v][lane + 2], qL[v], qR[v]);
         roe_flux<T, 3, 1>(qL, qR, nullptr, ay, K, Gj);
 #pragma unroll
-        for (int v = 0; v < 5; ++v) sm.f[w][v][lane] = Gj[v];
+        for (int v = 0; v < 5; ++v) sm.f[b][w][v][lane] = Gj[v];
 #pragma unroll
         for (int v = 0; v < 5; ++v)
           face_states<LIM>(rc, qrow[v * kS3 + lane], qrow[v * kS3 + lane + 1], T(q0[v]),
@@ -400,6 +411,13 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
         roe_flux<T, 3, 0>(qL, qR, nullptr, ax, K, Gi);
 #pragma unroll
         for (int v = 0; v < 5; ++v) sm.g[w][v][lane] = Gi[v];
+      }
+    }
+    // ---- (3b) stage plane k + 1 (the next step's) in the other buffer
+    if constexpr (!LASTP) {
+      if (r + 1 < n && rowact && act) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) sm.q[b ^ 1][qr][v][lane + 2] = T(qn[v]);
       }
     }
     // ---- (4) complete plane k-1
@@ -458,9 +476,14 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
 #pragma unroll
         for (int v = 0; v < 5; ++v)
           rg[v] = (((double)gsrc[v * gstr] - (double)Gi[v]) +
-                   ((double)sm.f[w + 1][v][lane] - (double)sm.f[w][v][lane])) -
+                   ((double)sm.f[b][w + 1][v][lane] - (double)sm.f[b][w][v][lane])) -
                   (double)Gk[v];
       }
+      // the next step rewrites this wave's g row: its lanes' reads above
+      // come first
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       // ---- (6) rotate
       if (k + 2 >= nk) fix3(s2.kind, s2.f, B, q2);
 #pragma unroll
