@@ -244,6 +244,14 @@ template <typename T>
 __device__ __forceinline__ T half_eps_minmod(T qeps, T a, T b) {
   return (copysign(qeps, a) + copysign(qeps, b)) * fmin(fabs(a), fabs(b));
 }
+// In FP32 the hardware median of three does it in one instruction: the
+// median of a, b and 0 is min(a, b) when both are positive, max(a, b) when
+// both are negative and 0 otherwise, i.e. minmod(a, b); times eps/2 (2 qeps,
+// exact) it rounds once, as the form above
+template <>
+__device__ __forceinline__ float half_eps_minmod(float qeps, float a, float b) {
+  return (2.0f * qeps) * __builtin_amdgcn_fmed3f(a, b, 0.0f);
+}
 
 template <int LIM = -1, typename T>
 __device__ __forceinline__ void extrap(const Recon<T>& R, T dm, T dp, T& ep, T& em) {
