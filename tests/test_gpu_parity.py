@@ -404,6 +404,50 @@ def ragged_3d():
     return CS.Case("ragged_3d", 3, [blk], [U], CS.Params(qref=CS.qref_of(prim, 3)), 1)
 
 
+def deep_3d():
+    """70 x 17 x 70 cells: a full and a ragged tile in i and in k (with
+    64-plane tiles), 17 rows (ragged for both 3- and 7-row tiles)."""
+    case = CS.blobs_case(24, nblobs=3, seed=5)
+    prim = case.meta["prim"]
+    ni, nj, nk = 70, 17, 70
+    rng = np.random.default_rng(23)
+    rho = prim[0] * (1 + 0.05 * rng.standard_normal((nk, nj, ni)))
+    vel = [np.full_like(rho, prim[1]), 0.1 * prim[1] * rng.standard_normal(rho.shape),
+           0.1 * prim[1] * rng.standard_normal(rho.shape)]
+    U = CS.conserved(rho, vel, np.full_like(rho, prim[4]))
+    bcs = [CS.BC(CS.INFLOW, prim=prim), CS.BC(CS.EXTRAP), CS.BC(CS.PERIODIC), CS.BC(CS.PERIODIC),
+           CS.BC(CS.SLIPWALL), CS.BC(CS.EXTRAP)]
+    blk = CS.Block(ni, nj, nk, None, None, (0, 0, 0), (1.0 / 70, 1.0 / 60, 1.0 / 65), bcs)
+    return CS.Case("deep_3d", 3, [blk], [U], CS.Params(qref=CS.qref_of(prim, 3)), 1)
+
+
+def test_3d_tile_shape_independence(env, tmp_path):
+    """Every 3D tile shape, up to 64 planes and with ragged tiles in i, j and
+    k, gives the same state bit for bit; one of them is checked against the
+    oracle."""
+    fv, O = env
+    case = deep_3d()
+    cls = int(math.floor(math.log2(case.ncells)))
+    outs = []
+    for planes, ny in ((4, 3), (13, 7), (64, 7), (64, 3), (8, 7)):
+        path = tmp_path / f"t{planes}_{ny}.json"
+        path.write_text(json.dumps({f"3d_fp64_c{cls}": {"rows": planes, "ny": ny, "ms": 0.0}}))
+        os.environ["FV_AUTOTUNE_CACHE"] = str(path)
+        try:
+            g, _ = gpu_run(fv, case, 6)
+            st = g.stats()
+            assert (st["tile_rows"], st["tile_ny"]) == (planes, ny)
+            outs.append(g.get_state())
+        finally:
+            del os.environ["FV_AUTOTUNE_CACHE"]
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
+    ref = O.OracleGrid(case)
+    ref.run(case.params, 6)
+    e = P.state_err(case, outs[0], ref.get_state())
+    say(f"  deep_3d, 5 tile shapes bitwise equal; 6 steps vs oracle e_U = {e:.3e}")
+    assert e <= P.FP64_TOL
+
+
 def two_block_3d():
     a = ragged_3d()
     b = ragged_3d()
