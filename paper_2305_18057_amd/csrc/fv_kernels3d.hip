@@ -286,8 +286,11 @@ __device__ void helper3d(const DevTile& tl, const DevBlock* __restrict__ blocks,
         for (int v = 0; v < 5; ++v) sm.edge[lane][v][r] = G[v];
       }
     }
+    // as the row waves: lower priority once the plane's fluxes are formed
+    __builtin_amdgcn_s_setprio(0);
     if (r + 1 < n) stage(r + 1, b ^ 1);
     __syncthreads();
+    __builtin_amdgcn_s_setprio(2);
   }
 }
 
@@ -420,6 +423,9 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
         for (int v = 0; v < 5; ++v) sm.q[b ^ 1][qr][v][lane + 2] = T(qn[v]);
       }
     }
+    // this plane's fluxes are formed: the other wave of the SIMD goes first
+    // until the barrier (both must reach it; the older one would run ahead)
+    __builtin_amdgcn_s_setprio(0);
     // ---- (4) complete plane k-1
     if constexpr (!FIRST) {
       if (rowact && act) {
@@ -469,6 +475,7 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
       // U^n of plane k for the next update
       if constexpr (SK::reads_un) col_load(Un, k, un);
       __syncthreads();
+      __builtin_amdgcn_s_setprio(2);
       // ---- (5) the pending in-plane part of plane k
       if (rowact) {
         const T* gsrc = lane == last ? &sm.edge[w][0][r] : &sm.g[w][0][lane + 1];
