@@ -78,6 +78,36 @@ def test_workspace_bytes_and_validation(fvb):
     assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) == 0
 
 
+def test_degenerate_grids_rejected(fvb):
+    """Empty and degenerate descriptors are errors (0 bytes and a message),
+    never a grid."""
+    L = fvb.lib()
+    for ni, nj in ((0, 8), (8, 0), (-4, 8)):
+        c = CS.vortex_2d(8, 8, noise=0.0)
+        b = c.blocks[0]
+        c.blocks[0] = CS.Block(ni, nj, 1, None, None, b.origin, b.h, b.bc)
+        gd = fvb.GridDesc(c)
+        assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) == 0
+        assert b"bad extents" in L.fv_last_error()
+    c = CS.vortex_2d(8, 8, noise=0.0)
+    gd = fvb.GridDesc(c)
+    gd.desc.nblocks = 0
+    assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) == 0
+    assert b"no blocks" in L.fv_last_error()
+    gd = fvb.GridDesc(c)
+    gd.desc.gamma = 1.0
+    assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) == 0
+    gd = fvb.GridDesc(c)
+    gd.desc.ndim = 4
+    assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) == 0
+    c = CS.vortex_2d(8, 8, noise=0.0)
+    b = c.blocks[0]
+    c.blocks[0] = CS.Block(8, 8, 1, None, None, b.origin, (0.0, b.h[1], b.h[2]), b.bc)
+    gd = fvb.GridDesc(c)
+    assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) == 0
+    assert b"spacing" in L.fv_last_error()
+
+
 def test_create_grid_rejects_small_workspace(fvb):
     L = fvb.lib()
     case = CS.vortex_2d(16, 8)
