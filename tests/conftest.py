@@ -22,14 +22,16 @@ def orc():
 
 def pytest_sessionfinish(session, exitstatus):
     """GPU runs: every parity error the tests measured, with its case, goes to
-    gpurun_out/parity_report.txt (the tests also print them)."""
+    the file named by FV_PARITY_REPORT, when set (the tests also print them)."""
+    path = os.environ.get("FV_PARITY_REPORT")
+    if not path:
+        return
     try:
         from tests import parity
     except Exception:
         return
     if not parity.REPORT:
         return
-    out = os.path.join(ROOT, "gpurun_out")
-    os.makedirs(out, exist_ok=True)
-    with open(os.path.join(out, "parity_report.txt"), "w") as fh:
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    with open(path, "w") as fh:
         fh.write("\n".join(parity.REPORT) + "\n")
