@@ -184,9 +184,9 @@ int fv_residual(fv_grid* g, const fv_params* p, double* R, int on_device, double
 size_t fv_ghost_count(const fv_grid* g);
 int fv_ghosts(fv_grid* g, double* G, int on_device);
 
-/* Advance nsteps SSP-RK3 steps (fewer if t_end is reached or the state
- * turns non-physical: then FV_E_NONPHYSICAL and info->steps counts the
- * completed steps).  The time step is dt_fixed, or cfl times the minimum
+/* Advance nsteps steps of the scheme p->rk (SSP-RK3 by default; fewer if
+ * t_end is reached or the state turns non-physical: then FV_E_NONPHYSICAL
+ * and info->steps counts the completed steps).  The time step is dt_fixed, or cfl times the minimum
  * over cells of |Omega| / sum_d(|u . S_d| + c |S_d|) at U^n. */
 int fv_step(fv_grid* g, const fv_params* p, int nsteps, fv_step_info* info);
 
