@@ -669,6 +669,10 @@ def main():
     roof["achievable_copy_gbs"] = copy_bandwidth()
 
     extra = {}
+    props = torch.cuda.get_device_properties(0)
+    extra["env"] = dict(device=torch.cuda.get_device_name(0), arch=getattr(props, "gcnArchName", ""),
+                        compute_units=getattr(props, "multi_processor_count", None), hip=torch.version.hip,
+                        torch=torch.__version__)
     rep = repeat_timing(fv, case, prm, args.steps, 5, tune_cache)
     extra["repeats"] = rep
     log(f"[bench] median of {rep['reps']} runs from the restored initial state: "
