@@ -513,28 +513,6 @@ __device__ __forceinline__ TileWalk xcd_walk(int ntiles, int slots_per_wg, int s
   return w;
 }
 
-// As xcd_walk, but each workgroup of an XCD takes a contiguous share of that
-// XCD's range (shares differ by at most one tile).  Consecutive tiles of one
-// workgroup then lie side by side in memory, so a new tile finds its address
-// translations and much of its data already cached.  One tile slot per
-// workgroup.
-__device__ __forceinline__ TileWalk xcd_walk_blocked(int ntiles) {
-  const int G = gridDim.x;
-  TileWalk w;
-  w.stride = 1;
-  if (G % kXcds != 0) {
-    w.t = (int)(((long long)blockIdx.x * ntiles) / G);
-    w.end = (int)(((long long)(blockIdx.x + 1) * ntiles) / G);
-    return w;
-  }
-  const int x = blockIdx.x % kXcds, k = blockIdx.x / kXcds, per = G / kXcds;
-  const int chunk = (ntiles + kXcds - 1) / kXcds;
-  const int beg = min(ntiles, x * chunk), len = min(ntiles, beg + chunk) - beg;
-  w.t = beg + (int)(((long long)k * len) / per);
-  w.end = beg + (int)(((long long)(k + 1) * len) / per);
-  return w;
-}
-
 // Issue priority of a wavefront from its progress through a 2D tile.  Two
 // tiles share each SIMD; with equal priorities the older wavefront is issued
 // first, runs ahead, and the younger one ends its tile alone with nothing to

@@ -577,7 +577,10 @@ __global__ __launch_bounds__(64 * (NY + 1), 2) void k_stage3d(const DevTile* __r
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // a count fixed at launch saves one dependent load before the first tile
   const int ntiles = nfix >= 0 ? nfix : *ntiles_p;
-  for (TileWalk tw = xcd_walk_blocked(ntiles); tw.t < tw.end; tw.t += tw.stride) {
+  // one tile per workgroup at a time, the XCD's workgroups on consecutive
+  // tiles: the tiles that run together are j-neighbours of one k-slab, so
+  // their halo rows are read once into the XCD's L2 and shared
+  for (TileWalk tw = xcd_walk(ntiles, 1, 0); tw.t < tw.end; tw.t += tw.stride) {
     const DevTile tl = tiles[tw.t];
     DevInstance& I = insts[tl.inst];
     if (MODE != 0 && I.stopped) continue;
