@@ -194,19 +194,25 @@ def test_tiny_grids(env):
         check_steps(fv, O, case, 5)
 
 
-def test_tile_shape_independence(env, tmp_path):
+@pytest.mark.parametrize("prec", [CS.FP64, CS.FP32_FLUX])
+def test_tile_shape_independence(env, tmp_path, prec):
     fv, O = env
     case = CS.inlet_case(200, 72, 2)
+    params = CS.Params(**{**case.params.__dict__, "precision": prec})
+    tag = "fp64" if prec == CS.FP64 else "fp32flux"
     outs = []
     for rows in (2, 3, 4, 16, 64):
         path = tmp_path / f"t{rows}.json"
         hg = CS.inlet_case(200, 72, 2)
         ncell = hg.ncells
         cls = int(math.floor(math.log2(ncell)))
-        path.write_text(json.dumps({f"2d_fp64_c{cls}": {"rows": rows, "ny": 1, "ms": 0.0}}))
+        path.write_text(json.dumps({f"2d_{tag}_c{cls}": {"rows": rows, "ny": 1, "ms": 0.0}}))
         os.environ["FV_AUTOTUNE_CACHE"] = str(path)
         try:
-            g, _ = gpu_run(fv, case, 12)
+            g = fv.Grid(case)
+            g.set_state(case.state_flat())
+            g.tune(params)
+            g.step(params, 12)
             assert g.stats()["tile_rows"] == rows
             outs.append(g.get_state())
         finally:
@@ -421,20 +427,26 @@ def deep_3d():
     return CS.Case("deep_3d", 3, [blk], [U], CS.Params(qref=CS.qref_of(prim, 3)), 1)
 
 
-def test_3d_tile_shape_independence(env, tmp_path):
+@pytest.mark.parametrize("prec", [CS.FP64, CS.FP32_FLUX])
+def test_3d_tile_shape_independence(env, tmp_path, prec):
     """Every 3D tile shape, up to 64 planes and with ragged tiles in i, j and
     k, gives the same state bit for bit; one of them is checked against the
     oracle."""
     fv, O = env
     case = deep_3d()
+    params = CS.Params(**{**case.params.__dict__, "precision": prec})
+    tag = "fp64" if prec == CS.FP64 else "fp32flux"
     cls = int(math.floor(math.log2(case.ncells)))
     outs = []
     for planes, ny in ((4, 3), (13, 7), (64, 7), (64, 3), (8, 7)):
         path = tmp_path / f"t{planes}_{ny}.json"
-        path.write_text(json.dumps({f"3d_fp64_c{cls}": {"rows": planes, "ny": ny, "ms": 0.0}}))
+        path.write_text(json.dumps({f"3d_{tag}_c{cls}": {"rows": planes, "ny": ny, "ms": 0.0}}))
         os.environ["FV_AUTOTUNE_CACHE"] = str(path)
         try:
-            g, _ = gpu_run(fv, case, 6)
+            g = fv.Grid(case)
+            g.set_state(case.state_flat())
+            g.tune(params)
+            g.step(params, 6)
             st = g.stats()
             assert (st["tile_rows"], st["tile_ny"]) == (planes, ny)
             outs.append(g.get_state())
@@ -444,8 +456,8 @@ def test_3d_tile_shape_independence(env, tmp_path):
     ref = O.OracleGrid(case)
     ref.run(case.params, 6)
     e = P.state_err(case, outs[0], ref.get_state())
-    say(f"  deep_3d, 5 tile shapes bitwise equal; 6 steps vs oracle e_U = {e:.3e}")
-    assert e <= P.FP64_TOL
+    say(f"  deep_3d {tag}, 5 tile shapes bitwise equal; 6 steps vs oracle e_U = {e:.3e}")
+    assert e <= (P.FP64_TOL if prec == CS.FP64 else P.FP32_RUN_TOL)
 
 
 def two_block_3d():
