@@ -519,3 +519,210 @@ def test_inflow_table_golden():
     prim = C.inlet_freestream()
     assert prim[0] == pytest.approx(gold["derived"]["rho"], rel=1e-6)
     assert prim[1] == pytest.approx(gold["derived"]["u"], rel=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# Residual norm and drop (reading of the residual print of Sec. 4: per
+# variable RMS of R/|Omega| over every interior cell of the instance; combined
+# norm sqrt(sum_v (r_v/q_v)^2); drop = norm / first step's norm).
+# The residual itself is a closed form here: with first-order states, uniform
+# u > 0 and p, and a density that varies along x only, every jump is a pure
+# contact, the Roe flux is exactly the upwind physical flux F(Q_L).n, and
+#   R_rho = u h_y (rho_i - rho_{i-1}),  R_mx = u R_rho,  R_my = 0,
+#   R_E = u^2/2 R_rho.
+# ---------------------------------------------------------------------------
+def _contact_ring(orc, hx_list, ni_list, nj, hy, u0, p0, rho_cols, qref):
+    """Blocks along i joined into a ring by block links; rows identical."""
+    nb = len(ni_list)
+    blocks, U0 = [], []
+    o = 0
+    for b in range(nb):
+        bc = [C.BC(C.BLOCK, (b - 1) % nb, 1), C.BC(C.BLOCK, (b + 1) % nb, 0),
+              C.BC(C.PERIODIC), C.BC(C.PERIODIC), C.BC(C.PERIODIC), C.BC(C.PERIODIC)]
+        blocks.append(C.Block(ni_list[b], nj, 1, None, None, (0, 0, 0), (hx_list[b], hy, 1.0), bc))
+        rho = np.tile(rho_cols[o:o + ni_list[b]], (nj, 1))
+        U0.append(C.conserved(rho, [np.full_like(rho, u0), np.zeros_like(rho)],
+                              np.full_like(rho, p0))[:, None])
+        o += ni_list[b]
+    prm = C.Params(dt_fixed=1e-6, limiter=C.FIRST_ORDER, qref=qref)
+    return C.Case("contact_ring", 2, blocks, U0, prm, 1)
+
+
+def test_residual_norm_closed_form_unequal_blocks(orc):
+    rng = np.random.default_rng(21)
+    ni_list, hx_list, nj, hy = [6, 10, 3], [0.1, 0.05, 0.2], 3, 0.2
+    u0, p0 = 0.8, 1.0
+    rho_cols = 1.0 + 0.2 * rng.random(sum(ni_list))
+    qref = (2.0, 0.5, 3.0, 4.0)
+    case = _contact_ring(orc, hx_list, ni_list, nj, hy, u0, p0, rho_cols, qref)
+    g = orc.OracleGrid(case)
+    info = g.run(case.params, 1)
+    # closed-form residual per cell, then R/|Omega| with each block's own volume
+    vol = np.concatenate([np.full(n, h * hy) for n, h in zip(ni_list, hx_list)])
+    r_rho = u0 * hy * (rho_cols - np.roll(rho_cols, 1)) / vol
+    N = nj * len(rho_cols)  # every interior cell of the instance
+    rms = math.sqrt(nj * np.sum(r_rho ** 2) / N)
+    expect = np.array([rms, u0 * rms, 0.0, 0.5 * u0 * u0 * rms])
+    assert np.max(np.abs(info["norms"][:4] - expect)) <= 1e-13 * rms
+    comb = math.sqrt(sum((expect[v] / qref[v]) ** 2 for v in range(4)))
+    assert info["norm"] == pytest.approx(comb, rel=1e-13)
+    assert info["drop"] == 1.0
+    # the per-variable norms from a residual evaluation are the same numbers
+    _, norms = orc.OracleGrid(case).residual(case.params)
+    assert np.max(np.abs(norms[:4] - expect)) <= 1e-13 * rms
+
+
+def test_residual_drop_closed_form_fourier_mode(orc):
+    # one Fourier mode of the density on a periodic line, first order: each
+    # SSP-RK3 step multiplies it by G = 1 + z + z^2/2 + z^3/6 with
+    # z = -nu (1 - e^{-i theta}); the norm of step n comes from R(U^{n-1}),
+    # so drop after n steps is |G|^{n-1}, and r_rho = sqrt(2) a |sin(theta/2)| u/h.
+    N, k, a = 40, 3, 1e-2
+    h, u0, p0, nu = 1.0 / N, 0.7, 1.0, 0.6
+    xi = np.arange(N)
+    th = 2 * math.pi * k / N
+    rho = 1.0 + a * np.cos(th * xi)
+    U = C.conserved(rho[None, :], [np.full((1, N), u0), np.zeros((1, N))], np.full((1, N), p0))[:, None]
+    blk = C.Block(N, 1, 1, None, None, (0, 0, 0), (h, h, 1.0), [C.BC(C.PERIODIC)] * 6)
+    prm = C.Params(dt_fixed=nu * h / u0, limiter=C.FIRST_ORDER, qref=(1.0, 1.0, 1.0, 1.0))
+    case = C.Case("wave", 2, [blk], [U], prm, 1)
+    z = -nu * (1 - np.exp(-1j * th))
+    Gabs = abs(1 + z + z * z / 2 + z ** 3 / 6)
+    g = orc.OracleGrid(case)
+    first = g.run(prm, 1)
+    r_rho = math.sqrt(2.0) * a * abs(math.sin(th / 2)) * u0 / h
+    assert first["norms"][0] == pytest.approx(r_rho, rel=1e-12)
+    assert first["norm"] == pytest.approx(r_rho * math.sqrt(1 + u0 ** 2 + (0.5 * u0 * u0) ** 2),
+                                          rel=1e-12)
+    for n in (2, 5, 9):
+        info = g.run(prm, n - g.run(prm, 0)["steps"])
+        assert info["steps"] == n
+        assert info["drop"] == pytest.approx(Gabs ** (n - 1), rel=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# Harten's entropy fix against an independent matrix form of the Roe flux:
+#   F = (F(Q_L).n + F(Q_R).n)/2 - R |Lambda|_delta R^{-1} (Q_R - Q_L) / 2,
+# with the Roe matrix taken as the Jacobian of F.n at the Roe-averaged
+# velocity and enthalpy (complex-step derivative of the physical flux),
+# |A| formed by Sylvester's formula over its eigenvalues, and on the two
+# acoustic eigenvalues
+# |l| replaced by (l^2 + delta^2)/(2 delta) where |l| < delta, delta being
+# entropy_fix times the sound speed, read off the eigenvalues as half the
+# spread between the acoustic pair.
+# ---------------------------------------------------------------------------
+def _flux_n(q, n, nd):
+    rho = q[0]
+    m = q[1:1 + nd]
+    E = q[nd + 1]
+    vel = m / rho
+    p = (G - 1) * (E - 0.5 * np.sum(m * vel))
+    Vn = np.sum(vel * n[:nd])
+    return np.concatenate([[rho * Vn], m * Vn + p * n[:nd], [(E + p) * Vn]])
+
+
+def _jacobian_at(vel, H, n, nd):
+    # a state with velocity vel and total enthalpy H (the density cancels)
+    rho = 1.0
+    p = (G - 1) / G * rho * (H - 0.5 * np.sum(vel ** 2))
+    q = np.concatenate([[rho], rho * vel, [p / (G - 1) + 0.5 * rho * np.sum(vel ** 2)]]).astype(complex)
+    A = np.zeros((nd + 2, nd + 2))
+    hs = 1e-30
+    for c in range(nd + 2):
+        qc = q.copy()
+        qc[c] += 1j * hs
+        A[:, c] = np.imag(_flux_n(qc, n.astype(complex), nd)) / hs
+    return A
+
+
+def _roe_matrix_form(qL, qR, n, nd, efix, delta_of=None):
+    def prim(q):
+        rho = q[0]
+        vel = q[1:1 + nd] / rho
+        p = (G - 1) * (q[nd + 1] - 0.5 * rho * np.sum(vel ** 2))
+        return rho, vel, (q[nd + 1] + p) / rho
+    rL, vL, HL = prim(qL)
+    rR, vR, HR = prim(qR)
+    wL, wR = math.sqrt(rL), math.sqrt(rR)
+    vel = (wL * vL + wR * vR) / (wL + wR)
+    H = (wL * HL + wR * HR) / (wL + wR)
+    A = _jacobian_at(vel, H, n, nd)
+    lam = np.sort(np.real(np.linalg.eigvals(A)))
+    # three distinct eigenvalues V_n - c, V_n (repeated), V_n + c; a function
+    # of the diagonalisable A is then Sylvester's sum over them
+    ev = [lam[0], 0.5 * (lam[0] + lam[-1]), lam[-1]]
+    c = 0.5 * (lam[-1] - lam[0])
+    delta = efix * c if delta_of is None else delta_of(c, vel)
+
+    def f(l, acoustic):
+        a = abs(l)
+        if acoustic and delta > 0 and a < delta:
+            a = (l * l + delta * delta) / (2 * delta)
+        return a
+    I = np.eye(nd + 2)
+    absA = np.zeros_like(A)
+    for k in range(3):
+        P = I.copy()
+        for j in range(3):
+            if j != k:
+                P = P @ (A - ev[j] * I) / (ev[k] - ev[j])
+        absA += f(ev[k], k != 1) * P
+    D = absA @ (qR - qL)
+    lo = 0
+    return 0.5 * (_flux_n(qL, n, nd) + _flux_n(qR, n, nd)) - 0.5 * D, ev[0], c
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+def test_roe_harten_fix_matrix_form(orc, nd):
+    ang = math.radians(30.0)
+    n = np.array([math.cos(ang), math.sin(ang), 0.0])[:3]
+    t = np.array([-math.sin(ang), math.cos(ang), 0.0])
+    active = 0
+    worst_alt = 0.0
+    cases_ = [(efix, s, sg) for efix in (0.05, 0.1, 0.3) for s in np.linspace(-0.25, 0.25, 41)
+              for sg in (1.0, -1.0)]
+    for efix, s, sg in cases_:
+        # left and right states about a sonic point of the 1-wave,
+        # with a transverse velocity so that |u| differs from V_n
+        c0 = math.sqrt(G * 1.0 / 1.0)
+        vL = (c0 + s) * n + 0.6 * t
+        vR = (c0 + s + 0.04) * n + 0.55 * t
+        if nd == 3:
+            vL = vL + np.array([0, 0, 0.2])
+            vR = vR + np.array([0, 0, 0.25])
+        qL = cons(1.0, vL[:nd], 1.0)
+        qR = cons(0.93, vR[:nd], 0.9)
+        # sg = -1: the same states seen through the opposite normal, so
+        # that the other acoustic wave (V_n + c) is the sonic one
+        nn = sg * n
+        F = orc.roe(qL, qR, nn[:nd], mode=-1, entropy_fix=efix)
+        E, l1, c = _roe_matrix_form(qL, qR, nn, nd, efix)
+        scale = np.max(np.abs(E))
+        assert np.max(np.abs(F - E)) <= 1e-12 * scale, (efix, s)
+        if min(abs(l1), abs(l1 + 2 * c)) < efix * c:
+            active += 1
+            # the same flux with delta = efix or delta = efix |u| is far off
+            for alt in (lambda c_, v_: efix, lambda c_, v_: efix * np.linalg.norm(v_)):
+                Ea, _, _ = _roe_matrix_form(qL, qR, nn, nd, efix, delta_of=alt)
+                worst_alt = max(worst_alt, np.max(np.abs(Ea - E)) / scale)
+    assert active >= 10  # the fix was really exercised
+    assert worst_alt >= 1e-6  # and the test tells delta = efix*c from the alternatives
+
+
+def test_spectral_min_trapezoid_hand_value(orc):
+    # one trapezoidal cell, nodes (0,0) (2,0) (0,1) (1,1):
+    #   i-faces S = (1, 0) and (1, 1)  -> mean (1, 1/2)
+    #   j-faces S = (0, 2) and (0, 1)  -> mean (0, 3/2)
+    #   |Omega| = (2 + 1)/2 = 3/2
+    x = np.array([[0.0, 2.0], [0.0, 1.0]])
+    y = np.array([[0.0, 0.0], [1.0, 1.0]])
+    prim = (1.2, 0.3, -0.4, 0.0, 0.8)
+    case = C.uniform_2d(1, 1, prim, [C.BC(C.EXTRAP)] * 4 + [C.BC(C.PERIODIC)] * 2, x=x, y=y)
+    g = orc.OracleGrid(case)
+    st, mn = g.spectral_min()
+    c = math.sqrt(G * 0.8 / 1.2)
+    lam = abs(0.3 * 1.0 - 0.4 * 0.5) + c * math.sqrt(1.25) + abs(-0.4 * 1.5) + c * 1.5
+    assert st == 0 and mn == pytest.approx(1.5 / lam, rel=1e-15)
+    # and through a run: dt = CFL * that minimum
+    info = g.run(C.Params(cfl=0.4, qref=C.qref_of(prim, 2)), 1, dt_hist=True)
+    assert info["dt_hist"][0] == pytest.approx(0.4 * 1.5 / lam, rel=1e-15)
