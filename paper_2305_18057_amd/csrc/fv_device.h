@@ -120,16 +120,6 @@ __device__ __forceinline__ void stg(double* p, double v) { *(g_double*)p = v; }
 // the hardware estimates are used directly.
 template <typename T>
 struct M;
-#ifdef FV_PLAIN_MATH
-template <>
-struct M<double> {
-  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-  static __device__ __forceinline__ void sqrt2(double x, double& s, double& h) {
-    s = sqrt(x);
-    h = 0.5 / s;
-  }
-};
-#else
 template <>
 struct M<double> {
   static __device__ __forceinline__ double rcp(double x) {
@@ -154,7 +144,6 @@ struct M<double> {
     s = __builtin_fma(d, h, g);
   }
 };
-#endif
 template <>
 struct M<float> {
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -167,19 +156,8 @@ struct M<float> {
 
 // wave-wide neighbour shifts (DPP): shr1 gives lane l the value of lane l-1,
 // shl1 the value of lane l+1; the lane without a source keeps its own value
-#ifndef FV_SHIFT_BPERMUTE
 __device__ __forceinline__ int dpp_shr1(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x138, 0xf, 0xf, false); }
 __device__ __forceinline__ int dpp_shl1(int x) { return __builtin_amdgcn_update_dpp(x, x, 0x130, 0xf, 0xf, false); }
-#else
-__device__ __forceinline__ int dpp_shr1(int x) {
-  const int l = __lane_id();
-  return __shfl(x, l > 0 ? l - 1 : l, 64);
-}
-__device__ __forceinline__ int dpp_shl1(int x) {
-  const int l = __lane_id();
-  return __shfl(x, l < 63 ? l + 1 : l, 64);
-}
-#endif
 __device__ __forceinline__ double shr1(double x) {
   int2 v = __builtin_bit_cast(int2, x);
   v.x = dpp_shr1(v.x);
@@ -520,12 +498,10 @@ __device__ __forceinline__ TileWalk xcd_walk(int ntiles, int slots_per_wg, int s
 // the one behind is preferred and the two end their tiles together.  Only
 // the order of issue changes, never a result.
 __device__ __forceinline__ void prio_by_progress(int rows_done) {
-#ifndef FV_NO_PRIO
   if (rows_done <= 0) __builtin_amdgcn_s_setprio(3);
   else if (rows_done == 1) __builtin_amdgcn_s_setprio(2);
   else if (rows_done == 2) __builtin_amdgcn_s_setprio(1);
   else __builtin_amdgcn_s_setprio(0);
-#endif
 }
 
 // --------------------------------------------------------------------------

@@ -337,7 +337,16 @@ extern "C" int fv_step_timed(fv_grid* g, const fv_params* p, int nsteps, fv_step
   if (st) return st;
   FV_HIP(fvk::launch_prepare(g->stream, g->d_inst, nullptr, 1));
   const int fp32 = p->precision == FV_FP32_FLUX;
-  std::vector<hipEvent_t> ev(5 * (size_t)std::max(nsteps, 1));
+  // the events are released on every return path
+  struct Events {
+    std::vector<hipEvent_t> v;
+    ~Events() {
+      for (auto& e : v)
+        if (e) (void)hipEventDestroy(e);
+    }
+  } evs;
+  evs.v.assign(5 * (size_t)std::max(nsteps, 1), nullptr);
+  std::vector<hipEvent_t>& ev = evs.v;
   for (auto& e : ev) FV_HIP(hipEventCreate(&e));
   for (int k = 0; k < nsteps; ++k) {
     hipEvent_t* E = &ev[5 * (size_t)k];
@@ -362,7 +371,6 @@ extern "C" int fv_step_timed(fv_grid* g, const fv_params* p, int nsteps, fv_step
       }
     for (int s = 0; s < 4; ++s) g->last_ms[s] = stage_ms[s];
   }
-  for (auto& e : ev) (void)hipEventDestroy(e);
   if (st) return st;
   st = get_inst(g);
   if (st) return st;
@@ -435,9 +443,17 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
   }
   const int fp32 = p->precision == FV_FP32_FLUX;
   const int rk = fvrt::rk_of(p);
-  hipEvent_t e0, e1;
-  FV_HIP(hipEventCreate(&e0));
-  FV_HIP(hipEventCreate(&e1));
+  // the two timing events are released on every return path
+  struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  FV_HIP(hipEventCreate(&ev.a));
+  FV_HIP(hipEventCreate(&ev.b));
+  hipEvent_t e0 = ev.a, e1 = ev.b;
   // per-step time of one candidate: steps run as they do in fv_step (graphs
   // of the step sequence), from the saved state; a warm-up, then the best of
   // three batches (a single short batch is too noisy to separate shapes a few
@@ -495,8 +511,6 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
       best_ms = ms[c];
       best = cands[c];
     }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   if (st) return st;
   g->shape = best;
   st = upload_tiles(g);

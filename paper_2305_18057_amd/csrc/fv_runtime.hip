@@ -53,6 +53,12 @@ int validate_and_copy(const fv_grid_desc* d, HostGrid& g) {
     }
     if (B.ni <= 0 || B.nj <= 0 || B.nk <= 0 || B.ni > kMaxDim || B.nj > kMaxDim || B.nk > kMaxDim)
       return set_error(FV_E_INVAL, "block %d: bad extents %d x %d x %d", b, B.ni, B.nj, B.nk);
+    // the 3D stage kernels address a cell within its k-plane by a 32-bit byte
+    // offset: a plane of one variable must stay below 4 GiB
+    if (g.ndim == 3 && (long long)B.ni * B.nj * 8LL >= (1LL << 32))
+      return set_error(FV_E_UNSUPPORTED,
+                       "block %d: a k-plane of %d x %d cells exceeds the 3D kernels' 32-bit "
+                       "in-plane offsets (ni * nj must stay below 2^29)", b, B.ni, B.nj);
     if (g.ndim == 3 && (B.x || B.y || B.z))
       return set_error(FV_E_UNSUPPORTED, "block %d: 3D grids must be uniform (x, y, z NULL)", b);
     if (g.ndim == 2 && ((B.x == nullptr) != (B.y == nullptr)))

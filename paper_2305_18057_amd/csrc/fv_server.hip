@@ -550,7 +550,7 @@ extern "C" int fv_submit(fv_server* S, const fv_grid_desc* desc, const double* U
   TileShape sh = default_shape(r->hg);
   TileShape tsh;
   if (tune_lookup(tune_path(S->tune_path.empty() ? nullptr : S->tune_path.c_str()),
-                  tune_key(r->hg, FV_FP64), tsh))
+                  tune_key(r->hg, S->d.precision), tsh))
     sh = tsh;
   r->shape = sh;
   r->kind = kind_of(r->hg, sh);

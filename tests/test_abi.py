@@ -115,3 +115,19 @@ def test_create_grid_rejects_small_workspace(fvb):
     h = C.c_void_p()
     st = L.fv_create_grid(C.byref(gd.desc), C.c_void_p(256), C.c_size_t(16), None, C.byref(h))
     assert st == fvb.FV_E_NOMEM and not h.value
+
+
+def test_3d_plane_beyond_32bit_offsets_rejected(fvb):
+    """The 3D kernels address a cell within a k-plane by a 32-bit byte offset,
+    so a plane of 2^29 or more cells is refused, with the reason."""
+    L = fvb.lib()
+    bc = [CS.BC(CS.PERIODIC)] * 6
+    for ni, nj, ok in ((32768, 16384, False), (16384, 32767, True)):
+        blk = CS.Block(ni, nj, 4, None, None, (0, 0, 0), (1.0, 1.0, 1.0), bc)
+        case = CS.Case("big_plane", 3, [blk], [], CS.Params(), 1)
+        gd = fvb.GridDesc(case)
+        n = L.fv_grid_workspace_bytes(C.byref(gd.desc), 0)
+        if ok:
+            assert n > 0
+        else:
+            assert n == 0 and b"32-bit" in L.fv_last_error()
