@@ -279,6 +279,24 @@ def roofline_of(case, stage_ms, steps, workload, fp32=False):
     return roof, alu
 
 
+def host_info():
+    """Host CPU model and core counts (the CPU baseline's machine)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return dict(host_cpu=model, nproc=usable, logical_cpus=os.cpu_count())
+
+
 def cpu_baseline(case, budget_s=12.0):
     from oracle import oracle as O
     ref = O.OracleGrid(case)
@@ -292,7 +310,8 @@ def cpu_baseline(case, budget_s=12.0):
     return dict(value=round(case.ncells * n / dt, 1), unit="cell-updates/s",
                 cores=O.num_threads(), kind="oracle",
                 sample=f"{case.name}: {n} SSP-RK3 steps of the full {case.ncells}-cell grid "
-                       f"({dt:.1f} s wall, FP64, OpenMP over faces/cells)")
+                       f"({dt:.1f} s wall, FP64, OpenMP over faces/cells)",
+                compiler="gcc " + " ".join(O.CFLAGS), **host_info())
 
 
 def cpu_single_core(case, budget_s=5.0):
@@ -313,7 +332,8 @@ def cpu_single_core(case, budget_s=5.0):
         O.set_threads(keep)
     return dict(value=round(case.ncells * n / dt, 1), unit="cell-updates/s", cores=1,
                 kind="oracle", sample=f"{case.name}: {n} SSP-RK3 steps of the full grid "
-                                      f"({dt:.1f} s wall, FP64, one thread)")
+                                      f"({dt:.1f} s wall, FP64, one thread)",
+                compiler="gcc " + " ".join(O.CFLAGS))
 
 
 # --------------------------------------------------------------------------
@@ -335,35 +355,71 @@ def _drain(srv, tickets, timeout=600.0):
 
 
 def _plain_solve(fv, case, drop_tol, max_steps, params=None):
-    """One request solved on its own: grid, upload, solve, download (wall)."""
+    """One request solved on its own: grid, upload, solve, download.  Returns
+    the wall time of all of it, the wall time of the solve alone (device
+    work of the steps, synchronised) and the solve's info."""
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     g = fv.Grid(case)
     g.set_state(case.state_flat())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
     info = g.solve(params or case.params, drop_tol=drop_tol, max_steps=max_steps, check=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
     g.get_state()
     dt = time.perf_counter() - t0
     g.close()
-    return dt, info
+    return dt, t2 - t1, info
+
+
+def size_class(ncells: int) -> int:
+    """floor(log2(cells)): the autotune table's size class of a grid."""
+    return max(0, int(ncells).bit_length() - 1)
+
+
+def tune_classes(fv, cases, cs, precisions, tune_cache):
+    """Tile shapes for every (dimension, size class, precision) among the
+    grids cs: the autotuner times each class once, on its first grid, and
+    records the fastest shape in the table the servers and grids read.
+    Returns {table key: {"rows", "ny"}} for the classes met."""
+    seen = set()
+    t0 = time.perf_counter()
+    for c in cs:
+        for pr in precisions:
+            key = f"{c.ndim}d_{'fp32flux' if pr == cases.FP32_FLUX else 'fp64'}_c{size_class(c.ncells)}"
+            if key in seen:
+                continue
+            seen.add(key)
+            g = fv.Grid(c)
+            g.set_state(c.state_flat())
+            g.tune(cases.Params(**{**c.params.__dict__, "precision": pr}), tune_cache)
+            g.close()
+    with open(tune_cache) as fh:
+        table = json.load(fh)
+    log(f"[bench] tuned {len(seen)} size classes in {time.perf_counter() - t0:.1f} s")
+    return {k: dict(rows=v["rows"], ny=v["ny"]) for k, v in sorted(table.items()) if k in seen}
 
 
 def arena_for(fv, cs, slack=1.5):
     return int(sum(fv.workspace_bytes(c) for c in cs) * slack) + (64 << 20)
 
 
-def bench_batched(fv, cases, steps=100, count=64, spl=10):
+def bench_batched(fv, cases, tune_cache, steps=100, count=64, spl=10):
     cs = cases.batch_2d(count, seed=4, nsteps=steps)  # FP32-flux
     cells = sum(c.ncells for c in cs)
     log(f"[bench] batched {count} instances, {cells} cells, {steps} steps")
-    # plain: one instance after the other, same precision
-    seq = 0.0
+    shapes = tune_classes(fv, cases, cs, [cases.FP32_FLUX], tune_cache) if tune_cache else {}
+    # plain: one instance after the other, same precision and tile shapes
+    seq = seq_steps = 0.0
     for c in cs:
-        dt, info = _plain_solve(fv, c, 0.0, steps)
+        dt, ds, info = _plain_solve(fv, c, 0.0, steps)
         assert info["steps"] == steps
         seq += dt
+        seq_steps += ds
     srv = fv.Server(arena_bytes=arena_for(fv, cs), max_instances=count,
-                    precision=cases.FP32_FLUX, steps_per_launch=spl)
+                    precision=cases.FP32_FLUX, steps_per_launch=spl, autotune_cache=tune_cache)
     # one untimed pass so that graphs and code objects are ready
     _drain(srv, [srv.submit(cs[0], drop_tol=0.0, max_steps=spl)])
     ts = [srv.submit(c, drop_tol=0.0, max_steps=steps) for c in cs]
@@ -374,14 +430,21 @@ def bench_batched(fv, cases, steps=100, count=64, spl=10):
     span = max(x[2] for x in tm) - min(x[0] for x in tm)
     return dict(instances=count, cells=cells, steps=steps, precision="fp32flux",
                 value=round(cells * steps / span, 1), unit="cell-updates/s",
-                makespan_s=round(span, 4), sequential_s=round(seq, 4),
-                sequential_value=round(cells * steps / seq, 1),
-                speedup=round(seq / span, 3), steps_per_launch=spl)
+                makespan_s=round(span, 4),
+                sequential_s=round(seq, 4), sequential_value=round(cells * steps / seq, 1),
+                speedup=round(seq / span, 3),
+                sequential_steps_only_s=round(seq_steps, 4),
+                sequential_steps_only_value=round(cells * steps / seq_steps, 1),
+                speedup_vs_steps_only=round(seq_steps / span, 3),
+                steps_per_launch=spl, tile_shapes=shapes,
+                note="makespan: first submission to last result, uploads included; sequential_s "
+                     "includes each instance's grid build, upload and download, "
+                     "sequential_steps_only_s only its solve")
 
 
-def _serve(fv, cases, reqs, built, arena, max_inst, spl, rate_scale=1.0):
+def _serve(fv, cases, reqs, built, arena, max_inst, spl, tune_cache, rate_scale=1.0):
     srv = fv.Server(arena_bytes=arena, max_instances=max_inst, precision=cases.FP32_FLUX,
-                    steps_per_launch=spl)
+                    steps_per_launch=spl, autotune_cache=tune_cache)
     _drain(srv, [srv.submit(built[0], drop_tol=0.0, max_steps=spl)])  # warm
     tickets = [None] * len(reqs)
     start = time.perf_counter()
@@ -409,7 +472,11 @@ def _serve(fv, cases, reqs, built, arena, max_inst, spl, rate_scale=1.0):
     span = max(x[2] for x in tm) - min(x[0] for x in tm)
     work = sum(built[q].ncells * done[q][2]["steps"] for q in range(len(reqs)))
     ok = sum(1 for q in range(len(reqs)) if done[q][0] == fv.FV_OK)
-    return lat, span, work, ok
+    conv = sum(1 for q in range(len(reqs)) if done[q][2]["flags"] & fv.FLAG_CONVERGED)
+    capped = sum(1 for q in range(len(reqs))
+                 if done[q][2]["steps"] >= reqs[q].spec["max_steps"]
+                 and not done[q][2]["flags"] & fv.FLAG_CONVERGED)
+    return lat, span, work, dict(ok=ok, converged=conv, capped=capped)
 
 
 def _pct(xs, p):
@@ -418,20 +485,37 @@ def _pct(xs, p):
     return s[i]
 
 
-def bench_serving(fv, cases, count=64, max_steps=500, spl=10, max_inst=32):
+def bench_serving(fv, cases, tune_cache, count=256, max_steps=2000, spl=10, max_inst=32):
+    """The serving trace as stated: 256 requests arriving as a Poisson stream
+    at 200/s, each solved to a residual drop of 1e-8 or 2000 steps, batched
+    in FP32-flux by the server, against plain FP64 solves one after the other
+    in arrival order on the same GPU."""
     reqs = cases.serving_trace(256, seed=5, max_steps=max_steps)[:count]
     built = [cases.build_request(r, precision=cases.FP32_FLUX) for r in reqs]
-    arena = min(arena_for(fv, built, 1.2), 48 << 30)
-    log(f"[bench] serving {count} requests (first {count} of the 256-request trace), "
-        f"max_steps {max_steps}, arena {arena >> 20} MiB")
-    lat, span, work, ok = _serve(fv, cases, reqs, built, arena, max_inst, spl)
-    # plain: sequential FP64 solves in arrival order on the same GPU
-    solve_s, steps_plain = [], []
-    for r in reqs:
-        c = cases.build_request(r, precision=cases.FP64)
-        dt, info = _plain_solve(fv, c, r.spec["drop_tol"], r.spec["max_steps"])
-        solve_s.append(dt)
-        steps_plain.append(info["steps"])
+    arena = min(arena_for(fv, built, 1.2), 64 << 30)
+    log(f"[bench] serving {count} requests, max_steps {max_steps}, arena {arena >> 20} MiB")
+    shapes = tune_classes(fv, cases, built, [cases.FP32_FLUX, cases.FP64], tune_cache) \
+        if tune_cache else {}
+    lat, span, work, cnt = _serve(fv, cases, reqs, built, arena, max_inst, spl, tune_cache)
+    log(f"[bench]   batched: makespan {span:.2f} s, {cnt}")
+    # plain: sequential FP64 solves in arrival order on the same GPU, with the
+    # FP64 shapes of the same table
+    keep = os.environ.get("FV_AUTOTUNE_CACHE")
+    if tune_cache:
+        os.environ["FV_AUTOTUNE_CACHE"] = tune_cache
+    solve_s, steps_plain, conv_p = [], [], 0
+    try:
+        for r, c in zip(reqs, built):
+            p64 = cases.Params(**{**c.params.__dict__, "precision": cases.FP64})
+            dt, _, info = _plain_solve(fv, c, r.spec["drop_tol"], r.spec["max_steps"], p64)
+            solve_s.append(dt)
+            steps_plain.append(info["steps"])
+            conv_p += 1 if info["flags"] & fv.FLAG_CONVERGED else 0
+    finally:
+        if keep is None:
+            os.environ.pop("FV_AUTOTUNE_CACHE", None)
+        else:
+            os.environ["FV_AUTOTUNE_CACHE"] = keep
     end = 0.0
     lat_p = []
     for r, s in zip(reqs, solve_s):
@@ -440,21 +524,28 @@ def bench_serving(fv, cases, count=64, max_steps=500, spl=10, max_inst=32):
         lat_p.append(end - r.arrival)
     span_p = end - reqs[0].arrival
     work_p = sum(b.ncells * n for b, n in zip(built, steps_plain))
+    log(f"[bench]   plain: makespan {span_p:.2f} s, {conv_p} converged")
     out = dict(requests=count, max_steps=max_steps, drop_tol=reqs[0].spec["drop_tol"],
-               arrival_rate_per_s=200.0, completed_ok=ok,
+               arrival_rate_per_s=200.0, completed_ok=cnt["ok"],
+               converged=cnt["converged"], capped=cnt["capped"],
                batched=dict(precision="fp32flux", p50_s=round(_pct(lat, 50), 4),
                             p99_s=round(_pct(lat, 99), 4), makespan_s=round(span, 4),
-                            value=round(work / span, 1), unit="cell-updates/s"),
+                            value=round(work / span, 1), unit="cell-updates/s",
+                            cell_steps=int(work)),
                plain=dict(precision="fp64", p50_s=round(_pct(lat_p, 50), 4),
                           p99_s=round(_pct(lat_p, 99), 4), makespan_s=round(span_p, 4),
-                          value=round(work_p / span_p, 1), unit="cell-updates/s"))
+                          value=round(work_p / span_p, 1), unit="cell-updates/s",
+                          converged=conv_p, cell_steps=int(work_p)),
+               tile_shapes=shapes)
     out["throughput_ratio"] = round(out["batched"]["value"] / out["plain"]["value"], 3)
     # supplementary: the same requests at about 0.7x the measured capacity
     cap_rate = count / span
     scale = (200.0 / (0.7 * cap_rate))
-    lat2, span2, work2, ok2 = _serve(fv, cases, reqs, built, arena, max_inst, spl, rate_scale=scale)
+    lat2, span2, work2, cnt2 = _serve(fv, cases, reqs, built, arena, max_inst, spl, tune_cache,
+                                      rate_scale=scale)
     out["low_load"] = dict(arrival_rate_per_s=round(200.0 / scale, 2), p50_s=round(_pct(lat2, 50), 4),
-                           p99_s=round(_pct(lat2, 99), 4), value=round(work2 / span2, 1))
+                           p99_s=round(_pct(lat2, 99), 4), value=round(work2 / span2, 1),
+                           converged=cnt2["converged"], capped=cnt2["capped"])
     return out
 
 
@@ -611,6 +702,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--no-tune", action="store_true", help="default tile shapes, no autotuning")
+    ap.add_argument("--serving-requests", type=int, default=256,
+                    help="requests of the 256-request serving trace to serve (default: all)")
     ap.add_argument("--tile-cache", help="autotune table (JSON); shapes already in it are reused "
                                          "without timing (default: a fresh temporary table)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -701,15 +794,18 @@ def main():
             gx.close()
             del gx
         extra["rk_schemes"] = bench_rk_schemes(fv, cases, tune_cache, args.steps)
-        extra["batched_64"] = bench_batched(fv, cases)
+        tc = tune_cache or os.path.join(tempfile.mkdtemp(prefix="fv_tune_"), "tiles.json")
+        extra["batched_64"] = bench_batched(fv, cases, None if args.no_tune else tc)
         b = extra["batched_64"]
         log(f"[bench]   batched {b['value']/1e9:.3f} G cell-updates/s vs sequential "
             f"{b['sequential_value']/1e9:.3f} G ({b['speedup']}x)")
-        extra["serving"] = bench_serving(fv, cases)
+        extra["serving"] = bench_serving(fv, cases, None if args.no_tune else tc,
+                                         count=args.serving_requests)
         s = extra["serving"]
         log(f"[bench]   serving p50 {s['batched']['p50_s']} s p99 {s['batched']['p99_s']} s, "
             f"{s['batched']['value']/1e9:.3f} G/s vs plain p50 {s['plain']['p50_s']} s "
-            f"p99 {s['plain']['p99_s']} s {s['plain']['value']/1e9:.3f} G/s")
+            f"p99 {s['plain']['p99_s']} s {s['plain']['value']/1e9:.3f} G/s; "
+            f"{s['converged']} converged, {s['capped']} at the step cap")
 
     cpu = None
     if not args.no_cpu:
@@ -753,6 +849,10 @@ def main():
         "cell_stage_updates_per_s": round(3 * value, 1),
         "ssspnt": round(1e-6 * case.ncells * 3 * args.steps / (dev_ms * 1e-3), 2),
         "roofline": roof,
+        # the 256^3 grid's stage kernel: its 2.1 GB working set does not fit the
+        # 256 MB last-level cache, so this is the DRAM-backed HBM figure
+        "roofline_blobs_3d": (dict(extra["blobs_3d_fp64"]["roofline"], workload="blobs_3d_fp64")
+                              if "blobs_3d_fp64" in extra else None),
         "alu": alu,
         "cpu_baseline": cpu,
         "extra": extra,

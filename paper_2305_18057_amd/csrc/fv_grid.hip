@@ -145,11 +145,14 @@ extern "C" int fv_create_grid(const fv_grid_desc* desc, void* d_workspace, size_
     delete g;
     return e;
   };
-  if (hipMemcpyAsync(g->d_blocks, g->hblocks.data(), sizeof(fvk::DevBlock) * g->hblocks.size(),
-                     hipMemcpyHostToDevice, g->stream) != hipSuccess ||
-      hipMemcpyAsync(g->d_segs, segs.data(), sizeof(fvk::GhostSeg) * segs.size(),
-                     hipMemcpyHostToDevice, g->stream) != hipSuccess)
-    return fail(set_error(FV_E_DEVICE, "upload of block descriptors failed"));
+  hipError_t he = hipMemcpyAsync(g->d_blocks, g->hblocks.data(),
+                                 sizeof(fvk::DevBlock) * g->hblocks.size(), hipMemcpyHostToDevice,
+                                 g->stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(g->d_segs, segs.data(), sizeof(fvk::GhostSeg) * segs.size(),
+                        hipMemcpyHostToDevice, g->stream);
+  if (he != hipSuccess)
+    return fail(set_error(FV_E_DEVICE, "upload of block descriptors failed: %s", hipGetErrorString(he)));
   // node coordinates
   {
     size_t noff = 0;
@@ -157,11 +160,14 @@ extern "C" int fv_create_grid(const fv_grid_desc* desc, void* d_workspace, size_
       if (g->hg.xs[b].empty()) continue;
       const size_t nn = g->hg.xs[b].size();
       char* dst = g->ws + g->L.nodes + noff * sizeof(double);
-      if (hipMemcpyAsync(dst, g->hg.xs[b].data(), nn * sizeof(double), hipMemcpyHostToDevice,
-                         g->stream) != hipSuccess ||
-          hipMemcpyAsync(dst + nn * sizeof(double), g->hg.ys[b].data(), nn * sizeof(double),
-                         hipMemcpyHostToDevice, g->stream) != hipSuccess)
-        return fail(set_error(FV_E_DEVICE, "upload of node coordinates failed"));
+      he = hipMemcpyAsync(dst, g->hg.xs[b].data(), nn * sizeof(double), hipMemcpyHostToDevice,
+                          g->stream);
+      if (he == hipSuccess)
+        he = hipMemcpyAsync(dst + nn * sizeof(double), g->hg.ys[b].data(), nn * sizeof(double),
+                            hipMemcpyHostToDevice, g->stream);
+      if (he != hipSuccess)
+        return fail(set_error(FV_E_DEVICE, "upload of node coordinates failed: %s",
+                              hipGetErrorString(he)));
       noff += 2 * nn;
     }
   }
@@ -186,8 +192,9 @@ extern "C" int fv_create_grid(const fv_grid_desc* desc, void* d_workspace, size_
   if (st) return fail(st);
   st = put_inst(g, true);
   if (st) return fail(st);
-  if (hipStreamSynchronize(g->stream) != hipSuccess)
-    return fail(set_error(FV_E_DEVICE, "stream synchronisation failed"));
+  he = hipStreamSynchronize(g->stream);
+  if (he != hipSuccess)
+    return fail(set_error(FV_E_DEVICE, "stream synchronisation failed: %s", hipGetErrorString(he)));
   *out = g;
   return FV_OK;
 }

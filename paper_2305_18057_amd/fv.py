@@ -102,6 +102,12 @@ def lib():
         raise FileNotFoundError(
             f"{LIB_PATH} is missing: build it with paper_2305_18057_amd/build.py "
             "(there is no CPU fallback)")
+    # device memory and streams come from PyTorch, so the library must run on
+    # PyTorch's HIP runtime: importing torch first makes the dynamic loader
+    # resolve the library's libamdhip64 to that copy (loaded the other way
+    # round, two runtimes would share the process and neither would know the
+    # other's memory and streams)
+    _torch()
     L = C.CDLL(LIB_PATH)
     vp, dp = C.c_void_p, C.POINTER(C.c_double)
     L.fv_strerror.restype = C.c_char_p

@@ -46,6 +46,26 @@ def state_err(case, Ug, Uo):
     return max(float(np.max(np.abs(gv - ov)) / s) for gv, ov, s in zip(g, o, sc))
 
 
+def component_errs(case, Ug, Uo):
+    """Per-variable errors, each relative to that variable's own max |U_v|,
+    reported beside state_err.  A momentum component whose own maximum is
+    below 1e-6 of the largest momentum magnitude (zero up to round-off, e.g.
+    the transverse momentum of a flow along x) has no scale of its own: it is
+    reported as "abs=" its absolute error."""
+    g, o = per_var(Ug, case), per_var(Uo, case)
+    nd = case.ndim
+    mom = float(np.max(np.sqrt(sum(o[1 + a] ** 2 for a in range(nd)))))
+    out = []
+    for v, (gv, ov) in enumerate(zip(g, o)):
+        s = float(np.max(np.abs(ov)))
+        d = float(np.max(np.abs(gv - ov)))
+        if 1 <= v <= nd and s < 1e-6 * mom:
+            out.append(f"abs={d:.2e}")
+        else:
+            out.append(f"{d / s:.2e}" if s > 0 else f"abs={d:.2e}")
+    return out
+
+
 def residual_err(case, Rg, Ro, scale):
     g, o, s = per_var(Rg, case), per_var(Ro, case), per_var(scale, case)
     return max(float(np.max(np.abs(gv - ov)) / np.max(sv)) for gv, ov, sv in zip(g, o, s))

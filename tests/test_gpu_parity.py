@@ -68,6 +68,7 @@ def check_steps(fv, O, case, nsteps, params=None, tol=P.FP64_TOL, ref_params=Non
     ref = O.OracleGrid(case)
     io = ref.run(ref_params or params, nsteps)
     Uo = ref.get_state()
+    io["U"] = Uo
     e = P.state_err(case, Ug, Uo)
     say(f"  {nsteps} steps {case.name} prec={params.precision}: e_U = {e:.3e}, "
         f"t gpu {info['t']:.9g} ref {io['t']:.9g}")
@@ -75,6 +76,20 @@ def check_steps(fv, O, case, nsteps, params=None, tol=P.FP64_TOL, ref_params=Non
     assert e <= tol
     assert abs(info["t"] - io["t"]) <= 1e-11 * abs(io["t"])
     return g, info, io, e
+
+
+def check_fp32_steps(fv, case, nsteps, io):
+    """FP32-flux steps against the oracle's FP64 run io (same case, same
+    steps): state at the after-N bar; t follows the FP32-flux states' time
+    steps, so it is held to the same relative bar."""
+    p32 = CS.Params(**{**case.params.__dict__, "precision": CS.FP32_FLUX})
+    g, info = gpu_run(fv, case, nsteps, p32)
+    e = P.state_err(case, g.get_state(), io["U"])
+    say(f"  {nsteps} steps {case.name} fp32-flux: e_U = {e:.3e}, t gpu {info['t']:.9g} "
+        f"ref {io['t']:.9g}")
+    assert info["steps"] == io["steps"] == nsteps
+    assert 1e-12 < e <= P.FP32_RUN_TOL
+    assert abs(info["t"] - io["t"]) <= P.FP32_RUN_TOL * abs(io["t"])
 
 
 # ---------------------------------------------------------------------------
@@ -376,18 +391,28 @@ def test_inlet_full_500_steps(env):
     fv, O = env
     case = CS.inlet_2d()
     ref = O.OracleGrid(case)
-    io = ref.run(case.params, 500)
+    ref.run(case.params, 250)
+    U250 = ref.get_state()
+    ref.run(case.params, 1)
+    U251 = ref.get_state()
+    io = ref.run(case.params, 249)
     Uo = ref.get_state()
     g, info = gpu_run(fv, case, 500)
     e64 = P.state_err(case, g.get_state(), Uo)
     p32 = CS.Params(**{**case.params.__dict__, "precision": CS.FP32_FLUX})
     g32, info32 = gpu_run(fv, case, 500, p32)
     e32 = P.state_err(case, g32.get_state(), Uo)
-    say(f"  inlet full 500 steps: fp64 e_U = {e64:.3e}, fp32-flux e_U = {e32:.3e}, "
-        f"t gpu {info['t']:.9g} ref {io['t']:.9g}")
+    # one FP32-flux step from the FP64 state at step N/2
+    g32.set_state(U250)
+    g32.step(p32, 1)
+    eh = P.state_err(case, g32.get_state(), U251)
+    say(f"  inlet full 500 steps: fp64 e_U = {e64:.3e} (per component "
+        f"{P.component_errs(case, g.get_state(), Uo)}), fp32-flux e_U = {e32:.3e}, "
+        f"fp32-flux one step from step 250 {eh:.2e}, t gpu {info['t']:.9g} ref {io['t']:.9g}")
     assert info["steps"] == io["steps"] == 500
     assert e64 <= P.FP64_TOL and abs(info["t"] - io["t"]) <= 1e-11 * io["t"]
     assert e32 <= P.FP32_RUN_TOL
+    assert 1e-12 < eh <= P.FP32_STEP_TOL
 
 
 # ---------------------------------------------------------------------------
@@ -499,23 +524,184 @@ def test_blobs_full_residual_and_step(env):
     check_steps(fv, O, case, 1)
 
 
-def test_blobs_full_50_steps_invariants(env):
-    """At full size after the configured 50 steps: with conserved MUSCL + Roe
-    an entropy wave keeps u and p uniform (a property exact at any size)."""
+def test_blobs_full_50_steps_against_oracle(env):
+    """The 256^3 blobs configuration as stated (50 steps), element by element
+    against the oracle run on the host cores, all five variables and t:
+    FP64 at the 1e-12 bar; FP32-flux after the 50 steps at the after-N bar,
+    and one FP32-flux step from the same FP64 state at step 0 and at step 25
+    at the per-step bar.  With conserved MUSCL + Roe the entropy wave also
+    keeps u and p uniform (a property exact at any size)."""
     fv, O = env
     case = CS.blobs_3d()
-    for prec in (CS.FP64, CS.FP32_FLUX):
-        prm = CS.Params(**{**case.params.__dict__, "precision": prec})
-        g, info = gpu_run(fv, case, 50, prm)
-        U = g.get_state().reshape(5, -1)
-        prim = case.meta["prim"]
+    p32 = CS.Params(**{**case.params.__dict__, "precision": CS.FP32_FLUX})
+    ref = O.OracleGrid(case)
+    say(f"  blobs 256^3: oracle on {O.num_threads()} host threads, 50 steps")
+    ref.run(case.params, 1)
+    U1 = ref.get_state()
+    ref.run(case.params, 24)
+    U25 = ref.get_state()
+    say("  blobs 256^3: oracle at step 25")
+    ref.run(case.params, 1)
+    U26 = ref.get_state()
+    io = ref.run(case.params, 24)
+    U50 = ref.get_state()
+    del ref
+    say(f"  blobs 256^3: oracle done, t = {io['t']:.9g}")
+    prim = case.meta["prim"]
+
+    def uniform_dev(U):
+        U = U.reshape(5, -1)
         u = U[1] / U[0]
         p = 0.4 * (U[4] - 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0])
-        eu = np.max(np.abs(u - prim[1])) / prim[1]
-        ep = np.max(np.abs(p - prim[4])) / prim[4]
-        say(f"  blobs 256^3 50 steps prec={prec}: u dev {eu:.2e}, p dev {ep:.2e}")
-        tol = 1e-12 if prec == CS.FP64 else 1e-4
-        assert info["steps"] == 50 and eu <= tol and ep <= tol
+        return np.max(np.abs(u - prim[1])) / prim[1], np.max(np.abs(p - prim[4])) / prim[4]
+
+    g, info = gpu_run(fv, case, 50)
+    e64 = P.state_err(case, g.get_state(), U50)
+    eu, ep = uniform_dev(g.get_state())
+    say(f"  blobs 256^3 fp64 50 steps: e_U = {e64:.3e} (per component "
+        f"{P.component_errs(case, g.get_state(), U50)}), u dev {eu:.2e}, p dev {ep:.2e}, "
+        f"t gpu {info['t']:.12g} ref {io['t']:.12g}")
+    assert info["steps"] == io["steps"] == 50
+    assert e64 <= P.FP64_TOL and abs(info["t"] - io["t"]) <= 1e-11 * io["t"]
+    assert eu <= 1e-12 and ep <= 1e-12
+    del g
+    g32, i32 = gpu_run(fv, case, 50, p32)
+    e32 = P.state_err(case, g32.get_state(), U50)
+    eu, ep = uniform_dev(g32.get_state())
+    g32.set_state(case.state_flat())
+    g32.step(p32, 1)
+    e0 = P.state_err(case, g32.get_state(), U1)
+    g32.set_state(U25)
+    g32.step(p32, 1)
+    e25 = P.state_err(case, g32.get_state(), U26)
+    say(f"  blobs 256^3 fp32-flux: 50 steps e_U = {e32:.3e}, one step from step 0 {e0:.2e}, "
+        f"from step 25 {e25:.2e}; u dev {eu:.2e}, p dev {ep:.2e}")
+    assert i32["steps"] == 50 and abs(i32["t"] - io["t"]) <= 1e-4 * io["t"]
+    assert e32 <= P.FP32_RUN_TOL and e0 <= P.FP32_STEP_TOL and e25 <= P.FP32_STEP_TOL
+    assert e0 > 1e-12  # the FP32 path really ran
+    assert eu <= 1e-4 and ep <= 1e-4
+
+
+# ---------------------------------------------------------------------------
+# block links along every direction
+# ---------------------------------------------------------------------------
+def split_2d_ij(nbi=2, nbj=2, Ni=160, Nj=72, jcut=(40,), icut=(96,)):
+    """The inlet-like curvilinear mesh cut into nbi x nbj blocks of uneven
+    sizes, linked 1:1 across every internal i- and j-face; inflow at i-min,
+    extrapolation at i-max, slip walls at j-min and j-max.  The state is the
+    free stream with a seeded density perturbation."""
+    assert len(icut) == nbi - 1 and len(jcut) == nbj - 1
+    X, Y = CS.inlet_mesh(Ni, Nj)
+    prim = CS.inlet_freestream(3.0, 4.0)
+    ib = [0, *icut, Ni]
+    jb = [0, *jcut, Nj]
+    rng = np.random.default_rng(31)
+    blocks, U0 = [], []
+    idx = lambda bi, bj: bj * nbi + bi
+    for bj in range(nbj):
+        for bi in range(nbi):
+            i0, i1, j0, j1 = ib[bi], ib[bi + 1], jb[bj], jb[bj + 1]
+            ni, nj = i1 - i0, j1 - j0
+            bc = [CS.BC(CS.INFLOW, prim=prim) if bi == 0 else CS.BC(CS.BLOCK, idx(bi - 1, bj), CS.IMAX),
+                  CS.BC(CS.EXTRAP) if bi == nbi - 1 else CS.BC(CS.BLOCK, idx(bi + 1, bj), CS.IMIN),
+                  CS.BC(CS.SLIPWALL) if bj == 0 else CS.BC(CS.BLOCK, idx(bi, bj - 1), CS.JMAX),
+                  CS.BC(CS.SLIPWALL) if bj == nbj - 1 else CS.BC(CS.BLOCK, idx(bi, bj + 1), CS.JMIN),
+                  CS.BC(CS.PERIODIC), CS.BC(CS.PERIODIC)]
+            x = np.ascontiguousarray(X[j0:j1 + 1, i0:i1 + 1])
+            y = np.ascontiguousarray(Y[j0:j1 + 1, i0:i1 + 1])
+            blocks.append(CS.Block(ni, nj, 1, x, y, (0, 0, 0), (1, 1, 1), bc))
+            rho = prim[0] * (1 + 0.05 * rng.uniform(-1, 1, (nj, ni)))
+            vel = [np.full_like(rho, prim[1]), np.full_like(rho, prim[2])]
+            U0.append(CS.conserved(rho, vel, np.full_like(rho, prim[4]))[:, None].copy())
+    return CS.Case("split_2d_ij", 2, blocks, U0, CS.Params(qref=CS.qref_of(prim, 2)), 1)
+
+
+def split_3d_jk():
+    """A 3D box cut into 1 x 2 x 2 blocks of uneven sizes (j: 13 + 9 rows,
+    k: 11 + 7 planes), linked 1:1 across the internal j- and k-faces, and
+    periodic in j and k through block links that wrap around (the j-max face
+    of the top blocks links to the j-min face of the bottom ones); inflow at
+    i-min and extrapolation at i-max, with transverse velocity so that
+    fluxes cross every link."""
+    ni, njs, nks = 70, (13, 9), (11, 7)
+    prim = CS.inlet_freestream(2.0, 0.0, ndim=3)
+    h = (1.0 / 70, 1.0 / 22, 1.0 / 18)
+    rng = np.random.default_rng(37)
+    idx = lambda bj, bk: bk * 2 + bj
+    blocks, U0 = [], []
+    for bk in range(2):
+        for bj in range(2):
+            nj, nk = njs[bj], nks[bk]
+            bc = [CS.BC(CS.INFLOW, prim=prim), CS.BC(CS.EXTRAP),
+                  CS.BC(CS.BLOCK, idx(1 - bj, bk), CS.JMAX), CS.BC(CS.BLOCK, idx(1 - bj, bk), CS.JMIN),
+                  CS.BC(CS.BLOCK, idx(bj, 1 - bk), CS.KMAX), CS.BC(CS.BLOCK, idx(bj, 1 - bk), CS.KMIN)]
+            blocks.append(CS.Block(ni, nj, nk, None, None, (0, 0, 0), h, bc))
+            rho = prim[0] * (1 + 0.05 * rng.standard_normal((nk, nj, ni)))
+            vel = [np.full_like(rho, prim[1]), 0.2 * prim[1] * rng.standard_normal(rho.shape),
+                   0.2 * prim[1] * rng.standard_normal(rho.shape)]
+            U0.append(CS.conserved(rho, vel, np.full_like(rho, prim[4])))
+    return CS.Case("split_3d_jk", 3, blocks, U0, CS.Params(qref=CS.qref_of(prim, 3)), 1)
+
+
+@pytest.mark.parametrize("maker", [split_2d_ij, split_3d_jk])
+def test_block_links_every_direction(env, maker):
+    """Block links across j-faces (2D, curvilinear, 2 x 2 blocks) and across
+    j- and k-faces with wrap-around (3D): ghost values, residual and 12 steps
+    against the oracle, FP64; 12 FP32-flux steps at the after-N bar."""
+    fv, O = env
+    case = maker()
+    g = fv.Grid(case)
+    g.set_state(case.state_flat())
+    Gg = g.ghosts()
+    Go = O.OracleGrid(case).ghosts()
+    eg = np.max(np.abs(Gg - Go)) / np.max(np.abs(Go))
+    say(f"  {case.name}: ghost values e = {eg:.2e}")
+    assert eg <= 1e-14
+    check_residual(fv, O, case)
+    _, _, io, _ = check_steps(fv, O, case, 12)
+    check_fp32_steps(fv, case, 12, io)
+
+
+# ---------------------------------------------------------------------------
+# sonic points: Harten's fix active
+# ---------------------------------------------------------------------------
+def transonic_rarefaction(n=200):
+    """A Riemann problem whose left rarefaction contains a sonic point
+    (rho, u, p = 1, 0.75, 1 | 0.125, 0, 0.1 at x = 0.3): the acoustic
+    eigenvalue u - c changes sign inside the fan, where Harten's fix acts."""
+    case = CS.sod_2d(n=n, nj=4, x0=0.3, t_end=0.0)
+    U = case.U0[0]
+    h = 1.0 / n
+    xc = (np.arange(n) + 0.5) * h
+    rho = np.where(xc < 0.3, 1.0, 0.125)
+    u = np.where(xc < 0.3, 0.75, 0.0)
+    p = np.where(xc < 0.3, 1.0, 0.1)
+    rho2, u2, p2 = (np.tile(a, (4, 1)) for a in (rho, u, p))
+    case.U0[0] = CS.conserved(rho2, [u2, np.zeros_like(u2)], p2)[:, None].copy()
+    case.name = "transonic_rarefaction"
+    return case
+
+
+def test_sonic_point_entropy_fix(env):
+    """The entropy fix changes the residual at the sonic point (oracle with
+    the fix against oracle without), and the GPU matches the oracle with it,
+    for the residual and for 150 steps, FP64 and FP32-flux."""
+    fv, O = env
+    case = transonic_rarefaction()
+    ref = O.OracleGrid(case)
+    io = ref.run(case.params, 40)
+    U40 = ref.get_state()
+    Rfix, _ = ref.residual(case.params)
+    Roff, _ = ref.residual(CS.Params(**{**case.params.__dict__, "entropy_fix": 0.0}))
+    d = np.max(np.abs(Rfix - Roff))
+    say(f"  transonic rarefaction at step 40: residual change by the fix {d:.3e} "
+        f"(max |R| {np.max(np.abs(Rfix)):.3e})")
+    assert d > 1e-6 * np.max(np.abs(Rfix))
+    # GPU residual with the fix, at the state where it acts
+    c40 = CS.Case(case.name, 2, case.blocks, case.split_flat(U40), case.params, 1)
+    check_residual(fv, O, c40)
+    _, _, io, _ = check_steps(fv, O, case, 150)
+    check_fp32_steps(fv, case, 150, io)
 
 
 # ---------------------------------------------------------------------------

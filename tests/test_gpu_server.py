@@ -64,6 +64,7 @@ def test_alone_equals_in_mix(env, prec):
     srv = fv.Server(arena_bytes=256 << 20, max_instances=3, precision=prec, steps_per_launch=7)
     ts = [srv.submit(c, drop_tol=0.0, max_steps=n) for c, n in zip(cs, steps)]
     mix = drain(srv, ts)
+    tol = P.FP64_TOL if prec == CS.FP64 else P.FP32_RUN_TOL
     for k, t in enumerate(ts):
         st, U, info = mix[t]
         st0, U0, info0 = alone[k]
@@ -71,6 +72,15 @@ def test_alone_equals_in_mix(env, prec):
         assert info["steps"] == steps[k] and info0["steps"] == steps[k]
         assert np.array_equal(U, U0), f"instance {k} differs alone vs in mix"
         assert info["t"] == info0["t"] and info["norm"] == info0["norm"]
+        # and each instance of the mix against the oracle (FP64)
+        ref = O.OracleGrid(cs[k])
+        io = ref.run(cs[k].params, steps[k])
+        e = P.state_err(cs[k], U, ref.get_state())
+        P.report("test_alone_equals_in_mix",
+                 f"prec={prec} in-mix {cs[k].name} ({cs[k].ndim}D, {len(cs[k].blocks)} blocks) "
+                 f"{steps[k]} steps: e_U = {e:.3e}")
+        assert io["steps"] == steps[k] and e <= tol, (cs[k].name, e)
+        assert abs(info["t"] - io["t"]) <= (1e-11 if prec == CS.FP64 else 1e-4) * io["t"]
     s = srv.stats()
     assert s["completed"] == len(cs) and s["arena_used"] == 0
     srv.close()
@@ -92,6 +102,53 @@ def test_served_equals_grid_and_reference(env):
         e = P.state_err(c, U, ref.get_state())
         P.report("test_served_equals_grid_and_reference", f"served {c.name} 25 steps: e_U = {e:.3e}")
         assert info["steps"] == io["steps"] == 25 and e <= P.FP64_TOL, e
+
+
+def batch_subset():
+    """A seeded subset of the 64-instance batch (the same generator and seed):
+    the two smallest instances of each block count 1..4."""
+    cs = CS.batch_2d(64)
+    out = []
+    for nb in (1, 2, 3, 4):
+        sel = sorted([c for c in cs if len(c.blocks) == nb], key=lambda c: c.ncells)[:2]
+        out += sel
+    return out
+
+
+def test_served_fp32_batch_against_oracle_and_grid(env):
+    """Instances of the batched workload (1-4 blocks, Mach 1.5-4, sheared
+    inlet mesh), served in FP32-flux with four resident at a time: each
+    within the after-N bar of the FP64 oracle and bitwise equal to the same
+    instance stepped alone on its own grid."""
+    fv, O = env
+    cs = batch_subset()
+    assert sorted({len(c.blocks) for c in cs}) == [1, 2, 3, 4]
+    steps = [23 + 4 * k for k in range(len(cs))]  # not multiples of the launch length
+    srv = fv.Server(arena_bytes=512 << 20, max_instances=4, precision=CS.FP32_FLUX,
+                    steps_per_launch=10)
+    ts = [srv.submit(c, drop_tol=0.0, max_steps=n) for c, n in zip(cs, steps)]
+    res = drain(srv, ts, timeout=300.0)
+    stats = srv.stats()
+    srv.close()
+    p32 = lambda c: CS.Params(**{**c.params.__dict__, "precision": CS.FP32_FLUX})
+    for c, n, t in zip(cs, steps, ts):
+        st, U, info = res[t]
+        assert st == fv.FV_OK and info["steps"] == n
+        g = fv.Grid(c)
+        g.set_state(c.state_flat())
+        g.step(p32(c), n)
+        assert np.array_equal(U, g.get_state()), f"{c.name} served differs from its own grid"
+        g.close()
+        ref = O.OracleGrid(c)
+        ref.run(c.params, n)
+        e = P.state_err(c, U, ref.get_state())
+        P.report("test_served_fp32_batch_against_oracle_and_grid",
+                 f"served fp32-flux {c.name} ({c.blocks[0].ni * len(c.blocks)}x{c.blocks[0].nj}, "
+                 f"{len(c.blocks)} blocks) {n} steps: e_U = {e:.3e}")
+        print(f"  {c.name}: {len(c.blocks)} blocks, {c.ncells} cells, {n} steps, e_U = {e:.3e}",
+              flush=True)
+        assert 1e-12 < e <= P.FP32_RUN_TOL, (c.name, e)
+    assert stats["completed"] == len(cs) and stats["arena_used"] == 0
 
 
 def test_drop_tolerance_stop_matches_solve(env):
