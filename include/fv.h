@@ -24,7 +24,8 @@
  *     string for the calling thread's last failing call.
  *   - The library never allocates device memory.  Device workspace and arena
  *     are supplied by the caller (e.g. PyTorch tensors) and must outlive the
- *     handle that uses them.  Every host array passed in is copied before the
+ *     handle that uses them; the allocation-free path (fv_step_noalloc) uses
+ *     a fixed static device array instead.  Every host array passed in is copied before the
  *     call returns; the caller keeps ownership.
  *   - State layout (host or device): [block][var][k][j][i], i fastest,
  *     interior cells only, IEEE binary64.  2D: var = rho, rho*u, rho*v,
@@ -222,6 +223,31 @@ typedef struct fv_grid_stats {
   double last_stage_ms[4];/* last timed launch of stage 1, 2, 3, finalize */
 } fv_grid_stats;
 int fv_grid_get_stats(const fv_grid* g, fv_grid_stats* out);
+
+/* ---------------------------------------------------------------------- */
+/* Allocation-free stepping.                                                */
+/* ---------------------------------------------------------------------- */
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fv_step_noalloc is fv_step without a grid handle or workspace.  d_U is the
+ * caller's device state ([block][var][k][j][i], interior cells, FP64, 8-byte
+ * aligned), advanced in place by nsteps steps of the scheme p->rk from t = 0,
+ * with the same kernels, tile shapes and results as fv_create_grid +
+ * fv_set_state + fv_step.  Every other buffer (block table, instance record,
+ * tile list, reduction partials, node coordinates, the two RK stage buffers)
+ * lives in one static device array of FV_NOALLOC_SCRATCH_BYTES per device,
+ * held until the process ends; a grid that needs more is rejected with
+ * FV_E_NOMEM before any device work (the 4 x 512 x 256 inlet grid needs about
+ * 42 MB).  The call calls no hipMalloc/hipFree, launches the kernels one by
+ * one (no graph) on hip_stream and returns when info is on the host.  All
+ * calls of the process on one device share the array: they are serialized by
+ * a lock and each waits for its own work, so they never overlap; work of
+ * another call on the same device that reaches the array by other means
+ * would race with it.  The info's t, steps and drop count from this call. */
+#define FV_NOALLOC_SCRATCH_BYTES (64u << 20)
+size_t fv_noalloc_scratch_bytes(void);
+int fv_step_noalloc(const fv_grid_desc* desc, double* d_U, const fv_params* p, int nsteps,
+                    void* hip_stream, fv_step_info* info);
 
 /* ---------------------------------------------------------------------- */
 /* Batched execution and serving (continuous batching over one arena).     */

@@ -88,6 +88,7 @@ EXPORTS = [
     "fv_grid_get_stats",
     "fv_server_create", "fv_submit", "fv_poll", "fv_cancel", "fv_request_times",
     "fv_server_clock", "fv_server_get_stats", "fv_server_destroy",
+    "fv_noalloc_scratch_bytes", "fv_step_noalloc",
 ]
 
 _lib = None
@@ -140,6 +141,10 @@ def lib():
     L.fv_server_clock.argtypes = [vp]
     L.fv_server_get_stats.argtypes = [vp, C.POINTER(fv_server_stats)]
     L.fv_server_destroy.argtypes = [vp]
+    L.fv_noalloc_scratch_bytes.restype = C.c_size_t
+    L.fv_noalloc_scratch_bytes.argtypes = []
+    L.fv_step_noalloc.argtypes = [C.POINTER(fv_grid_desc), vp, C.POINTER(fv_params), C.c_int, vp,
+                                  C.POINTER(fv_step_info)]
     _lib = L
     return L
 
@@ -315,6 +320,26 @@ class Grid:
         return dict(cells=s.cells, tiles=s.tiles, tile_rows=s.tile_rows, tile_cols=s.tile_cols,
                     tile_ny=s.tile_ny, launch_blocks=s.launch_blocks,
                     workspace_bytes=s.workspace_bytes)
+
+
+def step_noalloc(case: "_cases.Case", U, params=None, nsteps=1, stream: Optional[int] = None,
+                 check=True) -> dict:
+    """fv_step_noalloc: advance the device state tensor U (float64, contiguous,
+    the case's size) in place by nsteps steps, with no workspace."""
+    torch = _torch()
+    assert isinstance(U, torch.Tensor) and U.is_cuda and U.dtype == torch.float64
+    assert U.is_contiguous() and U.numel() == sum(case.nv * b.ncells for b in case.blocks)
+    gd = GridDesc(case)
+    p = make_params(params or case.params)
+    info = fv_step_info()
+    s = current_stream_handle(U.device) if stream is None else stream
+    st = lib().fv_step_noalloc(C.byref(gd.desc), C.c_void_p(U.data_ptr()), C.byref(p), int(nsteps),
+                               C.c_void_p(s), C.byref(info))
+    if check:
+        _check(st)
+    d = info_dict(info)
+    d["status"] = st
+    return d
 
 
 def workspace_bytes(case) -> int:

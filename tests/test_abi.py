@@ -131,3 +131,29 @@ def test_3d_plane_beyond_32bit_offsets_rejected(fvb):
             assert n > 0
         else:
             assert n == 0 and b"32-bit" in L.fv_last_error()
+
+
+def test_noalloc_rejects_grid_beyond_scratch_before_device_work(fvb):
+    """The allocation-free step refuses a grid whose buffers exceed its static
+    array, with the reason, before any device work (the pointer given is never
+    dereferenced), and checks its arguments like fv_step."""
+    L = fvb.lib()
+    cap = int(L.fv_noalloc_scratch_bytes())
+    assert cap == 64 << 20
+    n = int(np.ceil(np.sqrt(cap / (2 * 4 * 8)))) + 8
+    blk = CS.Block(n, n, 1, None, None, (0, 0, 0), (1.0, 1.0, 1.0), [CS.BC(CS.PERIODIC)] * 6)
+    case = CS.Case("beyond_scratch", 2, [blk], [], CS.Params(), 1)
+    gd = fvb.GridDesc(case)
+    p = fvb.make_params(case.params)
+    info = fvb.fv_step_info()
+    st = L.fv_step_noalloc(C.byref(gd.desc), C.c_void_p(256), C.byref(p), 1, None, C.byref(info))
+    assert st == fvb.FV_E_NOMEM and b"static scratch" in L.fv_last_error()
+    small = CS.vortex_2d(16, 8)
+    gd = fvb.GridDesc(small)
+    p = fvb.make_params(small.params)
+    assert L.fv_step_noalloc(C.byref(gd.desc), None, C.byref(p), 1, None, C.byref(info)) == fvb.FV_E_INVAL
+    assert L.fv_step_noalloc(C.byref(gd.desc), C.c_void_p(256), C.byref(p), -1, None,
+                             C.byref(info)) == fvb.FV_E_INVAL
+    p.rk = 5
+    assert L.fv_step_noalloc(C.byref(gd.desc), C.c_void_p(256), C.byref(p), 1, None,
+                             C.byref(info)) == fvb.FV_E_UNSUPPORTED
