@@ -15,7 +15,8 @@
  * Where it follows the paper:
  *   Q and the inviscid normal flux F_{i,n} ........ Sec. 2 (conserved vector, flux definitions)
  *   semi-discrete form |Omega| dU/dt + R = 0 ....... Sec. 3.1, Eq. (spatial_residual)
- *   R = sum over the f faces of F_{i,n} ds ......... Sec. 3.1, Eq. (residual), no source, no viscous part
+ *   R = sum over the f faces of (F_{i,n} - F_{nu,n}) ds  Sec. 3.1, Eq. (residual), no source;
+ *   F_{nu,n} with Stokes stresses tau and Theta ... Sec. 2 (viscous flux; 2D)
  *   explicit RK in Butcher form ..................... Sec. 3.2, Eq. (runge_kutta)
  *   MUSCL face states with limiter values Psi ...... Sec. 5, Eq. (flux)
  *   ghost cells refreshed before every RK substep .. Sec. 4 (workflow) and Sec. 5 (ghost extrapolation)
@@ -24,7 +25,11 @@
  * Harten's entropy fix, minmod limiter, SSP-RK3 in Shu-Osher form and the
  * coefficients of the 2- and 4-stage second-order schemes, a global
  * CFL time step from U^n, the ghost rules per boundary kind, an RMS residual
- * norm.
+ * norm; for the viscous flux: constant viscosity and Prandtl number, face
+ * gradients by Green-Gauss over the diamond of the face (the two cell
+ * centres and the two face nodes, node values the mean of the four cells
+ * around the node), corner ghosts, ghost-cell centres, a no-slip wall rule and
+ * a viscous term in the time-step limit.
  */
 #include "fv_oracle.h"
 
@@ -46,6 +51,7 @@ typedef struct {
   double* xn;          /* 2D node coordinates (owned copy) or NULL when uniform */
   double* yn;
   double h[3];
+  double origin[3];    /* uniform blocks: position of node (0, 0) */
   orc_bc bc[6];
   double* q;           /* nv * npad: state of the current stage, with ghosts */
   double* qn;          /* nv * npad: U^n */
@@ -64,6 +70,8 @@ struct orc_grid {
   i64 steps;
   double norms[5], norm, norm_first, drop;
   int have_first, physical;
+  /* viscosity of the time-step limit (that of the last run) */
+  double mu, prandtl;
 };
 
 /* ------------------------------------------------------------------------ */
@@ -303,8 +311,28 @@ void orc_reconstruct(const double* q4, int limiter, double eps, double kappa, do
 /*   SLIPWALL  ghost g = interior cell g-1 from the wall with its momentum   */
 /*             mirrored about the unit normal of that wall face; rho and     */
 /*             rho*e_t copied                                                */
-/* Corner ghosts are never read (the stencil is one direction at a time).   */
+/*   NOSLIP    ghost g = interior cell g-1 from the wall with the velocity   */
+/*             2 w - u (w the wall velocity), density and pressure kept: the */
+/*             face average of the velocity is w and the wall is adiabatic   */
+/* The inviscid stencil reads one direction at a time; the viscous flux     */
+/* (2D) also reads the first corner ghost of each block corner (below).     */
 /* ------------------------------------------------------------------------ */
+/* no-slip ghost of a copied interior state q: in conserved variables the
+ * momentum becomes m' = 2 rho w - m and the total energy gains the change of
+ * kinetic energy, (|m'|^2 - |m|^2) / (2 rho), so that rho and p are kept.
+ * A wall at rest gives m' = -m and rho e_t unchanged, exactly. */
+static void noslip_ghost(double* q, const double* wall, int nd) {
+  double m2 = 0.0, n2 = 0.0;
+  for (int a = 0; a < nd; ++a) {
+    const double m = q[1 + a];
+    const double mp = 2.0 * q[0] * wall[1 + a] - m;
+    m2 += m * m;
+    n2 += mp * mp;
+    q[1 + a] = mp;
+  }
+  q[nd + 1] += 0.5 * (n2 - m2) / q[0];
+}
+
 static void set3(int d, int along, int t1, int t2, int* i, int* j, int* k) {
   if (d == 0) { *i = along; *j = t1; *k = t2; }
   else if (d == 1) { *i = t1; *j = along; *k = t2; }
@@ -340,6 +368,7 @@ static void ghost_value(const orc_grid* G, int bi, int f, int g, int t1, int t2,
       along = side == 0 ? 0 : n - 1;
       break;
     case ORC_SLIPWALL:
+    case ORC_NOSLIP:
       along = side == 0 ? g - 1 : n - g;
       break;
     default:
@@ -359,6 +388,63 @@ static void ghost_value(const orc_grid* G, int bi, int f, int g, int t1, int t2,
     double mn = 0.0;
     for (int a = 0; a < nd; ++a) mn += out[1 + a] * nh[a];
     for (int a = 0; a < nd; ++a) out[1 + a] -= 2.0 * mn * nh[a];
+  }
+  if (bc->kind == ORC_NOSLIP) noslip_ghost(out, bc->prim, nd);
+}
+
+/* Value of cell (i, j) of 2D block bi, where i and j may each lie up to two
+ * cells outside the block.  A cell outside in i follows the i-face rule
+ * first; the cell that rule names (in this block or, through a block link,
+ * in the neighbour) is then resolved in its own block, by that block's
+ * j-face rule when j lies outside too, and the i-rule's wall mirror is
+ * applied last.  A cell outside in j only follows the j-face rule, which is
+ * the edge ghost above.  The corner ghosts this defines are read only by
+ * the viscous node values; across a block link they are the neighbour's own
+ * ghosts, so a node on the link has one value for both blocks. */
+static void cell_value_2d(const orc_grid* G, int bi, int i, int j, double* out) {
+  const blk_t* b = &G->b[bi];
+  const int nv = G->nv;
+  if (i >= 0 && i < b->ni && j >= 0 && j < b->nj) {
+    const i64 p = pidx(b, i, j, 0);
+    for (int v = 0; v < nv; ++v) out[v] = b->q[v * b->npad + p];
+    return;
+  }
+  const int d = (i < 0 || i >= b->ni) ? 0 : 1;
+  const int n = ext(b, d), x = d == 0 ? i : j;
+  const int side = x < 0 ? 0 : 1, g = side == 0 ? -x : x - n + 1;
+  const orc_bc* bc = &b->bc[2 * d + side];
+  int src = bi, along;
+  switch (bc->kind) {
+    case ORC_INFLOW:
+      cons_from_prim(bc->prim, 2, G->gamma, out);
+      return;
+    case ORC_PERIODIC:
+      along = side == 0 ? n - g : g - 1;
+      break;
+    case ORC_BLOCK:
+      src = bc->nbr_block;
+      along = side == 0 ? ext(&G->b[src], d) - g : g - 1;
+      break;
+    case ORC_EXTRAP:
+      along = side == 0 ? 0 : n - 1;
+      break;
+    default: /* SLIPWALL, NOSLIP */
+      along = side == 0 ? g - 1 : n - g;
+      break;
+  }
+  cell_value_2d(G, src, d == 0 ? along : i, d == 0 ? j : along, out);
+  if (bc->kind == ORC_SLIPWALL) {
+    /* wall face of the nearest row (column) inside the block */
+    const int t = d == 0 ? j : i, tn = d == 0 ? b->nj : b->ni;
+    const int tc = t < 0 ? 0 : (t >= tn ? tn - 1 : t);
+    double S[3];
+    face_vec(b, 2, d, d == 0 ? (side == 0 ? 0 : n) : tc, d == 0 ? tc : (side == 0 ? 0 : n), 0, S);
+    const double A = sqrt(S[0] * S[0] + S[1] * S[1]);
+    const double nh[2] = {S[0] / A, S[1] / A};
+    const double mn = out[1] * nh[0] + out[2] * nh[1];
+    for (int a = 0; a < 2; ++a) out[1 + a] -= 2.0 * mn * nh[a];
+  } else if (bc->kind == ORC_NOSLIP) {
+    noslip_ghost(out, bc->prim, 2);
   }
 }
 
@@ -382,11 +468,25 @@ static void fill_ghosts(orc_grid* G) {
           }
     }
   }
+  /* 2D: the corner ghosts (both layers), after every edge ghost is known */
+  if (nd != 2) return;
+  for (int bi = 0; bi < G->nblocks; ++bi) {
+    blk_t* b = &G->b[bi];
+    const int ci[4] = {-2, -1, b->ni, b->ni + 1}, cj[4] = {-2, -1, b->nj, b->nj + 1};
+    for (int a = 0; a < 4; ++a)
+      for (int c = 0; c < 4; ++c) {
+        double val[5];
+        cell_value_2d(G, bi, ci[a], cj[c], val);
+        const i64 p = pidx(b, ci[a], cj[c], 0);
+        for (int v = 0; v < nv; ++v) b->q[v * b->npad + p] = val[v];
+      }
+  }
 }
 
 /* ------------------------------------------------------------------------ */
-/* residual, Sec. 3.1, Eq. (residual) with no source and no viscous part:   */
-/*   R_cell = sum over its f faces of F_{i,n} ds (outward normals).         */
+/* residual, Sec. 3.1, Eq. (residual) with no source:                       */
+/*   R_cell = sum over its f faces of (F_{i,n} - F_{nu,n}) ds (outward      */
+/*   normals; the viscous part when mu > 0, 2D).                            */
 /* Each face flux is formed once, stored times its area, then each cell     */
 /* sums, direction by direction (i, j, k), the flux leaving through its     */
 /* +face minus the flux entering through its -face.                          */
@@ -415,7 +515,152 @@ static void face_flux_at(const orc_grid* G, const blk_t* b, const orc_params* P,
   for (int v = 0; v < nv; ++v) F[v] = Fu[v] * A;
 }
 
-static void residual_block(const orc_grid* G, blk_t* b, const orc_params* P, double* scale) {
+
+/* ------------------------------------------------------------------------ */
+/* viscous normal flux of Sec. 2 (2D): F_{nu,n} ds = (0, tau_x . S,         */
+/* tau_y . S, Theta . S) with S the face's area vector.  Readings (the     */
+/* paper names Stokes's hypothesis and "heat conduction and work of the     */
+/* viscous stresses" only):                                                 */
+/*   tau = mu (grad u + grad u^T) - (2/3) mu (div u) I, mu constant;        */
+/*   Theta = tau u + k grad T, Fourier's law with a constant Prandtl number:*/
+/*   k grad T = (mu / Pr) gamma/(gamma-1) grad(p/rho) for an ideal gas.     */
+/* Face gradients by Green-Gauss over the diamond of the face, whose        */
+/* corners are the centres L, R of its two cells and its end nodes A, B     */
+/* (ordered so that B - A turned by -90 degrees is S):                      */
+/*   grad phi = [(phi_R - phi_L) S - (phi_B - phi_A) d_perp] / (d . S),     */
+/*   d = x_R - x_L, d_perp = (d_y, -d_x),                                   */
+/* which gives d . grad phi = phi_R - phi_L and (B - A) . grad phi =        */
+/* phi_B - phi_A, i.e. the exact gradient of a linear field.  Node values   */
+/* are the mean of the four cells around the node (ghosts and corner ghosts */
+/* included), cell centres the mean of their four nodes, and u at the face  */
+/* the mean of L and R.  The differentiated variables are u, v and p/rho.  */
+/* ------------------------------------------------------------------------ */
+static void node_xy(const blk_t* b, int i, int j, double* x, double* y) {
+  if (b->xn) {
+    *x = X(b, i, j);
+    *y = Y(b, i, j);
+  } else {
+    *x = b->origin[0] + i * b->h[0];
+    *y = b->origin[1] + j * b->h[1];
+  }
+}
+
+static void centre_xy(const blk_t* b, int i, int j, double c[2]) {
+  double x0, y0, x1, y1, x2, y2, x3, y3;
+  node_xy(b, i, j, &x0, &y0);
+  node_xy(b, i + 1, j, &x1, &y1);
+  node_xy(b, i, j + 1, &x2, &y2);
+  node_xy(b, i + 1, j + 1, &x3, &y3);
+  c[0] = 0.25 * (((x0 + x1) + x2) + x3);
+  c[1] = 0.25 * (((y0 + y1) + y2) + y3);
+}
+
+/* midpoint of face (d, i, j): nodes (i, j) and (i, j+1) for d = 0, (i, j)
+ * and (i+1, j) for d = 1 */
+static void face_mid(const blk_t* b, int d, int i, int j, double m[2]) {
+  double x0, y0, x1, y1;
+  node_xy(b, i, j, &x0, &y0);
+  node_xy(b, d == 0 ? i : i + 1, d == 0 ? j + 1 : j, &x1, &y1);
+  m[0] = 0.5 * (x0 + x1);
+  m[1] = 0.5 * (y0 + y1);
+}
+
+/* Centre of cell (i, j) of block bi, or of a first-layer ghost outside one
+ * face (a reading for ghost cells): across a block link the neighbour's
+ * cell; across a periodic face the image cell moved by the offset between
+ * the two periodic faces; otherwise the interior neighbour's centre
+ * reflected through the boundary face's midpoint. */
+static void cell_centre_2d(const orc_grid* G, int bi, int i, int j, double c[2]) {
+  const blk_t* b = &G->b[bi];
+  if (i >= 0 && i < b->ni && j >= 0 && j < b->nj) {
+    centre_xy(b, i, j, c);
+    return;
+  }
+  const int d = (i < 0 || i >= b->ni) ? 0 : 1;
+  const int n = ext(b, d), side = (d == 0 ? i : j) < 0 ? 0 : 1;
+  const orc_bc* bc = &b->bc[2 * d + side];
+  double m[2];
+  face_mid(b, d, d == 0 ? (side ? n : 0) : i, d == 0 ? j : (side ? n : 0), m);
+  if (bc->kind == ORC_BLOCK) {
+    const blk_t* nb = &G->b[bc->nbr_block];
+    const int along = side == 0 ? ext(nb, d) - 1 : 0;
+    centre_xy(nb, d == 0 ? along : i, d == 0 ? j : along, c);
+  } else if (bc->kind == ORC_PERIODIC) {
+    const int along = side == 0 ? n - 1 : 0;
+    double mo[2];
+    face_mid(b, d, d == 0 ? (side ? 0 : n) : i, d == 0 ? j : (side ? 0 : n), mo);
+    centre_xy(b, d == 0 ? along : i, d == 0 ? j : along, c);
+    c[0] += m[0] - mo[0];
+    c[1] += m[1] - mo[1];
+  } else {
+    const int along = side == 0 ? 0 : n - 1;
+    centre_xy(b, d == 0 ? along : i, d == 0 ? j : along, c);
+    c[0] = 2.0 * m[0] - c[0];
+    c[1] = 2.0 * m[1] - c[1];
+  }
+}
+
+/* u, v and p/rho of the padded cell (i, j) */
+static void cell_uvt(const blk_t* b, int i, int j, double g, double o[3]) {
+  const i64 p = pidx(b, i, j, 0);
+  const double r = b->q[p], mx = b->q[b->npad + p], my = b->q[2 * b->npad + p];
+  const double E = b->q[3 * b->npad + p];
+  o[0] = mx / r;
+  o[1] = my / r;
+  const double pr = (g - 1.0) * (E - 0.5 * r * (o[0] * o[0] + o[1] * o[1]));
+  o[2] = pr / r;
+}
+
+/* node (i, j): mean of cells (i-1, j-1), (i, j-1), (i-1, j), (i, j) */
+static void node_uvt(const blk_t* b, int i, int j, double g, double o[3]) {
+  double a[3], s[3] = {0.0, 0.0, 0.0};
+  const int ci[4] = {i - 1, i, i - 1, i}, cj[4] = {j - 1, j - 1, j, j};
+  for (int c = 0; c < 4; ++c) {
+    cell_uvt(b, ci[c], cj[c], g, a);
+    for (int k = 0; k < 3; ++k) s[k] += a[k];
+  }
+  for (int k = 0; k < 3; ++k) o[k] = 0.25 * s[k];
+}
+
+/* F_{nu,n} ds of face (d, i, j) of block bi (ghosts filled) */
+static void viscous_flux_2d(const orc_grid* G, int bi, const orc_params* P, int d, int i, int j,
+                            double* F) {
+  const blk_t* b = &G->b[bi];
+  const double g = G->gamma, mu = P->mu;
+  const int iL = d == 0 ? i - 1 : i, jL = d == 0 ? j : j - 1;
+  const int ia = d == 0 ? i : i + 1, ja = j, ib = i, jb = d == 0 ? j + 1 : j;
+  double wL[3], wR[3], wA[3], wB[3], xL[2], xR[2], S[3];
+  cell_uvt(b, iL, jL, g, wL);
+  cell_uvt(b, i, j, g, wR);
+  node_uvt(b, ia, ja, g, wA);
+  node_uvt(b, ib, jb, g, wB);
+  cell_centre_2d(G, bi, iL, jL, xL);
+  cell_centre_2d(G, bi, i, j, xR);
+  face_vec(b, 2, d, i, j, 0, S);
+  const double dx = xR[0] - xL[0], dy = xR[1] - xL[1];
+  const double D = dx * S[0] + dy * S[1];
+  double gx[3], gy[3];
+  for (int k = 0; k < 3; ++k) {
+    const double a = wR[k] - wL[k], t = wB[k] - wA[k];
+    gx[k] = (a * S[0] - t * dy) / D;
+    gy[k] = (a * S[1] + t * dx) / D;
+  }
+  const double dv = gx[0] + gy[1];
+  const double txx = mu * (2.0 * gx[0] - (2.0 / 3.0) * dv);
+  const double tyy = mu * (2.0 * gy[1] - (2.0 / 3.0) * dv);
+  const double txy = mu * (gy[0] + gx[1]);
+  const double uf = 0.5 * (wL[0] + wR[0]), vf = 0.5 * (wL[1] + wR[1]);
+  const double kq = mu / P->prandtl * g / (g - 1.0);
+  const double thx = uf * txx + vf * txy + kq * gx[2];
+  const double thy = uf * txy + vf * tyy + kq * gy[2];
+  F[0] = 0.0;
+  F[1] = txx * S[0] + txy * S[1];
+  F[2] = txy * S[0] + tyy * S[1];
+  F[3] = thx * S[0] + thy * S[1];
+}
+
+static void residual_block(const orc_grid* G, int bi, const orc_params* P, double* scale) {
+  blk_t* b = &G->b[bi];
   const int nd = G->ndim, nv = G->nv;
   memset(b->res, 0, sizeof(double) * (size_t)nv * (size_t)b->ncell);
   if (scale) memset(scale, 0, sizeof(double) * (size_t)nv * (size_t)b->ncell);
@@ -429,6 +674,11 @@ static void residual_block(const orc_grid* G, blk_t* b, const orc_params* P, dou
         for (int i = 0; i < fi; ++i) {
           double F[5];
           face_flux_at(G, b, P, d, i, j, k, F);
+          if (P->mu > 0.0) {
+            double Fv[4];
+            viscous_flux_2d(G, bi, P, d, i, j, Fv);
+            for (int v = 0; v < nv; ++v) F[v] -= Fv[v];
+          }
           i64 f = ((i64)k * fj + j) * fi + i;
           for (int v = 0; v < nv; ++v) fl[v * nf + f] = F[v];
         }
@@ -452,7 +702,7 @@ static void residual_block(const orc_grid* G, blk_t* b, const orc_params* P, dou
 static void residual_all(orc_grid* G, const orc_params* P, double** scales) {
   fill_ghosts(G);
   for (int bi = 0; bi < G->nblocks; ++bi)
-    residual_block(G, &G->b[bi], P, scales ? scales[bi] : NULL);
+    residual_block(G, bi, P, scales ? scales[bi] : NULL);
 }
 
 /* RMS of R/|Omega| per variable over every interior cell of every block,
@@ -487,7 +737,9 @@ static void norms_of_residual(orc_grid* G, const orc_params* P, double* norms, d
 /* time step (reading: global CFL step from U^n).  For each cell the local  */
 /* limit is |Omega| / sum_d (|u . Sbar_d| + c |Sbar_d|), Sbar_d the mean of */
 /* the cell's two face vectors of direction d; dt = CFL * min over every    */
-/* cell of every block.  The state is also checked: rho > 0, p > 0, finite. */
+/* cell of every block.  With viscosity (a reading) the sum gains the       */
+/* diffusive term 2 max(4/3, gamma/Pr) (mu/rho) sum_d |Sbar_d|^2 / |Omega|. */
+/* The state is also checked: rho > 0, p > 0, finite.                       */
 /* ------------------------------------------------------------------------ */
 int orc_spectral_min(orc_grid* G, double* raw_min) {
   const int nd = G->ndim, nv = G->nv;
@@ -510,7 +762,7 @@ int orc_spectral_min(orc_grid* G, double* raw_min) {
             continue;
           }
           double c = sqrt(G->gamma * p / rho);
-          double lam = 0.0;
+          double lam = 0.0, ss = 0.0;
           for (int d = 0; d < nd; ++d) {
             double Sm[3], Sp[3];
             int e[3] = {0, 0, 0};
@@ -520,8 +772,14 @@ int orc_spectral_min(orc_grid* G, double* raw_min) {
             double Sb[3] = {0.5 * (Sm[0] + Sp[0]), 0.5 * (Sm[1] + Sp[1]), 0.5 * (Sm[2] + Sp[2])};
             double us = v[0] * Sb[0] + v[1] * Sb[1] + v[2] * Sb[2];
             lam += fabs(us) + c * sqrt(Sb[0] * Sb[0] + Sb[1] * Sb[1] + Sb[2] * Sb[2]);
+            ss += Sb[0] * Sb[0] + Sb[1] * Sb[1] + Sb[2] * Sb[2];
           }
-          double loc = cell_vol(b, nd, i, j, k) / lam;
+          const double vol = cell_vol(b, nd, i, j, k);
+          if (G->mu > 0.0) {
+            const double f = fmax(4.0 / 3.0, G->gamma / G->prandtl);
+            lam += 2.0 * f * (G->mu / rho) * ss / vol;
+          }
+          double loc = vol / lam;
           if (loc < mn) mn = loc;
         }
   }
@@ -707,7 +965,10 @@ orc_grid* orc_create(int ndim, int nblocks, const orc_block_desc* desc, double g
     b->gk = ndim == 3 ? 2 : 0;
     b->npad = (i64)b->pi * b->pj * b->pk;
     b->ncell = (i64)b->ni * b->nj * b->nk;
-    for (int a = 0; a < 3; ++a) b->h[a] = d->h[a];
+    for (int a = 0; a < 3; ++a) {
+      b->h[a] = d->h[a];
+      b->origin[a] = d->origin[a];
+    }
     memcpy(b->bc, d->bc, sizeof(b->bc));
     if (ndim == 2 && d->x && d->y) {
       size_t nn = (size_t)(b->ni + 1) * (size_t)(b->nj + 1);
@@ -734,7 +995,7 @@ orc_grid* orc_create(int ndim, int nblocks, const orc_block_desc* desc, double g
   for (int bi = 0; bi < nblocks; ++bi)
     for (int f = 0; f < 2 * ndim; ++f) {
       const orc_bc* bc = &G->b[bi].bc[f];
-      if (bc->kind < ORC_PERIODIC || bc->kind > ORC_SLIPWALL) { orc_destroy(G); return NULL; }
+      if (bc->kind < ORC_PERIODIC || bc->kind > ORC_NOSLIP) { orc_destroy(G); return NULL; }
       if (bc->kind != ORC_BLOCK) continue;
       int nb = bc->nbr_block;
       if (nb < 0 || nb >= nblocks || bc->nbr_face != (f ^ 1)) { orc_destroy(G); return NULL; }
@@ -790,8 +1051,23 @@ void orc_get_state(const orc_grid* G, double* U) {
   }
 }
 
+/* viscosity parameters: mu >= 0; mu > 0 needs a 2D grid and Pr > 0.  The
+ * time-step limit follows the viscosity of the latest call. */
+static int use_viscosity(orc_grid* G, const orc_params* P) {
+  if (!(P->mu >= 0.0) || !isfinite(P->mu)) return ORC_E_INVAL;
+  if (P->mu > 0.0 && (G->ndim != 2 || !(P->prandtl > 0.0))) return ORC_E_INVAL;
+  if (P->mu != G->mu || (P->mu > 0.0 && P->prandtl != G->prandtl)) {
+    G->mu = P->mu;
+    G->prandtl = P->prandtl;
+    double mn;
+    (void)orc_spectral_min(G, &mn);
+  }
+  return ORC_OK;
+}
+
 int orc_residual(orc_grid* G, const orc_params* P, double* R, double* norms, double* scale) {
   const int nv = G->nv;
+  if (use_viscosity(G, P) != ORC_OK) return ORC_E_INVAL;
   double** scales = NULL;
   if (scale) {
     scales = (double**)malloc(sizeof(double*) * (size_t)G->nblocks);
@@ -838,6 +1114,7 @@ void orc_get_info(const orc_grid* G, orc_info* info) {
 int orc_run(orc_grid* G, const orc_params* P, long long nsteps, double drop_tol, orc_info* info,
             double* dt_hist) {
   if (P->rk != 0 && P->rk != 2 && P->rk != 3 && P->rk != 4 && P->rk != 103) return ORC_E_INVAL;
+  if (use_viscosity(G, P) != ORC_OK) return ORC_E_INVAL;
   int status = G->physical ? ORC_OK : ORC_E_NONPHYSICAL;
   for (long long s = 0; s < nsteps && status == ORC_OK; ++s) {
     double dt = P->dt_fixed > 0.0 ? P->dt_fixed : P->cfl * G->raw_min;
@@ -909,6 +1186,15 @@ int orc_face_flux(orc_grid* G, const orc_params* P, int block, int dir, int i, i
   if (block < 0 || block >= G->nblocks || dir < 0 || dir >= G->ndim) return ORC_E_INVAL;
   fill_ghosts(G);
   face_flux_at(G, &G->b[block], P, dir, i, j, k, F);
+  return ORC_OK;
+}
+
+int orc_viscous_flux(orc_grid* G, const orc_params* P, int block, int dir, int i, int j,
+                     double* F) {
+  if (block < 0 || block >= G->nblocks || dir < 0 || dir > 1 || G->ndim != 2) return ORC_E_INVAL;
+  if (use_viscosity(G, P) != ORC_OK) return ORC_E_INVAL;
+  fill_ghosts(G);
+  viscous_flux_2d(G, block, P, dir, i, j, F);
   return ORC_OK;
 }
 

@@ -13,15 +13,16 @@
 extern "C" {
 #endif
 
-enum { ORC_PERIODIC = 0, ORC_BLOCK = 1, ORC_INFLOW = 2, ORC_EXTRAP = 3, ORC_SLIPWALL = 4 };
+enum { ORC_PERIODIC = 0, ORC_BLOCK = 1, ORC_INFLOW = 2, ORC_EXTRAP = 3, ORC_SLIPWALL = 4,
+       ORC_NOSLIP = 5 };
 enum { ORC_MINMOD = 0, ORC_UNLIMITED = 1, ORC_FIRST_ORDER = 2 };
 enum { ORC_OK = 0, ORC_E_INVAL = -1, ORC_E_NOMEM = -2, ORC_E_NONPHYSICAL = -4 };
 
 typedef struct {
-  int kind;        /* ORC_PERIODIC .. ORC_SLIPWALL */
+  int kind;        /* ORC_PERIODIC .. ORC_NOSLIP */
   int nbr_block;   /* ORC_BLOCK: neighbour block */
   int nbr_face;    /* ORC_BLOCK: neighbour face (must be the opposite face) */
-  double prim[5];  /* ORC_INFLOW: rho, u, v, w, p */
+  double prim[5];  /* ORC_INFLOW: rho, u, v, w, p; ORC_NOSLIP: wall velocity in prim[1..3] */
 } orc_bc;
 
 typedef struct {
@@ -39,6 +40,8 @@ typedef struct {
   int rk;                /* 3 (or 0): SSP-RK3; 2, 4: the 2- and 4-stage second-order
                             schemes of Sec. 3.2 in Butcher form; 103: SSP-RK3 in
                             Butcher form (tests) */
+  double mu;             /* dynamic viscosity (0: Euler); 2D only */
+  double prandtl;        /* Prandtl number of the heat flux (mu > 0) */
 } orc_params;
 
 typedef struct {
@@ -62,6 +65,8 @@ int orc_ghosts(orc_grid* g, double* G);
 int orc_spectral_min(orc_grid* g, double* raw_min);
 int orc_face_flux(orc_grid* g, const orc_params* p, int block, int dir, int i, int j, int k,
                   double* F);
+int orc_viscous_flux(orc_grid* g, const orc_params* p, int block, int dir, int i, int j,
+                     double* F);
 void orc_metrics_2d(const orc_grid* g, int block, double* Sxi, double* Seta, double* vol);
 void orc_roe(const double* qL, const double* qR, const double* n, int nd, double gamma,
              double entropy_fix, int mode, double* out);

@@ -45,7 +45,8 @@ class _Block(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("cfl", C.c_double), ("dt_fixed", C.c_double), ("t_end", C.c_double),
                 ("limiter", C.c_int), ("eps", C.c_double), ("kappa", C.c_double),
-                ("entropy_fix", C.c_double), ("qref", C.c_double * 5), ("rk", C.c_int)]
+                ("entropy_fix", C.c_double), ("qref", C.c_double * 5), ("rk", C.c_int),
+                ("mu", C.c_double), ("prandtl", C.c_double)]
 
 
 class _Info(C.Structure):
@@ -78,6 +79,8 @@ def lib():
         L.orc_face_flux.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_int, C.c_int, C.c_int,
                                     C.c_int, C.c_int, dp]
         L.orc_metrics_2d.argtypes = [C.c_void_p, C.c_int, dp, dp, dp]
+        L.orc_viscous_flux.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_int, C.c_int, C.c_int,
+                                       C.c_int, dp]
         L.orc_roe.argtypes = [dp, dp, dp, C.c_int, C.c_double, C.c_double, C.c_int, dp]
         L.orc_reconstruct.argtypes = [dp, C.c_int, C.c_double, C.c_double, dp, dp]
         L.orc_num_threads.restype = C.c_int
@@ -93,7 +96,8 @@ def _ptr(a: np.ndarray):
 def make_params(p) -> _Params:
     q = list(p.qref) + [1.0] * (5 - len(p.qref))
     return _Params(p.cfl, p.dt_fixed, p.t_end, p.limiter, p.eps, p.kappa, p.entropy_fix,
-                   (C.c_double * 5)(*q[:5]), getattr(p, "rk", 3))
+                   (C.c_double * 5)(*q[:5]), getattr(p, "rk", 3), getattr(p, "mu", 0.0),
+                   getattr(p, "prandtl", 0.72))
 
 
 def num_threads() -> int:
@@ -224,6 +228,15 @@ class OracleGrid:
         P = make_params(params)
         lib().orc_face_flux(self._h, C.byref(P), block, d, i, j, k, _ptr(out))
         return out[:self.nv]
+
+    def viscous_flux(self, params, block, d, i, j):
+        """F_nu,n ds of face (d, i, j) of a block (2D) for the current state."""
+        out = np.zeros(4)
+        P = make_params(params)
+        st = lib().orc_viscous_flux(self._h, C.byref(P), block, d, i, j, _ptr(out))
+        if st != OK:
+            raise ValueError("oracle rejected the viscous flux request")
+        return out
 
     def metrics_2d(self, block):
         b = self.case.blocks[block]

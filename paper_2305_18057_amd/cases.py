@@ -31,7 +31,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 # boundary kinds (match the C ABI enumeration)
-PERIODIC, BLOCK, INFLOW, EXTRAP, SLIPWALL = 0, 1, 2, 3, 4
+PERIODIC, BLOCK, INFLOW, EXTRAP, SLIPWALL, NOSLIP = 0, 1, 2, 3, 4, 5
 # face order
 IMIN, IMAX, JMIN, JMAX, KMIN, KMAX = 0, 1, 2, 3, 4, 5
 # reconstruction
@@ -53,7 +53,7 @@ class BC:
     kind: int
     nbr_block: int = -1
     nbr_face: int = -1
-    prim: Sequence[float] = (0.0, 0.0, 0.0, 0.0, 0.0)  # rho, u, v, w, p
+    prim: Sequence[float] = (0.0, 0.0, 0.0, 0.0, 0.0)  # rho, u, v, w, p (NOSLIP: wall u, v, w)
 
 
 @dataclass
@@ -84,6 +84,8 @@ class Params:
     entropy_fix: float = 0.1
     qref: Sequence[float] = (1.0, 1.0, 1.0, 1.0, 1.0)
     rk: int = 3  # 3: SSP-RK3; 2, 4: the 2- and 4-stage second-order schemes
+    mu: float = 0.0        # dynamic viscosity (0: Euler)
+    prandtl: float = 0.72  # Prandtl number of the heat flux
 
 
 @dataclass
