@@ -505,12 +505,14 @@ def bench_serving(fv, cases, tune_cache, count=256, max_steps=2000, spl=10, max_
         os.environ["FV_AUTOTUNE_CACHE"] = tune_cache
     solve_s, steps_plain, conv_p = [], [], 0
     try:
-        for r, c in zip(reqs, built):
+        for q, (r, c) in enumerate(zip(reqs, built)):
             p64 = cases.Params(**{**c.params.__dict__, "precision": cases.FP64})
             dt, _, info = _plain_solve(fv, c, r.spec["drop_tol"], r.spec["max_steps"], p64)
             solve_s.append(dt)
             steps_plain.append(info["steps"])
             conv_p += 1 if info["flags"] & fv.FLAG_CONVERGED else 0
+            if (q + 1) % 32 == 0:
+                log(f"[bench]   plain: {q + 1} of {len(reqs)} solved, {sum(solve_s):.1f} s")
     finally:
         if keep is None:
             os.environ.pop("FV_AUTOTUNE_CACHE", None)
