@@ -70,10 +70,18 @@ enum {
  *   SLIPWALL  ghost layer g = interior cell g-1 from the wall with its
  *             momentum mirrored about the unit normal of that wall face;
  *             rho and rho*e_t copied
- * PERIODIC, BLOCK and SLIPWALL read two distinct cells across the face, so
- * the source block needs at least 2 cells along that direction
- * (FV_E_INVAL otherwise). */
-enum { FV_BC_PERIODIC = 0, FV_BC_BLOCK = 1, FV_BC_INFLOW = 2, FV_BC_EXTRAP = 3, FV_BC_SLIPWALL = 4 };
+ *   NOSLIP    (2D) ghost layer g = interior cell g-1 from the wall with
+ *             rho and p kept and the velocity 2 w - u, w = prim_in[1..3]
+ *             the wall velocity (an adiabatic wall; a reading: the paper
+ *             names no wall rule).  Grids with no-slip faces take the
+ *             Navier-Stokes stage kernel.
+ * PERIODIC, BLOCK, SLIPWALL and NOSLIP read two distinct cells across the
+ * face, so the source block needs at least 2 cells along that direction
+ * (FV_E_INVAL otherwise).  In 2D a corner ghost (outside both an i- and a
+ * j-face; read only by the viscous flux) follows the i-face rule, then the
+ * j-face rule of the block that rule lands in. */
+enum { FV_BC_PERIODIC = 0, FV_BC_BLOCK = 1, FV_BC_INFLOW = 2, FV_BC_EXTRAP = 3, FV_BC_SLIPWALL = 4,
+       FV_BC_NOSLIP = 5 };
 enum { FV_IMIN = 0, FV_IMAX = 1, FV_JMIN = 2, FV_JMAX = 3, FV_KMIN = 4, FV_KMAX = 5 };
 
 /* arithmetic of reconstruction + flux: FP64 throughout, or FP32 from the
@@ -97,7 +105,8 @@ typedef struct fv_bc {
   int kind;          /* FV_BC_* */
   int nbr_block;     /* FV_BC_BLOCK: neighbour block index */
   int nbr_face;      /* FV_BC_BLOCK: neighbour face (FV_IMIN..FV_KMAX) */
-  double prim_in[5]; /* FV_BC_INFLOW: rho, u, v, w, p */
+  double prim_in[5]; /* FV_BC_INFLOW: rho, u, v, w, p; FV_BC_NOSLIP: wall u, v, w
+                        in prim_in[1..3] */
 } fv_bc;
 
 typedef struct fv_block_desc {
@@ -134,6 +143,16 @@ typedef struct fv_params {
                           fv_step_timed take 3 only. */
   double qref[5];      /* reference magnitudes of the combined residual norm
                           (0 entries count as 1) */
+  double mu;           /* dynamic viscosity: > 0 adds the viscous normal flux
+                          F_{nu,n} of Sec. 2 to Eq. (residual) (2D grids only;
+                          FV_E_UNSUPPORTED in 3D and on the server).  Stokes's
+                          hypothesis with constant mu; heat flux by Fourier's law
+                          with k = mu c_p / prandtl, i.e. k grad T =
+                          (mu/prandtl) gamma/(gamma-1) grad(p/rho); face gradients
+                          by Green-Gauss over the face's diamond (two cell
+                          centres, two face nodes).  The time-step limit gains
+                          2 max(4/3, gamma/prandtl) (mu/rho) sum_d |S_d|^2/|Omega|. */
+  double prandtl;      /* Prandtl number (> 0 when mu > 0) */
 } fv_params;
 
 typedef struct fv_step_info {
@@ -152,7 +171,8 @@ typedef struct fv_grid fv_grid;
 const char* fv_strerror(int status);
 /* Detail of the calling thread's last failing call ("" if none). */
 const char* fv_last_error(void);
-/* Defaults: cfl 0.5, FP64, minmod, eps 1, kappa -1, entropy_fix 0.1, rk 3. */
+/* Defaults: cfl 0.5, FP64, minmod, eps 1, kappa -1, entropy_fix 0.1, rk 3,
+ * mu 0 (Euler), prandtl 0.72. */
 void fv_default_params(fv_params* p);
 
 /* Device bytes a grid needs (state buffers, node coordinates, descriptors,

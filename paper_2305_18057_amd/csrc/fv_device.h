@@ -17,7 +17,7 @@ constexpr int kWave = 64;
 // stored value-major: value v of tile t at part[v * ntiles + t]
 constexpr int kPartStride = 8;
 
-enum { BC_PERIODIC = 0, BC_BLOCK = 1, BC_INFLOW = 2, BC_EXTRAP = 3, BC_SLIPWALL = 4 };
+enum { BC_PERIODIC = 0, BC_BLOCK = 1, BC_INFLOW = 2, BC_EXTRAP = 3, BC_SLIPWALL = 4, BC_NOSLIP = 5 };
 enum { LIM_MINMOD = 0, LIM_NONE = 1, LIM_FIRST = 2 };
 enum { FLAG_NONPHYS = 1, FLAG_CONVERGED = 2, FLAG_TEND = 4, FLAG_STEPLIMIT = 8 };
 
@@ -29,10 +29,11 @@ struct DevBlock {
   const double* yn;
   double area[3];           // uniform: face area per direction
   double vol;               // uniform: cell volume
+  double org[3];            // uniform: position of node (0, 0, 0)
   long long out_off;        // offset of this block in a residual output array
   int bc_kind[6];
   int bc_nbr[6];
-  double bc_q[6][5];        // INFLOW: conserved ghost state
+  double bc_q[6][5];        // INFLOW: conserved ghost state; NOSLIP: wall velocity in [1..3]
 };
 
 struct DevInstance {
@@ -45,6 +46,7 @@ struct DevInstance {
   int limiter, ndim, nv, ntiles;
   int rk, rk_pad;
   double rk_c[4];           // stage coefficients (see StageKind)
+  double mu, prandtl;       // viscosity (0: Euler) and Prandtl number
   double* part;             // [kPartStride][ntiles], value-major
   // marching state (device)
   double t, dt, dt_last, raw_min, norm_first, norm, drop;
@@ -385,6 +387,23 @@ __device__ __forceinline__ double nodey(const DevBlock& B, int i, int j) {
 // inflow state) and, for slip walls, the wall face's area vector about whose
 // normal the momentum is mirrored: m - 2 (m.S)/(S.S) S.
 // --------------------------------------------------------------------------
+// no-slip wall ghost of a copied interior state: velocity 2 w - u with rho
+// and p kept, in conserved form m' = 2 rho w - m, rho e_t' = rho e_t +
+// (|m'|^2 - |m|^2) / (2 rho) (a wall at rest: m' = -m, rho e_t unchanged)
+template <int ND>
+__device__ __forceinline__ void noslip_mirror(double* q, const double* w) {
+  double m2 = 0.0, n2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < ND; ++a) {
+    const double m = q[1 + a];
+    const double mp = 2.0 * q[0] * w[1 + a] - m;
+    m2 = fmad(m, m, m2);
+    n2 = fmad(mp, mp, n2);
+    q[1 + a] = mp;
+  }
+  q[ND + 1] += 0.5 * (n2 - m2) / q[0];
+}
+
 template <int NV>
 __device__ __forceinline__ void load_cell(const DevBlock* __restrict__ blocks, const DevBlock& B,
                                           int buf, int i, int j, int k, double* q) {
@@ -414,7 +433,7 @@ __device__ __forceinline__ void load_cell(const DevBlock* __restrict__ blocks, c
   int along;
   if (kind == BC_PERIODIC || kind == BC_BLOCK) along = side == 0 ? n - g : g - 1;
   else if (kind == BC_EXTRAP) along = side == 0 ? 0 : n - 1;
-  else along = side == 0 ? g - 1 : n - g;  // SLIPWALL
+  else along = side == 0 ? g - 1 : n - g;  // SLIPWALL, NOSLIP
   int si = i, sj = j, sk = k;
   if (d == 0) si = along;
   else if (d == 1) sj = along;
@@ -449,6 +468,8 @@ __device__ __forceinline__ void load_cell(const DevBlock* __restrict__ blocks, c
     const double fct = 2.0 * ms / ss;
 #pragma unroll
     for (int a = 0; a < ND; ++a) q[1 + a] -= fct * Sv[a];
+  } else if (kind == BC_NOSLIP) {
+    noslip_mirror<ND>(q, B.bc_q[f]);
   }
 }
 
@@ -579,6 +600,35 @@ __device__ __forceinline__ double cell_dt_limit(const double* q, const double (*
     }
     lam += fmad(c, sqrt(ss), fabs(us));
   }
+  return vol / lam;
+}
+
+// the same limit with the viscous term of a Navier-Stokes step:
+// |Omega| / (sum_d(|u.Sbar_d| + c|Sbar_d|) + 2 max(4/3, gamma/Pr) (mu/rho)
+// sum_d |Sbar_d|^2 / |Omega|)
+__device__ __forceinline__ double cell_dt_limit_visc(const double* q, const double (*Sb)[3],
+                                                     double vol, double gamma, double mu,
+                                                     double prandtl, int& bad) {
+  const double rho = q[0];
+  double ir = 1.0 / rho, u = q[1] * ir, v = q[2] * ir;
+  const double p = (gamma - 1.0) * fmad(-0.5, fmad(u, q[1], v * q[2]), q[3]);
+  const bool ok = isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && isfinite(q[3]) &&
+                  rho > 0.0 && p > 0.0;
+  if (!ok) {
+    bad = 1;
+    return INFINITY;
+  }
+  const double c = sqrt(gamma * p * ir);
+  double lam = 0.0, ss = 0.0;
+#pragma unroll
+  for (int d = 0; d < 2; ++d) {
+    const double us = fmad(u, Sb[d][0], v * Sb[d][1]);
+    const double s2 = fmad(Sb[d][0], Sb[d][0], Sb[d][1] * Sb[d][1]);
+    lam += fmad(c, sqrt(s2), fabs(us));
+    ss += s2;
+  }
+  const double f = fmax(4.0 / 3.0, gamma / prandtl);
+  lam += 2.0 * f * (mu * ir) * ss / vol;
   return vol / lam;
 }
 

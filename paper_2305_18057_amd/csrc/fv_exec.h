@@ -32,6 +32,8 @@ struct StepPlan {
   const int* ninst_dev = nullptr;  // device-resident live instance count
   int rk = 3;                   // 3: SSP-RK3; 2, 4: the 2- and 4-stage second-order schemes
   int lim = -1;                 // >= 0: the limiter of every instance; -1: each instance's own
+  bool ns = false;              // 2D sets run the Navier-Stokes stage kernel (viscous flux,
+                                // no-slip walls)
   std::vector<LaunchSet> sets;
 };
 
@@ -50,7 +52,7 @@ class GraphCache {
 };
 
 int graph_chunk();                       // steps per captured graph
-int launch_grid(const LaunchSet& s, int fp32);
+int launch_grid(const LaunchSet& s, int fp32, bool ns = false);
 int enqueue_stage(const StepPlan& P, int mode, int fp32, double* rout, hipStream_t s);
 int enqueue_cfl(const StepPlan& P, hipStream_t s);
 // nsteps full steps; with a cache, replays (and captures on first use) a graph

@@ -33,10 +33,14 @@ static bool graphs_enabled() {
   return on == 1;
 }
 
-int launch_grid(const LaunchSet& s, int fp32) {
+int launch_grid(const LaunchSet& s, int fp32, bool ns) {
   if (s.ntiles <= 0) return 0;
   int cap;
-  if (s.kind == kSet2D) {
+  if (s.kind == kSet2D && ns) {
+    // one 256-thread workgroup per tile
+    cap = fvrt::occupancy_blocks(fvk::stage2d_ns_kernel_ptr(fp32), 256);
+    cap = std::min(cap, s.ntiles);
+  } else if (s.kind == kSet2D) {
     cap = fvrt::occupancy_blocks(fvk::stage2d_kernel_ptr(1, fp32), 256);
     const int need = (s.ntiles + 3) / 4;
     cap = std::min(cap, need);
@@ -55,10 +59,13 @@ int launch_grid(const LaunchSet& s, int fp32) {
 int enqueue_stage(const StepPlan& P, int mode, int fp32, double* rout, hipStream_t st) {
   for (const LaunchSet& s : P.sets) {
     if (s.ntiles <= 0) continue;
-    const int grid = launch_grid(s, fp32);
+    const int grid = launch_grid(s, fp32, P.ns);
     const int nfix = s.count_fixed ? s.ntiles : -1;
     hipError_t e;
-    if (s.kind == kSet2D)
+    if (s.kind == kSet2D && P.ns)
+      e = fvk::launch_stage2d_ns(mode, fp32, grid, st, s.tiles, s.ntiles_dev, nfix, P.blocks, P.insts,
+                                 rout);
+    else if (s.kind == kSet2D)
       e = fvk::launch_stage2d(mode, fp32, grid, 256, st, s.tiles, s.ntiles_dev, nfix, P.lim, P.blocks,
                               P.insts, rout);
     else
@@ -116,8 +123,9 @@ int enqueue_steps(const StepPlan& P, int fp32, int nsteps, hipStream_t st, Graph
   }
   // a captured graph depends on the step count, the precision, the scheme,
   // the limiter given at launch and the caller's variant
-  const long long key = ((long long)(unsigned)variant << 40) | ((long long)(P.lim + 1) << 36) |
-                        ((long long)P.rk << 32) | ((long long)nsteps << 1) | (fp32 ? 1 : 0);
+  const long long key = ((long long)(unsigned)variant << 40) | ((long long)(P.ns ? 1 : 0) << 39) |
+                        ((long long)(P.lim + 1) << 36) | ((long long)P.rk << 32) |
+                        ((long long)nsteps << 1) | (fp32 ? 1 : 0);
   hipGraphExec_t ex = cache->get(key);
   if (!ex) {
     hipStream_t cs;

@@ -30,6 +30,9 @@ struct fv_grid {
   fvexec::GraphCache graphs;
   int have_state = 0;
   double last_ms[4] = {0, 0, 0, 0};
+  // viscosity with which the device's time-step bound of the current state
+  // was formed (the viscous term enters it)
+  double cfl_mu = 0.0, cfl_pr = 0.0;
 };
 
 namespace {
@@ -95,7 +98,24 @@ int cfl_pass(fv_grid* g) {
   const int err = fvexec::enqueue_cfl(g->plan, g->stream);
   if (err) return err;
   FV_HIP(fvk::launch_cfl_init(g->stream, g->d_inst, nullptr, 1));
+  g->cfl_mu = g->hinst.mu;
+  g->cfl_pr = g->hinst.prandtl;
   return get_inst(g);
+}
+
+// The stage kernels these parameters take: a viscosity or a no-slip face
+// needs the Navier-Stokes kernel (2D grids).  Called after the parameters
+// are on the device; when the viscosity differs from the one the current
+// time-step bound was formed with, the bound is formed again.
+int use_params(fv_grid* g, const fv_params* p) {
+  if (p->mu > 0.0 && g->hg.ndim != 2)
+    return set_error(FV_E_UNSUPPORTED, "the viscous flux is provided for 2D grids only");
+  g->plan.ns = p->mu > 0.0 || g->hg.has_noslip;
+  if (g->have_state && (g->hinst.mu != g->cfl_mu || g->hinst.prandtl != g->cfl_pr)) {
+    const int st = cfl_pass(g);
+    if (st) return st;
+  }
+  return FV_OK;
 }
 
 }  // namespace
@@ -247,6 +267,7 @@ extern "C" int fv_residual(fv_grid* g, const fv_params* p, double* R, int on_dev
   params_to_inst(p, g->hg.gamma, g->hinst);
   st = put_inst(g, false);
   if (st) return st;
+  if ((st = use_params(g, p))) return st;
   double* dst = (R && on_device) ? R : g->d_u[1];
   g->plan.lim = p->limiter;
   st = fvexec::enqueue_stage(g->plan, 0, p->precision == FV_FP32_FLUX, dst, g->stream);
@@ -294,6 +315,7 @@ static int run_steps(fv_grid* g, const fv_params* p, long long nsteps, double dr
   g->hinst.step_limit = g->hinst.steps + nsteps;
   st = put_inst(g, false);
   if (st) return st;
+  if ((st = use_params(g, p))) return st;
   FV_HIP(fvk::launch_prepare(g->stream, g->d_inst, nullptr, 1));
   const int fp32 = p->precision == FV_FP32_FLUX;
   g->plan.rk = fvrt::rk_of(p);
@@ -342,6 +364,7 @@ extern "C" int fv_step_timed(fv_grid* g, const fv_params* p, int nsteps, fv_step
   g->hinst.step_limit = g->hinst.steps + nsteps;
   st = put_inst(g, false);
   if (st) return st;
+  if ((st = use_params(g, p))) return st;
   FV_HIP(fvk::launch_prepare(g->stream, g->d_inst, nullptr, 1));
   const int fp32 = p->precision == FV_FP32_FLUX;
   // the events are released on every return path
@@ -414,11 +437,16 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
   int st = check_params(p);
   if (st) return st;
   if (!g->have_state) return set_error(FV_E_INVAL, "no state set");
+  // Navier-Stokes grids time (and record) the shapes of their own kernel
+  if (p->mu > 0.0 && g->hg.ndim != 2)
+    return set_error(FV_E_UNSUPPORTED, "the viscous flux is provided for 2D grids only");
+  const bool tns = p->mu > 0.0 || g->hg.has_noslip;
+  g->plan.ns = tns;
   {
     // a shape already recorded for this size class and precision is applied
     // as is; the state is untouched, only the per-tile minima are redone
     TileShape rec;
-    if (tune_lookup(tune_path(cache_path), tune_key(g->hg, p->precision), rec)) {
+    if (tune_lookup(tune_path(cache_path), tune_key(g->hg, p->precision, tns), rec)) {
       if (rec.rows != g->shape.rows || rec.ny != g->shape.ny) {
         g->shape = rec;
         if ((st = upload_tiles(g))) return st;
@@ -533,6 +561,6 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
   if (st) return st;
   g->hinst.steps = keep.steps;
   g->hinst.t = keep.t;
-  tune_store(tune_path(cache_path), tune_key(g->hg, p->precision), best, best_ms);
+  tune_store(tune_path(cache_path), tune_key(g->hg, p->precision, tns), best, best_ms);
   return FV_OK;
 }

@@ -694,7 +694,9 @@ __global__ __launch_bounds__(256) void k_cfl2d(const DevTile* __restrict__ tiles
           Sb[1][1] = B.area[1];
         }
         Sb[0][2] = Sb[1][2] = 0.0;
-        dmin = fmin(dmin, cell_dt_limit<2>(q, Sb, vol, I.gamma, bad));
+        dmin = fmin(dmin, I.mu > 0.0
+                              ? cell_dt_limit_visc(q, Sb, vol, I.gamma, I.mu, I.prandtl, bad)
+                              : cell_dt_limit<2>(q, Sb, vol, I.gamma, bad));
       }
     }
     const double m = wave_min(dmin);

@@ -19,6 +19,13 @@ hipError_t launch_cfl2d(int grid, int block, hipStream_t s, const DevTile* tiles
                         const int* ntiles, const DevBlock* blocks, DevInstance* insts);
 const void* stage2d_kernel_ptr(int mode, int fp32);
 
+// 2D Navier-Stokes stage (viscous flux added; one 256-thread workgroup per
+// tile); the same stage kinds as launch_stage2d
+hipError_t launch_stage2d_ns(int mode, int fp32, int grid, hipStream_t s, const DevTile* tiles,
+                             const int* ntiles, int ntiles_fixed, const DevBlock* blocks,
+                             DevInstance* insts, double* rout);
+const void* stage2d_ns_kernel_ptr(int fp32);
+
 // 3D: one workgroup per tile of ny j-rows (ny + 1 waves)
 hipError_t launch_stage3d(int mode, int fp32, int ny, int grid, hipStream_t s,
                           const DevTile* tiles, const int* ntiles, int ntiles_fixed,

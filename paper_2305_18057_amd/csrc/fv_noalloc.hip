@@ -71,6 +71,9 @@ extern "C" int fv_step_noalloc(const fv_grid_desc* desc, double* d_U, const fv_p
   HostGrid hg;
   st = validate_and_copy(desc, hg);
   if (st) return st;
+  if (p->mu > 0.0 && hg.ndim != 2)
+    return set_error(FV_E_UNSUPPORTED, "the viscous flux is provided for 2D grids only");
+  const bool ns = p->mu > 0.0 || hg.has_noslip;
   const InstLayout L = noalloc_layout(hg);
   if (L.total > kScratchBytes)
     return set_error(FV_E_NOMEM,
@@ -99,7 +102,7 @@ extern "C" int fv_step_noalloc(const fv_grid_desc* desc, double* d_U, const fv_p
   TileShape sh = default_shape(hg);
   {
     TileShape tsh;
-    if (tune_lookup(tune_path(nullptr), tune_key(hg, p->precision), tsh)) sh = tsh;
+    if (tune_lookup(tune_path(nullptr), tune_key(hg, p->precision, ns), tsh)) sh = tsh;
   }
   std::vector<fvk::DevTile> htiles;
   build_tiles(hg, sh, 0, 0, htiles);
@@ -153,6 +156,7 @@ extern "C" int fv_step_noalloc(const fv_grid_desc* desc, double* d_U, const fv_p
   plan.ninst = 1;
   plan.rk = rk_of(p);
   plan.lim = p->limiter;
+  plan.ns = ns;
   fvexec::LaunchSet ls;
   ls.tiles = d_tiles;
   ls.ntiles_dev = d_ntiles;

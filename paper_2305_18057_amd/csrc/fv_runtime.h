@@ -40,6 +40,7 @@ struct HostGrid {
   std::vector<std::vector<double>> xs, ys;     // node coordinates (2D curvilinear)
   long long ncells = 0, state_size = 0;
   long long node_doubles = 0;
+  bool has_noslip = false;  // a no-slip face: the Navier-Stokes stage kernel runs it
 };
 
 int validate_and_copy(const fv_grid_desc* d, HostGrid& out);
@@ -64,7 +65,7 @@ TileShape default_shape(const HostGrid& g);
 int size_class(const HostGrid& g);
 
 // autotune table (JSON file of "key": {"rows": r, "ny": y})
-std::string tune_key(const HostGrid& g, int precision);
+std::string tune_key(const HostGrid& g, int precision, bool ns = false);
 bool tune_lookup(const char* path, const std::string& key, TileShape& sh);
 void tune_store(const char* path, const std::string& key, const TileShape& sh, double ms);
 const char* tune_path(const char* given);

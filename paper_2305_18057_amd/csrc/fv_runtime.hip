@@ -85,8 +85,16 @@ int validate_and_copy(const fv_grid_desc* d, HostGrid& g) {
     const fv_block_desc& B = g.blocks[b];
     for (int f = 0; f < 2 * g.ndim; ++f) {
       const fv_bc& bc = B.face[f];
-      if (bc.kind < FV_BC_PERIODIC || bc.kind > FV_BC_SLIPWALL)
+      if (bc.kind < FV_BC_PERIODIC || bc.kind > FV_BC_NOSLIP)
         return set_error(FV_E_INVAL, "block %d face %d: unknown boundary kind %d", b, f, bc.kind);
+      if (bc.kind == FV_BC_NOSLIP) {
+        if (g.ndim != 2)
+          return set_error(FV_E_UNSUPPORTED, "block %d face %d: no-slip walls are provided in 2D only", b, f);
+        for (int a = 1; a <= 3; ++a)
+          if (!std::isfinite(bc.prim_in[a]))
+            return set_error(FV_E_INVAL, "block %d face %d: non-finite wall velocity", b, f);
+        g.has_noslip = true;
+      }
       if (bc.kind == FV_BC_BLOCK) {
         if (bc.nbr_block < 0 || bc.nbr_block >= g.nblocks)
           return set_error(FV_E_INVAL, "block %d face %d: neighbour block %d out of range", b, f, bc.nbr_block);
@@ -99,7 +107,8 @@ int validate_and_copy(const fv_grid_desc* d, HostGrid& g) {
           return set_error(FV_E_INVAL, "block %d face %d: transverse size %dx%d != neighbour's %dx%d", b, f, n1, n2, m1, m2);
       }
       // the two ghost layers of these rules are two distinct cells of the source block
-      if (bc.kind == FV_BC_PERIODIC || bc.kind == FV_BC_SLIPWALL || bc.kind == FV_BC_BLOCK) {
+      if (bc.kind == FV_BC_PERIODIC || bc.kind == FV_BC_SLIPWALL || bc.kind == FV_BC_BLOCK ||
+          bc.kind == FV_BC_NOSLIP) {
         const fv_block_desc& S = bc.kind == FV_BC_BLOCK ? g.blocks[bc.nbr_block] : B;
         if (face_ext(S, f / 2) < 2)
           return set_error(FV_E_INVAL, "block %d face %d: this rule needs at least 2 cells across the face", b, f);
@@ -182,6 +191,7 @@ void build_blocks(const HostGrid& g, char* base, const InstLayout& L, int inst_i
     B.nk = D.nk;
     B.inst = inst_index;
     B.ncell = (long long)D.ni * D.nj * D.nk;
+    for (int a = 0; a < 3; ++a) B.org[a] = D.origin[a];
     for (int s = 0; s < 3; ++s) B.u[s] = (double*)(base + L.u[s]) + soff;
     B.out_off = soff;
     if (D.x) {
@@ -216,6 +226,8 @@ void build_blocks(const HostGrid& g, char* base, const InstLayout& L, int inst_i
         }
         B.bc_q[f][g.ndim + 1] = bc.prim_in[4] / (g.gamma - 1.0) + 0.5 * rho * ke;
       }
+      if (bc.kind == FV_BC_NOSLIP && f < 2 * g.ndim)
+        for (int a = 1; a <= 3; ++a) B.bc_q[f][a] = bc.prim_in[a];  // wall velocity
     }
     out.push_back(B);
     soff += B.ncell * g.nv;
@@ -298,10 +310,10 @@ int size_class(const HostGrid& g) {
   return c;
 }
 
-std::string tune_key(const HostGrid& g, int precision) {
+std::string tune_key(const HostGrid& g, int precision, bool ns) {
   char buf[96];
-  snprintf(buf, sizeof(buf), "%dd_%s_c%d", g.ndim, precision == FV_FP32_FLUX ? "fp32flux" : "fp64",
-           size_class(g));
+  snprintf(buf, sizeof(buf), "%dd_%s_c%d%s", g.ndim, precision == FV_FP32_FLUX ? "fp32flux" : "fp64",
+           size_class(g), ns ? "_ns" : "");
   return buf;
 }
 
@@ -396,6 +408,10 @@ int check_params(const fv_params* p) {
   if (!std::isfinite(p->cfl) || !std::isfinite(p->dt_fixed) || !std::isfinite(p->t_end) ||
       !std::isfinite(p->eps) || !std::isfinite(p->kappa) || !(p->entropy_fix >= 0.0))
     return set_error(FV_E_INVAL, "non-finite parameter");
+  if (!(p->mu >= 0.0) || !std::isfinite(p->mu))
+    return set_error(FV_E_INVAL, "viscosity mu must be finite and >= 0");
+  if (p->mu > 0.0 && (!(p->prandtl > 0.0) || !std::isfinite(p->prandtl)))
+    return set_error(FV_E_INVAL, "a viscous run needs a Prandtl number > 0");
   return FV_OK;
 }
 
@@ -417,6 +433,8 @@ void params_to_inst(const fv_params* p, double gamma, fvk::DevInstance& I) {
   I.rk_c[1] = 1.0 / 3.0;
   I.rk_c[2] = 0.5;
   I.rk_c[3] = 1.0;
+  I.mu = p->mu;
+  I.prandtl = p->mu > 0.0 ? p->prandtl : 0.0;
 }
 
 int device_cu_count() {
@@ -470,4 +488,6 @@ extern "C" void fv_default_params(fv_params* p) {
   p->entropy_fix = 0.1;
   p->rk = 3;
   for (int v = 0; v < 5; ++v) p->qref[v] = 1.0;
+  p->mu = 0.0;
+  p->prandtl = 0.72;
 }

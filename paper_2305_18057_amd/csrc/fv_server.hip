@@ -529,6 +529,9 @@ extern "C" int fv_submit(fv_server* S, const fv_grid_desc* desc, const double* U
   if (st) return st;
   // resident instances share graph replays of one stage sequence
   if (rk_of(p) != 3) return set_error(FV_E_UNSUPPORTED, "the server runs SSP-RK3 (rk = 3) only");
+  if (p->mu > 0.0)
+    return set_error(FV_E_UNSUPPORTED, "the server runs the Euler stage kernels: viscous solves go "
+                                       "through fv_step / fv_solve");
   if (max_steps < 1) return set_error(FV_E_INVAL, "max_steps must be >= 1");
   if (!(drop_tol >= 0.0)) return set_error(FV_E_INVAL, "drop_tol must be >= 0");
   Request* r = new (std::nothrow) Request();
@@ -541,6 +544,11 @@ extern "C" int fv_submit(fv_server* S, const fv_grid_desc* desc, const double* U
   if (r->hg.nblocks > kMaxBlocksPerInst) {
     delete r;
     return set_error(FV_E_UNSUPPORTED, "at most %d blocks per served grid", kMaxBlocksPerInst);
+  }
+  if (r->hg.has_noslip) {
+    delete r;
+    return set_error(FV_E_UNSUPPORTED, "the server runs the Euler stage kernels: grids with no-slip "
+                                       "walls go through fv_step / fv_solve");
   }
   r->U0.assign(U0, U0 + r->hg.state_size);
   r->params = *p;

@@ -52,7 +52,7 @@ class fv_params(C.Structure):
     _fields_ = [("cfl", C.c_double), ("dt_fixed", C.c_double), ("t_end", C.c_double),
                 ("precision", C.c_int), ("limiter", C.c_int), ("eps", C.c_double),
                 ("kappa", C.c_double), ("entropy_fix", C.c_double), ("rk", C.c_int),
-                ("qref", C.c_double * 5)]
+                ("qref", C.c_double * 5), ("mu", C.c_double), ("prandtl", C.c_double)]
 
 
 class fv_step_info(C.Structure):
@@ -190,7 +190,8 @@ class GridDesc:
 def make_params(p: "_cases.Params") -> fv_params:
     q = list(p.qref) + [1.0] * (5 - len(p.qref))
     return fv_params(p.cfl, p.dt_fixed, p.t_end, p.precision, p.limiter, p.eps, p.kappa,
-                     p.entropy_fix, getattr(p, "rk", 3), (C.c_double * 5)(*q[:5]))
+                     p.entropy_fix, getattr(p, "rk", 3), (C.c_double * 5)(*q[:5]),
+                     getattr(p, "mu", 0.0), getattr(p, "prandtl", 0.72))
 
 
 def info_dict(info: fv_step_info) -> dict:

@@ -157,3 +157,39 @@ def test_noalloc_rejects_grid_beyond_scratch_before_device_work(fvb):
     p.rk = 5
     assert L.fv_step_noalloc(C.byref(gd.desc), C.c_void_p(256), C.byref(p), 1, None,
                              C.byref(info)) == fvb.FV_E_UNSUPPORTED
+
+
+def test_viscous_parameters_and_noslip_validation(fvb):
+    """Defaults give an inviscid run with Pr 0.72; no-slip walls are 2D only
+    and need two cells across; a negative viscosity or a viscous run without
+    a Prandtl number is refused before any device work."""
+    L = fvb.lib()
+    p = fvb.fv_params()
+    L.fv_default_params(C.byref(p))
+    assert p.mu == 0.0 and p.prandtl == 0.72
+    c = CS.inlet_case(64, 16, 1)
+    c.blocks[0].bc[2] = CS.BC(CS.NOSLIP, prim=(0, 0.5, 0, 0, 0))
+    gd = fvb.GridDesc(c)
+    assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) > 0
+    c3 = CS.blobs_case(8, nblobs=1)
+    c3.blocks[0].bc[2] = CS.BC(CS.NOSLIP)
+    gd = fvb.GridDesc(c3)
+    assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) == 0
+    assert b"2D only" in L.fv_last_error()
+    c1 = CS.vortex_2d(8, 1, noise=0.0)
+    c1.blocks[0].bc[2] = CS.BC(CS.NOSLIP)
+    gd = fvb.GridDesc(c1)
+    assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) == 0
+    assert b"at least 2 cells" in L.fv_last_error()
+    # parameter checks run before the device: the no-alloc entry shows them
+    small = CS.vortex_2d(16, 8)
+    gd = fvb.GridDesc(small)
+    info = fvb.fv_step_info()
+    for mu, pr in ((-1.0, 0.72), (1e-3, 0.0), (float("nan"), 0.72)):
+        q = fvb.make_params(CS.Params(mu=mu, prandtl=pr))
+        assert L.fv_step_noalloc(C.byref(gd.desc), C.c_void_p(256), C.byref(q), 1, None,
+                                 C.byref(info)) == fvb.FV_E_INVAL
+    q = fvb.make_params(CS.Params(mu=1e-3))
+    g3 = fvb.GridDesc(CS.blobs_case(8, nblobs=1))
+    assert L.fv_step_noalloc(C.byref(g3.desc), C.c_void_p(256), C.byref(q), 1, None,
+                             C.byref(info)) == fvb.FV_E_UNSUPPORTED

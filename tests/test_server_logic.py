@@ -128,3 +128,19 @@ def test_request_times_and_unknown_ticket(fvb):
     assert srv.poll(t)[0] == fvb.FV_OK
     assert srv.cancel(t) == fvb.FV_E_NOTFOUND
     srv.close()
+
+
+def test_server_refuses_viscous_solves(fvb):
+    """The server batches the Euler stage kernels; a viscosity or a no-slip
+    wall is for grids (fv_step / fv_solve), and the server says so."""
+    srv = fvb.Server(arena_bytes=32 << 20, max_instances=4, dry_run=True)
+    case = CS.inlet_case(64, 64, 1)
+    prm = CS.Params(**{**case.params.__dict__, "mu": 1e-3})
+    with pytest.raises(fvb.FVError) as e:
+        srv.submit(case, params=prm, max_steps=10)
+    assert e.value.status == fvb.FV_E_UNSUPPORTED
+    case.blocks[0].bc[2] = CS.BC(CS.NOSLIP)
+    with pytest.raises(fvb.FVError) as e:
+        srv.submit(case, max_steps=10)
+    assert e.value.status == fvb.FV_E_UNSUPPORTED
+    srv.close()
