@@ -95,9 +95,22 @@ def algorithmic_flops_per_cell_stage(case) -> int:
 # --------------------------------------------------------------------------
 # committed profile summaries (traffic and instruction counts)
 # --------------------------------------------------------------------------
-def kernel_sources_sha(ndim: int) -> str:
+def is_viscous(case) -> bool:
+    """The case runs the Navier-Stokes stage kernel (viscosity or no-slip wall)."""
+    return getattr(case.params, "mu", 0.0) > 0.0 or any(
+        bc.kind == 5 for blk in case.blocks for bc in blk.bc)
+
+
+def stage_kernel(case) -> str:
+    if case.ndim == 3:
+        return "k_stage3d"
+    return "k_stage2d_ns" if is_viscous(case) else "k_stage2d"
+
+
+def kernel_sources_sha(ndim: int, ns: bool = False) -> str:
     h = hashlib.sha256()
-    for f in ("fv_device.h", "fv_kernels2d.hip" if ndim == 2 else "fv_kernels3d.hip"):
+    src = "fv_kernels3d.hip" if ndim == 3 else ("fv_kernels2d_ns.hip" if ns else "fv_kernels2d.hip")
+    for f in ("fv_device.h", src):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -106,6 +119,7 @@ def kernel_sources_sha(ndim: int) -> str:
 def profile_record(kernel: str, workload: str, ndim: int):
     """key: value lines of profiles/<kernel>_<workload>_counters.txt, or None
     when absent or taken from kernel sources other than the current ones."""
+    ns = kernel.endswith("_ns")
     path = os.path.join(PROFILES, f"{kernel}_{workload}_counters.txt")
     if not os.path.exists(path):
         return None
@@ -115,7 +129,7 @@ def profile_record(kernel: str, workload: str, ndim: int):
             if ":" in line and not line.startswith((" ", "#", "|")):
                 k, v = line.split(":", 1)
                 rec[k.strip()] = v.strip()
-    if rec.get("kernel_sources_sha") != kernel_sources_sha(ndim):
+    if rec.get("kernel_sources_sha") != kernel_sources_sha(ndim, ns):
         return None
     return rec
 
@@ -243,7 +257,7 @@ def bench_rk_schemes(fv, cases, tune_cache, steps2d):
 
 def roofline_of(case, stage_ms, steps, workload, fp32=False):
     cells = case.ncells
-    kernel = "k_stage2d" if case.ndim == 2 else "k_stage3d"
+    kernel = stage_kernel(case)
     per_step = algorithmic_bytes_per_cell_step(case) * cells
     launches = 3 * steps
     avg_ms = float(sum(stage_ms[:3])) / launches
@@ -264,6 +278,16 @@ def roofline_of(case, stage_ms, steps, workload, fp32=False):
         tr = float(rec["trace_avg_us_per_launch"]) * 1e-3
         roof["trace_avg_launch_ms"] = round(tr, 5)
         roof["trace_achieved"] = round(bytes_per_launch / (tr * 1e-3) / 1e9, 1)
+    if is_viscous(case):
+        # the flop count above is the inviscid one; the viscous kernel reports
+        # its measured instruction figures only
+        alu = dict(peak_tflops=FP32_PEAK_TFS if fp32 else FP64_PEAK_TFS)
+        if rec is not None:
+            for k in ("valu_instr_per_cell_stage", "valu_busy_frac", "wait_frac", "vgprs",
+                      "scratch_bytes_per_lane"):
+                if k in rec:
+                    alu[k] = float(rec[k])
+        return roof, alu
     flops = algorithmic_flops_per_cell_stage(case)
     tfs = flops * cells / (avg_ms * 1e-3) / 1e12
     peak = FP32_PEAK_TFS if fp32 else FP64_PEAK_TFS
@@ -442,8 +466,10 @@ def bench_batched(fv, cases, tune_cache, steps=100, count=64, spl=10):
                      "sequential_steps_only_s only its solve")
 
 
-def _serve(fv, cases, reqs, built, arena, max_inst, spl, tune_cache, rate_scale=1.0):
-    srv = fv.Server(arena_bytes=arena, max_instances=max_inst, precision=cases.FP32_FLUX,
+def _serve(fv, cases, reqs, built, arena, max_inst, spl, tune_cache, rate_scale=1.0,
+           precision=None):
+    srv = fv.Server(arena_bytes=arena, max_instances=max_inst,
+                    precision=cases.FP64 if precision is None else precision,
                     steps_per_launch=spl, autotune_cache=tune_cache)
     _drain(srv, [srv.submit(built[0], drop_tol=0.0, max_steps=spl)])  # warm
     tickets = [None] * len(reqs)
@@ -487,17 +513,20 @@ def _pct(xs, p):
 
 def bench_serving(fv, cases, tune_cache, count=256, max_steps=2000, spl=10, max_inst=32):
     """The serving trace as stated: 256 requests arriving as a Poisson stream
-    at 200/s, each solved to a residual drop of 1e-8 or 2000 steps, batched
-    in FP32-flux by the server, against plain FP64 solves one after the other
-    in arrival order on the same GPU."""
+    at 200/s, each solved to a residual drop of 1e-8 or 2000 steps.  The
+    server batches them in FP64, against plain FP64 solves one after the
+    other in arrival order on the same GPU.  Supplementary: the same trace
+    served in FP32-flux (whose residual stalls near the FP32 round-off of
+    the fluxes, above a 1e-8 drop, so its requests mostly run to the cap),
+    and the first 64 requests in FP64 at about 0.7x the measured capacity."""
     reqs = cases.serving_trace(256, seed=5, max_steps=max_steps)[:count]
-    built = [cases.build_request(r, precision=cases.FP32_FLUX) for r in reqs]
+    built = [cases.build_request(r, precision=cases.FP64) for r in reqs]
     arena = min(arena_for(fv, built, 1.2), 64 << 30)
     log(f"[bench] serving {count} requests, max_steps {max_steps}, arena {arena >> 20} MiB")
-    shapes = tune_classes(fv, cases, built, [cases.FP32_FLUX, cases.FP64], tune_cache) \
+    shapes = tune_classes(fv, cases, built, [cases.FP64, cases.FP32_FLUX], tune_cache) \
         if tune_cache else {}
     lat, span, work, cnt = _serve(fv, cases, reqs, built, arena, max_inst, spl, tune_cache)
-    log(f"[bench]   batched: makespan {span:.2f} s, {cnt}")
+    log(f"[bench]   batched fp64: makespan {span:.2f} s, {cnt}")
     # plain: sequential FP64 solves in arrival order on the same GPU, with the
     # FP64 shapes of the same table
     keep = os.environ.get("FV_AUTOTUNE_CACHE")
@@ -506,8 +535,7 @@ def bench_serving(fv, cases, tune_cache, count=256, max_steps=2000, spl=10, max_
     solve_s, steps_plain, conv_p = [], [], 0
     try:
         for q, (r, c) in enumerate(zip(reqs, built)):
-            p64 = cases.Params(**{**c.params.__dict__, "precision": cases.FP64})
-            dt, _, info = _plain_solve(fv, c, r.spec["drop_tol"], r.spec["max_steps"], p64)
+            dt, _, info = _plain_solve(fv, c, r.spec["drop_tol"], r.spec["max_steps"])
             solve_s.append(dt)
             steps_plain.append(info["steps"])
             conv_p += 1 if info["flags"] & fv.FLAG_CONVERGED else 0
@@ -530,24 +558,37 @@ def bench_serving(fv, cases, tune_cache, count=256, max_steps=2000, spl=10, max_
     out = dict(requests=count, max_steps=max_steps, drop_tol=reqs[0].spec["drop_tol"],
                arrival_rate_per_s=200.0, completed_ok=cnt["ok"],
                converged=cnt["converged"], capped=cnt["capped"],
-               batched=dict(precision="fp32flux", p50_s=round(_pct(lat, 50), 4),
+               batched=dict(precision="fp64", p50_s=round(_pct(lat, 50), 4),
                             p99_s=round(_pct(lat, 99), 4), makespan_s=round(span, 4),
                             value=round(work / span, 1), unit="cell-updates/s",
-                            cell_steps=int(work)),
+                            cell_steps=int(work), requests_per_s=round(count / span, 2)),
                plain=dict(precision="fp64", p50_s=round(_pct(lat_p, 50), 4),
                           p99_s=round(_pct(lat_p, 99), 4), makespan_s=round(span_p, 4),
                           value=round(work_p / span_p, 1), unit="cell-updates/s",
-                          converged=conv_p, cell_steps=int(work_p)),
+                          converged=conv_p, cell_steps=int(work_p),
+                          requests_per_s=round(count / span_p, 2)),
                tile_shapes=shapes)
     out["throughput_ratio"] = round(out["batched"]["value"] / out["plain"]["value"], 3)
-    # supplementary: the same requests at about 0.7x the measured capacity
+    out["request_rate_ratio"] = round(span_p / span, 3)
+    # supplementary: FP32-flux batching of the same trace
+    built32 = [cases.build_request(r, precision=cases.FP32_FLUX) for r in reqs]
+    lat3, span3, work3, cnt3 = _serve(fv, cases, reqs, built32, arena, max_inst, spl, tune_cache,
+                                      precision=cases.FP32_FLUX)
+    log(f"[bench]   batched fp32-flux: makespan {span3:.2f} s, {cnt3}")
+    out["batched_fp32flux"] = dict(p50_s=round(_pct(lat3, 50), 4), p99_s=round(_pct(lat3, 99), 4),
+                                   makespan_s=round(span3, 4), value=round(work3 / span3, 1),
+                                   cell_steps=int(work3), converged=cnt3["converged"],
+                                   capped=cnt3["capped"])
+    # supplementary: the first 64 requests at about 0.7x the measured capacity
+    sub = min(64, count)
     cap_rate = count / span
     scale = (200.0 / (0.7 * cap_rate))
-    lat2, span2, work2, cnt2 = _serve(fv, cases, reqs, built, arena, max_inst, spl, tune_cache,
-                                      rate_scale=scale)
-    out["low_load"] = dict(arrival_rate_per_s=round(200.0 / scale, 2), p50_s=round(_pct(lat2, 50), 4),
-                           p99_s=round(_pct(lat2, 99), 4), value=round(work2 / span2, 1),
-                           converged=cnt2["converged"], capped=cnt2["capped"])
+    lat2, span2, work2, cnt2 = _serve(fv, cases, reqs[:sub], built[:sub], arena, max_inst, spl,
+                                      tune_cache, rate_scale=scale)
+    out["low_load"] = dict(requests=sub, precision="fp64", arrival_rate_per_s=round(200.0 / scale, 2),
+                           p50_s=round(_pct(lat2, 50), 4), p99_s=round(_pct(lat2, 99), 4),
+                           value=round(work2 / span2, 1), converged=cnt2["converged"],
+                           capped=cnt2["capped"])
     return out
 
 
@@ -646,13 +687,14 @@ def summarize(dirs, kernel_filter, out_path, command, calib=None, workload=None,
         lines.append("")
     if workload and cnt:
         from paper_2305_18057_amd import cases
-        case = cases.inlet_2d() if workload == "inlet_2d" else cases.blobs_3d()
+        case = {"inlet_2d": cases.inlet_2d, "blobs_3d": cases.blobs_3d,
+                "inlet_2d_ns": cases.inlet_2d_ns}[workload]()
         cells = case.ncells
         st = [a for n, a in cnt.items() if "stage" in n]
         def mean(k):
             v = [a[k] for a in st if k in a]
             return sum(v) / len(v) if v else None
-        lines.append(f"kernel_sources_sha: {kernel_sources_sha(case.ndim)}")
+        lines.append(f"kernel_sources_sha: {kernel_sources_sha(case.ndim, is_viscous(case))}")
         lines.append(f"workload: {workload}_{precision}")
         lines.append(f"cells: {cells}")
         alg = algorithmic_bytes_per_cell_step(case) * cells / 3.0
@@ -698,7 +740,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="inlet_2d", choices=["inlet_2d", "blobs_3d"],
+    ap.add_argument("--workload", default="inlet_2d", choices=["inlet_2d", "blobs_3d", "inlet_2d_ns"],
                     help="headline workload (default: the 2D inlet-like grid)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32flux"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
@@ -748,7 +790,8 @@ def main():
 
     # ---- headline
     prec = cases.FP64 if args.precision == "fp64" else cases.FP32_FLUX
-    case = cases.inlet_2d() if args.workload == "inlet_2d" else cases.blobs_3d()
+    case = {"inlet_2d": cases.inlet_2d, "blobs_3d": cases.blobs_3d,
+            "inlet_2d_ns": cases.inlet_2d_ns}[args.workload]()
     prm = cases.Params(**{**case.params.__dict__, "precision": prec})
     log(f"[bench] headline {case.name} {args.precision} cells={case.ncells} steps={args.steps} "
         f"warmup={args.warmup}")
@@ -776,7 +819,9 @@ def main():
         others = [("inlet_2d", cases.inlet_2d, cases.FP64, args.steps),
                   ("inlet_2d", cases.inlet_2d, cases.FP32_FLUX, args.steps),
                   ("blobs_3d", cases.blobs_3d, cases.FP64, 50),
-                  ("blobs_3d", cases.blobs_3d, cases.FP32_FLUX, 50)]
+                  ("blobs_3d", cases.blobs_3d, cases.FP32_FLUX, 50),
+                  ("inlet_2d_ns", cases.inlet_2d_ns, cases.FP64, args.steps),
+                  ("inlet_2d_ns", cases.inlet_2d_ns, cases.FP32_FLUX, args.steps)]
         for wl, mk, pr, steps in others:
             name = f"{wl}_{'fp64' if pr == cases.FP64 else 'fp32flux'}"
             if wl == args.workload and pr == prec:
@@ -817,7 +862,12 @@ def main():
         extra["cpu_single_core"] = cpu_single_core(case)
         log(f"[bench] cpu one core {extra['cpu_single_core']['value']/1e6:.2f} M cell-updates/s")
 
-    if args.workload == "inlet_2d":
+    if args.workload == "inlet_2d_ns":
+        desc = ("inlet_2d_ns: 2D Navier-Stokes, 4 blocks x 512x256 cells on the sheared wavy "
+                "inlet-like curvilinear mesh, Mach 4 inflow (p=12270 Pa, T=217 K), no-slip walls, "
+                "extrapolation outflow, mu=1.5e-2 Pa s, Pr=0.72, MUSCL-minmod + Roe + viscous flux, "
+                "SSP-RK3, CFL 0.5")
+    elif args.workload == "inlet_2d":
         desc = ("inlet_2d: 2D Euler, 4 blocks x 512x256 cells on the sheared wavy inlet-like "
                 "curvilinear mesh, Mach 4 inflow (p=12270 Pa, T=217 K), slip walls, extrapolation "
                 "outflow, MUSCL-minmod + Roe, SSP-RK3, CFL 0.5")

@@ -18,17 +18,39 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "fv_oracle.c")
 LIB = os.path.join(HERE, "liborc.so")
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math", "-ffp-contract=off"]
+# host sanitizer build (ORC_SANITIZE=1): AddressSanitizer and UndefinedBehaviorSanitizer,
+# loaded by a Python started with the matching runtime preloaded (see sanitize_env)
+SAN_LIB = os.path.join(HERE, "liborc_san.so")
+SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+             "-fno-sanitize-recover=undefined"]
+SANITIZE = os.environ.get("ORC_SANITIZE") == "1"
 
 OK, E_INVAL, E_NOMEM, E_NONPHYSICAL = 0, -1, -2, -4
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(LIB):
-        cmd = ["gcc", *CFLAGS, "-o", LIB + ".tmp", SRC, "-lm"]
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (no fast-math, no FMA contraction); with
+    sanitize, the AddressSanitizer / UndefinedBehaviorSanitizer build."""
+    out = SAN_LIB if sanitize else LIB
+    if force or not os.path.exists(out):
+        cmd = ["gcc", *CFLAGS, *(SAN_FLAGS if sanitize else []), "-o", out + ".tmp", SRC, "-lm"]
         subprocess.check_call(cmd)
-        os.replace(LIB + ".tmp", LIB)
-    return LIB
+        os.replace(out + ".tmp", out)
+    return out
+
+
+def sanitize_env() -> dict:
+    """Environment for a Python process that loads the sanitizer build: the
+    gcc ASan runtime preloaded, leak checks off (the interpreter's own
+    allocations are not ours), every report fatal."""
+    env = dict(os.environ)
+    asan = subprocess.check_output(["gcc", "-print-file-name=libasan.so"], text=True).strip()
+    ubsan = subprocess.check_output(["gcc", "-print-file-name=libubsan.so"], text=True).strip()
+    env["LD_PRELOAD"] = f"{asan}:{ubsan}"
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1:halt_on_error=1"
+    env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
+    env["ORC_SANITIZE"] = "1"
+    return env
 
 
 class _BC(C.Structure):
@@ -61,9 +83,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            build(force=True)
-        L = C.CDLL(LIB)
+        path = SAN_LIB if SANITIZE else LIB
+        if not os.path.exists(path):
+            build(force=True, sanitize=SANITIZE)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.c_int, C.c_int, C.POINTER(_Block), C.c_double]

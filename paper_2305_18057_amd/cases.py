@@ -244,6 +244,20 @@ def inlet_2d(nblocks=4, ni=512, nj=256, precision=FP64, nsteps=500):
 # --------------------------------------------------------------------------
 # workload 3: 3D uniform block with seeded density blobs
 # --------------------------------------------------------------------------
+def inlet_2d_ns(mu=1.5e-2, prandtl=0.72, precision=FP64, nsteps=500):
+    """The inlet-like grid (4 x 512 x 256 cells, Mach 4 inflow of the paper's
+    inflow table) with no-slip walls at rest at j-min and j-max and a
+    viscosity in the grid's units (metres, SI state): mu = 1.5e-2 Pa s gives
+    a cell Reynolds number of about 30 at the inflow."""
+    case = inlet_2d(precision=precision, nsteps=nsteps)
+    for blk in case.blocks:
+        blk.bc[2] = BC(NOSLIP)
+        blk.bc[3] = BC(NOSLIP)
+    case.name = "inlet_2d_ns"
+    case.params = Params(**{**case.params.__dict__, "mu": mu, "prandtl": prandtl})
+    return case
+
+
 def blobs_fields(n, centres, amp=0.05, width_cells=8.0, rho_inf=1.0, chunk=16):
     """rho(k, j, i) = rho_inf (1 + amp sum_b exp(-|x - x_b|^2 / (2 w^2))).
 

@@ -70,7 +70,7 @@ int enqueue_stage(const StepPlan& P, int mode, int fp32, double* rout, hipStream
                               P.insts, rout);
     else
       e = fvk::launch_stage3d(mode, fp32, s.kind == kSet3D7 ? 7 : 3, grid, st, s.tiles, s.ntiles_dev,
-                              nfix, P.blocks, P.insts, rout);
+                              nfix, P.lim, P.blocks, P.insts, rout);
     if (e != hipSuccess)
       return fvrt::set_error(FV_E_DEVICE, "stage launch failed: %s", hipGetErrorString(e));
   }

@@ -140,8 +140,9 @@ extern "C" int fv_create_grid(const fv_grid_desc* desc, void* d_workspace, size_
   }
   g->L = layout_of(g->hg);
   if (!d_workspace || bytes < g->L.total) {
+    const size_t need = g->L.total;
     delete g;
-    return set_error(FV_E_NOMEM, "workspace of %zu bytes, need %zu", bytes, g->L.total);
+    return set_error(FV_E_NOMEM, "workspace of %zu bytes, need %zu", bytes, need);
   }
   if (((uintptr_t)d_workspace) % kAlign) {
     delete g;

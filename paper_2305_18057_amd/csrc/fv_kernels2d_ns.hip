@@ -40,13 +40,27 @@ constexpr int kQH = kNsRows + 4;    // state rows j0-2 .. j0+5
 constexpr int kWW = 64 + 2;         // primitive / centre columns i0-1 .. i0+64
 constexpr int kWH = kNsRows + 2;    // rows j0-1 .. j0+4
 
+// The face fluxes of a slab are formed in registers and then written over the
+// state and primitive arrays, which no thread reads any more by then (the
+// right and top edges have slots of their own): 51 KB per workgroup, three
+// workgroups per CU (their VGPR budget is the limit as well).
 struct NsLds {
-  double q[4][kQH][kQW];            // conserved state of the slab and its halo
-  double w[3][kWH][kWW];            // u, v, p/rho
+  union {
+    struct {
+      double q[4][kQH][kQW];        // conserved state of the slab and its halo
+      double w[3][kWH][kWW];        // u, v, p/rho
+    } s;
+    struct {
+      double fi[4][kNsRows][65];    // i-face fluxes (flux times area, minus viscous)
+      double fj[4][kNsRows + 1][64];  // j-face fluxes
+    } f;
+  } u;
   double cx[kWH][kWW], cy[kWH][kWW];  // cell centres
-  double nx[kNsRows + 1][65], ny[kNsRows + 1][65];  // nodes of the slab
-  double fi[4][kNsRows][65];        // i-face fluxes (flux times area, minus viscous)
-  double fj[4][kNsRows + 1][64];    // j-face fluxes
+  double nx[kNsRows + 3][67], ny[kNsRows + 3][67];  // nodes of the slab and one ring
+                                                    // (rows j0-1.., columns i0-1..)
+  double un[4][kNsRows][64];        // U^n of the slab (stage kinds that read it)
+  double er[4][kNsRows];            // fluxes of the slab's right edge
+  double et[4][64];                 // fluxes of the slab's top edge
   double red[4][8];                 // per-wave partials
 };
 
@@ -252,7 +266,7 @@ __device__ __forceinline__ void visc_flux(const double* wL, const double* wR, co
   F[3] = fmad(thx, tSx, thy * tSy);
 }
 
-template <typename T>
+template <int LIM, typename T>
 __device__ __forceinline__ void inv_flux(const Recon<T>& rc, const FluxK<T>& K, const double* c0,
                                          const double* c1, const double* c2, const double* c3,
                                          double Sx, double Sy, T* G) {
@@ -260,8 +274,8 @@ __device__ __forceinline__ void inv_flux(const Recon<T>& rc, const FluxK<T>& K, 
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     T ep, em, ep2, em2;
-    extrap<-1, T>(rc, T(c1[v] - c0[v]), T(c2[v] - c1[v]), ep, em);
-    extrap<-1, T>(rc, T(c2[v] - c1[v]), T(c3[v] - c2[v]), ep2, em2);
+    extrap<LIM, T>(rc, T(c1[v] - c0[v]), T(c2[v] - c1[v]), ep, em);
+    extrap<LIM, T>(rc, T(c2[v] - c1[v]), T(c3[v] - c2[v]), ep2, em2);
     qL[v] = T(c1[v]) + ep;
     qR[v] = T(c2[v]) - em2;
   }
@@ -272,7 +286,7 @@ __device__ __forceinline__ void inv_flux(const Recon<T>& rc, const FluxK<T>& K, 
   roe_flux<T, 2, -1>(qL, qR, n, T(A), K, G);
 }
 
-template <int MODE, typename T>
+template <int MODE, typename T, int LIM>
 __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, DevInstance& I,
                         double* __restrict__ rout, NsLds& L) {
   using SK = StageKind<MODE>;
@@ -309,15 +323,18 @@ __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, 
       double q[4];
       ns_cell(blocks, &B, bin, i0 - 2 + c, js - 2 + r, q);
 #pragma unroll
-      for (int v = 0; v < 4; ++v) L.q[v][r][c] = q[v];
+      for (int v = 0; v < 4; ++v) L.u.s.q[v][r][c] = q[v];
     }
-    for (int x = tid; x < (nr + 1) * (nc + 1); x += kNsThreads) {
-      const int r = x / (nc + 1), c = x - r * (nc + 1);
+    // nodes of the slab and one ring around it (clamped into the block: the
+    // ring nodes outside it are never used); face vectors and volumes
+    for (int x = tid; x < (nr + 3) * (nc + 3); x += kNsThreads) {
+      const int r = x / (nc + 3), c = x - r * (nc + 3);
       double xx, yy;
-      node_of(B, i0 + c, js + r, xx, yy);
+      node_of(B, min(max(i0 - 1 + c, 0), ni), min(max(js - 1 + r, 0), B.nj), xx, yy);
       L.nx[r][c] = xx;
       L.ny[r][c] = yy;
     }
+    // cell centres of the slab and its ring (ghost centres by their rule)
     for (int x = tid; x < (nr + 2) * (nc + 2); x += kNsThreads) {
       const int r = x / (nc + 2), c = x - r * (nc + 2);
       double cx, cy;
@@ -325,15 +342,24 @@ __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, 
       L.cx[r][c] = cx;
       L.cy[r][c] = cy;
     }
+    if constexpr (SK::reads_un) {
+      for (int x = tid; x < nr * nc; x += kNsThreads) {
+        const int r = x / nc, c = x - r * nc;
+        const double* p = B.u[0] + (long long)(js + r) * ni + i0 + c;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) L.un[v][r][c] = ldg(p + v * ncell);
+      }
+    }
     __syncthreads();
     for (int x = tid; x < (nr + 2) * (nc + 2); x += kNsThreads) {
       const int r = x / (nc + 2), c = x - r * (nc + 2);
-      const double rho = L.q[0][r + 1][c + 1];
-      const double u = L.q[1][r + 1][c + 1] / rho, v = L.q[2][r + 1][c + 1] / rho;
-      const double p = (gamma - 1.0) * (L.q[3][r + 1][c + 1] - 0.5 * rho * (u * u + v * v));
-      L.w[0][r][c] = u;
-      L.w[1][r][c] = v;
-      L.w[2][r][c] = p / rho;
+      const double rho = L.u.s.q[0][r + 1][c + 1];
+      const double ir = M<double>::rcp(rho);
+      const double u = L.u.s.q[1][r + 1][c + 1] * ir, v = L.u.s.q[2][r + 1][c + 1] * ir;
+      const double p = (gamma - 1.0) * (L.u.s.q[3][r + 1][c + 1] - 0.5 * rho * (u * u + v * v));
+      L.u.s.w[0][r][c] = u;
+      L.u.s.w[1][r][c] = v;
+      L.u.s.w[2][r][c] = p * ir;
     }
     __syncthreads();
 
@@ -346,33 +372,32 @@ __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, 
     auto node_w = [&](int c, int r, double* o) {
 #pragma unroll
       for (int k = 0; k < 3; ++k)
-        o[k] = 0.25 * (((L.w[k][r - 1][c - 1] + L.w[k][r - 1][c]) + L.w[k][r][c - 1]) + L.w[k][r][c]);
+        o[k] = 0.25 * (((L.u.s.w[k][r - 1][c - 1] + L.u.s.w[k][r - 1][c]) + L.u.s.w[k][r][c - 1]) + L.u.s.w[k][r][c]);
     };
     // i-face at node column fc (0..nc) of slab row lj
-    auto iface = [&](int fc) {
+    auto iface = [&](int fc, double (&F)[4]) {
       const int qr = lj + 2, wr = lj + 1;
       double c0[4], c1[4], c2[4], c3[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        c0[v] = L.q[v][qr][fc];
-        c1[v] = L.q[v][qr][fc + 1];
-        c2[v] = L.q[v][qr][fc + 2];
-        c3[v] = L.q[v][qr][fc + 3];
+        c0[v] = L.u.s.q[v][qr][fc];
+        c1[v] = L.u.s.q[v][qr][fc + 1];
+        c2[v] = L.u.s.q[v][qr][fc + 2];
+        c3[v] = L.u.s.q[v][qr][fc + 3];
       }
       // area vector: from the nodes, or exactly h_y e_x on a uniform block
-      const double Sx = B.xn ? L.ny[lj + 1][fc] - L.ny[lj][fc] : B.area[0];
-      const double Sy = B.xn ? -(L.nx[lj + 1][fc] - L.nx[lj][fc]) : 0.0;
+      const double Sx = B.xn ? L.ny[lj + 2][fc + 1] - L.ny[lj + 1][fc + 1] : B.area[0];
+      const double Sy = B.xn ? -(L.nx[lj + 2][fc + 1] - L.nx[lj + 1][fc + 1]) : 0.0;
       T G[4];
-      inv_flux<T>(rc, K, c0, c1, c2, c3, Sx, Sy, G);
-      double F[4];
+      inv_flux<LIM, T>(rc, K, c0, c1, c2, c3, Sx, Sy, G);
 #pragma unroll
       for (int v = 0; v < 4; ++v) F[v] = (double)G[v];
       if (mu > 0.0) {
         double wL[3], wR[3], wA[3], wB[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          wL[k] = L.w[k][wr][fc];
-          wR[k] = L.w[k][wr][fc + 1];
+          wL[k] = L.u.s.w[k][wr][fc];
+          wR[k] = L.u.s.w[k][wr][fc + 1];
         }
         node_w(fc + 1, wr, wA);      // node (i, j)
         node_w(fc + 1, wr + 1, wB);  // node (i, j+1)
@@ -382,33 +407,30 @@ __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, 
 #pragma unroll
         for (int v = 0; v < 4; ++v) F[v] -= (double)Fv[v];
       }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) L.fi[v][lj][fc] = F[v];
     };
     // j-face at node row fr (0..nr) of slab column li
-    auto jface = [&](int fr) {
+    auto jface = [&](int fr, double (&F)[4]) {
       const int qc = li + 2, wc = li + 1;
       double c0[4], c1[4], c2[4], c3[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        c0[v] = L.q[v][fr][qc];
-        c1[v] = L.q[v][fr + 1][qc];
-        c2[v] = L.q[v][fr + 2][qc];
-        c3[v] = L.q[v][fr + 3][qc];
+        c0[v] = L.u.s.q[v][fr][qc];
+        c1[v] = L.u.s.q[v][fr + 1][qc];
+        c2[v] = L.u.s.q[v][fr + 2][qc];
+        c3[v] = L.u.s.q[v][fr + 3][qc];
       }
-      const double Sx = B.xn ? -(L.ny[fr][li + 1] - L.ny[fr][li]) : 0.0;
-      const double Sy = B.xn ? L.nx[fr][li + 1] - L.nx[fr][li] : B.area[1];
+      const double Sx = B.xn ? -(L.ny[fr + 1][li + 2] - L.ny[fr + 1][li + 1]) : 0.0;
+      const double Sy = B.xn ? L.nx[fr + 1][li + 2] - L.nx[fr + 1][li + 1] : B.area[1];
       T G[4];
-      inv_flux<T>(rc, K, c0, c1, c2, c3, Sx, Sy, G);
-      double F[4];
+      inv_flux<LIM, T>(rc, K, c0, c1, c2, c3, Sx, Sy, G);
 #pragma unroll
       for (int v = 0; v < 4; ++v) F[v] = (double)G[v];
       if (mu > 0.0) {
         double wL[3], wR[3], wA[3], wB[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          wL[k] = L.w[k][fr][wc];
-          wR[k] = L.w[k][fr + 1][wc];
+          wL[k] = L.u.s.w[k][fr][wc];
+          wR[k] = L.u.s.w[k][fr + 1][wc];
         }
         node_w(wc + 1, fr + 1, wA);  // node (i+1, j)
         node_w(wc, fr + 1, wB);      // node (i, j)
@@ -418,14 +440,33 @@ __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, 
 #pragma unroll
         for (int v = 0; v < 4; ++v) F[v] -= (double)Fv[v];
       }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) L.fj[v][fr][li] = F[v];
     };
+    double Fl[4], Fb[4], qin[4];
     if (act) {
-      iface(li);
-      if (li == nc - 1) iface(nc);
-      jface(lj);
-      if (lj == nr - 1) jface(nr);
+      if (li == nc - 1) {
+        double Fr[4];
+        iface(nc, Fr);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) L.er[v][lj] = Fr[v];
+      }
+      if (lj == nr - 1) {
+        double Ft[4];
+        jface(nr, Ft);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) L.et[v][li] = Ft[v];
+      }
+      iface(li, Fl);
+      jface(lj, Fb);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) qin[v] = L.u.s.q[v][lj + 2][li + 2];
+    }
+    __syncthreads();  // state and primitives are read no more: the fluxes take their place
+    if (act) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        L.u.f.fi[v][lj][li] = Fl[v];
+        L.u.f.fj[v][lj][li] = Fb[v];
+      }
     }
     __syncthreads();
 
@@ -435,11 +476,15 @@ __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, 
       double R[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        R[v] = (0.0 + (L.fi[v][lj][li + 1] - L.fi[v][lj][li])) + (L.fj[v][lj + 1][li] - L.fj[v][lj][li]);
-      const double xa = L.nx[lj][li], ya = L.ny[lj][li];
-      const double xb = L.nx[lj][li + 1], yb = L.ny[lj][li + 1];
-      const double xc = L.nx[lj + 1][li], yc = L.ny[lj + 1][li];
-      const double xd = L.nx[lj + 1][li + 1], yd = L.ny[lj + 1][li + 1];
+      {
+        const double fr = li == nc - 1 ? L.er[v][lj] : L.u.f.fi[v][lj][li + 1];
+        const double ft = lj == nr - 1 ? L.et[v][li] : L.u.f.fj[v][lj + 1][li];
+        R[v] = (0.0 + (fr - Fl[v])) + (ft - Fb[v]);
+      }
+      const double xa = L.nx[lj + 1][li + 1], ya = L.ny[lj + 1][li + 1];
+      const double xb = L.nx[lj + 1][li + 2], yb = L.ny[lj + 1][li + 2];
+      const double xc = L.nx[lj + 2][li + 1], yc = L.ny[lj + 2][li + 1];
+      const double xd = L.nx[lj + 2][li + 2], yd = L.ny[lj + 2][li + 2];
       const double vol = B.xn ? 0.5 * fmad(xd - xa, yc - yb, -((xc - xb) * (yd - ya))) : B.vol;
       const double iv = M<double>::rcp(vol);
       const long long ro = (long long)j * ni + i;
@@ -455,13 +500,12 @@ __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, 
         double out[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const double qin = L.q[v][lj + 2][li + 2];
           double un = 0.0;
-          if constexpr (SK::reads_un) un = ldg(B.u[0] + v * ncell + ro);
+          if constexpr (SK::reads_un) un = L.un[v][lj][li];
           if constexpr (SK::low) {
             out[v] = fmad(-f, R[v], un);
           } else {
-            const double us = fmad(-f, R[v], qin);
+            const double us = fmad(-f, R[v], qin[v]);
             if (MODE == 1) out[v] = us;
             else if (MODE == 2) out[v] = fmad(0.75, un, 0.25 * us);
             else out[v] = fmad(1.0 / 3.0, un, (2.0 / 3.0) * us);
@@ -532,7 +576,7 @@ __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, 
 }
 
 template <int MODE, typename T>
-__global__ __launch_bounds__(kNsThreads) void k_stage2d_ns(const DevTile* __restrict__ tiles,
+__global__ __launch_bounds__(kNsThreads, 3) void k_stage2d_ns(const DevTile* __restrict__ tiles,
                                                          const int* __restrict__ ntiles_p, int nfix,
                                                          const DevBlock* __restrict__ blocks,
                                                          DevInstance* __restrict__ insts,
@@ -541,7 +585,10 @@ __global__ __launch_bounds__(kNsThreads) void k_stage2d_ns(const DevTile* __rest
   const int ntiles = nfix >= 0 ? nfix : *ntiles_p;
   for (TileWalk tw = xcd_walk(ntiles, 1, 0); tw.t < tw.end; tw.t += tw.stride) {
     const DevTile tl = tiles[tw.t];
-    tile_ns<MODE, T>(tl, blocks, insts[tl.inst], rout, s_lds);
+    DevInstance& I = insts[tl.inst];
+    // minmod, the common limiter, is compiled with the limiter fixed
+    if (I.limiter == LIM_MINMOD) tile_ns<MODE, T, LIM_MINMOD>(tl, blocks, I, rout, s_lds);
+    else tile_ns<MODE, T, -1>(tl, blocks, I, rout, s_lds);
   }
 }
 

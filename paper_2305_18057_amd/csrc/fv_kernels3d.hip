@@ -569,6 +569,7 @@ __device__ __forceinline__ void run_tile3d(const DevTile& tl, const DevBlock* __
 template <int MODE, typename T, int NY>
 __global__ __launch_bounds__(64 * (NY + 1), 2) void k_stage3d(const DevTile* __restrict__ tiles,
                                                               const int* __restrict__ ntiles_p, int nfix,
+                                                              int lim_fixed,
                                                               const DevBlock* __restrict__ blocks,
                                                               DevInstance* __restrict__ insts,
                                                               double* __restrict__ rout) {
@@ -584,7 +585,9 @@ __global__ __launch_bounds__(64 * (NY + 1), 2) void k_stage3d(const DevTile* __r
     const DevTile tl = tiles[tw.t];
     DevInstance& I = insts[tl.inst];
     if (MODE != 0 && I.stopped) continue;
-    if (I.limiter == LIM_MINMOD) run_tile3d<MODE, T, NY, LIM_MINMOD>(tl, blocks, I, rout, lane, w, sm);
+    // the limiter given at launch (grid path) needs no descriptor read
+    const int lim = lim_fixed >= 0 ? lim_fixed : I.limiter;
+    if (lim == LIM_MINMOD) run_tile3d<MODE, T, NY, LIM_MINMOD>(tl, blocks, I, rout, lane, w, sm);
     else run_tile3d<MODE, T, NY, -1>(tl, blocks, I, rout, lane, w, sm);
     __syncthreads();
     if (threadIdx.x == 0) tile_partials3d<MODE>(tl, I, sm.red);
@@ -639,12 +642,12 @@ __global__ __launch_bounds__(256) void k_cfl3d(const DevTile* __restrict__ tiles
 }  // namespace
 
 hipError_t launch_stage3d(int mode, int fp32, int ny, int grid, hipStream_t s, const DevTile* tiles,
-                          const int* ntiles, int ntiles_fixed, const DevBlock* blocks, DevInstance* insts,
-                          double* rout) {
+                          const int* ntiles, int ntiles_fixed, int lim_fixed, const DevBlock* blocks,
+                          DevInstance* insts, double* rout) {
   if (mode < 0 || mode > 6) return hipErrorInvalidValue;
 #define FV_L3(M, T, N)                                                                          \
   hipLaunchKernelGGL((k_stage3d<M, T, N>), dim3(grid), dim3(64 * (N + 1)), 0, s, tiles, ntiles, \
-                     ntiles_fixed, blocks, insts, rout)
+                     ntiles_fixed, lim_fixed, blocks, insts, rout)
 #define FV_L3N(M, T) \
   if (ny >= 7) FV_L3(M, T, 7); else FV_L3(M, T, 3)
 #define FV_L3_ALL(T)               \

@@ -28,7 +28,7 @@ const void* stage2d_ns_kernel_ptr(int fp32);
 
 // 3D: one workgroup per tile of ny j-rows (ny + 1 waves)
 hipError_t launch_stage3d(int mode, int fp32, int ny, int grid, hipStream_t s,
-                          const DevTile* tiles, const int* ntiles, int ntiles_fixed,
+                          const DevTile* tiles, const int* ntiles, int ntiles_fixed, int lim_fixed,
                           const DevBlock* blocks, DevInstance* insts, double* rout);
 hipError_t launch_cfl3d(int grid, int block, hipStream_t s, const DevTile* tiles,
                         const int* ntiles, const DevBlock* blocks, DevInstance* insts);

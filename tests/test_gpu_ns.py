@@ -131,19 +131,11 @@ def periodic_wavy(N=96, mu=5e-3):
     return case
 
 
-def ns_inlet_full(mu=1.5e-2):
-    """The inlet-like grid of the throughput workload (4 x 512 x 256 cells,
-    Mach 4 inflow of the paper's inflow table) with no-slip walls at rest
-    at j-min and j-max.  The viscosity is in the grid's units (metres,
-    SI state): mu = 1.5e-2 Pa s gives a cell Reynolds number of about 30 at
-    the inflow, so the viscous flux is a visible part of every face flux."""
-    case = CS.inlet_2d()
-    for blk in case.blocks:
-        blk.bc[2] = CS.BC(CS.NOSLIP)
-        blk.bc[3] = CS.BC(CS.NOSLIP)
-    case.name = "inlet_2d_ns"
-    case.params = with_(case.params, mu=mu, prandtl=0.72)
-    return case
+def ns_inlet_full():
+    """The inlet-like grid of the throughput workload with no-slip walls and
+    a viscosity that makes the viscous flux a visible part of every face
+    flux (cell Reynolds number about 30)."""
+    return CS.inlet_2d_ns()
 
 
 def check_residual(fv, O, case, params=None, tol=P.FP64_TOL):

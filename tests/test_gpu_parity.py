@@ -415,6 +415,28 @@ def test_inlet_full_500_steps(env):
     assert 1e-12 < eh <= P.FP32_STEP_TOL
 
 
+def test_inlet_2000_steps(env):
+    """As many steps as a served request may take (the 2000-step cap), on a
+    4 x 128 x 64 inlet grid: FP64 at the 1e-12 bar with the same t, and
+    FP32-flux after the same 2000 steps at the after-N bar."""
+    fv, O = env
+    case = CS.inlet_case(4 * 128, 64, 4, angle_deg=2.0)
+    ref = O.OracleGrid(case)
+    io = ref.run(case.params, 2000)
+    Uo = ref.get_state()
+    g, info = gpu_run(fv, case, 2000)
+    e64 = P.state_err(case, g.get_state(), Uo)
+    p32 = CS.Params(**{**case.params.__dict__, "precision": CS.FP32_FLUX})
+    g32, i32 = gpu_run(fv, case, 2000, p32)
+    e32 = P.state_err(case, g32.get_state(), Uo)
+    say(f"  inlet 4x128x64, 2000 steps: fp64 e_U = {e64:.3e} (per component "
+        f"{P.component_errs(case, g.get_state(), Uo)}), fp32-flux e_U = {e32:.3e}, "
+        f"t gpu {info['t']:.12g} ref {io['t']:.12g}")
+    assert info["steps"] == io["steps"] == 2000 and i32["steps"] == 2000
+    assert e64 <= P.FP64_TOL and abs(info["t"] - io["t"]) <= 1e-11 * io["t"]
+    assert e32 <= P.FP32_RUN_TOL
+
+
 # ---------------------------------------------------------------------------
 # 3D uniform block with density blobs
 # ---------------------------------------------------------------------------
