@@ -15,7 +15,7 @@
  * Where it follows the paper:
  *   Q and the inviscid normal flux F_{i,n} ........ Sec. 2 (conserved vector, flux definitions)
  *   semi-discrete form |Omega| dU/dt + R = 0 ....... Sec. 3.1, Eq. (spatial_residual)
- *   R = sum over the f faces of (F_{i,n} - F_{nu,n}) ds  Sec. 3.1, Eq. (residual), no source;
+ *   R = sum over the f faces of (F_{i,n} - F_{nu,n}) ds - |Omega| S_h   Sec. 3.1, Eq. (residual);
  *   F_{nu,n} with Stokes stresses tau and Theta ... Sec. 2 (viscous flux; 2D)
  *   explicit RK in Butcher form ..................... Sec. 3.2, Eq. (runge_kutta)
  *   MUSCL face states with limiter values Psi ...... Sec. 5, Eq. (flux)
@@ -29,7 +29,9 @@
  * gradients by Green-Gauss over the diamond of the face (the two cell
  * centres and the two face nodes, node values the mean of the four cells
  * around the node), corner ghosts, ghost-cell centres, a no-slip wall rule and
- * a viscous term in the time-step limit.
+ * a viscous term in the time-step limit; for 3D curvilinear cells: face area
+ * vectors from the cross product of the face diagonals and volumes from the
+ * divergence theorem over the six faces.
  */
 #include "fv_oracle.h"
 
@@ -48,8 +50,10 @@ typedef struct {
   int gk;              /* ghost offset along k: 2 in 3D, 0 in 2D */
   i64 npad;            /* padded cells per variable */
   i64 ncell;           /* interior cells */
-  double* xn;          /* 2D node coordinates (owned copy) or NULL when uniform */
-  double* yn;
+  double* xn;          /* node coordinates (owned copies) or NULL when uniform:  */
+  double* yn;          /* 2D (nj+1)(ni+1); 3D (nk+1)(nj+1)(ni+1), i fastest  */
+  double* zn;          /* 3D curvilinear only                                   */
+  double* src;         /* nv * ncell: cell-averaged source S_h, or NULL         */
   double h[3];
   double origin[3];    /* uniform blocks: position of node (0, 0) */
   orc_bc bc[6];
@@ -90,14 +94,65 @@ static inline int ext(const blk_t* b, int d) { return d == 0 ? b->ni : (d == 1 ?
 /* ------------------------------------------------------------------------ */
 static inline double X(const blk_t* b, int i, int j) { return b->xn[(i64)j * (b->ni + 1) + i]; }
 static inline double Y(const blk_t* b, int i, int j) { return b->yn[(i64)j * (b->ni + 1) + i]; }
+/* node (i, j, k) of a 3D curvilinear block */
+static inline void P3(const blk_t* b, int i, int j, int k, double p[3]) {
+  const i64 n = ((i64)k * (b->nj + 1) + j) * (b->ni + 1) + i;
+  p[0] = b->xn[n];
+  p[1] = b->yn[n];
+  p[2] = b->zn[n];
+}
+
+/* 3D curvilinear face (d, i, j, k): the quadrilateral of nodes
+ *   d = 0: (i,j,k) (i,j+1,k) (i,j+1,k+1) (i,j,k+1)
+ *   d = 1: (i,j,k) (i+1,j,k) (i+1,j,k+1) (i,j,k+1)
+ *   d = 2: (i,j,k) (i+1,j,k) (i+1,j+1,k) (i,j+1,k)
+ * with a, b, c, e its corners in this order.  Area vector (a reading: the
+ * vector area of the bilinear face, which the paper's face area ds and
+ * normal n come from): S = (c - a) x (e - b) / 2 oriented towards +index,
+ * i.e. half the cross product of the diagonals.  Face centre: the mean of
+ * the four corners. */
+static void face3(const blk_t* b, int d, int i, int j, int k, double S[3], double C[3]) {
+  int q[4][3];
+  for (int m = 0; m < 4; ++m) {
+    q[m][0] = i;
+    q[m][1] = j;
+    q[m][2] = k;
+  }
+  const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;  /* the two transverse axes */
+  q[1][t1] += 1;
+  q[2][t1] += 1;
+  q[2][t2] += 1;
+  q[3][t2] += 1;
+  double p[4][3];
+  for (int m = 0; m < 4; ++m) P3(b, q[m][0], q[m][1], q[m][2], p[m]);
+  double d1[3], d2[3];
+  for (int a = 0; a < 3; ++a) {
+    d1[a] = p[2][a] - p[0][a];
+    d2[a] = p[3][a] - p[1][a];
+  }
+  S[0] = 0.5 * (d1[1] * d2[2] - d1[2] * d2[1]);
+  S[1] = 0.5 * (d1[2] * d2[0] - d1[0] * d2[2]);
+  S[2] = 0.5 * (d1[0] * d2[1] - d1[1] * d2[0]);
+  if (d == 1) {
+    /* (i,j,k) (i+1,j,k) (i+1,j,k+1) (i,j,k+1) winds about -y: flip */
+    S[0] = -S[0];
+    S[1] = -S[1];
+    S[2] = -S[2];
+  }
+  for (int a = 0; a < 3; ++a) C[a] = 0.25 * (((p[0][a] + p[1][a]) + p[2][a]) + p[3][a]);
+}
 
 /* Area vector of face (i,j,k) along direction d, pointing towards +index.
  * Face (i,j,k) of direction 0 separates cells (i-1,j,k) and (i,j,k).
  * 2D: the face is the segment between two nodes; its area vector is that
  * segment turned by -90 degrees (length = face length, per unit depth). */
 static void face_vec(const blk_t* b, int nd, int d, int i, int j, int k, double S[3]) {
-  (void)k;
   S[0] = S[1] = S[2] = 0.0;
+  if (b->zn) {
+    double C[3];
+    face3(b, d, i, j, k, S, C);
+    return;
+  }
   if (b->xn) {
     if (d == 0) {
       S[0] = Y(b, i, j + 1) - Y(b, i, j);
@@ -117,6 +172,22 @@ static void face_vec(const blk_t* b, int nd, int d, int i, int j, int k, double 
 
 /* Cell volume: half the cross product of the two diagonals (2D), or hx*hy[*hz]. */
 static double cell_vol(const blk_t* b, int nd, int i, int j, int k) {
+  if (b->zn) {
+    /* 3D curvilinear (a reading): the divergence theorem with x . n taken at
+     * the face centres, |Omega| = (1/3) sum over the six faces of C_f . S_f
+     * with outward area vectors; exact for parallelepipeds, and the sum
+     * over a mesh telescopes to its boundary */
+    double v = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      int e[3] = {0, 0, 0};
+      e[d] = 1;
+      double Sm[3], Cm[3], Sp[3], Cp[3];
+      face3(b, d, i, j, k, Sm, Cm);
+      face3(b, d, i + e[0], j + e[1], k + e[2], Sp, Cp);
+      v += (Cp[0] * Sp[0] + Cp[1] * Sp[1] + Cp[2] * Sp[2]) - (Cm[0] * Sm[0] + Cm[1] * Sm[1] + Cm[2] * Sm[2]);
+    }
+    return v / 3.0;
+  }
   (void)k;
   if (b->xn) {
     double a = (X(b, i + 1, j + 1) - X(b, i, j)) * (Y(b, i, j + 1) - Y(b, i + 1, j));
@@ -484,9 +555,10 @@ static void fill_ghosts(orc_grid* G) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* residual, Sec. 3.1, Eq. (residual) with no source:                       */
+/* residual, Sec. 3.1, Eq. (residual):                                      */
 /*   R_cell = sum over its f faces of (F_{i,n} - F_{nu,n}) ds (outward      */
-/*   normals; the viscous part when mu > 0, 2D).                            */
+/*   normals; the viscous part when mu > 0, 2D) - |Omega| S_h, the source   */
+/*   term when one is set.                                                  */
 /* Each face flux is formed once, stored times its area, then each cell     */
 /* sums, direction by direction (i, j, k), the flux leaving through its     */
 /* +face minus the flux entering through its -face.                          */
@@ -697,6 +769,20 @@ static void residual_block(const orc_grid* G, int bi, const orc_params* P, doubl
           }
         }
   }
+  /* the source part of Eq. (residual): - |Omega| S_h, after every face */
+  if (!b->src) return;
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int k = 0; k < b->nk; ++k)
+    for (int j = 0; j < b->nj; ++j)
+      for (int i = 0; i < b->ni; ++i) {
+        const i64 c = cidx(b, i, j, k);
+        const double vol = cell_vol(b, nd, i, j, k);
+        for (int v = 0; v < nv; ++v) {
+          const double s = vol * b->src[v * b->ncell + c];
+          b->res[v * b->ncell + c] -= s;
+          if (scale) scale[v * b->ncell + c] += fabs(s);
+        }
+      }
 }
 
 static void residual_all(orc_grid* G, const orc_params* P, double** scales) {
@@ -970,13 +1056,22 @@ orc_grid* orc_create(int ndim, int nblocks, const orc_block_desc* desc, double g
       b->origin[a] = d->origin[a];
     }
     memcpy(b->bc, d->bc, sizeof(b->bc));
-    if (ndim == 2 && d->x && d->y) {
-      size_t nn = (size_t)(b->ni + 1) * (size_t)(b->nj + 1);
+    if (ndim == 3 && (d->x || d->y || d->z) && !(d->x && d->y && d->z)) {
+      orc_destroy(G);
+      return NULL;
+    }
+    if (d->x && d->y && (ndim == 2 || d->z)) {
+      size_t nn = (size_t)(b->ni + 1) * (size_t)(b->nj + 1) * (size_t)(ndim == 3 ? b->nk + 1 : 1);
       b->xn = (double*)malloc(nn * sizeof(double));
       b->yn = (double*)malloc(nn * sizeof(double));
       if (!b->xn || !b->yn) { orc_destroy(G); return NULL; }
       memcpy(b->xn, d->x, nn * sizeof(double));
       memcpy(b->yn, d->y, nn * sizeof(double));
+      if (ndim == 3) {
+        b->zn = (double*)malloc(nn * sizeof(double));
+        if (!b->zn) { orc_destroy(G); return NULL; }
+        memcpy(b->zn, d->z, nn * sizeof(double));
+      }
     }
     i64 nfmax = 0;
     for (int dd = 0; dd < ndim; ++dd) {
@@ -1012,7 +1107,8 @@ void orc_destroy(orc_grid* G) {
   if (G->b) {
     for (int bi = 0; bi < G->nblocks; ++bi) {
       blk_t* b = &G->b[bi];
-      free(b->xn); free(b->yn); free(b->q); free(b->qn); free(b->res); free(b->flux);
+      free(b->xn); free(b->yn); free(b->zn); free(b->src);
+      free(b->q); free(b->qn); free(b->res); free(b->flux);
     }
     free(G->b);
   }
@@ -1215,6 +1311,41 @@ void orc_metrics_2d(const orc_grid* G, int block, double* Sxi, double* Seta, dou
     }
   for (int j = 0; j < b->nj; ++j)
     for (int i = 0; i < b->ni; ++i) vol[(i64)j * b->ni + i] = cell_vol(b, 2, i, j, 0);
+}
+
+void orc_metrics_3d(const orc_grid* G, int block, double* S, double* vol) {
+  /* S: [dir][k][j][i][3] over each direction's (ni+e0)(nj+e1)(nk+e2) faces */
+  const blk_t* b = &G->b[block];
+  i64 o = 0;
+  for (int d = 0; d < 3; ++d)
+    for (int k = 0; k < b->nk + (d == 2); ++k)
+      for (int j = 0; j < b->nj + (d == 1); ++j)
+        for (int i = 0; i < b->ni + (d == 0); ++i) {
+          face_vec(b, 3, d, i, j, k, S + 3 * o);
+          ++o;
+        }
+  for (int k = 0; k < b->nk; ++k)
+    for (int j = 0; j < b->nj; ++j)
+      for (int i = 0; i < b->ni; ++i) vol[((i64)k * b->nj + j) * b->ni + i] = cell_vol(b, 3, i, j, k);
+}
+
+int orc_set_source(orc_grid* G, const double* S) {
+  const int nv = G->nv;
+  i64 o = 0;
+  for (int bi = 0; bi < G->nblocks; ++bi) {
+    blk_t* b = &G->b[bi];
+    const size_t n = (size_t)nv * (size_t)b->ncell;
+    if (!S) {
+      free(b->src);
+      b->src = NULL;
+      continue;
+    }
+    if (!b->src) b->src = (double*)malloc(n * sizeof(double));
+    if (!b->src) return ORC_E_INVAL;
+    memcpy(b->src, S + o, n * sizeof(double));
+    o += (i64)n;
+  }
+  return ORC_OK;
 }
 
 int orc_num_threads(void) {

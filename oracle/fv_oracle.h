@@ -27,7 +27,9 @@ typedef struct {
 
 typedef struct {
   int ni, nj, nk;        /* interior cells (nk = 1 in 2D) */
-  const double *x, *y;   /* 2D node coordinates (nj+1)*(ni+1), i fastest; NULL: uniform */
+  const double *x, *y;   /* node coordinates, i fastest: 2D (nj+1)*(ni+1); 3D with z,
+                            (nk+1)*(nj+1)*(ni+1); NULL: uniform */
+  const double* z;       /* 3D node coordinates (curvilinear 3D blocks) */
   double origin[3], h[3];
   orc_bc bc[6];          /* imin, imax, jmin, jmax, kmin, kmax */
 } orc_block_desc;
@@ -73,6 +75,10 @@ void orc_roe(const double* qL, const double* qR, const double* n, int nd, double
 void orc_reconstruct(const double* q4, int limiter, double eps, double kappa,
                      double* qL, double* qR);
 int orc_num_threads(void);
+/* cell-averaged source S_h of Eq. (residual), [block][var][k][j][i] (NULL
+ * removes it); the residual becomes sum_faces F ds - |Omega| S_h */
+int orc_set_source(orc_grid* g, const double* S);
+void orc_metrics_3d(const orc_grid* g, int block, double* S, double* vol);
 
 #ifdef __cplusplus
 }

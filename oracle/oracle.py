@@ -61,7 +61,7 @@ class _BC(C.Structure):
 class _Block(C.Structure):
     _fields_ = [("ni", C.c_int), ("nj", C.c_int), ("nk", C.c_int),
                 ("x", C.POINTER(C.c_double)), ("y", C.POINTER(C.c_double)),
-                ("origin", C.c_double * 3), ("h", C.c_double * 3), ("bc", _BC * 6)]
+                ("z", C.POINTER(C.c_double)), ("origin", C.c_double * 3), ("h", C.c_double * 3), ("bc", _BC * 6)]
 
 
 class _Params(C.Structure):
@@ -102,6 +102,8 @@ def lib():
         L.orc_face_flux.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_int, C.c_int, C.c_int,
                                     C.c_int, C.c_int, dp]
         L.orc_metrics_2d.argtypes = [C.c_void_p, C.c_int, dp, dp, dp]
+        L.orc_metrics_3d.argtypes = [C.c_void_p, C.c_int, dp, dp]
+        L.orc_set_source.argtypes = [C.c_void_p, dp]
         L.orc_viscous_flux.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_int, C.c_int, C.c_int,
                                        C.c_int, dp]
         L.orc_roe.argtypes = [dp, dp, dp, C.c_int, C.c_double, C.c_double, C.c_int, dp]
@@ -174,6 +176,10 @@ class OracleGrid:
                 y = np.ascontiguousarray(blk.y, dtype=np.float64)
                 self._keep += [x, y]
                 d.x, d.y = _ptr(x), _ptr(y)
+            if getattr(blk, "z", None) is not None:
+                z = np.ascontiguousarray(blk.z, dtype=np.float64)
+                self._keep.append(z)
+                d.z = _ptr(z)
             for a in range(3):
                 d.origin[a] = blk.origin[a]
                 d.h[a] = blk.h[a]
@@ -188,6 +194,9 @@ class OracleGrid:
         if not self._h:
             raise ValueError("oracle rejected the grid description")
         self.size = sum(self.nv * b.ncells for b in case.blocks)
+        src = case.source_flat() if hasattr(case, "source_flat") else None
+        if src is not None:
+            self.set_source(src)
         self.status = self.set_state(case.state_flat())
 
     def __del__(self):
@@ -201,6 +210,16 @@ class OracleGrid:
         assert U.size == self.size
         self.status = lib().orc_set_state(self._h, _ptr(U))
         return self.status
+
+    def set_source(self, S) -> None:
+        """Cell-averaged source S_h, [block][var][k][j][i] (None removes it)."""
+        if S is None:
+            lib().orc_set_source(self._h, None)
+            return
+        S = np.ascontiguousarray(S, dtype=np.float64).ravel()
+        assert S.size == self.size
+        if lib().orc_set_source(self._h, _ptr(S)) != OK:
+            raise MemoryError("oracle could not store the source")
 
     def get_state(self) -> np.ndarray:
         out = np.empty(self.size)
@@ -268,3 +287,18 @@ class OracleGrid:
         vol = np.empty((b.nj, b.ni))
         lib().orc_metrics_2d(self._h, block, _ptr(Sxi), _ptr(Seta), _ptr(vol))
         return Sxi, Seta, vol
+
+    def metrics_3d(self, block):
+        """Face area vectors of the three directions and cell volumes of a 3D block."""
+        b = self.case.blocks[block]
+        shapes = [(b.nk, b.nj, b.ni + 1, 3), (b.nk, b.nj + 1, b.ni, 3), (b.nk + 1, b.nj, b.ni, 3)]
+        n = sum(int(np.prod(s)) for s in shapes)
+        S = np.empty(n)
+        vol = np.empty((b.nk, b.nj, b.ni))
+        lib().orc_metrics_3d(self._h, block, _ptr(S), _ptr(vol))
+        out, o = [], 0
+        for s in shapes:
+            m = int(np.prod(s))
+            out.append(S[o:o + m].reshape(s))
+            o += m
+        return out, vol

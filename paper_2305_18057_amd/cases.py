@@ -61,11 +61,12 @@ class Block:
     ni: int
     nj: int
     nk: int = 1
-    x: Optional[np.ndarray] = None  # 2D node coordinates, shape (nj+1, ni+1)
+    x: Optional[np.ndarray] = None  # node coordinates: 2D (nj+1, ni+1); 3D (nk+1, nj+1, ni+1)
     y: Optional[np.ndarray] = None
     origin: Sequence[float] = (0.0, 0.0, 0.0)
     h: Sequence[float] = (1.0, 1.0, 1.0)
     bc: List[BC] = field(default_factory=list)
+    z: Optional[np.ndarray] = None  # 3D curvilinear: z of the nodes, shape (nk+1, nj+1, ni+1)
 
     @property
     def ncells(self) -> int:
@@ -98,6 +99,8 @@ class Case:
     nsteps: int = 1
     gamma: float = GAMMA
     meta: dict = field(default_factory=dict)
+    # cell-averaged source S_h per block, (nv, nk, nj, ni), or None
+    source: Optional[List[np.ndarray]] = None
 
     @property
     def nv(self) -> int:
@@ -110,6 +113,12 @@ class Case:
     def state_flat(self) -> np.ndarray:
         """Interior state, layout [block][var][k][j][i], float64."""
         return np.concatenate([np.ascontiguousarray(u, dtype=np.float64).ravel() for u in self.U0])
+
+    def source_flat(self) -> Optional[np.ndarray]:
+        """Source S_h in the state's layout, float64, or None."""
+        if self.source is None:
+            return None
+        return np.concatenate([np.ascontiguousarray(s, dtype=np.float64).ravel() for s in self.source])
 
     def split_flat(self, flat: np.ndarray) -> List[np.ndarray]:
         out, o = [], 0
@@ -384,3 +393,129 @@ def sod_2d(n=400, nj=4, x0=0.5, t_end=0.2, limiter=MINMOD, cfl=0.5, transpose=Fa
         blk = Block(nj, n, 1, None, None, (0.0, 0.0, 0.0), (h, h, 1.0), bcs)
     prm = Params(cfl=cfl, t_end=t_end, limiter=limiter, qref=(1.0, 1.0, 1.0, 2.5, 1.0))
     return Case("sod", 2, [blk], [U.copy()], prm, 10 ** 6, meta=dict(x0=x0, t_end=t_end))
+
+
+# --------------------------------------------------------------------------
+# 3D curvilinear multi-block grids and manufactured solutions
+# --------------------------------------------------------------------------
+def curv3d_nodes(ni, nj, nk, L=(1.0, 1.0, 1.0), amp=0.04, walls_k=False):
+    """Nodes (x, y, z), each of shape (nk+1, nj+1, ni+1), of a box of sides L
+    deformed by smooth displacements of relative size ``amp``:
+        x = X + amp Lx sin(2 pi Y/Ly) sin(2 pi Z/Lz)
+        y = Y + amp Ly sin(2 pi Z/Lz) sin(2 pi X/Lx)
+        z = Z + amp Lz sin(2 pi X/Lx) sin(2 pi Y/Ly) s(Z)
+    with s = 1, or s = sin(pi Z/Lz) when ``walls_k`` (then the k-min and
+    k-max planes stay flat and undeformed).  The displacement is periodic
+    in every direction, so opposite faces of the box are translates of each
+    other and the grid can be periodic; the cells are not parallelepipeds
+    and their faces are not planar."""
+    Lx, Ly, Lz = L
+    X = np.linspace(0.0, Lx, ni + 1)[None, None, :]
+    Y = np.linspace(0.0, Ly, nj + 1)[None, :, None]
+    Z = np.linspace(0.0, Lz, nk + 1)[:, None, None]
+    tp = 2.0 * math.pi
+    sz = np.sin(math.pi * Z / Lz) if walls_k else 1.0
+    x = X + amp * Lx * np.sin(tp * Y / Ly) * np.sin(tp * Z / Lz)
+    y = Y + amp * Ly * np.sin(tp * Z / Lz) * np.sin(tp * X / Lx)
+    z = Z + amp * Lz * np.sin(tp * X / Lx) * np.sin(tp * Y / Ly) * sz
+    shape = (nk + 1, nj + 1, ni + 1)
+    return [np.ascontiguousarray(np.broadcast_to(a, shape), dtype=np.float64) for a in (x, y, z)]
+
+
+def cell_centres_3d(x, y, z):
+    """Mean of the eight nodes of each cell, each of shape (nk, nj, ni)."""
+    def c(a):
+        return 0.125 * (a[:-1, :-1, :-1] + a[:-1, :-1, 1:] + a[:-1, 1:, :-1] + a[:-1, 1:, 1:]
+                        + a[1:, :-1, :-1] + a[1:, :-1, 1:] + a[1:, 1:, :-1] + a[1:, 1:, 1:])
+    return c(x), c(y), c(z)
+
+
+def mms_primitives(x, y, z, L=(1.0, 1.0, 1.0)):
+    """A smooth manufactured state, periodic on the box L: (rho, u, v, w, p).
+    Works on complex arguments (the source below differentiates it by the
+    complex step)."""
+    tp = 2.0 * np.pi
+    a, b, c = tp * x / L[0], tp * y / L[1], tp * z / L[2]
+    rho = 1.0 + 0.15 * np.sin(a + 0.3) * np.cos(b) + 0.1 * np.cos(c + 0.7)
+    u = 0.7 + 0.12 * np.cos(a) * np.sin(c + 0.2)
+    v = 0.35 + 0.1 * np.sin(b + 0.5) * np.cos(a + 0.1)
+    w = -0.25 + 0.08 * np.cos(c) * np.sin(b + 0.9)
+    p = 1.0 / GAMMA + 0.12 * np.cos(a + b) + 0.05 * np.sin(c + 0.4)
+    return rho, u, v, w, p
+
+
+def _mms_physical_flux(prim, a, gamma):
+    """Component a (0, 1, 2) of the Cartesian Euler flux (Sec. 2) of the
+    manufactured state: the analytic input of the source below."""
+    rho, u, v, w, p = prim
+    vel = (u, v, w)
+    ua = vel[a]
+    et = p / ((gamma - 1.0) * rho) + 0.5 * (u * u + v * v + w * w)
+    out = [rho * ua]
+    for b in range(3):
+        out.append(rho * vel[b] * ua + (p if a == b else 0.0))
+    out.append((rho * et + p) * ua)
+    return out
+
+
+def mms_source(x, y, z, L=(1.0, 1.0, 1.0), gamma=GAMMA, h=1e-30):
+    """S = div F(U_m) of the manufactured state (the steady Euler equations
+    with S on the right-hand side hold for U_m), by the complex-step
+    derivative of each flux component: exact to rounding.  Shape (5, ...)."""
+    S = None
+    pts = [np.asarray(t, dtype=np.complex128) for t in (x, y, z)]
+    for a in range(3):
+        q = list(pts)
+        q[a] = q[a] + 1j * h
+        F = _mms_physical_flux(mms_primitives(*q, L=L), a, gamma)
+        d = np.stack([np.imag(f) / h for f in F])
+        S = d if S is None else S + d
+    return S
+
+
+def curv3d_case(ni=24, nj=16, nk=16, nblocks=2, amp=0.04, state="random", seed=6,
+                walls_k=False, precision=FP64, nsteps=5, L=(1.0, 1.0, 1.0), cfl=0.5):
+    """A 3D curvilinear multi-block grid: the deformed box above, split along
+    i into ``nblocks`` blocks linked face to face; periodic in i and j, and in
+    k unless ``walls_k`` (slip walls).  ``state``: "uniform" (a free stream),
+    "random" (a smooth field plus seeded noise) or "mms" (the manufactured
+    state, with its source S_h at the cell centres)."""
+    x, y, z = curv3d_nodes(ni, nj, nk, L, amp, walls_k)
+    xc, yc, zc = cell_centres_3d(x, y, z)
+    prim_inf = (1.0, 0.6, 0.3, 0.0, 1.0 / GAMMA)
+    if state == "uniform":
+        rho = np.full(xc.shape, prim_inf[0])
+        vel = [np.full(xc.shape, prim_inf[1]), np.full(xc.shape, prim_inf[2]), np.zeros(xc.shape)]
+        p = np.full(xc.shape, prim_inf[4])
+    elif state == "mms":
+        rho, u, v, w, p = mms_primitives(xc, yc, zc, L)
+        vel = [u, v, w]
+    elif state == "random":
+        rng = np.random.default_rng(seed)
+        rho, u, v, w, p = mms_primitives(xc, yc, zc, L)
+        rho = rho * (1.0 + 0.02 * rng.standard_normal(xc.shape))
+        p = p * (1.0 + 0.02 * rng.standard_normal(xc.shape))
+        vel = [u + 0.02 * rng.standard_normal(xc.shape), v, w]
+    else:
+        raise ValueError(state)
+    U = conserved(rho, vel, p)
+    S = mms_source(xc, yc, zc, L) if state == "mms" else None
+    cuts = np.cumsum([0] + _split_even(ni, nblocks))
+    nb = len(cuts) - 1
+    blocks, U0, src = [], [], []
+    kbc = BC(SLIPWALL) if walls_k else BC(PERIODIC)
+    for b in range(nb):
+        i0, i1 = int(cuts[b]), int(cuts[b + 1])
+        lo = BC(BLOCK, b - 1, 1) if b > 0 else (BC(BLOCK, nb - 1, 1) if nb > 1 else BC(PERIODIC))
+        hi = BC(BLOCK, b + 1, 0) if b < nb - 1 else (BC(BLOCK, 0, 0) if nb > 1 else BC(PERIODIC))
+        bcs = [lo, hi, BC(PERIODIC), BC(PERIODIC), kbc, kbc]
+        sl = (slice(None), slice(None), slice(i0, i1 + 1))
+        blocks.append(Block(i1 - i0, nj, nk, x[sl].copy(), y[sl].copy(), (0.0, 0.0, 0.0),
+                            (1.0, 1.0, 1.0), bcs, z[sl].copy()))
+        U0.append(np.ascontiguousarray(U[:, :, :, i0:i1]))
+        if S is not None:
+            src.append(np.ascontiguousarray(S[:, :, :, i0:i1]))
+    prm = Params(cfl=cfl, precision=precision, qref=qref_of(prim_inf, 3))
+    return Case(f"curv3d_{state}", 3, blocks, U0, prm, nsteps,
+                meta=dict(amp=amp, L=L, seed=seed, walls_k=walls_k),
+                source=src if S is not None else None)
