@@ -11,8 +11,10 @@
  *     (Sec. 5, Eq. (flux)),
  *   - an upwind numerical normal flux of the inviscid flux F_{i,n}
  *     (Sec. 2, flux definitions; Roe's solver is the reading taken),
- *   - the residual R = sum over the cell's faces of F_{i,n} ds
- *     (Sec. 3.1, Eq. (residual); no source, no viscous part),
+ *   - the residual R = sum over the cell's faces of (F_{i,n} - F_{nu,n}) ds
+ *     - |Omega| S_h (Sec. 3.1, Eq. (residual); the viscous part F_{nu,n} of
+ *     Sec. 2 on 2D grids with mu > 0, the cell-averaged source S_h on grids
+ *     created with a source buffer),
  *   - the explicit Runge-Kutta update |Omega| dU/dt + R = 0
  *     (Sec. 3.1, Eq. (spatial_residual); Sec. 3.2, Eq. (runge_kutta),
  *     taken as the three-stage strong-stability-preserving scheme),
@@ -27,6 +29,9 @@
  *     handle that uses them; the allocation-free path (fv_step_noalloc) uses
  *     a fixed static device array instead.  Every host array passed in is copied before the
  *     call returns; the caller keeps ownership.
+ *   - Grids: structured blocks, uniform (spacing h) or curvilinear (node
+ *     coordinates) in 2D and 3D; face area vectors and cell volumes of
+ *     curvilinear cells come from the nodes (see fv_block_desc).
  *   - State layout (host or device): [block][var][k][j][i], i fastest,
  *     interior cells only, IEEE binary64.  2D: var = rho, rho*u, rho*v,
  *     rho*e_t (4 vars); 3D: rho, rho*u, rho*v, rho*w, rho*e_t (5 vars).
@@ -111,9 +116,20 @@ typedef struct fv_bc {
 
 typedef struct fv_block_desc {
   int ni, nj, nk;          /* interior cells; nk = 1 in 2D */
-  const double *x, *y, *z; /* 2D: node coordinates (nj+1)*(ni+1), i fastest;
-                              NULL => uniform spacing h.  3D grids are
-                              uniform (z is reserved, must be NULL). */
+  const double *x, *y, *z; /* node coordinates, i fastest, or all NULL (uniform
+                              spacing h):
+                              2D: x, y of (nj+1)*(ni+1) nodes, z NULL;
+                              3D: x, y, z of (nk+1)*(nj+1)*(ni+1) nodes.
+                              3D curvilinear cells (a reading of the paper's
+                              face area ds, normal n and volume |Omega| for
+                              hexahedra with bilinear faces): the area vector
+                              of a face is half the cross product of its two
+                              diagonals, oriented towards increasing index;
+                              the volume is one third of the sum over the six
+                              faces of (outward area vector . face centre), the
+                              centre the mean of the face's four nodes.  Both
+                              are exact for the trilinear cell.  Slip walls
+                              mirror about the wall face's own normal. */
   double origin[3], h[3];  /* uniform spacing per direction */
   fv_bc face[6];           /* imin, imax, jmin, jmax, kmin, kmax */
 } fv_block_desc;
@@ -123,6 +139,11 @@ typedef struct fv_grid_desc {
   int nblocks;
   const fv_block_desc* blocks;
   double gamma;                 /* ratio of specific heats */
+  int with_source;              /* 1: reserve a cell-averaged source S_h (Sec. 2,
+                                   the source term; Sec. 3.1, Eq. (residual)),
+                                   zero until fv_set_source; 0: none.  Grid API
+                                   only (FV_E_UNSUPPORTED on the server and in
+                                   fv_step_noalloc). */
 } fv_grid_desc;
 
 typedef struct fv_params {
@@ -194,9 +215,18 @@ int fv_destroy_grid(fv_grid* g);
 int fv_set_state(fv_grid* g, const double* U, int on_device);
 int fv_get_state(const fv_grid* g, double* U, int on_device);
 
-/* Residual R(U) of the current state (Sec. 3.1, Eq. (residual)) after the
- * ghost fill, in the state layout; norms (may be NULL) receives the RMS of
- * R_v/|Omega| per variable.  The state is not changed. */
+/* Cell-averaged source S_h of Eq. (residual) (Sec. 3.1): body forces,
+ * chemistry or a manufactured solution's forcing, in the state layout (host
+ * or device per on_device); the residual of every later call is
+ * R = sum_faces (F_{i,n} - F_{nu,n}) ds - |Omega| S_h.  S = NULL sets it to
+ * zero.  FV_E_INVAL unless the grid was created with with_source = 1.  The
+ * time-step bound does not depend on it. */
+int fv_set_source(fv_grid* g, const double* S, int on_device);
+
+/* Residual R(U) of the current state (Sec. 3.1, Eq. (residual), with the
+ * source when the grid has one) after the ghost fill, in the state layout;
+ * norms (may be NULL) receives the RMS of R_v/|Omega| per variable.  The
+ * state is not changed. */
 int fv_residual(fv_grid* g, const fv_params* p, double* R, int on_device, double norms[5]);
 
 /* Ghost values the boundary rules give for the current state, laid out

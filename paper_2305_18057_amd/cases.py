@@ -458,19 +458,26 @@ def _mms_physical_flux(prim, a, gamma):
     return out
 
 
-def mms_source(x, y, z, L=(1.0, 1.0, 1.0), gamma=GAMMA, h=1e-30):
+def mms_source(x, y, z, L=(1.0, 1.0, 1.0), gamma=GAMMA, h=1e-30, chunk=8):
     """S = div F(U_m) of the manufactured state (the steady Euler equations
     with S on the right-hand side hold for U_m), by the complex-step
-    derivative of each flux component: exact to rounding.  Shape (5, ...)."""
-    S = None
-    pts = [np.asarray(t, dtype=np.complex128) for t in (x, y, z)]
-    for a in range(3):
-        q = list(pts)
-        q[a] = q[a] + 1j * h
-        F = _mms_physical_flux(mms_primitives(*q, L=L), a, gamma)
-        d = np.stack([np.imag(f) / h for f in F])
-        S = d if S is None else S + d
-    return S
+    derivative of each flux component: exact to rounding.  Shape (5, ...);
+    evaluated in slabs of ``chunk`` entries of the first axis."""
+    x, y, z = (np.asarray(t, dtype=np.float64) for t in (x, y, z))
+    out = np.empty((5,) + x.shape)
+    n0 = x.shape[0] if x.ndim else 1
+    for a0 in range(0, n0, chunk):
+        sl = slice(a0, a0 + chunk) if x.ndim else slice(None)
+        pts = [t[sl].astype(np.complex128) for t in (x, y, z)]
+        S = None
+        for a in range(3):
+            q = list(pts)
+            q[a] = q[a] + 1j * h
+            F = _mms_physical_flux(mms_primitives(*q, L=L), a, gamma)
+            d = np.stack([np.imag(f) / h for f in F])
+            S = d if S is None else S + d
+        out[(slice(None),) + (sl,)] = S
+    return out
 
 
 def curv3d_case(ni=24, nj=16, nk=16, nblocks=2, amp=0.04, state="random", seed=6,
@@ -519,3 +526,13 @@ def curv3d_case(ni=24, nj=16, nk=16, nblocks=2, amp=0.04, state="random", seed=6
     return Case(f"curv3d_{state}", 3, blocks, U0, prm, nsteps,
                 meta=dict(amp=amp, L=L, seed=seed, walls_k=walls_k),
                 source=src if S is not None else None)
+
+
+def curv3d_mms(n=256, precision=FP64, nsteps=20):
+    """The manufactured-solution workload on the deformed periodic box:
+    n^3 cells in two blocks linked around in i, the manufactured state and its
+    source S_h at the cell centres."""
+    c = curv3d_case(ni=n, nj=n, nk=n, nblocks=2, amp=0.04, state="mms", precision=precision,
+                    nsteps=nsteps)
+    c.name = "curv3d_mms"
+    return c

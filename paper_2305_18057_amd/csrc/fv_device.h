@@ -5,7 +5,9 @@
 //   state buffers u[0] = U^n, u[1], u[2]: per block [var][k][j][i], i fastest,
 //   interior cells only (ghost cells are never stored: every stencil read
 //   outside a block is resolved on the fly from the boundary rule).
-//   2D curvilinear node coordinates x, y: (nj+1)(ni+1) per block.
+//   node coordinates of curvilinear blocks: x, y of (nj+1)(ni+1) nodes (2D);
+//   x, y, z of (nk+1)(nj+1)(ni+1) nodes (3D), i fastest.
+//   source S_h (grids created with one): per block [var][k][j][i].
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -25,8 +27,10 @@ struct DevBlock {
   int ni, nj, nk, inst;
   long long ncell;          // ni*nj*nk: stride between variables
   double* u[3];             // U^n, stage buffer a, stage buffer b
-  const double* xn;         // 2D node coordinates or nullptr (uniform)
+  const double* xn;         // node coordinates or nullptr (uniform)
   const double* yn;
+  const double* zn;         // 3D curvilinear blocks: z of the nodes (nullptr otherwise)
+  const double* src;        // cell-averaged source S_h, [var][k][j][i], or nullptr
   double area[3];           // uniform: face area per direction
   double vol;               // uniform: cell volume
   double org[3];            // uniform: position of node (0, 0, 0)
@@ -381,6 +385,70 @@ __device__ __forceinline__ double nodey(const DevBlock& B, int i, int j) {
 }
 
 // --------------------------------------------------------------------------
+// 3D curvilinear geometry.  The face (d, i, j, k) of a cell has the corners
+// p0 = node (i, j, k), p1 = p0 + e_t1, p2 = p0 + e_t1 + e_t2, p3 = p0 + e_t2
+// with (t1, t2) = (j, k), (i, k), (i, j) for d = 0, 1, 2.  Its area vector,
+// oriented towards increasing index d, is half the cross product of the
+// diagonals p2 - p0 and p3 - p1 (the opposite sign for d = 1, where that
+// order winds the other way); its centre is the mean of the corners.
+// The volume of a cell is 1/3 of the sum over its faces of the outward area
+// vector dotted with the face centre (the divergence theorem for x).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void node3(const DevBlock& B, int i, int j, int k, double* p) {
+  const long long n = ((long long)k * (B.nj + 1) + j) * (B.ni + 1) + i;
+  p[0] = ldg(B.xn + n);
+  p[1] = ldg(B.yn + n);
+  p[2] = ldg(B.zn + n);
+}
+
+// area vector S and S . centre of a face from its corners p0..p3 (above)
+__device__ __forceinline__ void quad_face(const double* p0, const double* p1, const double* p2,
+                                          const double* p3, bool flip, double* S, double& cs) {
+  double a[3], b[3], c[3];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    a[x] = p2[x] - p0[x];
+    b[x] = flip ? p1[x] - p3[x] : p3[x] - p1[x];
+    c[x] = 0.25 * (((p0[x] + p1[x]) + p2[x]) + p3[x]);
+  }
+  S[0] = 0.5 * (a[1] * b[2] - a[2] * b[1]);
+  S[1] = 0.5 * (a[2] * b[0] - a[0] * b[2]);
+  S[2] = 0.5 * (a[0] * b[1] - a[1] * b[0]);
+  cs = (c[0] * S[0] + c[1] * S[1]) + c[2] * S[2];
+}
+
+// face (d, i, j, k) of a 3D curvilinear block, corners read from memory
+__device__ __forceinline__ void face3(const DevBlock& B, int d, int i, int j, int k, double* S,
+                                      double& cs) {
+  double p[4][3];
+  const int a1 = d == 0 ? 1 : 0, a2 = d == 2 ? 1 : 2;  // transverse axes
+  int o[4][3] = {{i, j, k}, {i, j, k}, {i, j, k}, {i, j, k}};
+  o[1][a1] += 1;
+  o[2][a1] += 1;
+  o[2][a2] += 1;
+  o[3][a2] += 1;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) node3(B, o[m][0], o[m][1], o[m][2], p[m]);
+  quad_face(p[0], p[1], p[2], p[3], d == 1, S, cs);
+}
+
+// mean area vectors Sb[d] = (S_d- + S_d+)/2 and the volume of cell (i, j, k)
+__device__ inline void cell_geom3(const DevBlock& B, int i, int j, int k, double (*Sb)[3],
+                                  double& vol) {
+  double v = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    double Sm[3], Sp[3], cm, cp;
+    face3(B, d, i, j, k, Sm, cm);
+    face3(B, d, i + (d == 0), j + (d == 1), k + (d == 2), Sp, cp);
+#pragma unroll
+    for (int x = 0; x < 3; ++x) Sb[d][x] = 0.5 * (Sm[x] + Sp[x]);
+    v += cp - cm;
+  }
+  vol = v / 3.0;
+}
+
+// --------------------------------------------------------------------------
 // ghost resolution: value of cell (i, j, k) of block B in state buffer buf,
 // where at most one index lies outside the block, by at most 2 cells.  The
 // boundary rule gives a source cell (same block, a neighbour block, or the
@@ -443,7 +511,12 @@ __device__ __forceinline__ void load_cell(const DevBlock* __restrict__ blocks, c
   for (int v = 0; v < NV; ++v) q[v] = ldg(s + v * S->ncell);
   if (kind == BC_SLIPWALL) {
     double Sv[3] = {0.0, 0.0, 0.0};
-    if (B.xn != nullptr) {
+    if (B.zn != nullptr) {
+      // the wall face at the ghost's transverse position
+      const int w = side == 0 ? 0 : n;
+      double cs;
+      face3(B, d, d == 0 ? w : i, d == 1 ? w : j, d == 2 ? w : k, Sv, cs);
+    } else if (B.xn != nullptr) {
       const double* X = B.xn;
       const double* Y = B.yn;
       const long long w1 = B.ni + 1;

@@ -12,8 +12,15 @@
 
 namespace fvexec {
 
-// tile sets: 2D, 3D with 3 j-rows per tile (4-wave workgroups), 3D with 7 (8 waves)
-enum { kSet2D = 0, kSet3D3 = 1, kSet3D7 = 2 };
+// tile sets: 2D, 3D with 3 j-rows per tile (4-wave workgroups), 3D with 7
+// (8 waves), general 3D (curvilinear blocks or a source; 4 j-rows, 4 waves)
+enum { kSet2D = 0, kSet3D3 = 1, kSet3D7 = 2, kSet3DG = 3 };
+// the set kind of a grid: 2D, general 3D, or uniform 3D by its tile rows
+inline int set_kind(int ndim, bool general3d, int ny) {
+  if (ndim == 2) return kSet2D;
+  if (general3d) return kSet3DG;
+  return ny >= 7 ? kSet3D7 : kSet3D3;
+}
 
 struct LaunchSet {
   fvk::DevTile* tiles = nullptr;
@@ -33,7 +40,7 @@ struct StepPlan {
   int rk = 3;                   // 3: SSP-RK3; 2, 4: the 2- and 4-stage second-order schemes
   int lim = -1;                 // >= 0: the limiter of every instance; -1: each instance's own
   bool ns = false;              // 2D sets run the Navier-Stokes stage kernel (viscous flux,
-                                // no-slip walls)
+                                // no-slip walls, source term)
   std::vector<LaunchSet> sets;
 };
 

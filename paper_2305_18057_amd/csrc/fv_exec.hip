@@ -44,6 +44,9 @@ int launch_grid(const LaunchSet& s, int fp32, bool ns) {
     cap = fvrt::occupancy_blocks(fvk::stage2d_kernel_ptr(1, fp32), 256);
     const int need = (s.ntiles + 3) / 4;
     cap = std::min(cap, need);
+  } else if (s.kind == kSet3DG) {
+    cap = fvrt::occupancy_blocks(fvk::stage3d_gen_kernel_ptr(fp32), 256);
+    cap = std::min(cap, s.ntiles);
   } else {
     const int ny = s.kind == kSet3D7 ? 7 : 3;
     cap = fvrt::occupancy_blocks(fvk::stage3d_kernel_ptr(1, fp32, ny), 64 * (ny + 1));
@@ -68,6 +71,9 @@ int enqueue_stage(const StepPlan& P, int mode, int fp32, double* rout, hipStream
     else if (s.kind == kSet2D)
       e = fvk::launch_stage2d(mode, fp32, grid, 256, st, s.tiles, s.ntiles_dev, nfix, P.lim, P.blocks,
                               P.insts, rout);
+    else if (s.kind == kSet3DG)
+      e = fvk::launch_stage3d_gen(mode, fp32, grid, st, s.tiles, s.ntiles_dev, nfix, P.lim, P.blocks,
+                                  P.insts, rout);
     else
       e = fvk::launch_stage3d(mode, fp32, s.kind == kSet3D7 ? 7 : 3, grid, st, s.tiles, s.ntiles_dev,
                               nfix, P.lim, P.blocks, P.insts, rout);

@@ -60,7 +60,7 @@ int upload_tiles(fv_grid* g) {
   ls.ntiles = nt;
   // graphs are captured again after every change of the tile list (below)
   ls.count_fixed = true;
-  ls.kind = g->hg.ndim == 2 ? fvexec::kSet2D : (g->shape.ny >= 7 ? fvexec::kSet3D7 : fvexec::kSet3D3);
+  ls.kind = fvexec::set_kind(g->hg.ndim, g->hg.gen3, g->shape.ny);
   g->plan.sets.push_back(ls);
   g->graphs.clear();
   // the tile list and the instance's tile count must be on the device before
@@ -103,6 +103,12 @@ int cfl_pass(fv_grid* g) {
   return get_inst(g);
 }
 
+// 2D grids run the Navier-Stokes stage kernel for a viscosity, a no-slip
+// face or a source term
+bool ns_kernel(const HostGrid& hg, const fv_params* p) {
+  return hg.ndim == 2 && (p->mu > 0.0 || hg.has_noslip || hg.with_source);
+}
+
 // The stage kernels these parameters take: a viscosity or a no-slip face
 // needs the Navier-Stokes kernel (2D grids).  Called after the parameters
 // are on the device; when the viscosity differs from the one the current
@@ -110,7 +116,7 @@ int cfl_pass(fv_grid* g) {
 int use_params(fv_grid* g, const fv_params* p) {
   if (p->mu > 0.0 && g->hg.ndim != 2)
     return set_error(FV_E_UNSUPPORTED, "the viscous flux is provided for 2D grids only");
-  g->plan.ns = p->mu > 0.0 || g->hg.has_noslip;
+  g->plan.ns = ns_kernel(g->hg, p);
   if (g->have_state && (g->hinst.mu != g->cfl_mu || g->hinst.prandtl != g->cfl_pr)) {
     const int st = cfl_pass(g);
     if (st) return st;
@@ -174,23 +180,14 @@ extern "C" int fv_create_grid(const fv_grid_desc* desc, void* d_workspace, size_
                         hipMemcpyHostToDevice, g->stream);
   if (he != hipSuccess)
     return fail(set_error(FV_E_DEVICE, "upload of block descriptors failed: %s", hipGetErrorString(he)));
-  // node coordinates
-  {
-    size_t noff = 0;
-    for (int b = 0; b < g->hg.nblocks; ++b) {
-      if (g->hg.xs[b].empty()) continue;
-      const size_t nn = g->hg.xs[b].size();
-      char* dst = g->ws + g->L.nodes + noff * sizeof(double);
-      he = hipMemcpyAsync(dst, g->hg.xs[b].data(), nn * sizeof(double), hipMemcpyHostToDevice,
-                          g->stream);
-      if (he == hipSuccess)
-        he = hipMemcpyAsync(dst + nn * sizeof(double), g->hg.ys[b].data(), nn * sizeof(double),
-                            hipMemcpyHostToDevice, g->stream);
-      if (he != hipSuccess)
-        return fail(set_error(FV_E_DEVICE, "upload of node coordinates failed: %s",
-                              hipGetErrorString(he)));
-      noff += 2 * nn;
-    }
+  // node coordinates; the source starts at zero
+  he = upload_nodes(g->hg, g->ws + g->L.nodes, g->stream);
+  if (he != hipSuccess)
+    return fail(set_error(FV_E_DEVICE, "upload of node coordinates failed: %s", hipGetErrorString(he)));
+  if (g->hg.with_source) {
+    he = hipMemsetAsync(g->ws + g->L.src, 0, sizeof(double) * (size_t)g->hg.state_size, g->stream);
+    if (he != hipSuccess)
+      return fail(set_error(FV_E_DEVICE, "clearing the source failed: %s", hipGetErrorString(he)));
   }
   std::memset(&g->hinst, 0, sizeof(g->hinst));
   fv_params p;
@@ -247,6 +244,20 @@ extern "C" int fv_set_state(fv_grid* g, const double* U, int on_device) {
   g->have_state = 1;
   if (g->hinst.flags & fvk::FLAG_NONPHYS)
     return set_error(FV_E_NONPHYSICAL, "initial state has a cell with rho <= 0, p <= 0 or a non-finite value");
+  return FV_OK;
+}
+
+extern "C" int fv_set_source(fv_grid* g, const double* S, int on_device) {
+  if (!g) return set_error(FV_E_INVAL, "null grid");
+  if (!g->hg.with_source)
+    return set_error(FV_E_INVAL, "the grid was created without a source buffer (with_source = 0)");
+  const size_t bytes = sizeof(double) * (size_t)g->hg.state_size;
+  if (S)
+    FV_HIP(hipMemcpyAsync(g->ws + g->L.src, S, bytes,
+                          on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, g->stream));
+  else
+    FV_HIP(hipMemsetAsync(g->ws + g->L.src, 0, bytes, g->stream));
+  FV_HIP(hipStreamSynchronize(g->stream));
   return FV_OK;
 }
 
@@ -441,7 +452,7 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
   // Navier-Stokes grids time (and record) the shapes of their own kernel
   if (p->mu > 0.0 && g->hg.ndim != 2)
     return set_error(FV_E_UNSUPPORTED, "the viscous flux is provided for 2D grids only");
-  const bool tns = p->mu > 0.0 || g->hg.has_noslip;
+  const bool tns = ns_kernel(g->hg, p);
   g->plan.ns = tns;
   {
     // a shape already recorded for this size class and precision is applied
@@ -466,6 +477,13 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
       TileShape s;
       s.rows = r;
       s.ny = 1;
+      cands.push_back(s);
+    }
+  } else if (g->hg.gen3) {
+    for (int r : {4, 8, 12, 16, 24, 32, 48, 64}) {
+      TileShape s;
+      s.rows = r;
+      s.ny = 4;
       cands.push_back(s);
     }
   } else {

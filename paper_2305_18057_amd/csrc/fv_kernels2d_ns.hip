@@ -1,8 +1,9 @@
 // 2D Navier-Stokes stage kernel: the residual of Sec. 3.1, Eq. (residual)
-// with both parts of the face flux, F_{i,n} - F_{nu,n} (Sec. 2), fused with
-// the RK stage update and the step-end partials, like the Euler stage
-// kernel.  It runs every 2D grid whose parameters carry a viscosity or whose
-// faces include a no-slip wall.
+// with both parts of the face flux, F_{i,n} - F_{nu,n} (Sec. 2), and the
+// source term - |Omega| S_h, fused with the RK stage update and the step-end
+// partials, like the Euler stage kernel.  It runs every 2D grid whose
+// parameters carry a viscosity, whose faces include a no-slip wall or that
+// has a source.
 //
 // One workgroup of 256 threads takes a tile (64 columns by n rows) in slabs
 // of 4 rows, one cell per thread:
@@ -488,6 +489,10 @@ __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, 
       const double vol = B.xn ? 0.5 * fmad(xd - xa, yc - yb, -((xc - xb) * (yd - ya))) : B.vol;
       const double iv = M<double>::rcp(vol);
       const long long ro = (long long)j * ni + i;
+      if (B.src != nullptr) {  // the source part of Eq. (residual): - |Omega| S_h
+#pragma unroll
+        for (int v = 0; v < 4; ++v) R[v] -= vol * ldg(B.src + v * ncell + ro);
+      }
       if (MODE == 0) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {

@@ -619,7 +619,13 @@ __global__ __launch_bounds__(256) void k_cfl3d(const DevTile* __restrict__ tiles
           double q[5];
 #pragma unroll
           for (int v = 0; v < 5; ++v) q[v] = ldg(B.u[0] + v * B.ncell + idx);
-          dmin = fmin(dmin, cell_dt_limit<3>(q, Sb, B.vol, I.gamma, bad));
+          if (B.zn != nullptr) {  // curvilinear: the cell's own metrics
+            double Sc[3][3], vol;
+            cell_geom3(B, i, tl.j0 + y, tl.k0 + r, Sc, vol);
+            dmin = fmin(dmin, cell_dt_limit<3>(q, Sc, vol, I.gamma, bad));
+          } else {
+            dmin = fmin(dmin, cell_dt_limit<3>(q, Sb, B.vol, I.gamma, bad));
+          }
         }
     }
     const double m = wave_min(dmin);

@@ -34,6 +34,13 @@ hipError_t launch_cfl3d(int grid, int block, hipStream_t s, const DevTile* tiles
                         const int* ntiles, const DevBlock* blocks, DevInstance* insts);
 const void* stage3d_kernel_ptr(int mode, int fp32, int ny);
 
+// general 3D stage (curvilinear blocks, source term; one 256-thread
+// workgroup per tile of 4 j-rows); the same stage kinds and arguments
+hipError_t launch_stage3d_gen(int mode, int fp32, int grid, hipStream_t s, const DevTile* tiles,
+                              const int* ntiles, int ntiles_fixed, int lim_fixed,
+                              const DevBlock* blocks, DevInstance* insts, double* rout);
+const void* stage3d_gen_kernel_ptr(int fp32);
+
 // per-instance bookkeeping (one wavefront per instance)
 //   prepare:  stop flags and time step of the coming steps from the parameters
 //   finalize: step end: norms, first norm, drop, t, steps, spectral minimum,

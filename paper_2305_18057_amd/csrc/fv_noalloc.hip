@@ -71,6 +71,9 @@ extern "C" int fv_step_noalloc(const fv_grid_desc* desc, double* d_U, const fv_p
   HostGrid hg;
   st = validate_and_copy(desc, hg);
   if (st) return st;
+  if (hg.with_source)
+    return set_error(FV_E_UNSUPPORTED, "a source term needs a grid handle (fv_create_grid, "
+                                       "fv_set_source): the allocation-free path takes none");
   if (p->mu > 0.0 && hg.ndim != 2)
     return set_error(FV_E_UNSUPPORTED, "the viscous flux is provided for 2D grids only");
   const bool ns = p->mu > 0.0 || hg.has_noslip;
@@ -135,18 +138,7 @@ extern "C" int fv_step_noalloc(const fv_grid_desc* desc, double* d_U, const fv_p
                         hipMemcpyHostToDevice, s));
   FV_HIP(hipMemcpyAsync(d_tiles, htiles.data(), sizeof(fvk::DevTile) * nt, hipMemcpyHostToDevice, s));
   FV_HIP(hipMemcpyAsync(d_ntiles, &nt, sizeof(int), hipMemcpyHostToDevice, s));
-  {
-    size_t noff = 0;
-    for (int b = 0; b < hg.nblocks; ++b) {
-      if (hg.xs[b].empty()) continue;
-      const size_t nn = hg.xs[b].size();
-      char* dst = base + L.nodes + noff * sizeof(double);
-      FV_HIP(hipMemcpyAsync(dst, hg.xs[b].data(), nn * sizeof(double), hipMemcpyHostToDevice, s));
-      FV_HIP(hipMemcpyAsync(dst + nn * sizeof(double), hg.ys[b].data(), nn * sizeof(double),
-                            hipMemcpyHostToDevice, s));
-      noff += 2 * nn;
-    }
-  }
+  FV_HIP(upload_nodes(hg, base + L.nodes, s));
   FV_HIP(hipMemcpyAsync(d_inst, &I, sizeof(I), hipMemcpyHostToDevice, s));
 
   fvexec::StepPlan plan;
@@ -162,7 +154,7 @@ extern "C" int fv_step_noalloc(const fv_grid_desc* desc, double* d_U, const fv_p
   ls.ntiles_dev = d_ntiles;
   ls.ntiles = nt;
   ls.count_fixed = true;
-  ls.kind = hg.ndim == 2 ? fvexec::kSet2D : (sh.ny >= 7 ? fvexec::kSet3D7 : fvexec::kSet3D3);
+  ls.kind = fvexec::set_kind(hg.ndim, hg.gen3, sh.ny);
   plan.sets.push_back(ls);
 
   // time-step bound and physical check of the initial state, as a new state

@@ -37,17 +37,19 @@ struct HostGrid {
   int ndim = 2, nv = 4, nblocks = 0;
   double gamma = 1.4;
   std::vector<fv_block_desc> blocks;           // pointers below are owned copies
-  std::vector<std::vector<double>> xs, ys;     // node coordinates (2D curvilinear)
+  std::vector<std::vector<double>> xs, ys, zs; // node coordinates (curvilinear blocks)
   long long ncells = 0, state_size = 0;
   long long node_doubles = 0;
-  bool has_noslip = false;  // a no-slip face: the Navier-Stokes stage kernel runs it
+  bool has_noslip = false;   // a no-slip face: the Navier-Stokes stage kernel runs it
+  bool with_source = false;  // a source buffer S_h (2D: the Navier-Stokes kernel runs it)
+  bool gen3 = false;         // 3D with curvilinear blocks or a source: the general 3D kernel
 };
 
 int validate_and_copy(const fv_grid_desc* d, HostGrid& out);
 
 // size of the per-instance device region and its layout
 struct InstLayout {
-  size_t blocks, inst, ntiles, tiles, part, segs, nodes, u[3], total;
+  size_t blocks, inst, ntiles, tiles, part, segs, nodes, src, u[3], total;
   long long max_tiles;
   int nseg;
   long long ghost_cells, ghost_doubles;
@@ -59,6 +61,9 @@ InstLayout layout_of(const HostGrid& g);
 void build_blocks(const HostGrid& g, char* base, const InstLayout& L, int inst_index,
                   std::vector<fvk::DevBlock>& out, int block_index_offset);
 void build_segs(const HostGrid& g, std::vector<fvk::GhostSeg>& segs);
+// node coordinates of every curvilinear block to dst (the layout's node
+// region): per block x, y (and z in 3D), in block order
+hipError_t upload_nodes(const HostGrid& g, char* dst, hipStream_t s);
 void build_tiles(const HostGrid& g, const TileShape& sh, int inst_index, int block_index_offset,
                  std::vector<fvk::DevTile>& out);
 TileShape default_shape(const HostGrid& g);

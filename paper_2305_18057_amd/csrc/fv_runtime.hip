@@ -44,6 +44,10 @@ int validate_and_copy(const fv_grid_desc* d, HostGrid& g) {
   g.blocks.assign(d->blocks, d->blocks + d->nblocks);
   g.xs.resize(d->nblocks);
   g.ys.resize(d->nblocks);
+  g.zs.resize(d->nblocks);
+  if (d->with_source != 0 && d->with_source != 1)
+    return set_error(FV_E_INVAL, "with_source must be 0 or 1 (got %d)", d->with_source);
+  g.with_source = d->with_source == 1;
   const long long kMaxDim = 1 << 20;
   for (int b = 0; b < g.nblocks; ++b) {
     fv_block_desc& B = g.blocks[b];
@@ -59,25 +63,29 @@ int validate_and_copy(const fv_grid_desc* d, HostGrid& g) {
       return set_error(FV_E_UNSUPPORTED,
                        "block %d: a k-plane of %d x %d cells exceeds the 3D kernels' 32-bit "
                        "in-plane offsets (ni * nj must stay below 2^29)", b, B.ni, B.nj);
-    if (g.ndim == 3 && (B.x || B.y || B.z))
-      return set_error(FV_E_UNSUPPORTED, "block %d: 3D grids must be uniform (x, y, z NULL)", b);
+    if (g.ndim == 3 && (B.x || B.y || B.z) && !(B.x && B.y && B.z))
+      return set_error(FV_E_INVAL, "block %d: give x, y and z or none of them", b);
     if (g.ndim == 2 && ((B.x == nullptr) != (B.y == nullptr)))
       return set_error(FV_E_INVAL, "block %d: give both x and y or neither", b);
-    if (B.z) return set_error(FV_E_INVAL, "block %d: z must be NULL", b);
+    if (g.ndim == 2 && B.z) return set_error(FV_E_INVAL, "block %d: z must be NULL in 2D", b);
     if (!B.x) {
       for (int a = 0; a < g.ndim; ++a)
         if (!(B.h[a] > 0.0) || !std::isfinite(B.h[a]))
           return set_error(FV_E_INVAL, "block %d: spacing h[%d] must be > 0", b, a);
     } else {
-      const size_t nn = (size_t)(B.ni + 1) * (size_t)(B.nj + 1);
+      const size_t nn = (size_t)(B.ni + 1) * (size_t)(B.nj + 1) * (size_t)(g.ndim == 3 ? B.nk + 1 : 1);
       g.xs[b].assign(B.x, B.x + nn);
       g.ys[b].assign(B.y, B.y + nn);
+      if (g.ndim == 3) g.zs[b].assign(B.z, B.z + nn);
       for (size_t q = 0; q < nn; ++q)
-        if (!std::isfinite(g.xs[b][q]) || !std::isfinite(g.ys[b][q]))
+        if (!std::isfinite(g.xs[b][q]) || !std::isfinite(g.ys[b][q]) ||
+            (g.ndim == 3 && !std::isfinite(g.zs[b][q])))
           return set_error(FV_E_INVAL, "block %d: non-finite node coordinate", b);
       B.x = g.xs[b].data();
       B.y = g.ys[b].data();
-      g.node_doubles += 2 * (long long)nn;
+      B.z = g.ndim == 3 ? g.zs[b].data() : nullptr;
+      g.node_doubles += (g.ndim == 3 ? 3 : 2) * (long long)nn;
+      if (g.ndim == 3) g.gen3 = true;
     }
     g.ncells += (long long)B.ni * B.nj * B.nk;
   }
@@ -120,6 +128,7 @@ int validate_and_copy(const fv_grid_desc* d, HostGrid& g) {
     }
   }
   g.state_size = g.ncells * g.nv;
+  if (g.ndim == 3 && g.with_source) g.gen3 = true;
   return FV_OK;
 }
 
@@ -170,6 +179,7 @@ InstLayout layout_of(const HostGrid& g) {
   L.part = off;   off += align_up(sizeof(double) * fvk::kPartStride * (size_t)L.max_tiles);
   L.segs = off;   off += align_up(sizeof(fvk::GhostSeg) * (size_t)L.nseg);
   L.nodes = off;  off += align_up(sizeof(double) * (size_t)g.node_doubles);
+  L.src = off;    off += g.with_source ? align_up(sizeof(double) * (size_t)g.state_size) : 0;
   for (int s = 0; s < 3; ++s) {
     L.u[s] = off;
     off += align_up(sizeof(double) * (size_t)g.state_size);
@@ -195,11 +205,13 @@ void build_blocks(const HostGrid& g, char* base, const InstLayout& L, int inst_i
     for (int s = 0; s < 3; ++s) B.u[s] = (double*)(base + L.u[s]) + soff;
     B.out_off = soff;
     if (D.x) {
-      const long long nn = (long long)(D.ni + 1) * (D.nj + 1);
+      const long long nn = (long long)(D.ni + 1) * (D.nj + 1) * (g.ndim == 3 ? D.nk + 1 : 1);
       B.xn = (const double*)(base + L.nodes) + noff;
       B.yn = B.xn + nn;
-      noff += 2 * nn;
+      if (g.ndim == 3) B.zn = B.yn + nn;
+      noff += (g.ndim == 3 ? 3 : 2) * nn;
     }
+    if (g.with_source) B.src = (const double*)(base + L.src) + soff;
     if (g.ndim == 2) {
       B.area[0] = D.h[1];
       B.area[1] = D.h[0];
@@ -234,6 +246,21 @@ void build_blocks(const HostGrid& g, char* base, const InstLayout& L, int inst_i
   }
 }
 
+hipError_t upload_nodes(const HostGrid& g, char* dst, hipStream_t s) {
+  size_t off = 0;
+  for (int b = 0; b < g.nblocks; ++b) {
+    if (g.xs[b].empty()) continue;
+    const size_t bytes = g.xs[b].size() * sizeof(double);
+    const std::vector<double>* c[3] = {&g.xs[b], &g.ys[b], &g.zs[b]};
+    for (int a = 0; a < (g.ndim == 3 ? 3 : 2); ++a) {
+      const hipError_t e = hipMemcpyAsync(dst + off, c[a]->data(), bytes, hipMemcpyHostToDevice, s);
+      if (e != hipSuccess) return e;
+      off += bytes;
+    }
+  }
+  return hipSuccess;
+}
+
 TileShape default_shape(const HostGrid& g) {
   TileShape s;
   if (g.ndim == 2) {
@@ -244,6 +271,9 @@ TileShape default_shape(const HostGrid& g) {
     while (rows < 64 && rows * 2 <= want) rows *= 2;
     s.rows = rows;
     s.ny = 1;
+  } else if (g.gen3) {
+    s.ny = 4;
+    s.rows = 16;
   } else {
     s.ny = 7;
     s.rows = 32;
@@ -279,7 +309,7 @@ void build_tiles(const HostGrid& g, const TileShape& sh, int inst_index, int bof
     } else {
       // at most 64 planes: the kernel keeps a row's right-edge fluxes in 64 LDS slots, one per plane
       const int P = std::min(64, std::max(kMinPlanes3D, sh.rows));
-      const int NY = sh.ny >= 7 ? 7 : 3;
+      const int NY = g.gen3 ? 4 : (sh.ny >= 7 ? 7 : 3);
       for (int k0 = 0; k0 < B.nk; k0 += P)
         for (int j0 = 0; j0 < B.nj; j0 += NY)
           for (int i0 = 0; i0 < B.ni; i0 += 64) {
@@ -312,8 +342,8 @@ int size_class(const HostGrid& g) {
 
 std::string tune_key(const HostGrid& g, int precision, bool ns) {
   char buf[96];
-  snprintf(buf, sizeof(buf), "%dd_%s_c%d%s", g.ndim, precision == FV_FP32_FLUX ? "fp32flux" : "fp64",
-           size_class(g), ns ? "_ns" : "");
+  snprintf(buf, sizeof(buf), "%dd_%s_c%d%s%s", g.ndim, precision == FV_FP32_FLUX ? "fp32flux" : "fp64",
+           size_class(g), ns ? "_ns" : "", g.gen3 ? "_gen" : "");
   return buf;
 }
 

@@ -191,16 +191,7 @@ int upload(fv_server* S, Request* r) {
   build_blocks(r->hg, base, L, slot, r->blocks, boff);
   FV_HIP(hipMemcpyAsync(S->d_blocks + boff, r->blocks.data(), sizeof(fvk::DevBlock) * r->blocks.size(),
                         hipMemcpyHostToDevice, S->stream));
-  size_t noff = r->off_nodes;
-  for (int b = 0; b < r->hg.nblocks; ++b) {
-    if (r->hg.xs[b].empty()) continue;
-    const size_t nn = r->hg.xs[b].size();
-    FV_HIP(hipMemcpyAsync(base + noff, r->hg.xs[b].data(), nn * sizeof(double),
-                          hipMemcpyHostToDevice, S->stream));
-    FV_HIP(hipMemcpyAsync(base + noff + nn * sizeof(double), r->hg.ys[b].data(),
-                          nn * sizeof(double), hipMemcpyHostToDevice, S->stream));
-    noff += 2 * nn * sizeof(double);
-  }
+  FV_HIP(upload_nodes(r->hg, base + r->off_nodes, S->stream));
   FV_HIP(hipMemcpyAsync(base + r->off_u[0], r->U0.data(), sizeof(double) * r->U0.size(),
                         hipMemcpyHostToDevice, S->stream));
   fvk::DevInstance I;
@@ -549,6 +540,12 @@ extern "C" int fv_submit(fv_server* S, const fv_grid_desc* desc, const double* U
     delete r;
     return set_error(FV_E_UNSUPPORTED, "the server runs the Euler stage kernels: grids with no-slip "
                                        "walls go through fv_step / fv_solve");
+  }
+  if (r->hg.with_source || r->hg.gen3) {
+    delete r;
+    return set_error(FV_E_UNSUPPORTED, "the server runs the Euler stage kernels of uniform 3D and "
+                                       "2D grids: 3D curvilinear grids and source terms go through "
+                                       "fv_step / fv_solve");
   }
   r->U0.assign(U0, U0 + r->hg.state_size);
   r->params = *p;

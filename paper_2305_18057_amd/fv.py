@@ -45,7 +45,8 @@ class fv_block_desc(C.Structure):
 
 class fv_grid_desc(C.Structure):
     _fields_ = [("ndim", C.c_int), ("nblocks", C.c_int),
-                ("blocks", C.POINTER(fv_block_desc)), ("gamma", C.c_double)]
+                ("blocks", C.POINTER(fv_block_desc)), ("gamma", C.c_double),
+                ("with_source", C.c_int)]
 
 
 class fv_params(C.Structure):
@@ -83,7 +84,8 @@ class fv_server_stats(C.Structure):
 
 EXPORTS = [
     "fv_strerror", "fv_last_error", "fv_default_params", "fv_grid_workspace_bytes",
-    "fv_create_grid", "fv_destroy_grid", "fv_set_state", "fv_get_state", "fv_residual",
+    "fv_create_grid", "fv_destroy_grid", "fv_set_state", "fv_get_state", "fv_set_source",
+    "fv_residual",
     "fv_ghost_count", "fv_ghosts", "fv_step", "fv_step_timed", "fv_solve", "fv_tune",
     "fv_grid_get_stats",
     "fv_server_create", "fv_submit", "fv_poll", "fv_cancel", "fv_request_times",
@@ -121,6 +123,7 @@ def lib():
     L.fv_destroy_grid.argtypes = [vp]
     L.fv_set_state.argtypes = [vp, vp, C.c_int]
     L.fv_get_state.argtypes = [vp, vp, C.c_int]
+    L.fv_set_source.argtypes = [vp, vp, C.c_int]
     L.fv_residual.argtypes = [vp, C.POINTER(fv_params), vp, C.c_int, dp]
     L.fv_ghost_count.restype = C.c_size_t
     L.fv_ghost_count.argtypes = [vp]
@@ -174,6 +177,10 @@ class GridDesc:
                 self.keep += [x, y]
                 d.x = x.ctypes.data_as(C.POINTER(C.c_double))
                 d.y = y.ctypes.data_as(C.POINTER(C.c_double))
+            if getattr(blk, "z", None) is not None:
+                z = np.ascontiguousarray(blk.z, dtype=np.float64)
+                self.keep.append(z)
+                d.z = z.ctypes.data_as(C.POINTER(C.c_double))
             for a in range(3):
                 d.origin[a] = blk.origin[a]
                 d.h[a] = blk.h[a]
@@ -184,7 +191,8 @@ class GridDesc:
                 d.face[f].nbr_face = bc.nbr_face
                 for a in range(5):
                     d.face[f].prim_in[a] = bc.prim[a]
-        self.desc = fv_grid_desc(case.ndim, nb, self.arr, case.gamma)
+        self.desc = fv_grid_desc(case.ndim, nb, self.arr, case.gamma,
+                                 1 if getattr(case, "source", None) is not None else 0)
 
 
 def make_params(p: "_cases.Params") -> fv_params:
@@ -229,6 +237,8 @@ class Grid:
                                 C.c_size_t(nbytes), C.c_void_p(self.stream), C.byref(h)))
         self._h = h
         self.workspace_bytes = int(nbytes)
+        if getattr(case, "source", None) is not None:
+            self.set_source(case.source_flat())
 
     def close(self):
         if getattr(self, "_h", None):
@@ -254,6 +264,19 @@ class Grid:
         if check:
             _check(st)
         return st
+
+    def set_source(self, S) -> None:
+        """Cell-averaged source S_h in the state layout (None: zero)."""
+        torch = _torch()
+        if S is None:
+            _check(lib().fv_set_source(self._h, None, 0))
+        elif isinstance(S, torch.Tensor):
+            assert S.dtype == torch.float64 and S.is_contiguous() and S.numel() == self.size
+            _check(lib().fv_set_source(self._h, C.c_void_p(S.data_ptr()), 1 if S.is_cuda else 0))
+        else:
+            a = np.ascontiguousarray(S, dtype=np.float64).ravel()
+            assert a.size == self.size
+            _check(lib().fv_set_source(self._h, C.c_void_p(a.ctypes.data), 0))
 
     def get_state(self, out=None):
         torch = _torch()

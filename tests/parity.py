@@ -71,11 +71,14 @@ def residual_err(case, Rg, Ro, scale):
     return max(float(np.max(np.abs(gv - ov)) / np.max(sv)) for gv, ov, sv in zip(g, o, s))
 
 
-def cell_volumes(case):
-    """Cell volumes in the state order of one variable (all blocks)."""
+def cell_volumes(case, ref=None):
+    """Cell volumes in the state order of one variable (all blocks); 3D
+    curvilinear blocks take theirs from the oracle grid ref."""
     out = []
-    for b in case.blocks:
-        if b.x is not None:
+    for n, b in enumerate(case.blocks):
+        if case.ndim == 3 and getattr(b, "z", None) is not None:
+            out.append(ref.metrics_3d(n)[1].ravel())
+        elif b.x is not None:
             X, Y = b.x, b.y
             a = (X[1:, 1:] - X[:-1, :-1]) * (Y[1:, :-1] - Y[:-1, 1:])
             c = (X[1:, :-1] - X[:-1, 1:]) * (Y[1:, 1:] - Y[:-1, :-1])

@@ -70,12 +70,52 @@ def test_workspace_bytes_and_validation(fvb):
     gd = fvb.GridDesc(c1)
     assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) == 0
     assert b"at least 2 cells" in L.fv_last_error()
-    # 3D curvilinear is not provided
+    # a 3D curvilinear block needs x, y and z
     c3 = CS.blobs_case(8, nblobs=1)
-    c3.blocks[0].x = np.zeros((9, 9))
-    c3.blocks[0].y = np.zeros((9, 9))
+    c3.blocks[0].x = np.zeros((9, 9, 9))
+    c3.blocks[0].y = np.zeros((9, 9, 9))
     gd = fvb.GridDesc(c3)
     assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) == 0
+    assert b"x, y and z" in L.fv_last_error()
+
+
+def test_curvilinear_3d_and_source_descriptors(fvb):
+    """3D node coordinates and the source buffer enter the workspace size;
+    a 2D z, non-finite nodes or a bad with_source flag are refused; the
+    allocation-free path and the server refuse a source (and the server 3D
+    curvilinear grids) before any device work."""
+    L = fvb.lib()
+    c = CS.curv3d_case(ni=16, nj=8, nk=8, nblocks=2, state="random")
+    gd = fvb.GridDesc(c)
+    n_curv = L.fv_grid_workspace_bytes(C.byref(gd.desc), 0)
+    nodes = sum(3 * 8 * (b.ni + 1) * (b.nj + 1) * (b.nk + 1) for b in c.blocks)
+    assert n_curv >= 3 * 8 * c.nv * c.ncells + nodes
+    cs = CS.curv3d_case(ni=16, nj=8, nk=8, nblocks=2, state="mms")
+    gds = fvb.GridDesc(cs)
+    assert gds.desc.with_source == 1
+    n_src = L.fv_grid_workspace_bytes(C.byref(gds.desc), 0)
+    assert n_src >= n_curv + 8 * c.nv * c.ncells
+    gds.desc.with_source = 2
+    assert L.fv_grid_workspace_bytes(C.byref(gds.desc), 0) == 0
+    assert b"with_source" in L.fv_last_error()
+    bad = CS.curv3d_case(ni=16, nj=8, nk=8, nblocks=1, state="random")
+    bad.blocks[0].z[1, 2, 3] = np.nan
+    g_bad = fvb.GridDesc(bad)
+    assert L.fv_grid_workspace_bytes(C.byref(g_bad.desc), 0) == 0
+    assert b"non-finite node" in L.fv_last_error()
+    c2 = CS.inlet_case(64, 16, 1)
+    c2.blocks[0].z = np.zeros((17, 65))
+    g2 = fvb.GridDesc(c2)
+    assert L.fv_grid_workspace_bytes(C.byref(g2.desc), 0) == 0
+    assert b"z must be NULL" in L.fv_last_error()
+    info = fvb.fv_step_info()
+    p = fvb.make_params(cs.params)
+    assert L.fv_step_noalloc(C.byref(gds.desc), C.c_void_p(256), C.byref(p), 1, None,
+                             C.byref(info)) == fvb.FV_E_INVAL  # with_source = 2
+    gds.desc.with_source = 1
+    assert L.fv_step_noalloc(C.byref(gds.desc), C.c_void_p(256), C.byref(p), 1, None,
+                             C.byref(info)) == fvb.FV_E_UNSUPPORTED
+    assert b"source" in L.fv_last_error()
 
 
 def test_degenerate_grids_rejected(fvb):

@@ -144,3 +144,20 @@ def test_server_refuses_viscous_solves(fvb):
         srv.submit(case, max_steps=10)
     assert e.value.status == fvb.FV_E_UNSUPPORTED
     srv.close()
+
+
+def test_server_refuses_curvilinear_3d_and_sources(fvb):
+    """3D curvilinear grids and source terms run the general stage kernels of
+    the grid API; the server refuses them with FV_E_UNSUPPORTED."""
+    srv = fvb.Server(arena_bytes=64 << 20, max_instances=4, dry_run=True)
+    for state in ("random", "mms"):
+        case = CS.curv3d_case(ni=16, nj=8, nk=8, nblocks=2, state=state)
+        with pytest.raises(fvb.FVError) as e:
+            srv.submit(case, max_steps=10)
+        assert e.value.status == fvb.FV_E_UNSUPPORTED
+    c2 = CS.inlet_case(64, 64, 1)
+    c2.source = [np.zeros_like(u) for u in c2.U0]
+    with pytest.raises(fvb.FVError) as e:
+        srv.submit(c2, max_steps=10)
+    assert e.value.status == fvb.FV_E_UNSUPPORTED
+    srv.close()
