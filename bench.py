@@ -46,6 +46,20 @@ PROFILES = os.path.join(ROOT, "profiles")
 CSRC = os.path.join(ROOT, "paper_2305_18057_amd", "csrc")
 
 
+def _cases():
+    from paper_2305_18057_amd import cases
+    return cases
+
+
+# workload makers by name
+WORKLOADS = {
+    "inlet_2d": lambda: _cases().inlet_2d(),
+    "blobs_3d": lambda: _cases().blobs_3d(),
+    "inlet_2d_ns": lambda: _cases().inlet_2d_ns(),
+    "curv3d_mms": lambda: _cases().curv3d_mms(192),
+}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -64,7 +78,10 @@ def algorithmic_bytes_per_cell_step(case) -> int:
     nv = case.nv
     b = 8 * 8 * nv
     if any(blk.x is not None for blk in case.blocks):
-        b += 3 * 16
+        # node coordinates, read in every stage: about one node per cell
+        b += 3 * (24 if case.ndim == 3 else 16)
+    if getattr(case, "source", None) is not None:
+        b += 3 * 8 * nv  # the source S_h, read in every stage
     return b
 
 
@@ -84,12 +101,18 @@ def algorithmic_flops_per_cell_stage(case) -> int:
         upd = 17 + (11 if curv else 0)    # + volume and face vectors from nodes
         red = 19
         return 2 * flux + recon + div + upd + red
-    flux = 155
+    curv = any(getattr(blk, "z", None) is not None for blk in case.blocks)
+    flux = 155 + (12 if curv else 0)  # + |S| and n of a general normal
     recon = 5 * 5 * 3
     div = 5 * 5
     upd = 21
     red = 19
-    return 3 * flux + recon + div + upd + red
+    # curvilinear: three face vectors per cell (each shared by two cells):
+    # diagonals 6, cross product 9 + halving 3, centre 12, S . centre 5; the
+    # volume from the six S . centre values 7.  Source: - |Omega| S_h, 10.
+    metrics = (3 * 35 + 7) if curv else 0
+    src = 10 if getattr(case, "source", None) is not None else 0
+    return 3 * flux + recon + div + upd + red + metrics + src
 
 
 # --------------------------------------------------------------------------
@@ -101,15 +124,25 @@ def is_viscous(case) -> bool:
         bc.kind == 5 for blk in case.blocks for bc in blk.bc)
 
 
+def is_general3d(case) -> bool:
+    """The case runs the general 3D stage kernel (curvilinear blocks or a source)."""
+    return case.ndim == 3 and (getattr(case, "source", None) is not None or any(
+        getattr(blk, "z", None) is not None for blk in case.blocks))
+
+
 def stage_kernel(case) -> str:
     if case.ndim == 3:
-        return "k_stage3d"
-    return "k_stage2d_ns" if is_viscous(case) else "k_stage2d"
+        return "k_stage3d_gen" if is_general3d(case) else "k_stage3d"
+    return "k_stage2d_ns" if is_viscous(case) or getattr(case, "source", None) is not None \
+        else "k_stage2d"
 
 
-def kernel_sources_sha(ndim: int, ns: bool = False) -> str:
+def kernel_sources_sha(ndim: int, ns: bool = False, gen: bool = False) -> str:
     h = hashlib.sha256()
-    src = "fv_kernels3d.hip" if ndim == 3 else ("fv_kernels2d_ns.hip" if ns else "fv_kernels2d.hip")
+    if ndim == 3:
+        src = "fv_kernels3d_gen.hip" if gen else "fv_kernels3d.hip"
+    else:
+        src = "fv_kernels2d_ns.hip" if ns else "fv_kernels2d.hip"
     for f in ("fv_device.h", src):
         with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
@@ -120,6 +153,7 @@ def profile_record(kernel: str, workload: str, ndim: int):
     """key: value lines of profiles/<kernel>_<workload>_counters.txt, or None
     when absent or taken from kernel sources other than the current ones."""
     ns = kernel.endswith("_ns")
+    gen = kernel.endswith("_gen")
     path = os.path.join(PROFILES, f"{kernel}_{workload}_counters.txt")
     if not os.path.exists(path):
         return None
@@ -129,7 +163,7 @@ def profile_record(kernel: str, workload: str, ndim: int):
             if ":" in line and not line.startswith((" ", "#", "|")):
                 k, v = line.split(":", 1)
                 rec[k.strip()] = v.strip()
-    if rec.get("kernel_sources_sha") != kernel_sources_sha(ndim, ns):
+    if rec.get("kernel_sources_sha") != kernel_sources_sha(ndim, ns, gen):
         return None
     return rec
 
@@ -687,14 +721,14 @@ def summarize(dirs, kernel_filter, out_path, command, calib=None, workload=None,
         lines.append("")
     if workload and cnt:
         from paper_2305_18057_amd import cases
-        case = {"inlet_2d": cases.inlet_2d, "blobs_3d": cases.blobs_3d,
-                "inlet_2d_ns": cases.inlet_2d_ns}[workload]()
+        case = WORKLOADS[workload]()
         cells = case.ncells
         st = [a for n, a in cnt.items() if "stage" in n]
         def mean(k):
             v = [a[k] for a in st if k in a]
             return sum(v) / len(v) if v else None
-        lines.append(f"kernel_sources_sha: {kernel_sources_sha(case.ndim, is_viscous(case))}")
+        lines.append(f"kernel_sources_sha: "
+                     f"{kernel_sources_sha(case.ndim, is_viscous(case), is_general3d(case))}")
         lines.append(f"workload: {workload}_{precision}")
         lines.append(f"cells: {cells}")
         alg = algorithmic_bytes_per_cell_step(case) * cells / 3.0
@@ -740,7 +774,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="inlet_2d", choices=["inlet_2d", "blobs_3d", "inlet_2d_ns"],
+    ap.add_argument("--workload", default="inlet_2d", choices=sorted(WORKLOADS),
                     help="headline workload (default: the 2D inlet-like grid)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32flux"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference timing")
@@ -790,8 +824,7 @@ def main():
 
     # ---- headline
     prec = cases.FP64 if args.precision == "fp64" else cases.FP32_FLUX
-    case = {"inlet_2d": cases.inlet_2d, "blobs_3d": cases.blobs_3d,
-            "inlet_2d_ns": cases.inlet_2d_ns}[args.workload]()
+    case = WORKLOADS[args.workload]()
     prm = cases.Params(**{**case.params.__dict__, "precision": prec})
     log(f"[bench] headline {case.name} {args.precision} cells={case.ncells} steps={args.steps} "
         f"warmup={args.warmup}")
@@ -821,7 +854,9 @@ def main():
                   ("blobs_3d", cases.blobs_3d, cases.FP64, 50),
                   ("blobs_3d", cases.blobs_3d, cases.FP32_FLUX, 50),
                   ("inlet_2d_ns", cases.inlet_2d_ns, cases.FP64, args.steps),
-                  ("inlet_2d_ns", cases.inlet_2d_ns, cases.FP32_FLUX, args.steps)]
+                  ("inlet_2d_ns", cases.inlet_2d_ns, cases.FP32_FLUX, args.steps),
+                  ("curv3d_mms", WORKLOADS["curv3d_mms"], cases.FP64, 20),
+                  ("curv3d_mms", WORKLOADS["curv3d_mms"], cases.FP32_FLUX, 20)]
         for wl, mk, pr, steps in others:
             name = f"{wl}_{'fp64' if pr == cases.FP64 else 'fp32flux'}"
             if wl == args.workload and pr == prec:
@@ -867,6 +902,10 @@ def main():
                 "inlet-like curvilinear mesh, Mach 4 inflow (p=12270 Pa, T=217 K), no-slip walls, "
                 "extrapolation outflow, mu=1.5e-2 Pa s, Pr=0.72, MUSCL-minmod + Roe + viscous flux, "
                 "SSP-RK3, CFL 0.5")
+    elif args.workload == "curv3d_mms":
+        desc = ("curv3d_mms: 3D Euler with a manufactured solution's source, 192^3 cells in two "
+                "linked blocks of a smoothly deformed periodic box (curvilinear hexahedra), "
+                "MUSCL-minmod + Roe - |Omega| S_h, SSP-RK3, CFL 0.5")
     elif args.workload == "inlet_2d":
         desc = ("inlet_2d: 2D Euler, 4 blocks x 512x256 cells on the sheared wavy inlet-like "
                 "curvilinear mesh, Mach 4 inflow (p=12270 Pa, T=217 K), slip walls, extrapolation "

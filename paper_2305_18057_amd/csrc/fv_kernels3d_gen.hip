@@ -32,18 +32,97 @@ constexpr int kGT = 256;
 constexpr int kGR = 4;           // j-rows per tile, one wave each
 constexpr int kGQW = 64 + 4;     // state columns i0-2 .. i0+65
 constexpr int kGQH = kGR + 4;    // state rows j0-2 .. j0+5
+constexpr int kGHalo = 4 * (64 + kGR);  // halo cells of a tile plane (at most)
 
-// 60 KB: two workgroups (eight waves) per CU, as the registers allow
+// 78 KB: two workgroups (eight waves) per CU, as the registers allow
 struct GenLds {
   double q[5][kGQH][kGQW];       // plane k with its in-plane halo (a cross:
                                  // the corner slots are never read)
-  double fi[5][kGR][64];         // i-face fluxes at i-1/2 (times area)
-  double fj[5][kGR][64];         // j-face fluxes at j-1/2
-  double er[5][kGR];             // fluxes through the tile's right edge
-  double et[5][64];              // fluxes through its top edge
-  double nd[2][3][kGR + 1][65];  // node planes by parity of k: x, y, z
+  double fi[5][kGR][65];         // i-face fluxes (times area), faces i0 .. i0+nc
+  double fj[5][kGR + 1][64];     // j-face fluxes, faces j0 .. j0+nr
+  double ci[kGR][65];            // S . centre of those faces (curvilinear volumes)
+  double cj[kGR + 1][64];
+  double nd[3][3][kGR + 1][65];  // node planes k0 + r in slot r % 3: x, y, z
   double red[4][8];              // per-wave partials
+  // source of each halo cell, resolved once per tile (the same for every
+  // plane): the cell in plane 0 of its block's input buffer, that block's
+  // variable and plane strides, and kind | face << 4 | transverse index << 8
+  // (kind 0: copy, 1: inflow state of the face, 2: copy mirrored about the
+  // slip-wall face)
+  const double* hp[kGHalo];
+  long long hvs[kGHalo];
+  int hps[kGHalo];
+  int hkf[kGHalo];
 };
+
+// halo cell x of a tile plane: its row and column in the LDS plane
+__device__ __forceinline__ void halo_slot(int x, int nc, int nr, int& qr, int& qc) {
+  if (x < 4 * nc) {  // rows j0-2, j0-1, j0+nr, j0+nr+1
+    const int a = x / nc;
+    qc = x - a * nc + 2;
+    qr = a < 2 ? a : nr + a;
+  } else {           // columns i0-2, i0-1, i0+nc, i0+nc+1
+    const int y = x - 4 * nc, a = y >> 2, b = y & 3;
+    qr = a + 2;
+    qc = b < 2 ? b : nc + b;
+  }
+}
+
+// Source of the in-plane cell (ii, jj) of block B (at most one of the two
+// outside, by at most 2): the rules of load_cell, without the plane.
+__device__ void halo_source(const DevBlock* __restrict__ blocks, const DevBlock& B, int buf, int ii,
+                            int jj, const double*& p, long long& vs, int& ps, int& kf) {
+  const DevBlock* S = &B;
+  int si = ii, sj = jj, kind = 0, f = 0, t = 0;
+  if (ii < 0 || ii >= B.ni || jj < 0 || jj >= B.nj) {
+    const int d = (ii < 0 || ii >= B.ni) ? 0 : 1;
+    const int x = d == 0 ? ii : jj, n0 = d == 0 ? B.ni : B.nj;
+    const int side = x < 0 ? 0 : 1, g = side == 0 ? -x : x - n0 + 1;
+    f = 2 * d + side;
+    t = d == 0 ? jj : ii;
+    const int bk = B.bc_kind[f];
+    if (bk == BC_INFLOW) {
+      kind = 1;
+    } else {
+      if (bk == BC_BLOCK) S = &blocks[B.bc_nbr[f]];
+      const int n = d == 0 ? S->ni : S->nj;
+      int along;
+      if (bk == BC_PERIODIC || bk == BC_BLOCK) along = side == 0 ? n - g : g - 1;
+      else if (bk == BC_EXTRAP) along = side == 0 ? 0 : n - 1;
+      else along = side == 0 ? g - 1 : n - g;  // slip wall
+      if (d == 0) si = along;
+      else sj = along;
+      kind = bk == BC_SLIPWALL ? 2 : 0;
+    }
+  }
+  p = kind == 1 ? nullptr : S->u[buf] + (long long)sj * S->ni + si;
+  vs = S->ncell;
+  ps = S->ni * S->nj;
+  kf = kind | (f << 4) | (t << 8);
+}
+
+// momentum of q mirrored about the slip-wall face f (an i- or j-face) of B
+// at transverse index t in plane k: m - 2 (m.S)/(S.S) S, as load_cell
+__device__ void slip_mirror3(const DevBlock& B, int f, int t, int k, double* q) {
+  const int d = f >> 1, side = f & 1;
+  double Sv[3] = {0.0, 0.0, 0.0};
+  if (B.zn != nullptr) {
+    const int w = side == 0 ? 0 : (d == 0 ? B.ni : B.nj);
+    double cs;
+    face3(B, d, d == 0 ? w : t, d == 0 ? t : w, k, Sv, cs);
+  } else {
+    Sv[d] = 1.0;
+  }
+  double ms = 0.0, ss = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ms += q[1 + a] * Sv[a];
+    ss += Sv[a] * Sv[a];
+  }
+  const double fct = 2.0 * ms / ss;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) q[1 + a] -= fct * Sv[a];
+}
 
 template <int LIM, typename T>
 __device__ __forceinline__ void inv_flux3(const Recon<T>& rc, const FluxK<T>& K, const double* c0,
@@ -93,7 +172,7 @@ __device__ void tile_gen(const DevTile& tl, const DevBlock* __restrict__ blocks,
   double dmin = INFINITY;
   int bad = 0;
 
-  // node plane k of the tile, (nr + 1) x (nc + 1) nodes, into parity slot par
+  // node plane k of the tile, (nr + 1) x (nc + 1) nodes, into slot par
   auto stage_nodes = [&](int k, int par) {
     for (int x = tid; x < (nr + 1) * (nc + 1); x += kGT) {
       const int r = x / (nc + 1), c = x - r * (nc + 1);
@@ -110,10 +189,10 @@ __device__ void tile_gen(const DevTile& tl, const DevBlock* __restrict__ blocks,
     o[2] = L.nd[par][2][r][c];
   };
   // Area vector S (and S . centre) of the face of direction d on side
-  // `side` (0: at i-1/2, j-1/2 or k-1/2; 1: the far face) of the thread's
-  // cell in plane k, whose bottom and top node planes are in slots p0, p1.
-  // Uniform blocks: the axis times the face area.
-  auto face_at = [&](int d, int side, int p0, int p1, double* S, double& cs) {
+  // `side` (0: at i-1/2, j-1/2 or k-1/2; 1: the far face) of the cell at row
+  // fr, column fc of the tile in plane k, whose bottom and top node planes
+  // are in slots p0, p1.  Uniform blocks: the axis times the face area.
+  auto face_at = [&](int d, int side, int p0, int p1, int fr, int fc, double* S, double& cs) {
     if (!curv) {
       S[0] = d == 0 ? B.area[0] : 0.0;
       S[1] = d == 1 ? B.area[1] : 0.0;
@@ -123,41 +202,44 @@ __device__ void tile_gen(const DevTile& tl, const DevBlock* __restrict__ blocks,
     }
     double a[3], b[3], c[3], e[3];
     if (d == 0) {
-      const int cc = li + side;
-      ndp(p0, lj, cc, a);
-      ndp(p0, lj + 1, cc, b);
-      ndp(p1, lj + 1, cc, c);
-      ndp(p1, lj, cc, e);
+      const int cc = fc + side;
+      ndp(p0, fr, cc, a);
+      ndp(p0, fr + 1, cc, b);
+      ndp(p1, fr + 1, cc, c);
+      ndp(p1, fr, cc, e);
     } else if (d == 1) {
-      const int rr = lj + side;
-      ndp(p0, rr, li, a);
-      ndp(p0, rr, li + 1, b);
-      ndp(p1, rr, li + 1, c);
-      ndp(p1, rr, li, e);
+      const int rr = fr + side;
+      ndp(p0, rr, fc, a);
+      ndp(p0, rr, fc + 1, b);
+      ndp(p1, rr, fc + 1, c);
+      ndp(p1, rr, fc, e);
     } else {
       const int pp = side ? p1 : p0;
-      ndp(pp, lj, li, a);
-      ndp(pp, lj, li + 1, b);
-      ndp(pp, lj + 1, li + 1, c);
-      ndp(pp, lj + 1, li, e);
+      ndp(pp, fr, fc, a);
+      ndp(pp, fr, fc + 1, b);
+      ndp(pp, fr + 1, fc + 1, c);
+      ndp(pp, fr + 1, fc, e);
     }
     quad_face(a, b, c, e, d == 1, S, cs);
   };
 
   // column states at k-1, k, k+1, k+2 (at the loop head) and the k-face
   // flux at k-1/2
-  double ca[5], cb[5], cc[5], cd[5], fk[5];
-  if (curv) {
-    stage_nodes(k0, 0);
-    __syncthreads();
+  double ca[5], cb[5], cc[5], cd[5], fk[5], csk = 0.0;
+  for (int x = tid; x < 4 * (nc + nr); x += kGT) {
+    int qr, qc;
+    halo_slot(x, nc, nr, qr, qc);
+    halo_source(blocks, B, bin, i0 - 2 + qc, j0 - 2 + qr, L.hp[x], L.hvs[x], L.hps[x], L.hkf[x]);
   }
+  if (curv) stage_nodes(k0, 0);
+  __syncthreads();
   if (act) {
     load_cell<5>(blocks, B, bin, i, j, k0 - 2, ca);
     load_cell<5>(blocks, B, bin, i, j, k0 - 1, cb);
     load_cell<5>(blocks, B, bin, i, j, k0, cc);
     load_cell<5>(blocks, B, bin, i, j, k0 + 1, cd);
-    double S[3], cs;
-    face_at(2, 0, 0, 0, S, cs);  // node plane k0 (slot 0)
+    double S[3];
+    face_at(2, 0, 0, 0, lj, li, S, csk);  // node plane k0 (slot 0)
     T G[5];
     inv_flux3<LIM, T>(rc, K, ca, cb, cc, cd, S, G);
 #pragma unroll
@@ -172,7 +254,9 @@ __device__ void tile_gen(const DevTile& tl, const DevBlock* __restrict__ blocks,
 
   for (int r = 0; r < nz; ++r) {
     const int k = k0 + r;
-    const int p0 = r & 1, p1 = p0 ^ 1;
+    // node slots of planes k (bottom) and k+1 (top); the third slot still
+    // holds plane k-1, which a wave behind may read until the next barrier
+    const int p0 = r % 3, p1 = (r + 1) % 3;
     // ---- 1. plane k into LDS: the tile's cells from registers, the halo
     //         cross (rows j0-2, j0-1, j0+nr, j0+nr+1 and columns i0-2, i0-1,
     //         i0+nc, i0+nc+1) from memory; node plane k+1
@@ -180,83 +264,110 @@ __device__ void tile_gen(const DevTile& tl, const DevBlock* __restrict__ blocks,
 #pragma unroll
       for (int v = 0; v < 5; ++v) L.q[v][lj + 2][li + 2] = cb[v];
     }
-    for (int x = tid; x < 4 * (nc + nr); x += kGT) {
-      int qr, qc;
-      if (x < 4 * nc) {
-        const int a = x / nc;
-        qc = x - a * nc + 2;
-        qr = a < 2 ? a : nr + a;
-      } else {
-        const int y = x - 4 * nc, a = y >> 2, b = y & 3;
-        qr = a + 2;
-        qc = b < 2 ? b : nc + b;
-      }
-      double q[5];
-      load_cell<5>(blocks, B, bin, i0 - 2 + qc, j0 - 2 + qr, k, q);
+    {
+      // every load of the plane's halo first (one per halo cell: its source
+      // is known), then the LDS writes
+      const int nh = 4 * (nc + nr);
+      double hq[2][5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) L.q[v][qr][qc] = q[v];
+      for (int h = 0; h < 2; ++h) {
+        const int x = tid + h * kGT;
+        if (x < nh) {
+          const int kf = L.hkf[x];
+          if ((kf & 15) == 1) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) hq[h][v] = B.bc_q[(kf >> 4) & 15][v];
+          } else {
+            const double* q = L.hp[x] + (long long)k * L.hps[x];
+            const long long vs = L.hvs[x];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) hq[h][v] = ldg(q + v * vs);
+          }
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int x = tid + h * kGT;
+        if (x < nh) {
+          const int kf = L.hkf[x];
+          if ((kf & 15) == 2) slip_mirror3(B, (kf >> 4) & 15, kf >> 8, k, hq[h]);
+          int qr, qc;
+          halo_slot(x, nc, nr, qr, qc);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) L.q[v][qr][qc] = hq[h][v];
+        }
+      }
     }
     if (curv) stage_nodes(k + 1, p1);
     __syncthreads();
 
-    // ---- 2. face fluxes: the cell's i-face and j-face to LDS (and the
-    //         tile's edges), its k-face at k+1/2 kept in registers
-    double Fh[5];
-    if (act) {
+    // ---- 2. in-plane face fluxes to LDS, one face per thread and pass:
+    //         the i-face at i-1/2 and the j-face at j-1/2 of the thread's
+    //         cell, then the tile's nr right-edge and nc top-edge faces as
+    //         one list of tasks, dealt to the waves in an order that turns
+    //         with the plane (so that no SIMD always gets the extra pass)
+    auto in_plane = [&](int d, int fr, int fc) {
+      // face of direction d at row fr, column fc of the tile (i-face: at
+      // i0+fc-1/2 of row j0+fr; j-face: at j0+fr-1/2 of column i0+fc)
       double S[3], cs, c0[5], c1[5], c2[5], c3[5];
+      if (d == 0) {
+        face_at(0, 0, p0, p1, fr, fc, S, cs);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          c0[v] = L.q[v][fr + 2][fc];
+          c1[v] = L.q[v][fr + 2][fc + 1];
+          c2[v] = L.q[v][fr + 2][fc + 2];
+          c3[v] = L.q[v][fr + 2][fc + 3];
+        }
+      } else {
+        face_at(1, 0, p0, p1, fr, fc, S, cs);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+          c0[v] = L.q[v][fr][fc + 2];
+          c1[v] = L.q[v][fr + 1][fc + 2];
+          c2[v] = L.q[v][fr + 2][fc + 2];
+          c3[v] = L.q[v][fr + 3][fc + 2];
+        }
+      }
       T G[5];
-      // i-face at i-1/2: cells i-2 .. i+1 of row lj
-      face_at(0, 0, p0, p1, S, cs);
-#pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        c0[v] = L.q[v][lj + 2][li];
-        c1[v] = L.q[v][lj + 2][li + 1];
-        c2[v] = L.q[v][lj + 2][li + 2];
-        c3[v] = L.q[v][lj + 2][li + 3];
-      }
       inv_flux3<LIM, T>(rc, K, c0, c1, c2, c3, S, G);
+      if (d == 0) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) L.fi[v][lj][li] = (double)G[v];
-      if (li == nc - 1) {
-        face_at(0, 1, p0, p1, S, cs);
+        for (int v = 0; v < 5; ++v) L.fi[v][fr][fc] = (double)G[v];
+        L.ci[fr][fc] = cs;
+      } else {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          c0[v] = L.q[v][lj + 2][li + 1];
-          c1[v] = L.q[v][lj + 2][li + 2];
-          c2[v] = L.q[v][lj + 2][li + 3];
-          c3[v] = L.q[v][lj + 2][li + 4];
-        }
-        inv_flux3<LIM, T>(rc, K, c0, c1, c2, c3, S, G);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) L.er[v][lj] = (double)G[v];
+        for (int v = 0; v < 5; ++v) L.fj[v][fr][fc] = (double)G[v];
+        L.cj[fr][fc] = cs;
       }
-      // j-face at j-1/2: cells j-2 .. j+1 of column li
-      face_at(1, 0, p0, p1, S, cs);
+    };
+    // U^n and the source of the cell, loaded before the fluxes are formed
+    // so that their latency hides behind them
+    const long long idx = ((long long)k * B.nj + j) * B.ni + i;
+    double unp[5] = {0, 0, 0, 0, 0}, srp[5] = {0, 0, 0, 0, 0};
+    if (act) {
+      if constexpr (SK::reads_un) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        c0[v] = L.q[v][lj][li + 2];
-        c1[v] = L.q[v][lj + 1][li + 2];
-        c2[v] = L.q[v][lj + 2][li + 2];
-        c3[v] = L.q[v][lj + 3][li + 2];
+        for (int v = 0; v < 5; ++v) unp[v] = ldg(B.u[0] + v * ncell + idx);
       }
-      inv_flux3<LIM, T>(rc, K, c0, c1, c2, c3, S, G);
+      if (B.src != nullptr) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) L.fj[v][lj][li] = (double)G[v];
-      if (lj == nr - 1) {
-        face_at(1, 1, p0, p1, S, cs);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) {
-          c0[v] = L.q[v][lj + 1][li + 2];
-          c1[v] = L.q[v][lj + 2][li + 2];
-          c2[v] = L.q[v][lj + 3][li + 2];
-          c3[v] = L.q[v][lj + 4][li + 2];
-        }
-        inv_flux3<LIM, T>(rc, K, c0, c1, c2, c3, S, G);
-#pragma unroll
-        for (int v = 0; v < 5; ++v) L.et[v][li] = (double)G[v];
+        for (int v = 0; v < 5; ++v) srp[v] = ldg(B.src + v * ncell + idx);
       }
-      // k-face at k+1/2: the column's k-1 .. k+2
-      face_at(2, 1, p0, p1, S, cs);
+      in_plane(0, lj, li);
+      in_plane(1, lj, li);
+    }
+    {
+      const int e = (tid + 64 * (r & 3)) & (kGT - 1);
+      if (e < nr) in_plane(0, e, nc);
+      else if (e < nr + nc) in_plane(1, nr, e - nr);
+    }
+    // k-face at k+1/2 from the column's k-1 .. k+2 (registers)
+    double Fh[5], cskt = 0.0;
+    if (act) {
+      double S[3];
+      face_at(2, 1, p0, p1, lj, li, S, cskt);
+      T G[5];
       inv_flux3<LIM, T>(rc, K, ca, cb, cc, cd, S, G);
 #pragma unroll
       for (int v = 0; v < 5; ++v) Fh[v] = (double)G[v];
@@ -265,33 +376,18 @@ __device__ void tile_gen(const DevTile& tl, const DevBlock* __restrict__ blocks,
 
     // ---- 3. residual, source, update, partials; the column moves up
     if (act) {
-      const long long idx = ((long long)k * B.nj + j) * B.ni + i;
       double R[5];
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        const double fr = li == nc - 1 ? L.er[v][lj] : L.fi[v][lj][li + 1];
-        const double ft = lj == nr - 1 ? L.et[v][li] : L.fj[v][lj + 1][li];
-        R[v] = ((0.0 + (fr - L.fi[v][lj][li])) + (ft - L.fj[v][lj][li])) + (Fh[v] - fk[v]);
-      }
-      // volume: 1/3 of the sum over the faces of the outward S . centre;
-      // mean area vectors per direction for the time-step bound
-      double vol = B.vol, Sb[3][3];
-      {
-        double v3 = 0.0;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          double Sm[3], Sp[3], cm, cp;
-          face_at(d, 0, p0, p1, Sm, cm);
-          face_at(d, 1, p0, p1, Sp, cp);
-          v3 += cp - cm;
-#pragma unroll
-          for (int x = 0; x < 3; ++x) Sb[d][x] = 0.5 * (Sm[x] + Sp[x]);
-        }
-        if (curv) vol = v3 / 3.0;
-      }
+      for (int v = 0; v < 5; ++v)
+        R[v] = ((0.0 + (L.fi[v][lj][li + 1] - L.fi[v][lj][li])) +
+                (L.fj[v][lj + 1][li] - L.fj[v][lj][li])) + (Fh[v] - fk[v]);
+      // volume: 1/3 of the sum over the faces of the outward S . centre
+      const double vol = curv ? (((0.0 + (L.ci[lj][li + 1] - L.ci[lj][li])) +
+                                  (L.cj[lj + 1][li] - L.cj[lj][li])) + (cskt - csk)) / 3.0
+                              : B.vol;
       if (B.src != nullptr) {  // the source part of Eq. (residual): - |Omega| S_h
 #pragma unroll
-        for (int v = 0; v < 5; ++v) R[v] -= vol * ldg(B.src + v * ncell + idx);
+        for (int v = 0; v < 5; ++v) R[v] -= vol * srp[v];
       }
       const double iv = M<double>::rcp(vol);
       if (MODE == 0) {
@@ -307,7 +403,7 @@ __device__ void tile_gen(const DevTile& tl, const DevBlock* __restrict__ blocks,
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
           double un = 0.0;
-          if constexpr (SK::reads_un) un = ldg(B.u[0] + v * ncell + idx);
+          if constexpr (SK::reads_un) un = unp[v];
           if constexpr (SK::low) {
             out[v] = fmad(-f, R[v], un);
           } else {
@@ -325,7 +421,19 @@ __device__ void tile_gen(const DevTile& tl, const DevBlock* __restrict__ blocks,
             nacc[v] = fmad(rv, rv, nacc[v]);
           }
         }
-        if constexpr (SK::cfl) dmin = fmin(dmin, cell_dt_limit<3>(out, Sb, vol, gamma, bad));
+        if constexpr (SK::cfl) {
+          // mean area vectors per direction (formed again here: one stage in three)
+          double Sb[3][3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            double Sm[3], Sp[3], cm, cp;
+            face_at(d, 0, p0, p1, lj, li, Sm, cm);
+            face_at(d, 1, p0, p1, lj, li, Sp, cp);
+#pragma unroll
+            for (int x = 0; x < 3; ++x) Sb[d][x] = 0.5 * (Sm[x] + Sp[x]);
+          }
+          dmin = fmin(dmin, cell_dt_limit<3>(out, Sb, vol, gamma, bad));
+        }
       }
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
@@ -334,10 +442,15 @@ __device__ void tile_gen(const DevTile& tl, const DevBlock* __restrict__ blocks,
         cb[v] = cc[v];
         cc[v] = cd[v];
       }
+      csk = cskt;
       if (r + 1 < nz) load_cell<5>(blocks, B, bin, i, j, k + 3, cd);
     }
-    __syncthreads();  // LDS is staged again for the next plane
+    // no barrier here: the next plane's staging writes q (read before the
+    // last barrier) and the node slot of plane k+2 (neither k nor k+1), and
+    // its flux writes follow the next barrier, which every wave reaches only
+    // after this update
   }
+  __syncthreads();
 
   // ---- per-tile partials: fixed-order wave reductions, then the four waves
   double* part = I.part + tl.local;
