@@ -289,6 +289,65 @@ def bench_rk_schemes(fv, cases, tune_cache, steps2d):
     return out
 
 
+def bench_hetero(fv, cases, tune_cache, steps=20, workers=16):
+    """The CPU-GPU heterogeneous mode (Sec. 4 workflow, Sec. 6 model) on the
+    inlet-like grid as one 2048 x 256 block, FP64: the pure-GPU step time,
+    one host core's time per cell t_I, a sweep of the workload ratio r (the
+    cells of the GPU over the cells of one of `workers` host workers) with
+    the measured time per step, and the model of Sec. 6 fitted to the sweep
+    (r_gc from the pure modes, kappa = (1 + alpha) beta by least squares;
+    alpha quoted for the paper's beta range 0.2 .. 0.5)."""
+    from paper_2305_18057_amd import perfmodel as PM
+    c = cases.inlet_case(2048, 256, 1, name="inlet_2d_1block")
+    Nl, Nw, N = 2048, 256, c.ncells
+    p = cases.Params(**{**c.params.__dict__, "precision": cases.FP64})
+    gx, _, _, dx, _, _ = time_grid(fv, c, p, steps, 5, tune_cache, stage_times=False)
+    gx.close()
+    t_gpu = dx / steps * 1e-3
+    U0 = c.state_flat()
+
+    def run(split, nw, n=steps):
+        h = fv.Hetero(c, split, nw)
+        h.set_state(U0)
+        h.step(p, 3)
+        h.set_state(U0)
+        info = h.step(p, n)
+        h.close()
+        return [t / n * 1e-3 for t in info["times_ms"]]
+
+    # one host core: t_I from the host part's substep time of 16 columns
+    one = run(Nl - 16, 1)
+    tI = one[1] / (16 * Nw)
+    r_gc = N * tI / t_gpu
+    rows = []
+    for nc in (2, 4, 8, 16, 32, 64, 128):
+        split = Nl - nc
+        r = split * workers / nc
+        tm = run(split, workers)
+        rows.append(dict(cpu_columns=nc, ratio=round(r, 1), wall_ms=round(tm[3] * 1e3, 4),
+                         gpu_ms=round(tm[0] * 1e3, 4), host_ms=round(tm[1] * 1e3, 4),
+                         exchange_ms=round(tm[2] * 1e3, 4),
+                         ssspnt=round(1e-6 * N * 3 / tm[3], 2)))
+    fit = PM.fit_kappa(Nl, Nw, 1, workers, [x["ratio"] for x in rows],
+                       [x["wall_ms"] * 1e-3 for x in rows], r_gc, tI)
+    for x in rows:
+        x["model_ms"] = round(PM.time_ratio(Nl, Nw, 1, workers, x["ratio"], r_gc, tI, fit.kappa) * 1e3, 4)
+    best = min(rows, key=lambda x: x["wall_ms"])
+    out = dict(cells=N, steps=steps, workers=workers, pure_gpu_ms=round(t_gpu * 1e3, 4),
+               pure_gpu_ssspnt=round(1e-6 * N * 3 / t_gpu, 2),
+               host_core_tI_ns=round(tI * 1e9, 2), host_core_cell_updates_per_s=round(1 / tI, 1),
+               r_gc=round(r_gc, 1), kappa=round(fit.kappa, 3), fit_rms_rel=round(fit.rms_rel, 4),
+               alpha_at_beta_0_2=round(fit.alpha(0.2), 2), alpha_at_beta_0_5=round(fit.alpha(0.5), 2),
+               model_balance_ms=round(PM.time_ratio(Nl, Nw, 1, workers, r_gc, r_gc, tI, fit.kappa) * 1e3, 4),
+               best=dict(ratio=best["ratio"], wall_ms=best["wall_ms"],
+                         vs_pure_gpu=round(t_gpu * 1e3 / best["wall_ms"], 4)),
+               sweep=rows)
+    log(f"[bench] hetero: pure GPU {out['pure_gpu_ms']} ms/step, host core {1e-6 / tI:.2f} M "
+        f"cell-updates/s, r_gc {r_gc:.0f}; best ratio {best['ratio']} at {best['wall_ms']} ms/step "
+        f"({out['best']['vs_pure_gpu']}x pure GPU); kappa {fit.kappa:.2f} (fit rms {fit.rms_rel:.2f})")
+    return out
+
+
 def roofline_of(case, stage_ms, steps, workload, fp32=False):
     cells = case.ncells
     kernel = stage_kernel(case)
@@ -876,6 +935,7 @@ def main():
             gx.close()
             del gx
         extra["rk_schemes"] = bench_rk_schemes(fv, cases, tune_cache, args.steps)
+        extra["hetero"] = bench_hetero(fv, cases, tune_cache)
         tc = tune_cache or os.path.join(tempfile.mkdtemp(prefix="fv_tune_"), "tiles.json")
         extra["batched_64"] = bench_batched(fv, cases, None if args.no_tune else tc)
         b = extra["batched_64"]

@@ -275,6 +275,42 @@ typedef struct fv_grid_stats {
 int fv_grid_get_stats(const fv_grid* g, fv_grid_stats* out);
 
 /* ---------------------------------------------------------------------- */
+/* CPU-GPU heterogeneous stepping (Sec. 4 workflow, Sec. 6 model).         */
+/* ---------------------------------------------------------------------- */
+/* The residual and RK update of one 2D block shared by the GPU and host-core
+ * workers, the paper's synchronous heterogeneous mode with a 1D domain
+ * decomposition along i (Sec. 6): the GPU takes columns [0, split), the
+ * host takes [split, ni), itself split by rows over cpu_workers threads.
+ * Every RK substep: the two columns on each side of the cut are exchanged
+ * (device-to-host and host-to-device copies on the handle's stream), both
+ * workers then compute the substep at once, and all of them synchronize.
+ * The step end combines the norms (RMS over every cell) and the time-step
+ * bound (minimum over every cell) of both parts; the host then sets the
+ * common time step.  Results are those of fv_step on the whole block (the
+ * same formulas; the host's divisions and roots are the correctly rounded
+ * IEEE ones).
+ * Grids: 2D, one block, Euler (mu = 0, no no-slip face, no source), i-faces
+ * neither periodic nor linked (FV_E_UNSUPPORTED otherwise);
+ * 2 <= split <= ni - 2 (FV_E_INVAL).  The workspace is device memory the
+ * caller owns (>= fv_hetero_workspace_bytes); the host worker's arrays and
+ * pinned exchange buffers are allocated by the handle and freed by
+ * fv_hetero_destroy. */
+typedef struct fv_hetero fv_hetero;
+size_t fv_hetero_workspace_bytes(const fv_grid_desc* desc, int split);
+int fv_hetero_create(const fv_grid_desc* desc, int split, int cpu_workers, void* d_workspace,
+                     size_t bytes, void* hip_stream, fv_hetero** out);
+/* whole-block state in the usual layout, host memory */
+int fv_hetero_set_state(fv_hetero* h, const double* U);
+int fv_hetero_get_state(fv_hetero* h, double* U);
+/* nsteps steps of p->rk (2, 3 or 4; p->precision applies to the GPU part,
+ * the host computes in FP64); times_ms (may be NULL) receives the summed
+ * wall time of the GPU stage kernels [0] (events), of the host substeps [1],
+ * of the exchanges with their synchronizations [2], and the whole call [3]. */
+int fv_hetero_step(fv_hetero* h, const fv_params* p, int nsteps, fv_step_info* info,
+                   double times_ms[4]);
+int fv_hetero_destroy(fv_hetero* h);
+
+/* ---------------------------------------------------------------------- */
 /* Allocation-free stepping.                                                */
 /* ---------------------------------------------------------------------- */
 /* For callers that cannot allocate device memory (code under HIP graph

@@ -22,7 +22,7 @@ ARCH = os.environ.get("FV_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["fv_runtime.hip", "fv_exec.hip", "fv_grid.hip", "fv_server.hip",
            "fv_kernels2d.hip", "fv_kernels3d.hip", "fv_reduce.hip", "fv_noalloc.hip",
-           "fv_kernels2d_ns.hip", "fv_kernels3d_gen.hip"]
+           "fv_kernels2d_ns.hip", "fv_kernels3d_gen.hip", "fv_hetero.hip"]
 
 # -ffp-contract=off: no automatic fused multiply-adds; the kernels write the
 # fused forms explicitly, so every inlined copy of a formula rounds alike

@@ -123,11 +123,20 @@ __device__ __forceinline__ void stg(double* p, double v) { *(g_double*)p = v; }
 // refined by Newton-Raphson (reciprocal) and Goldschmidt (square root and its
 // reciprocal together) iterations.  In FP64 the result is within a few ulp of
 // the correctly rounded value for the normal-range arguments met here; in FP32
-// the hardware estimates are used directly.
+// the hardware estimates are used directly.  The flux arithmetic below also
+// runs on the host (the host-core worker of the CPU-GPU split): there these
+// are the correctly rounded IEEE operations.
 template <typename T>
 struct M;
 template <>
 struct M<double> {
+#if !defined(__HIP_DEVICE_COMPILE__)
+  static __host__ inline double rcp(double x) { return 1.0 / x; }
+  static __host__ inline void sqrt2(double x, double& s, double& h) {
+    s = __builtin_sqrt(x);
+    h = 0.5 / s;
+  }
+#else
   static __device__ __forceinline__ double rcp(double x) {
     double r = __builtin_amdgcn_rcp(x);
     double e = __builtin_fma(-x, r, 1.0);
@@ -149,6 +158,7 @@ struct M<double> {
     const double d = __builtin_fma(-g, g, x);
     s = __builtin_fma(d, h, g);
   }
+#endif
 };
 template <>
 struct M<float> {
@@ -197,11 +207,13 @@ __device__ __forceinline__ float lane_value(float x, int l) {
 // contraction, so every inlined copy of a formula rounds the same way (a face
 // flux formed by two different tiles is bitwise the same); the fused forms
 // are written out where they belong.
-__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__host__ __device__ __forceinline__ double fmad(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+__host__ __device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 template <typename T>
-__device__ __forceinline__ T minmod(T a, T b) {
+__host__ __device__ __forceinline__ T minmod(T a, T b) {
   const bool same = (a > T(0) && b > T(0)) || (a < T(0) && b < T(0));
   const T m = fabs(a) < fabs(b) ? a : b;
   return same ? m : T(0);
@@ -225,7 +237,7 @@ struct Recon {
 // is eps/2, -eps/2 or 0 exactly, times min(|a|, |b|): the same value as the
 // select form (bitwise, up to the sign of a zero result), with no compares
 template <typename T>
-__device__ __forceinline__ T half_eps_minmod(T qeps, T a, T b) {
+__host__ __device__ __forceinline__ T half_eps_minmod(T qeps, T a, T b) {
   return (copysign(qeps, a) + copysign(qeps, b)) * fmin(fabs(a), fabs(b));
 }
 // In FP32 the hardware median of three does it in one instruction: the
@@ -233,12 +245,16 @@ __device__ __forceinline__ T half_eps_minmod(T qeps, T a, T b) {
 // both are negative and 0 otherwise, i.e. minmod(a, b); times eps/2 (2 qeps,
 // exact) it rounds once, as the form above
 template <>
-__device__ __forceinline__ float half_eps_minmod(float qeps, float a, float b) {
+__host__ __device__ __forceinline__ float half_eps_minmod(float qeps, float a, float b) {
+#if defined(__HIP_DEVICE_COMPILE__)
   return (2.0f * qeps) * __builtin_amdgcn_fmed3f(a, b, 0.0f);
+#else
+  return (copysignf(qeps, a) + copysignf(qeps, b)) * fminf(fabsf(a), fabsf(b));
+#endif
 }
 
 template <int LIM = -1, typename T>
-__device__ __forceinline__ void extrap(const Recon<T>& R, T dm, T dp, T& ep, T& em) {
+__host__ __device__ __forceinline__ void extrap(const Recon<T>& R, T dm, T dp, T& ep, T& em) {
   if constexpr (LIM == LIM_MINMOD) {
     const T s = half_eps_minmod(T(0.5) * R.heps, dm, dp);
     ep = s;
@@ -276,7 +292,7 @@ struct FluxK {
 // Returns the flux times the face area.  ND = 2 or 3; AX >= 0: the unit
 // normal is the coordinate axis AX (n unused), AX < 0: general unit normal n.
 template <typename T, int ND, int AX>
-__device__ __forceinline__ void roe_flux(const T* __restrict__ qL, const T* __restrict__ qR,
+__host__ __device__ __forceinline__ void roe_flux(const T* __restrict__ qL, const T* __restrict__ qR,
                                          const T* __restrict__ n, T area, const FluxK<T>& K,
                                          T* __restrict__ F) {
   constexpr int E = ND + 1;
@@ -641,12 +657,12 @@ __device__ __forceinline__ int wave_or(int v) {
 // local time-step limit |Omega| / sum_d(|u.Sbar_d| + c|Sbar_d|) of a cell and
 // the physical check (rho > 0, p > 0, finite)
 template <int ND>
-__device__ __forceinline__ double cell_dt_limit(const double* q, const double (*Sb)[3], double vol,
+__host__ __device__ __forceinline__ double cell_dt_limit(const double* q, const double (*Sb)[3], double vol,
                                                 double gamma, int& bad) {
   constexpr int E = ND + 1;
   bool ok = true;
 #pragma unroll
-  for (int v = 0; v < ND + 2; ++v) ok = ok && isfinite(q[v]);
+  for (int v = 0; v < ND + 2; ++v) ok = ok && __builtin_isfinite(q[v]);
   const double rho = q[0];
   const double ir = 1.0 / rho;
   double u[3] = {0.0, 0.0, 0.0};

@@ -4,38 +4,11 @@
 #include <cmath>
 #include <cstring>
 
-#include "fv_exec.h"
-#include "fv_runtime.h"
+#include "fv_grid_impl.h"
 
 using namespace fvrt;
 
-struct fv_grid {
-  HostGrid hg;
-  InstLayout L;
-  hipStream_t stream = nullptr;
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  fvk::DevBlock* d_blocks = nullptr;
-  fvk::DevInstance* d_inst = nullptr;
-  int* d_ntiles = nullptr;
-  fvk::DevTile* d_tiles = nullptr;
-  double* d_part = nullptr;
-  fvk::GhostSeg* d_segs = nullptr;
-  double* d_u[3] = {nullptr, nullptr, nullptr};
-  std::vector<fvk::DevBlock> hblocks;
-  std::vector<fvk::DevTile> htiles;
-  fvk::DevInstance hinst;
-  TileShape shape;
-  fvexec::StepPlan plan;
-  fvexec::GraphCache graphs;
-  int have_state = 0;
-  double last_ms[4] = {0, 0, 0, 0};
-  // viscosity with which the device's time-step bound of the current state
-  // was formed (the viscous term enters it)
-  double cfl_mu = 0.0, cfl_pr = 0.0;
-};
-
-namespace {
+namespace fvgrid {
 
 int upload_tiles(fv_grid* g) {
   build_tiles(g->hg, g->shape, 0, 0, g->htiles);
@@ -124,7 +97,9 @@ int use_params(fv_grid* g, const fv_params* p) {
   return FV_OK;
 }
 
-}  // namespace
+}  // namespace fvgrid
+
+using namespace fvgrid;
 
 extern "C" size_t fv_grid_workspace_bytes(const fv_grid_desc* desc, int precision) {
   (void)precision;
@@ -137,13 +112,18 @@ extern "C" int fv_create_grid(const fv_grid_desc* desc, void* d_workspace, size_
                               void* hip_stream, fv_grid** out) {
   if (!out) return set_error(FV_E_INVAL, "null output handle");
   *out = nullptr;
+  HostGrid hg;
+  const int st = validate_and_copy(desc, hg);
+  if (st) return st;
+  return fvgrid::create(std::move(hg), d_workspace, bytes, hip_stream, out);
+}
+
+int fvgrid::create(HostGrid&& hg, void* d_workspace, size_t bytes, void* hip_stream, fv_grid** out) {
+  *out = nullptr;
   fv_grid* g = new (std::nothrow) fv_grid();
   if (!g) return set_error(FV_E_NOMEM, "host allocation failed");
-  int st = validate_and_copy(desc, g->hg);
-  if (st) {
-    delete g;
-    return st;
-  }
+  g->hg = std::move(hg);
+  int st = FV_OK;
   g->L = layout_of(g->hg);
   if (!d_workspace || bytes < g->L.total) {
     const size_t need = g->L.total;
@@ -195,7 +175,7 @@ extern "C" int fv_create_grid(const fv_grid_desc* desc, void* d_workspace, size_
   params_to_inst(&p, g->hg.gamma, g->hinst);
   g->hinst.ndim = g->hg.ndim;
   g->hinst.nv = g->hg.nv;
-  g->hinst.ncells = g->hg.ncells;
+  g->hinst.ncells = g->hg.compute_cells();
   g->hinst.part = g->d_part;
   g->hinst.step_limit = 0;
   g->hinst.stopped = 1;
@@ -206,9 +186,9 @@ extern "C" int fv_create_grid(const fv_grid_desc* desc, void* d_workspace, size_
   TileShape tsh;
   if (tune_lookup(tp, tune_key(g->hg, FV_FP64), tsh)) sh = tsh;
   g->shape = sh;
-  st = upload_tiles(g);
+  st = fvgrid::upload_tiles(g);
   if (st) return fail(st);
-  st = put_inst(g, true);
+  st = fvgrid::put_inst(g, true);
   if (st) return fail(st);
   he = hipStreamSynchronize(g->stream);
   if (he != hipSuccess)

@@ -43,6 +43,11 @@ struct HostGrid {
   bool has_noslip = false;   // a no-slip face: the Navier-Stokes stage kernel runs it
   bool with_source = false;  // a source buffer S_h (2D: the Navier-Stokes kernel runs it)
   bool gen3 = false;         // 3D with curvilinear blocks or a source: the general 3D kernel
+  // trailing blocks that are read only, as the neighbours of block links,
+  // and never computed (the halo block of the CPU-GPU split's GPU part)
+  int nphantom = 0;
+  long long phantom_cells = 0;
+  long long compute_cells() const { return ncells - phantom_cells; }
 };
 
 int validate_and_copy(const fv_grid_desc* d, HostGrid& out);

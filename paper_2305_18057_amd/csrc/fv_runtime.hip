@@ -285,7 +285,7 @@ void build_tiles(const HostGrid& g, const TileShape& sh, int inst_index, int bof
                  std::vector<fvk::DevTile>& out) {
   out.clear();
   int local = 0;
-  for (int b = 0; b < g.nblocks; ++b) {
+  for (int b = 0; b < g.nblocks - g.nphantom; ++b) {
     const fv_block_desc& B = g.blocks[b];
     if (g.ndim == 2) {
       // at most 64 rows: the right-edge fluxes of a tile are formed one row per lane

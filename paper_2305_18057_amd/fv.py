@@ -91,6 +91,8 @@ EXPORTS = [
     "fv_server_create", "fv_submit", "fv_poll", "fv_cancel", "fv_request_times",
     "fv_server_clock", "fv_server_get_stats", "fv_server_destroy",
     "fv_noalloc_scratch_bytes", "fv_step_noalloc",
+    "fv_hetero_workspace_bytes", "fv_hetero_create", "fv_hetero_set_state", "fv_hetero_get_state",
+    "fv_hetero_step", "fv_hetero_destroy",
 ]
 
 _lib = None
@@ -148,6 +150,14 @@ def lib():
     L.fv_noalloc_scratch_bytes.argtypes = []
     L.fv_step_noalloc.argtypes = [C.POINTER(fv_grid_desc), vp, C.POINTER(fv_params), C.c_int, vp,
                                   C.POINTER(fv_step_info)]
+    L.fv_hetero_workspace_bytes.restype = C.c_size_t
+    L.fv_hetero_workspace_bytes.argtypes = [C.POINTER(fv_grid_desc), C.c_int]
+    L.fv_hetero_create.argtypes = [C.POINTER(fv_grid_desc), C.c_int, C.c_int, vp, C.c_size_t, vp,
+                                   C.POINTER(vp)]
+    L.fv_hetero_set_state.argtypes = [vp, dp]
+    L.fv_hetero_get_state.argtypes = [vp, dp]
+    L.fv_hetero_step.argtypes = [vp, C.POINTER(fv_params), C.c_int, C.POINTER(fv_step_info), dp]
+    L.fv_hetero_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -460,3 +470,65 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class Hetero:
+    """One 2D block stepped by the GPU (columns [0, split)) and a pool of
+    host-core workers (columns [split, ni)) together, exchanging the two
+    columns on each side of the cut every RK substep."""
+
+    def __init__(self, case: "_cases.Case", split: int, cpu_workers: int, device="cuda",
+                 stream: Optional[int] = None):
+        torch = _torch()
+        L = lib()
+        self.case = case
+        self.size = sum(case.nv * b.ncells for b in case.blocks)
+        self._gd = GridDesc(case)
+        nbytes = L.fv_hetero_workspace_bytes(C.byref(self._gd.desc), int(split))
+        if nbytes == 0:
+            _check(FV_E_INVAL)
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+        self.stream = current_stream_handle(self.workspace.device) if stream is None else stream
+        h = C.c_void_p()
+        _check(L.fv_hetero_create(C.byref(self._gd.desc), int(split), int(cpu_workers),
+                                  C.c_void_p(self.workspace.data_ptr()), C.c_size_t(nbytes),
+                                  C.c_void_p(self.stream), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fv_hetero_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, U, check=True) -> int:
+        a = np.ascontiguousarray(U, dtype=np.float64).ravel()
+        assert a.size == self.size
+        st = lib().fv_hetero_set_state(self._h, a.ctypes.data_as(C.POINTER(C.c_double)))
+        if check:
+            _check(st)
+        return st
+
+    def get_state(self):
+        a = np.empty(self.size)
+        _check(lib().fv_hetero_get_state(self._h, a.ctypes.data_as(C.POINTER(C.c_double))))
+        return a
+
+    def step(self, params=None, nsteps=1, check=True):
+        """nsteps steps; the info dict also holds times_ms = (GPU stage kernels,
+        host substeps, exchanges with their synchronizations, whole call)."""
+        p = make_params(params or self.case.params)
+        info = fv_step_info()
+        tm = (C.c_double * 4)()
+        st = lib().fv_hetero_step(self._h, C.byref(p), int(nsteps), C.byref(info), tm)
+        if check:
+            _check(st)
+        d = info_dict(info)
+        d["status"] = st
+        d["times_ms"] = list(tm)
+        return d

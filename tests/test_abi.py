@@ -233,3 +233,36 @@ def test_viscous_parameters_and_noslip_validation(fvb):
     g3 = fvb.GridDesc(CS.blobs_case(8, nblobs=1))
     assert L.fv_step_noalloc(C.byref(g3.desc), C.c_void_p(256), C.byref(q), 1, None,
                              C.byref(info)) == fvb.FV_E_UNSUPPORTED
+
+
+def test_hetero_split_validation(fvb):
+    """The CPU-GPU split takes one 2D Euler block cut along i with both parts
+    at least 2 columns wide; everything else is refused before any device
+    work (workspace size 0 and the reason)."""
+    L = fvb.lib()
+    c = CS.inlet_case(64, 16, 1)
+    gd = fvb.GridDesc(c)
+    n = L.fv_hetero_workspace_bytes(C.byref(gd.desc), 40)
+    # the GPU part (40 columns and a 2-column halo block) in three state buffers
+    assert n >= 3 * 8 * 4 * 16 * 42
+    assert n < L.fv_grid_workspace_bytes(C.byref(gd.desc), 0)
+    for split in (1, 63, 0, 64):
+        assert L.fv_hetero_workspace_bytes(C.byref(gd.desc), split) == 0
+        assert b"at least 2 columns" in L.fv_last_error()
+    assert L.fv_hetero_workspace_bytes(C.byref(gd.desc), 2) > 0
+    assert L.fv_hetero_workspace_bytes(C.byref(gd.desc), 62) > 0
+    cases = [
+        (CS.inlet_case(128, 16, 2), b"one 2D block"),
+        (CS.blobs_case(8, nblobs=1), b"one 2D block"),
+        (CS.vortex_2d(32, 16), b"may not be periodic"),
+    ]
+    c_ns = CS.inlet_case(64, 16, 1)
+    c_ns.blocks[0].bc[2] = CS.BC(CS.NOSLIP)
+    cases.append((c_ns, b"Euler"))
+    c_src = CS.inlet_case(64, 16, 1)
+    c_src.source = [np.zeros_like(u) for u in c_src.U0]
+    cases.append((c_src, b"Euler"))
+    for case, msg in cases:
+        g = fvb.GridDesc(case)
+        assert L.fv_hetero_workspace_bytes(C.byref(g.desc), 8) == 0, case.name
+        assert msg in L.fv_last_error(), (case.name, L.fv_last_error())
