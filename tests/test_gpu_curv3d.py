@@ -64,6 +64,20 @@ def curv_walls():
     return c
 
 
+def curv_walls_ij():
+    """Curved slip walls on the j-faces and the i-max face (the halo path of
+    the general kernel), inflow at i-min, periodic in k; two blocks."""
+    c = CS.curv3d_case(ni=90, nj=11, nk=10, nblocks=2, amp=0.06, state="random", seed=23)
+    prim = (1.05, 0.3, 0.1, 0.05, 0.75)
+    c.blocks[0].bc[0] = CS.BC(CS.INFLOW, prim=prim)
+    c.blocks[-1].bc[1] = CS.BC(CS.SLIPWALL)
+    for b in c.blocks:
+        b.bc[2] = CS.BC(CS.SLIPWALL)
+        b.bc[3] = CS.BC(CS.SLIPWALL)
+    c.name = "curv_walls_ij"
+    return c
+
+
 def curv_mms(n=24):
     c = CS.curv3d_case(ni=2 * n, nj=n, nk=n, nblocks=2, amp=0.04, state="mms",
                        L=(2.0, 1.0, 1.0))
@@ -141,9 +155,10 @@ def check_steps(fv, O, case, nsteps, params=None):
 # ---------------------------------------------------------------------------
 # tests
 # ---------------------------------------------------------------------------
-def test_curv3d_ghosts_with_curved_slip_walls(env):
+@pytest.mark.parametrize("maker", [curv_walls, curv_walls_ij])
+def test_curv3d_ghosts_with_curved_slip_walls(env, maker):
     fv, O = env
-    case = curv_walls()
+    case = maker()
     g = fv.Grid(case)
     g.set_state(case.state_flat())
     Gg = g.ghosts()
@@ -154,7 +169,7 @@ def test_curv3d_ghosts_with_curved_slip_walls(env):
     assert e <= 1e-14
 
 
-@pytest.mark.parametrize("maker", [curv_periodic, curv_walls])
+@pytest.mark.parametrize("maker", [curv_periodic, curv_walls, curv_walls_ij])
 @pytest.mark.parametrize("limiter", [CS.MINMOD, CS.UNLIMITED])
 def test_curv3d_residual(env, maker, limiter):
     fv, O = env
@@ -162,7 +177,7 @@ def test_curv3d_residual(env, maker, limiter):
     check_residual(fv, O, case, with_(case.params, limiter=limiter))
 
 
-@pytest.mark.parametrize("maker", [curv_periodic, curv_walls])
+@pytest.mark.parametrize("maker", [curv_periodic, curv_walls, curv_walls_ij])
 def test_curv3d_steps(env, maker):
     fv, O = env
     check_steps(fv, O, maker(), 12)

@@ -62,6 +62,17 @@ def test_noalloc_3d_fp32_flux_then_smaller():
     _run_pair(small, _with(small.params, rk=4), 5)
 
 
+def test_noalloc_3d_curvilinear_then_smaller():
+    """3D curvilinear grids run the general 3D stage kernel, here too."""
+    from paper_2305_18057_amd import fv
+    fv.lib()
+    big = CS.curv3d_case(ni=96, nj=20, nk=18, nblocks=2, amp=0.05, state="random", seed=12)
+    _run_pair(big, big.params, 6)
+    small = CS.curv3d_case(ni=40, nj=9, nk=8, nblocks=1, amp=0.04, state="random", seed=13,
+                           walls_k=True)
+    _run_pair(small, _with(small.params, precision=CS.FP32_FLUX), 4)
+
+
 def test_noalloc_rejects_grid_beyond_scratch():
     import torch
     from paper_2305_18057_amd import fv
