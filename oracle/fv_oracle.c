@@ -423,15 +423,28 @@ static void ghost_value(const orc_grid* G, int bi, int f, int g, int t1, int t2,
   const orc_bc* bc = &b->bc[f];
   const blk_t* src = b;
   int along;
+  int sd = d, s1 = t1, s2 = t2; /* source direction and transverse indices */
   int i, j, k;
   switch (bc->kind) {
     case ORC_PERIODIC:
       along = side == 0 ? n - g : g - 1;
       break;
-    case ORC_BLOCK:
+    case ORC_BLOCK: {
+      /* the neighbour's cell g-1 in from its face nbr_face, at the transverse
+       * position the orientation gives (t1, t2): swapped (bit 0), then each
+       * reversed (bits 1, 2) in the neighbour's own index range */
       src = &G->b[bc->nbr_block];
-      along = side == 0 ? ext(src, d) - g : g - 1;
+      sd = bc->nbr_face / 2;
+      const int nside = bc->nbr_face % 2;
+      int m1, m2;
+      trans_ext(src, sd, &m1, &m2);
+      s1 = (bc->orient & 1) ? t2 : t1;
+      s2 = (bc->orient & 1) ? t1 : t2;
+      if (bc->orient & 2) s1 = m1 - 1 - s1;
+      if (bc->orient & 4) s2 = m2 - 1 - s2;
+      along = nside == 0 ? g - 1 : ext(src, sd) - g;
       break;
+    }
     case ORC_INFLOW:
       cons_from_prim(bc->prim, nd, G->gamma, out);
       return;
@@ -446,7 +459,7 @@ static void ghost_value(const orc_grid* G, int bi, int f, int g, int t1, int t2,
       for (int v = 0; v < nv; ++v) out[v] = NAN;
       return;
   }
-  set3(d, along, t1, t2, &i, &j, &k);
+  set3(sd, along, s1, s2, &i, &j, &k);
   i64 p = pidx(src, i, j, k);
   for (int v = 0; v < nv; ++v) out[v] = src->q[v * src->npad + p];
   if (bc->kind == ORC_SLIPWALL) {
@@ -1086,18 +1099,27 @@ orc_grid* orc_create(int ndim, int nblocks, const orc_block_desc* desc, double g
     if (!b->q || !b->qn || !b->res || !b->flux) { orc_destroy(G); return NULL; }
     G->ncells += b->ncell;
   }
-  /* block connectivity must pair opposite faces of equal transverse size */
+  /* block links: in 2D opposite faces, same orientation; in 3D any face
+   * pair whose transverse extents agree under the orientation */
   for (int bi = 0; bi < nblocks; ++bi)
     for (int f = 0; f < 2 * ndim; ++f) {
       const orc_bc* bc = &G->b[bi].bc[f];
       if (bc->kind < ORC_PERIODIC || bc->kind > ORC_NOSLIP) { orc_destroy(G); return NULL; }
       if (bc->kind != ORC_BLOCK) continue;
       int nb = bc->nbr_block;
-      if (nb < 0 || nb >= nblocks || bc->nbr_face != (f ^ 1)) { orc_destroy(G); return NULL; }
+      if (nb < 0 || nb >= nblocks || bc->nbr_face < 0 || bc->nbr_face >= 2 * ndim ||
+          bc->orient < 0 || bc->orient > 7 ||
+          (ndim == 2 && (bc->nbr_face != (f ^ 1) || bc->orient != 0))) {
+        orc_destroy(G);
+        return NULL;
+      }
       int n1, n2, m1, m2;
       trans_ext(&G->b[bi], f / 2, &n1, &n2);
-      trans_ext(&G->b[nb], f / 2, &m1, &m2);
-      if (n1 != m1 || n2 != m2) { orc_destroy(G); return NULL; }
+      trans_ext(&G->b[nb], bc->nbr_face / 2, &m1, &m2);
+      if ((bc->orient & 1) ? (n1 != m2 || n2 != m1) : (n1 != m1 || n2 != m2)) {
+        orc_destroy(G);
+        return NULL;
+      }
     }
   return G;
 }

@@ -21,7 +21,11 @@ enum { ORC_OK = 0, ORC_E_INVAL = -1, ORC_E_NOMEM = -2, ORC_E_NONPHYSICAL = -4 };
 typedef struct {
   int kind;        /* ORC_PERIODIC .. ORC_NOSLIP */
   int nbr_block;   /* ORC_BLOCK: neighbour block */
-  int nbr_face;    /* ORC_BLOCK: neighbour face (must be the opposite face) */
+  int nbr_face;    /* ORC_BLOCK: neighbour face (2D: the opposite face; 3D: any face) */
+  int orient;      /* ORC_BLOCK, 3D: how this face's transverse indices (t1, t2)
+                      map onto the neighbour face's (t1', t2'): bit 0 swaps them,
+                      bits 1 and 2 reverse t1' and t2'.  0 with the opposite
+                      face is the plain 1:1 link. */
   double prim[5];  /* ORC_INFLOW: rho, u, v, w, p; ORC_NOSLIP: wall velocity in prim[1..3] */
 } orc_bc;
 

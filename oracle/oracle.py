@@ -55,7 +55,7 @@ def sanitize_env() -> dict:
 
 class _BC(C.Structure):
     _fields_ = [("kind", C.c_int), ("nbr_block", C.c_int), ("nbr_face", C.c_int),
-                ("prim", C.c_double * 5)]
+                ("orient", C.c_int), ("prim", C.c_double * 5)]
 
 
 class _Block(C.Structure):
@@ -188,6 +188,7 @@ class OracleGrid:
                 d.bc[f].kind = bc.kind
                 d.bc[f].nbr_block = bc.nbr_block
                 d.bc[f].nbr_face = bc.nbr_face
+                d.bc[f].orient = getattr(bc, "orient", 0)
                 for a in range(5):
                     d.bc[f].prim[a] = bc.prim[a]
         self._h = lib().orc_create(case.ndim, nb, arr, case.gamma)

@@ -54,6 +54,7 @@ class BC:
     nbr_block: int = -1
     nbr_face: int = -1
     prim: Sequence[float] = (0.0, 0.0, 0.0, 0.0, 0.0)  # rho, u, v, w, p (NOSLIP: wall u, v, w)
+    orient: int = 0  # BLOCK, 3D: bit 0 swaps the transverse indices, bits 1, 2 reverse them
 
 
 @dataclass
@@ -536,3 +537,144 @@ def curv3d_mms(n=256, precision=FP64, nsteps=20):
                     nsteps=nsteps)
     c.name = "curv3d_mms"
     return c
+
+
+# --------------------------------------------------------------------------
+# 3D blocks in rotated index frames, linked face to face with orientations
+# --------------------------------------------------------------------------
+def _frame_maps(frame, ext):
+    """frame = ((a0, s0), (a1, s1), (a2, s2)): local axis m runs along global
+    axis a_m, forwards (s = +1) or backwards (s = -1).  ext: the piece's
+    global cell extents.  Returns the local extents and cell / node maps."""
+    loc_ext = [ext[a] for a, _ in frame]
+
+    def cell(loc):  # local cell index -> global cell offset within the piece
+        g = [0, 0, 0]
+        for m, (a, sg) in enumerate(frame):
+            g[a] = loc[m] if sg > 0 else ext[a] - 1 - loc[m]
+        return g
+
+    def node(loc):
+        g = [0, 0, 0]
+        for m, (a, sg) in enumerate(frame):
+            g[a] = loc[m] if sg > 0 else ext[a] - loc[m]
+        return g
+    return loc_ext, cell, node
+
+
+def reindex_3d(case, cuts, frames, name="reindexed"):
+    """Split a one-block 3D case along i at the global columns `cuts` and give
+    each piece the index frame `frames[p]` (a right-handed signed permutation,
+    see _frame_maps).  Faces inside the box become block links with the
+    orientation that maps each side's transverse indices onto the other's;
+    the box's own faces keep their rules (periodic faces stay within a piece
+    and must not be cut).  Returns the new case and, per piece, the map from
+    its state layout to the single block's (index arrays)."""
+    B0 = case.blocks[0]
+    ni, nj, nk = B0.ni, B0.nj, B0.nk
+    for fr in frames:
+        M = np.zeros((3, 3))
+        for m, (a, sg) in enumerate(fr):
+            M[a, m] = sg
+        if round(np.linalg.det(M)) != 1:
+            raise ValueError(f"frame {fr} is not right-handed")
+    edges = [0, *cuts, ni]
+    pieces = []
+    for p in range(len(edges) - 1):
+        i0, i1 = edges[p], edges[p + 1]
+        ext = (i1 - i0, nj, nk)
+        loc_ext, cmap, nmap = _frame_maps(frames[p], ext)
+        pieces.append(dict(i0=i0, ext=ext, loc=loc_ext, cmap=cmap, nmap=nmap, frame=frames[p]))
+    # the face of a piece (local face index) that lies on a global face
+    def local_face(piece, gaxis, gside):
+        for m, (a, sg) in enumerate(piece["frame"]):
+            if a == gaxis:
+                return 2 * m + (gside if sg > 0 else 1 - gside)
+        raise AssertionError
+
+    def owner(gi):
+        for p, P in enumerate(pieces):
+            if P["i0"] <= gi < P["i0"] + P["ext"][0]:
+                return p
+        return None
+
+    def to_local(P, g):  # global cell -> local cell of piece P
+        off = [g[0] - P["i0"], g[1], g[2]]
+        loc = [0, 0, 0]
+        for m, (a, sg) in enumerate(P["frame"]):
+            loc[m] = off[a] if sg > 0 else P["ext"][a] - 1 - off[a]
+        return loc
+
+    def trans_axes(m):
+        return [x for x in range(3) if x != m]
+    blocks, U0, maps = [], [], []
+    X, Y, Z, U = B0.x, B0.y, B0.z, case.U0[0]
+    for p, P in enumerate(pieces):
+        li, lj, lk = P["loc"]
+        kk, jj, ii = np.meshgrid(np.arange(lk), np.arange(lj), np.arange(li), indexing="ij")
+        gi = np.empty_like(ii); gj = np.empty_like(ii); gk = np.empty_like(ii)
+        for m, (a, sg) in enumerate(P["frame"]):
+            lm = (ii, jj, kk)[m]
+            g = lm if sg > 0 else P["ext"][a] - 1 - lm
+            (gi, gj, gk)[a][...] = g
+        gi = gi + P["i0"]
+        maps.append((gk, gj, gi))
+        U0.append(np.ascontiguousarray(U[:, gk, gj, gi]))
+        nk_, nj_, ni_ = np.meshgrid(np.arange(lk + 1), np.arange(lj + 1), np.arange(li + 1), indexing="ij")
+        gn = [None, None, None]
+        for m, (a, sg) in enumerate(P["frame"]):
+            lm = (ni_, nj_, nk_)[m]
+            gn[a] = lm if sg > 0 else P["ext"][a] - lm
+        gn[0] = gn[0] + P["i0"]
+        xs = [np.ascontiguousarray(A[gn[2], gn[1], gn[0]]) for A in (X, Y, Z)]
+        bcs = [None] * 6
+        for gaxis in range(3):
+            for gside in range(2):
+                f = local_face(P, gaxis, gside)
+                rule = B0.bc[2 * gaxis + gside]
+                if gaxis == 0 and ((gside == 0 and P["i0"] > 0) or
+                                   (gside == 1 and P["i0"] + P["ext"][0] < ni)):
+                    q = p - 1 if gside == 0 else p + 1
+                    Q = pieces[q]
+                    fq = local_face(Q, 0, 1 - gside)
+                    # orientation: brute force over the 8 codes
+                    m0 = f // 2
+                    ta = trans_axes(m0)
+                    mq = fq // 2
+                    tq = trans_axes(mq)
+                    nq = [Q["loc"][x] for x in tq]
+                    found = None
+                    for o in range(8):
+                        ok = True
+                        for t1 in (0, P["loc"][ta[0]] - 1):
+                            for t2 in (0, P["loc"][ta[1]] - 1):
+                                # the ghost layer-1 cell beyond face f at (t1, t2)
+                                loc = [0, 0, 0]
+                                loc[m0] = -1 if f % 2 == 0 else P["loc"][m0]
+                                loc[ta[0]], loc[ta[1]] = t1, t2
+                                off = [0, 0, 0]
+                                for m, (a, sg) in enumerate(P["frame"]):
+                                    off[a] = loc[m] if sg > 0 else P["ext"][a] - 1 - loc[m]
+                                g = [off[0] + P["i0"], off[1], off[2]]
+                                want = to_local(Q, g)
+                                s1, s2 = (t2, t1) if o & 1 else (t1, t2)
+                                if o & 2: s1 = nq[0] - 1 - s1
+                                if o & 4: s2 = nq[1] - 1 - s2
+                                got = [0, 0, 0]
+                                got[mq] = 0 if fq % 2 == 0 else Q["loc"][mq] - 1
+                                got[tq[0]], got[tq[1]] = s1, s2
+                                ok = ok and got == want
+                        if ok:
+                            found = o
+                            break
+                    assert found is not None
+                    bcs[f] = BC(BLOCK, q, fq, orient=found)
+                else:
+                    bcs[f] = BC(rule.kind, rule.nbr_block, rule.nbr_face, tuple(rule.prim))
+        blocks.append(Block(li, lj, lk, xs[0], xs[1], (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), bcs, xs[2]))
+    src = None
+    if case.source is not None:
+        src = [np.ascontiguousarray(case.source[0][:, gk, gj, gi]) for (gk, gj, gi) in maps]
+    out = Case(name, 3, blocks, U0, Params(**case.params.__dict__), case.nsteps,
+               gamma=case.gamma, meta=dict(case.meta), source=src)
+    return out, maps
