@@ -109,7 +109,21 @@ enum {
 typedef struct fv_bc {
   int kind;          /* FV_BC_* */
   int nbr_block;     /* FV_BC_BLOCK: neighbour block index */
-  int nbr_face;      /* FV_BC_BLOCK: neighbour face (FV_IMIN..FV_KMAX) */
+  int nbr_face;      /* FV_BC_BLOCK: neighbour face (FV_IMIN..FV_KMAX).  2D: the
+                        opposite face (f ^ 1).  3D: any face (the multi-block
+                        structured grids of Sec. 2: blocks meet face to face,
+                        each in its own index frame) */
+  int orient;        /* FV_BC_BLOCK, 3D: how the transverse indices (t1, t2) of
+                        this face map onto (s1, s2) of the neighbour's face.
+                        Transverse indices of a face normal to i, j, k are
+                        (j, k), (i, k), (i, j).  Bit 0: s1 = t2, s2 = t1 (else
+                        s1 = t1, s2 = t2); bit 1: then s1 -> m1 - 1 - s1; bit 2:
+                        then s2 -> m2 - 1 - s2, (m1, m2) the neighbour face's
+                        transverse sizes.  Ghost layer g (1, 2) copies the
+                        neighbour's cell at depth g - 1 inside its face.  Must
+                        be 0 in 2D.  A 3D grid with a link that is not
+                        opposite-face and unoriented is stepped by the general
+                        3D kernel. */
   double prim_in[5]; /* FV_BC_INFLOW: rho, u, v, w, p; FV_BC_NOSLIP: wall u, v, w
                         in prim_in[1..3] */
 } fv_bc;

@@ -542,34 +542,41 @@ def curv3d_mms(n=256, precision=FP64, nsteps=20):
 # --------------------------------------------------------------------------
 # 3D blocks in rotated index frames, linked face to face with orientations
 # --------------------------------------------------------------------------
-def _frame_maps(frame, ext):
-    """frame = ((a0, s0), (a1, s1), (a2, s2)): local axis m runs along global
-    axis a_m, forwards (s = +1) or backwards (s = -1).  ext: the piece's
-    global cell extents.  Returns the local extents and cell / node maps."""
-    loc_ext = [ext[a] for a, _ in frame]
+# Index frames of pieces: local axis m runs along global axis a_m, forwards
+# (s = +1) or backwards (s = -1), frame = ((a0, s0), (a1, s1), (a2, s2)).
+# "swapped" exchanges transverse axes (links of orientation 0 and 1);
+# "reversed" also reverses them (orientations 3, 5 and 7, each reversal bit
+# alone on some link).
+ROTATED_FRAMES = {
+    "swapped": [((0, 1), (1, 1), (2, 1)), ((1, 1), (0, -1), (2, 1)), ((2, 1), (0, 1), (1, 1))],
+    "reversed": [((0, 1), (1, -1), (2, -1)), ((1, -1), (0, -1), (2, -1)),
+                 ((2, 1), (1, -1), (0, 1)), ((0, -1), (1, 1), (2, -1))],
+}
 
-    def cell(loc):  # local cell index -> global cell offset within the piece
-        g = [0, 0, 0]
-        for m, (a, sg) in enumerate(frame):
-            g[a] = loc[m] if sg > 0 else ext[a] - 1 - loc[m]
-        return g
 
-    def node(loc):
-        g = [0, 0, 0]
-        for m, (a, sg) in enumerate(frame):
-            g[a] = loc[m] if sg > 0 else ext[a] - loc[m]
-        return g
-    return loc_ext, cell, node
+def twisted_box_3d(n=24, nblobs=4, seed=5):
+    """A uniform n^3 box of density blobs whose opposite faces are joined to
+    each other with a twist: the i-faces with their transverse indices
+    swapped and both reversed (orientation 7), the j-faces with i reversed
+    (2), the k-faces with j reversed (4).  Each map is its own inverse, so
+    the two sides of every link agree."""
+    c = blobs_case(n, nblobs=nblobs, seed=seed, name="twisted_box")
+    b = c.blocks[0]
+    b.bc = [BC(BLOCK, 0, 1, orient=7), BC(BLOCK, 0, 0, orient=7),
+            BC(BLOCK, 0, 3, orient=2), BC(BLOCK, 0, 2, orient=2),
+            BC(BLOCK, 0, 5, orient=4), BC(BLOCK, 0, 4, orient=4)]
+    return c
 
 
 def reindex_3d(case, cuts, frames, name="reindexed"):
-    """Split a one-block 3D case along i at the global columns `cuts` and give
-    each piece the index frame `frames[p]` (a right-handed signed permutation,
-    see _frame_maps).  Faces inside the box become block links with the
-    orientation that maps each side's transverse indices onto the other's;
-    the box's own faces keep their rules (periodic faces stay within a piece
-    and must not be cut).  Returns the new case and, per piece, the map from
-    its state layout to the single block's (index arrays)."""
+    """Split a one-block 3D curvilinear case along i at the global columns
+    `cuts` and give each piece the index frame `frames[p]` (a right-handed
+    signed permutation, see ROTATED_FRAMES).  Faces inside the box become
+    block links with the orientation that maps each side's transverse
+    indices onto the other's; the box's own faces keep their rules (periodic
+    faces stay within a piece and must not be cut).  Returns the new case
+    and, per piece, the map from its state layout to the single block's
+    (index arrays)."""
     B0 = case.blocks[0]
     ni, nj, nk = B0.ni, B0.nj, B0.nk
     for fr in frames:
@@ -583,20 +590,14 @@ def reindex_3d(case, cuts, frames, name="reindexed"):
     for p in range(len(edges) - 1):
         i0, i1 = edges[p], edges[p + 1]
         ext = (i1 - i0, nj, nk)
-        loc_ext, cmap, nmap = _frame_maps(frames[p], ext)
-        pieces.append(dict(i0=i0, ext=ext, loc=loc_ext, cmap=cmap, nmap=nmap, frame=frames[p]))
+        loc_ext = [ext[a] for a, _ in frames[p]]
+        pieces.append(dict(i0=i0, ext=ext, loc=loc_ext, frame=frames[p]))
     # the face of a piece (local face index) that lies on a global face
     def local_face(piece, gaxis, gside):
         for m, (a, sg) in enumerate(piece["frame"]):
             if a == gaxis:
                 return 2 * m + (gside if sg > 0 else 1 - gside)
         raise AssertionError
-
-    def owner(gi):
-        for p, P in enumerate(pieces):
-            if P["i0"] <= gi < P["i0"] + P["ext"][0]:
-                return p
-        return None
 
     def to_local(P, g):  # global cell -> local cell of piece P
         off = [g[0] - P["i0"], g[1], g[2]]

@@ -37,6 +37,7 @@ struct DevBlock {
   long long out_off;        // offset of this block in a residual output array
   int bc_kind[6];
   int bc_nbr[6];
+  int bc_link[6];           // BLOCK: neighbour face | orientation << 3 (see link_cell)
   double bc_q[6][5];        // INFLOW: conserved ghost state; NOSLIP: wall velocity in [1..3]
 };
 
@@ -488,6 +489,29 @@ __device__ __forceinline__ void noslip_mirror(double* q, const double* w) {
   q[ND + 1] += 0.5 * (n2 - m2) / q[0];
 }
 
+// Cell (si, sj, sk) of block S that ghost layer g (1 or 2) copies through a
+// block link (the multi-block grids of Sec. 2) whose far side is face nf = link & 7
+// of S with orientation o = link >> 3.  (t1, t2) are the ghost's transverse
+// indices on its own face, in the order (j, k), (i, k), (i, j) for faces
+// normal to i, j, k.  Bit 0 of o swaps them; bits 1 and 2 then reverse the
+// first and the second along S's face.  The copied cell lies g - 1 cells
+// inside face nf.
+__device__ __forceinline__ void link_cell(const DevBlock& S, int link, int g, int t1, int t2,
+                                          int& si, int& sj, int& sk) {
+  const int nf = link & 7, o = link >> 3, sd = nf >> 1;
+  const int m1 = sd == 0 ? S.nj : S.ni;
+  const int m2 = sd == 2 ? S.nj : S.nk;
+  int s1 = (o & 1) ? t2 : t1;
+  int s2 = (o & 1) ? t1 : t2;
+  if (o & 2) s1 = m1 - 1 - s1;
+  if (o & 4) s2 = m2 - 1 - s2;
+  const int n = sd == 0 ? S.ni : (sd == 1 ? S.nj : S.nk);
+  const int along = (nf & 1) == 0 ? g - 1 : n - g;
+  si = sd == 0 ? along : s1;
+  sj = sd == 1 ? along : (sd == 0 ? s1 : s2);
+  sk = sd == 2 ? along : s2;
+}
+
 template <int NV>
 __device__ __forceinline__ void load_cell(const DevBlock* __restrict__ blocks, const DevBlock& B,
                                           int buf, int i, int j, int k, double* q) {
@@ -512,16 +536,21 @@ __device__ __forceinline__ void load_cell(const DevBlock* __restrict__ blocks, c
     for (int v = 0; v < NV; ++v) q[v] = B.bc_q[f][v];
     return;
   }
-  const DevBlock* S = (kind == BC_BLOCK) ? &blocks[B.bc_nbr[f]] : &B;
-  const int n = d == 0 ? S->ni : (d == 1 ? S->nj : S->nk);
-  int along;
-  if (kind == BC_PERIODIC || kind == BC_BLOCK) along = side == 0 ? n - g : g - 1;
-  else if (kind == BC_EXTRAP) along = side == 0 ? 0 : n - 1;
-  else along = side == 0 ? g - 1 : n - g;  // SLIPWALL, NOSLIP
+  const DevBlock* S = &B;
+  const int n = d == 0 ? B.ni : (d == 1 ? B.nj : B.nk);
   int si = i, sj = j, sk = k;
-  if (d == 0) si = along;
-  else if (d == 1) sj = along;
-  else sk = along;
+  if (kind == BC_BLOCK) {
+    S = &blocks[B.bc_nbr[f]];
+    link_cell(*S, B.bc_link[f], g, d == 0 ? j : i, d == 2 ? j : k, si, sj, sk);
+  } else {
+    int along;
+    if (kind == BC_PERIODIC) along = side == 0 ? n - g : g - 1;
+    else if (kind == BC_EXTRAP) along = side == 0 ? 0 : n - 1;
+    else along = side == 0 ? g - 1 : n - g;  // SLIPWALL, NOSLIP
+    if (d == 0) si = along;
+    else if (d == 1) sj = along;
+    else sk = along;
+  }
   const double* s = S->u[buf] + ((long long)sk * S->nj + sj) * S->ni + si;
 #pragma unroll
   for (int v = 0; v < NV; ++v) q[v] = ldg(s + v * S->ncell);

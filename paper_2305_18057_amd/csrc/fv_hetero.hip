@@ -423,9 +423,11 @@ int split_grids(const fv_grid_desc* desc, int split, HostGrid& whole, HostGrid& 
   b[0].face[1].kind = FV_BC_BLOCK;
   b[0].face[1].nbr_block = 1;
   b[0].face[1].nbr_face = FV_IMIN;
+  b[0].face[1].orient = 0;
   b[1].face[0].kind = FV_BC_BLOCK;
   b[1].face[0].nbr_block = 0;
   b[1].face[0].nbr_face = FV_IMAX;
+  b[1].face[0].orient = 0;
   b[1].face[1].kind = FV_BC_EXTRAP;
   fv_grid_desc d = *desc;
   d.nblocks = 2;

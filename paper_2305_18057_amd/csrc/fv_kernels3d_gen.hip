@@ -69,11 +69,14 @@ __device__ __forceinline__ void halo_slot(int x, int nc, int nr, int& qr, int& q
 }
 
 // Source of the in-plane cell (ii, jj) of block B (at most one of the two
-// outside, by at most 2): the rules of load_cell, without the plane.
+// outside, by at most 2): the rules of load_cell, without the plane.  The
+// cell of plane k is at p + k * ps: through an oriented block link the
+// planes of B may run along any axis of the neighbour, either way.
 __device__ void halo_source(const DevBlock* __restrict__ blocks, const DevBlock& B, int buf, int ii,
                             int jj, const double*& p, long long& vs, int& ps, int& kf) {
   const DevBlock* S = &B;
   int si = ii, sj = jj, kind = 0, f = 0, t = 0;
+  long long c0 = -1, plane = (long long)B.ni * B.nj;  // c0 >= 0: start set by a block link
   if (ii < 0 || ii >= B.ni || jj < 0 || jj >= B.nj) {
     const int d = (ii < 0 || ii >= B.ni) ? 0 : 1;
     const int x = d == 0 ? ii : jj, n0 = d == 0 ? B.ni : B.nj;
@@ -83,11 +86,18 @@ __device__ void halo_source(const DevBlock* __restrict__ blocks, const DevBlock&
     const int bk = B.bc_kind[f];
     if (bk == BC_INFLOW) {
       kind = 1;
+    } else if (bk == BC_BLOCK) {
+      // the cells of planes 0 and 1 give the neighbour's start and stride
+      S = &blocks[B.bc_nbr[f]];
+      int sk, ai, aj, ak;
+      link_cell(*S, B.bc_link[f], g, t, 0, si, sj, sk);
+      link_cell(*S, B.bc_link[f], g, t, 1, ai, aj, ak);
+      c0 = ((long long)sk * S->nj + sj) * S->ni + si;
+      plane = ((long long)ak * S->nj + aj) * S->ni + ai - c0;
     } else {
-      if (bk == BC_BLOCK) S = &blocks[B.bc_nbr[f]];
-      const int n = d == 0 ? S->ni : S->nj;
+      const int n = d == 0 ? B.ni : B.nj;
       int along;
-      if (bk == BC_PERIODIC || bk == BC_BLOCK) along = side == 0 ? n - g : g - 1;
+      if (bk == BC_PERIODIC) along = side == 0 ? n - g : g - 1;
       else if (bk == BC_EXTRAP) along = side == 0 ? 0 : n - 1;
       else along = side == 0 ? g - 1 : n - g;  // slip wall
       if (d == 0) si = along;
@@ -95,9 +105,10 @@ __device__ void halo_source(const DevBlock* __restrict__ blocks, const DevBlock&
       kind = bk == BC_SLIPWALL ? 2 : 0;
     }
   }
-  p = kind == 1 ? nullptr : S->u[buf] + (long long)sj * S->ni + si;
+  if (c0 < 0) c0 = (long long)sj * S->ni + si;
+  p = kind == 1 ? nullptr : S->u[buf] + c0;
   vs = S->ncell;
-  ps = S->ni * S->nj;
+  ps = (int)plane;
   kf = kind | (f << 4) | (t << 8);
 }
 

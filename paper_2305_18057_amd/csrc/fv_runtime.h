@@ -42,7 +42,8 @@ struct HostGrid {
   long long node_doubles = 0;
   bool has_noslip = false;   // a no-slip face: the Navier-Stokes stage kernel runs it
   bool with_source = false;  // a source buffer S_h (2D: the Navier-Stokes kernel runs it)
-  bool gen3 = false;         // 3D with curvilinear blocks or a source: the general 3D kernel
+  bool gen3 = false;         // 3D with curvilinear blocks, a source or an oriented block
+                             // link: the general 3D kernel
   // trailing blocks that are read only, as the neighbours of block links,
   // and never computed (the halo block of the CPU-GPU split's GPU part)
   int nphantom = 0;

@@ -106,19 +106,29 @@ int validate_and_copy(const fv_grid_desc* d, HostGrid& g) {
       if (bc.kind == FV_BC_BLOCK) {
         if (bc.nbr_block < 0 || bc.nbr_block >= g.nblocks)
           return set_error(FV_E_INVAL, "block %d face %d: neighbour block %d out of range", b, f, bc.nbr_block);
-        if (bc.nbr_face != (f ^ 1))
-          return set_error(FV_E_INVAL, "block %d face %d: neighbour face must be the opposite face %d", b, f, f ^ 1);
+        if (g.ndim == 2 && (bc.nbr_face != (f ^ 1) || bc.orient != 0))
+          return set_error(FV_E_INVAL, "block %d face %d: 2D links join opposite faces (neighbour face "
+                           "%d, orient 0)", b, f, f ^ 1);
+        if (bc.nbr_face < 0 || bc.nbr_face > 5)
+          return set_error(FV_E_INVAL, "block %d face %d: neighbour face %d out of range", b, f, bc.nbr_face);
+        if (bc.orient < 0 || bc.orient > 7)
+          return set_error(FV_E_INVAL, "block %d face %d: orient %d out of range 0..7", b, f, bc.orient);
         int n1, n2, m1, m2;
         trans(B, f / 2, n1, n2);
-        trans(g.blocks[bc.nbr_block], f / 2, m1, m2);
+        trans(g.blocks[bc.nbr_block], bc.nbr_face / 2, m1, m2);
+        if (bc.orient & 1) std::swap(n1, n2);
         if (n1 != m1 || n2 != m2)
-          return set_error(FV_E_INVAL, "block %d face %d: transverse size %dx%d != neighbour's %dx%d", b, f, n1, n2, m1, m2);
+          return set_error(FV_E_INVAL, "block %d face %d: transverse size %dx%d (in the neighbour's "
+                           "order) != neighbour's %dx%d", b, f, n1, n2, m1, m2);
+        // the uniform 3D kernel reads its neighbours' opposite faces unoriented
+        if (bc.nbr_face != (f ^ 1) || bc.orient != 0) g.gen3 = true;
       }
       // the two ghost layers of these rules are two distinct cells of the source block
       if (bc.kind == FV_BC_PERIODIC || bc.kind == FV_BC_SLIPWALL || bc.kind == FV_BC_BLOCK ||
           bc.kind == FV_BC_NOSLIP) {
         const fv_block_desc& S = bc.kind == FV_BC_BLOCK ? g.blocks[bc.nbr_block] : B;
-        if (face_ext(S, f / 2) < 2)
+        const int sd = bc.kind == FV_BC_BLOCK ? bc.nbr_face / 2 : f / 2;
+        if (face_ext(S, sd) < 2)
           return set_error(FV_E_INVAL, "block %d face %d: this rule needs at least 2 cells across the face", b, f);
       }
       if (bc.kind == FV_BC_INFLOW) {
@@ -227,6 +237,7 @@ void build_blocks(const HostGrid& g, char* base, const InstLayout& L, int inst_i
       const fv_bc& bc = D.face[f];
       B.bc_kind[f] = (f < 2 * g.ndim) ? bc.kind : FV_BC_PERIODIC;
       B.bc_nbr[f] = bc.kind == FV_BC_BLOCK ? bc.nbr_block + boff : -1;
+      B.bc_link[f] = bc.kind == FV_BC_BLOCK ? bc.nbr_face | bc.orient << 3 : 0;
       if (bc.kind == FV_BC_INFLOW && f < 2 * g.ndim) {
         // conserved state of the prescribed primitive (rho, u, v, w, p)
         const double rho = bc.prim_in[0];

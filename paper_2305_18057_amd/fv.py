@@ -33,7 +33,7 @@ class FVError(RuntimeError):
 
 class fv_bc(C.Structure):
     _fields_ = [("kind", C.c_int), ("nbr_block", C.c_int), ("nbr_face", C.c_int),
-                ("prim_in", C.c_double * 5)]
+                ("orient", C.c_int), ("prim_in", C.c_double * 5)]
 
 
 class fv_block_desc(C.Structure):
@@ -199,6 +199,7 @@ class GridDesc:
                 d.face[f].kind = bc.kind
                 d.face[f].nbr_block = bc.nbr_block
                 d.face[f].nbr_face = bc.nbr_face
+                d.face[f].orient = getattr(bc, "orient", 0)
                 for a in range(5):
                     d.face[f].prim_in[a] = bc.prim[a]
         self.desc = fv_grid_desc(case.ndim, nb, self.arr, case.gamma,

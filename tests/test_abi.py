@@ -118,6 +118,37 @@ def test_curvilinear_3d_and_source_descriptors(fvb):
     assert b"source" in L.fv_last_error()
 
 
+def test_oriented_block_links_validation(fvb):
+    """3D links may join any two faces with any of the 8 orientations when the
+    transverse sizes agree under it; 2D links stay opposite-face and
+    unoriented; out-of-range faces and codes are refused."""
+    L = fvb.lib()
+    c = CS.curv3d_case(ni=24, nj=10, nk=8, nblocks=1, amp=0.05, state="random", seed=3)
+    c.blocks[0].bc[0] = CS.BC(CS.INFLOW, prim=(1.0, 0.8, 0.1, 0.05, 0.7))
+    c.blocks[0].bc[1] = CS.BC(CS.EXTRAP)
+    r, _ = CS.reindex_3d(c, [6, 12, 18], CS.ROTATED_FRAMES["reversed"])
+    gd = fvb.GridDesc(r)
+    assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) > 0
+    b, f = next((b, f) for b, blk in enumerate(r.blocks) for f, bc in enumerate(blk.bc)
+                if bc.kind == CS.BLOCK and bc.orient & 1)
+    for field, value, msg in (("orient", lambda o: o ^ 1, b"transverse size"),
+                              ("orient", lambda o: 8, b"orient"),
+                              ("nbr_face", lambda o: 6, b"neighbour face")):
+        gd = fvb.GridDesc(r)
+        fc = gd.arr[b].face[f]
+        setattr(fc, field, value(getattr(fc, field)))
+        assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) == 0, (field, value)
+        assert msg in L.fv_last_error()
+    gd = fvb.GridDesc(CS.twisted_box_3d(12))
+    assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) > 0
+    c2 = CS.inlet_case(64, 16, 2)
+    for fld, val in (("orient", 2), ("nbr_face", 2)):
+        gd = fvb.GridDesc(c2)
+        setattr(gd.arr[0].face[1], fld, val)
+        assert L.fv_grid_workspace_bytes(C.byref(gd.desc), 0) == 0
+        assert b"2D links join opposite faces" in L.fv_last_error()
+
+
 def test_degenerate_grids_rejected(fvb):
     """Empty and degenerate descriptors are errors (0 bytes and a message),
     never a grid."""

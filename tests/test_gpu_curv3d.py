@@ -1,6 +1,7 @@
 """General 3D path on the GPU (through the C ABI) against the CPU reference,
 element by element: curvilinear 3D blocks (face area vectors and volumes from
-the nodes, slip walls about curved wall faces), the source term of
+the nodes, slip walls about curved wall faces), blocks in rotated index
+frames joined face to face by oriented links, the source term of
 Eq. (residual) in 3D (general kernel) and 2D (the Navier-Stokes kernel's
 route), and the manufactured-solution order.
 
@@ -83,6 +84,26 @@ def curv_mms(n=24):
                        L=(2.0, 1.0, 1.0))
     c.name = f"curv_mms_{n}"
     return c
+
+
+ROT_CUTS = {"swapped": [70, 110], "reversed": [70, 100, 125]}
+
+
+def rotated(which, walls=False, state="random"):
+    """A deformed 150 x 20 x 12 box cut along i into pieces with rotated and
+    reflected index frames (the first piece 70 columns wide: a 64-column
+    tile and a ragged one), joined by oriented links: inflow at i-min,
+    extrapolation at i-max, periodic in k and in j, or slip walls on the
+    j-faces (which fall on i-, j- or k-faces of the pieces)."""
+    c = CS.curv3d_case(ni=150, nj=20, nk=12, nblocks=1, amp=0.05, state=state, seed=24)
+    c.blocks[0].bc[0] = CS.BC(CS.INFLOW, prim=(1.0, 0.8, 0.1, 0.05, 0.7))
+    c.blocks[0].bc[1] = CS.BC(CS.EXTRAP)
+    if walls:
+        c.blocks[0].bc[2] = CS.BC(CS.SLIPWALL)
+        c.blocks[0].bc[3] = CS.BC(CS.SLIPWALL)
+    r, _ = CS.reindex_3d(c, ROT_CUTS[which], CS.ROTATED_FRAMES[which],
+                         name=f"rot_{which}{'_walls' if walls else ''}_{state}")
+    return r
 
 
 def uniform_with_source():
@@ -298,3 +319,68 @@ def test_curv3d_mms_full_size(env):
     say(f"  curv3d_mms 192^3: {case.ncells} cells")
     check_residual(fv, O, case)
     check_steps(fv, O, case, 1)
+
+
+# ---------------------------------------------------------------------------
+# oriented block links
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which", sorted(CS.ROTATED_FRAMES))
+def test_oriented_links_ghosts(env, which):
+    fv, O = env
+    case = rotated(which, walls=True)
+    g = fv.Grid(case)
+    g.set_state(case.state_flat())
+    Gg = g.ghosts()
+    Go = O.OracleGrid(case).ghosts()
+    e = float(np.max(np.abs(Gg - Go)) / np.max(np.abs(Go)))
+    say(f"  ghosts {case.name}: max rel {e:.2e}")
+    assert e <= 1e-14
+
+
+@pytest.mark.parametrize("which", sorted(CS.ROTATED_FRAMES))
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("limiter", [CS.MINMOD, CS.UNLIMITED])
+def test_oriented_links_residual(env, which, walls, limiter):
+    fv, O = env
+    case = rotated(which, walls)
+    check_residual(fv, O, case, with_(case.params, limiter=limiter))
+
+
+@pytest.mark.parametrize("which", sorted(CS.ROTATED_FRAMES))
+def test_oriented_links_steps(env, which):
+    fv, O = env
+    check_steps(fv, O, rotated(which, walls=True), 10)
+
+
+def test_oriented_links_mms_source(env):
+    fv, O = env
+    case = rotated("reversed", state="mms")
+    check_residual(fv, O, case)
+    check_steps(fv, O, case, 8)
+
+
+def test_oriented_links_fp32_flux(env):
+    fv, O = env
+    case = rotated("reversed", walls=True)
+    p32 = with_(case.params, precision=CS.FP32_FLUX)
+    g = fv.Grid(case)
+    g.set_state(case.state_flat())
+    g.step(p32, 1)
+    ref = O.OracleGrid(case)
+    ref.run(case.params, 1)
+    e1 = P.state_err(case, g.get_state(), ref.get_state())
+    g.step(p32, 11)
+    ref.run(case.params, 11)
+    eN = P.state_err(case, g.get_state(), ref.get_state())
+    say(f"  fp32-flux {case.name}: 1 step {e1:.2e}, 12 steps {eN:.2e}")
+    assert e1 <= P.FP32_STEP_TOL and eN <= P.FP32_RUN_TOL
+
+
+def test_twisted_uniform_box(env):
+    """Uniform blocks whose links are oriented run the general kernel too
+    (the uniform 3D kernel reads opposite faces unoriented): a 70^3 box
+    joined to itself with reversed and swapped transverse indices."""
+    fv, O = env
+    case = CS.twisted_box_3d(70)
+    check_residual(fv, O, case)
+    check_steps(fv, O, case, 6)

@@ -222,23 +222,14 @@ def test_mms_truncation_second_order():
     assert np.sqrt(np.mean((R / vol) ** 2)) > 20 * e32[0]
 
 
-# Index frames of the pieces, local axis m = (global axis, direction).  The
-# first set swaps transverse axes (orient 0 and 1); the second reverses them
-# too (orient 3, 5 and 7), each bit alone on some link.
-FRAME_SETS = {
-    "swapped": ([9, 17], [((0, 1), (1, 1), (2, 1)), ((1, 1), (0, -1), (2, 1)),
-                          ((2, 1), (0, 1), (1, 1))]),
-    "reversed": ([6, 12, 18], [((0, 1), (1, -1), (2, -1)), ((1, -1), (0, -1), (2, -1)),
-                               ((2, 1), (1, -1), (0, 1)), ((0, -1), (1, 1), (2, -1))]),
-}
+CUTS = {"swapped": [9, 17], "reversed": [6, 12, 18]}
 
 
 def _rotated_pieces(c, which="swapped"):
     """The box cut along i into pieces with rotated and reflected (right-
     handed) index frames: links between different faces with swapped and
     reversed transverse indices."""
-    cuts, frames = FRAME_SETS[which]
-    return CS.reindex_3d(c, cuts, frames)
+    return CS.reindex_3d(c, CUTS[which], CS.ROTATED_FRAMES[which])
 
 
 def _scatter(blocks, flat, maps, shape):
@@ -251,7 +242,7 @@ def _scatter(blocks, flat, maps, shape):
     return out
 
 
-@pytest.mark.parametrize("which", sorted(FRAME_SETS))
+@pytest.mark.parametrize("which", sorted(CS.ROTATED_FRAMES))
 @pytest.mark.parametrize("state", ["random", "mms"])
 def test_oriented_block_links_match_single_block(state, which):
     """A block cut into pieces whose index frames are rotated and reflected

@@ -147,8 +147,9 @@ def test_server_refuses_viscous_solves(fvb):
 
 
 def test_server_refuses_curvilinear_3d_and_sources(fvb):
-    """3D curvilinear grids and source terms run the general stage kernels of
-    the grid API; the server refuses them with FV_E_UNSUPPORTED."""
+    """3D curvilinear grids, source terms and oriented block links run the
+    general stage kernels of the grid API; the server refuses them with
+    FV_E_UNSUPPORTED."""
     srv = fvb.Server(arena_bytes=64 << 20, max_instances=4, dry_run=True)
     for state in ("random", "mms"):
         case = CS.curv3d_case(ni=16, nj=8, nk=8, nblocks=2, state=state)
@@ -159,5 +160,9 @@ def test_server_refuses_curvilinear_3d_and_sources(fvb):
     c2.source = [np.zeros_like(u) for u in c2.U0]
     with pytest.raises(fvb.FVError) as e:
         srv.submit(c2, max_steps=10)
+    assert e.value.status == fvb.FV_E_UNSUPPORTED
+    # oriented block links (uniform blocks too) also take the general kernel
+    with pytest.raises(fvb.FVError) as e:
+        srv.submit(CS.twisted_box_3d(12), max_steps=10)
     assert e.value.status == fvb.FV_E_UNSUPPORTED
     srv.close()

@@ -73,6 +73,19 @@ def test_noalloc_3d_curvilinear_then_smaller():
     _run_pair(small, _with(small.params, precision=CS.FP32_FLUX), 4)
 
 
+def test_noalloc_oriented_links_then_smaller():
+    """Oriented block links (the general 3D kernel's signed plane strides)."""
+    from paper_2305_18057_amd import fv
+    fv.lib()
+    big = CS.twisted_box_3d(40)
+    _run_pair(big, big.params, 5)
+    c = CS.curv3d_case(ni=24, nj=10, nk=8, nblocks=1, amp=0.05, state="random", seed=3)
+    c.blocks[0].bc[0] = CS.BC(CS.INFLOW, prim=(1.0, 0.8, 0.1, 0.05, 0.7))
+    c.blocks[0].bc[1] = CS.BC(CS.EXTRAP)
+    small, _ = CS.reindex_3d(c, [6, 12, 18], CS.ROTATED_FRAMES["reversed"], name="rot_small")
+    _run_pair(small, small.params, 4)
+
+
 def test_noalloc_rejects_grid_beyond_scratch():
     import torch
     from paper_2305_18057_amd import fv
