@@ -289,16 +289,22 @@ def bench_rk_schemes(fv, cases, tune_cache, steps2d):
     return out
 
 
-def bench_hetero(fv, cases, tune_cache, steps=20, workers=16):
+def bench_hetero(fv, cases, tune_cache, steps=20, workers=16, viscous=False):
     """The CPU-GPU heterogeneous mode (Sec. 4 workflow, Sec. 6 model) on the
-    inlet-like grid as one 2048 x 256 block, FP64: the pure-GPU step time,
-    one host core's time per cell t_I, a sweep of the workload ratio r (the
+    inlet-like grid as one 2048 x 256 block, FP64, with the Euler solver or
+    (viscous) the Navier-Stokes solver of the viscous inlet workload (no-slip
+    walls, mu = 1.5e-2; Sec. 8 measures both): the pure-GPU step time, one
+    host core's time per cell t_I, a sweep of the workload ratio r (the
     cells of the GPU over the cells of one of `workers` host workers) with
     the measured time per step, and the model of Sec. 6 fitted to the sweep
     (r_gc from the pure modes, kappa = (1 + alpha) beta by least squares;
     alpha quoted for the paper's beta range 0.2 .. 0.5)."""
     from paper_2305_18057_amd import perfmodel as PM
-    c = cases.inlet_case(2048, 256, 1, name="inlet_2d_1block")
+    c = cases.inlet_case(2048, 256, 1, name="inlet_2d_ns_1block" if viscous else "inlet_2d_1block")
+    if viscous:
+        for f in (2, 3):
+            c.blocks[0].bc[f] = cases.BC(cases.NOSLIP)
+        c.params = cases.Params(**{**c.params.__dict__, "mu": 1.5e-2, "prandtl": 0.72})
     Nl, Nw, N = 2048, 256, c.ncells
     p = cases.Params(**{**c.params.__dict__, "precision": cases.FP64})
     gx, _, _, dx, _, _ = time_grid(fv, c, p, steps, 5, tune_cache, stage_times=False)
@@ -333,7 +339,8 @@ def bench_hetero(fv, cases, tune_cache, steps=20, workers=16):
     for x in rows:
         x["model_ms"] = round(PM.time_ratio(Nl, Nw, 1, workers, x["ratio"], r_gc, tI, fit.kappa) * 1e3, 4)
     best = min(rows, key=lambda x: x["wall_ms"])
-    out = dict(cells=N, steps=steps, workers=workers, pure_gpu_ms=round(t_gpu * 1e3, 4),
+    out = dict(solver="navier-stokes" if viscous else "euler", cells=N, steps=steps,
+               workers=workers, pure_gpu_ms=round(t_gpu * 1e3, 4),
                pure_gpu_ssspnt=round(1e-6 * N * 3 / t_gpu, 2),
                host_core_tI_ns=round(tI * 1e9, 2), host_core_cell_updates_per_s=round(1 / tI, 1),
                r_gc=round(r_gc, 1), kappa=round(fit.kappa, 3), fit_rms_rel=round(fit.rms_rel, 4),
@@ -342,7 +349,7 @@ def bench_hetero(fv, cases, tune_cache, steps=20, workers=16):
                best=dict(ratio=best["ratio"], wall_ms=best["wall_ms"],
                          vs_pure_gpu=round(t_gpu * 1e3 / best["wall_ms"], 4)),
                sweep=rows)
-    log(f"[bench] hetero: pure GPU {out['pure_gpu_ms']} ms/step, host core {1e-6 / tI:.2f} M "
+    log(f"[bench] hetero {out['solver']}: pure GPU {out['pure_gpu_ms']} ms/step, host core {1e-6 / tI:.2f} M "
         f"cell-updates/s, r_gc {r_gc:.0f}; best ratio {best['ratio']} at {best['wall_ms']} ms/step "
         f"({out['best']['vs_pure_gpu']}x pure GPU); kappa {fit.kappa:.2f} (fit rms {fit.rms_rel:.2f})")
     return out
@@ -936,6 +943,7 @@ def main():
             del gx
         extra["rk_schemes"] = bench_rk_schemes(fv, cases, tune_cache, args.steps)
         extra["hetero"] = bench_hetero(fv, cases, tune_cache)
+        extra["hetero_ns"] = bench_hetero(fv, cases, tune_cache, viscous=True)
         tc = tune_cache or os.path.join(tempfile.mkdtemp(prefix="fv_tune_"), "tiles.json")
         extra["batched_64"] = bench_batched(fv, cases, None if args.no_tune else tc)
         b = extra["batched_64"]

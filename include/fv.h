@@ -303,8 +303,12 @@ int fv_grid_get_stats(const fv_grid* g, fv_grid_stats* out);
  * common time step.  Results are those of fv_step on the whole block (the
  * same formulas; the host's divisions and roots are the correctly rounded
  * IEEE ones).
- * Grids: 2D, one block, Euler (mu = 0, no no-slip face, no source), i-faces
- * neither periodic nor linked (FV_E_UNSUPPORTED otherwise);
+ * The Euler and the Navier-Stokes solver (Sec. 8 runs both in this mode): a
+ * viscosity (p->mu > 0) or a no-slip face runs the Navier-Stokes stage kernel
+ * on the GPU part, and the host part forms the same viscous flux (diamond
+ * gradients with the kernel's corner-ghost and ghost-centre rules).
+ * Grids: 2D, one block, no source, i-faces neither periodic nor linked
+ * (FV_E_UNSUPPORTED otherwise);
  * 2 <= split <= ni - 2 (FV_E_INVAL).  The workspace is device memory the
  * caller owns (>= fv_hetero_workspace_bytes); the host worker's arrays and
  * pinned exchange buffers are allocated by the handle and freed by

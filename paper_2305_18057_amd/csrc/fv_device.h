@@ -476,7 +476,7 @@ __device__ inline void cell_geom3(const DevBlock& B, int i, int j, int k, double
 // and p kept, in conserved form m' = 2 rho w - m, rho e_t' = rho e_t +
 // (|m'|^2 - |m|^2) / (2 rho) (a wall at rest: m' = -m, rho e_t unchanged)
 template <int ND>
-__device__ __forceinline__ void noslip_mirror(double* q, const double* w) {
+__host__ __device__ __forceinline__ void noslip_mirror(double* q, const double* w) {
   double m2 = 0.0, n2 = 0.0;
 #pragma unroll
   for (int a = 0; a < ND; ++a) {
@@ -721,17 +721,50 @@ __host__ __device__ __forceinline__ double cell_dt_limit(const double* q, const 
   return vol / lam;
 }
 
+// Viscous flux F_nu . S (Sec. 2) of a face from u, v, p/rho at its cells L,
+// R (centres dx, dy apart) and its nodes A, B (B - A turned by -90 degrees
+// is S): Green-Gauss gradients over the face's diamond, Stokes stresses
+// with constant mu, heat flux kq grad(p/rho).  Differences in FP64, the
+// rest in T.
+template <typename T>
+__host__ __device__ __forceinline__ void visc_flux(const double* wL, const double* wR,
+                                                   const double* wA, const double* wB, double dx,
+                                                   double dy, double Sx, double Sy, T mu, T kq,
+                                                   T* F) {
+  const T tSx = T(Sx), tSy = T(Sy), tdx = T(dx), tdy = T(dy);
+  const T iD = M<T>::rcp(fmad(tdx, tSx, tdy * tSy));
+  T gx[3], gy[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const T a = T(wR[k] - wL[k]), t = T(wB[k] - wA[k]);
+    gx[k] = fmad(a, tSx, -(t * tdy)) * iD;
+    gy[k] = fmad(a, tSy, t * tdx) * iD;
+  }
+  const T dv = gx[0] + gy[1];
+  const T c23 = T(2.0 / 3.0);
+  const T txx = mu * fmad(T(2), gx[0], -(c23 * dv));
+  const T tyy = mu * fmad(T(2), gy[1], -(c23 * dv));
+  const T txy = mu * (gy[0] + gx[1]);
+  const T uf = T(0.5 * (wL[0] + wR[0])), vf = T(0.5 * (wL[1] + wR[1]));
+  const T thx = fmad(uf, txx, fmad(vf, txy, kq * gx[2]));
+  const T thy = fmad(uf, txy, fmad(vf, tyy, kq * gy[2]));
+  F[0] = T(0);
+  F[1] = fmad(txx, tSx, txy * tSy);
+  F[2] = fmad(txy, tSx, tyy * tSy);
+  F[3] = fmad(thx, tSx, thy * tSy);
+}
+
 // the same limit with the viscous term of a Navier-Stokes step:
 // |Omega| / (sum_d(|u.Sbar_d| + c|Sbar_d|) + 2 max(4/3, gamma/Pr) (mu/rho)
 // sum_d |Sbar_d|^2 / |Omega|)
-__device__ __forceinline__ double cell_dt_limit_visc(const double* q, const double (*Sb)[3],
-                                                     double vol, double gamma, double mu,
-                                                     double prandtl, int& bad) {
+__host__ __device__ __forceinline__ double cell_dt_limit_visc(const double* q, const double (*Sb)[3],
+                                                              double vol, double gamma, double mu,
+                                                              double prandtl, int& bad) {
   const double rho = q[0];
   double ir = 1.0 / rho, u = q[1] * ir, v = q[2] * ir;
   const double p = (gamma - 1.0) * fmad(-0.5, fmad(u, q[1], v * q[2]), q[3]);
-  const bool ok = isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && isfinite(q[3]) &&
-                  rho > 0.0 && p > 0.0;
+  const bool ok = __builtin_isfinite(q[0]) && __builtin_isfinite(q[1]) &&
+                  __builtin_isfinite(q[2]) && __builtin_isfinite(q[3]) && rho > 0.0 && p > 0.0;
   if (!ok) {
     bad = 1;
     return INFINITY;

@@ -1,13 +1,15 @@
 // CPU-GPU heterogeneous stepping of one 2D block: the synchronous workflow of
-// Sec. 4 with the 1D domain decomposition of Sec. 6.  The GPU part runs the
-// 2D stage kernels on columns [0, split) of the block, with a two-column
-// block after it that its block link reads and nothing computes (its storage
-// is the halo the host part sends).  The host part runs the same stage
-// arithmetic (the flux formulas of fv_device.h compiled for the host) on
-// columns [split, ni), its rows dealt to a pool of worker threads.  Every RK
-// substep: the two columns on each side of the cut cross over, both parts
-// compute, everybody synchronizes.  The step end combines norms and
-// time-step bounds and the host sets the common time step.
+// Sec. 4 with the 1D domain decomposition of Sec. 6, for the Euler and the
+// Navier-Stokes solver (Sec. 8 runs both this way).  The GPU part runs the
+// 2D stage kernels (Euler, or Navier-Stokes for a viscosity or a no-slip
+// face) on columns [0, split) of the block, with a two-column block after it
+// that its block link reads and nothing computes (its storage is the halo
+// the host part sends).  The host part runs the same stage arithmetic (the
+// flux formulas of fv_device.h compiled for the host) on columns [split, ni),
+// its rows dealt to a pool of worker threads.  Every RK substep: the two
+// columns on each side of the cut cross over, both parts compute, everybody
+// synchronizes.  The step end combines norms and time-step bounds and the
+// host sets the common time step.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -124,7 +126,12 @@ struct HostPart {
   // nc), volumes and the time-step bound's mean area vectors (nj x nc)
   std::vector<double> six, siy, sjx, sjy, vol, sb;
   int bc_kind[4] = {0, 0, 0, 0};
-  double bcq[4][NV] = {};
+  double bcq[4][NV] = {};  // INFLOW: conserved state; NOSLIP: wall velocity in [1..2]
+  // Navier-Stokes: node coordinates of node columns [s-2, ni], rows [0, nj];
+  // (u, v, p/rho) and centres of the cells in columns [s-1, ni] and rows
+  // [-1, nj] (ghost centres by the rule of the stage kernel; corners unused)
+  std::vector<double> nx, ny, cx, cy, W;
+  double bound_mu = 0.0, bound_pr = 0.0;  // viscosity of the current time-step bound
   std::vector<double> P;       // padded stage input [var][nj+4][nc+4]
   std::vector<double> fi, fj;  // face fluxes times area: [var][j][nc+1], [var][nj+1][c]
   std::vector<double> rsum;    // per row: 4 norm sums, minimum, flag
@@ -133,6 +140,10 @@ struct HostPart {
   int bad = 0;
 
   int pw() const { return nc + 4; }
+  int cw() const { return nc + 2; }
+  size_t nd(int i, int j) const { return (size_t)j * (nc + 3) + (i - (s - 2)); }
+  size_t ce(int i, int j) const { return (size_t)(j + 1) * cw() + (i - (s - 1)); }
+  double& w(int k, int i, int j) { return W[(size_t)k * (nj + 2) * cw() + ce(i, j)]; }
   double& p(int v, int jj, int cc) { return P[((size_t)v * (nj + 4) + jj) * pw() + cc]; }
   double& U(int b, int v, int j, int c) { return u[b][((size_t)v * nj + j) * nc + c]; }
 };
@@ -152,41 +163,138 @@ inline void mirror(double* q, double Sx, double Sy) {
   q[2] -= fct * Sy;
 }
 
-// Ghost row jj (0, 1: below; nj+2, nj+3: above) of local column c, by the
-// j-face rules (inflow, extrapolation, slip wall, periodic within the part)
-void j_ghost(HostPart& H, int bin, int jj, int c, double* q) {
-  const int side = jj < 2 ? 0 : 1;
-  const int g = side == 0 ? 2 - jj : jj - (H.nj + 1);
-  const int f = 2 + side, kind = H.bc_kind[f];
-  if (kind == FV_BC_INFLOW) {
-    for (int v = 0; v < NV; ++v) q[v] = H.bcq[f][v];
+// area vector of the wall face of a j-face side f (2, 3) at column i (i in
+// [s-2, ni-1]), or of the i-max face at row j
+void jwall_vec(const HostPart& H, int f, int i, double& sx, double& sy) {
+  if (!H.curv) {
+    sx = 0.0;
+    sy = 1.0;
     return;
   }
-  int sj;
-  if (kind == FV_BC_PERIODIC) sj = side == 0 ? H.nj - g : g - 1;
-  else if (kind == FV_BC_EXTRAP) sj = side == 0 ? 0 : H.nj - 1;
-  else sj = side == 0 ? g - 1 : H.nj - g;  // slip wall
-  for (int v = 0; v < NV; ++v) q[v] = H.U(bin, v, sj, c);
-  if (kind == FV_BC_SLIPWALL) {
-    const int r = side == 0 ? 0 : H.nj;
-    if (H.curv) mirror(q, H.sjx[(size_t)r * H.nc + c], H.sjy[(size_t)r * H.nc + c]);
-    else mirror(q, 0.0, 1.0);
+  const int r = f == 2 ? 0 : H.nj;
+  sx = -(H.ny[H.nd(i + 1, r)] - H.ny[H.nd(i, r)]);
+  sy = H.nx[H.nd(i + 1, r)] - H.nx[H.nd(i, r)];
+}
+void imax_wall_vec(const HostPart& H, int j, double& sx, double& sy) {
+  if (!H.curv) {
+    sx = 1.0;
+    sy = 0.0;
+    return;
+  }
+  const size_t f = (size_t)j * (H.nc + 1) + H.nc;
+  sx = H.six[f];
+  sy = H.siy[f];
+}
+
+// State of cell (i, j) of the block, columns [s-2, ni+1] and rows [-2, nj+1],
+// in buffer bin: the i-face rule first (the block's i-max face; columns s-2
+// and s-1 are the GPU part's, from gh: [var][j][2]), then the j-face rule of
+// the block, then the two transforms in reverse order, as the stage kernels
+// resolve ghost and corner cells.
+void cell_at(const HostPart& H, int bin, const double* gh, int i, int j, double* q) {
+  int si = i, ikind = -1;
+  if (i >= H.ni) {
+    const int g = i - H.ni + 1;
+    ikind = H.bc_kind[1];
+    if (ikind == FV_BC_INFLOW) {
+      for (int v = 0; v < NV; ++v) q[v] = H.bcq[1][v];
+      return;
+    }
+    si = ikind == FV_BC_EXTRAP ? H.ni - 1 : H.ni - g;  // extrapolation or a wall
+  }
+  int sj = j, jkind = -1, jface = 2;
+  bool set = false;
+  if (j < 0 || j >= H.nj) {
+    const int side = j < 0 ? 0 : 1;
+    const int g = side == 0 ? -j : j - H.nj + 1;
+    jface = 2 + side;
+    jkind = H.bc_kind[jface];
+    if (jkind == FV_BC_INFLOW) {
+      for (int v = 0; v < NV; ++v) q[v] = H.bcq[jface][v];
+      set = true;
+    } else if (jkind == FV_BC_PERIODIC) {
+      sj = side == 0 ? H.nj - g : g - 1;
+    } else if (jkind == FV_BC_EXTRAP) {
+      sj = side == 0 ? 0 : H.nj - 1;
+    } else {
+      sj = side == 0 ? g - 1 : H.nj - g;  // slip or no-slip wall
+    }
+  }
+  if (!set) {
+    for (int v = 0; v < NV; ++v)
+      q[v] = si >= H.s ? H.u[bin][((size_t)v * H.nj + sj) * H.nc + (si - H.s)]
+                       : gh[((size_t)v * H.nj + sj) * 2 + (si - (H.s - 2))];
+    if (jkind == FV_BC_SLIPWALL) {
+      double sx, sy;
+      jwall_vec(H, jface, si, sx, sy);
+      mirror(q, sx, sy);
+    } else if (jkind == FV_BC_NOSLIP) {
+      fvk::noslip_mirror<2>(q, H.bcq[jface]);
+    }
+  }
+  if (ikind == FV_BC_SLIPWALL) {
+    double sx, sy;
+    imax_wall_vec(H, std::min(std::max(j, 0), H.nj - 1), sx, sy);
+    mirror(q, sx, sy);
+  } else if (ikind == FV_BC_NOSLIP) {
+    fvk::noslip_mirror<2>(q, H.bcq[1]);
   }
 }
 
-// ghost column g (1, 2) beyond the block's i-max face, row j
-void imax_ghost(HostPart& H, int bin, int g, int j, double* q) {
-  const int kind = H.bc_kind[1];
-  if (kind == FV_BC_INFLOW) {
-    for (int v = 0; v < NV; ++v) q[v] = H.bcq[1][v];
+// centre of cell (i, j), i in [s-1, ni], j in [-1, nj], from the nodes; a
+// ghost centre is the interior one reflected through the boundary face's
+// midpoint, or across a periodic face its image moved by the offset between
+// the two faces (the rule of the Navier-Stokes stage kernel)
+void centre_at(const HostPart& H, int i, int j, double& cx, double& cy) {
+  auto node = [&](int a, int b, double& x, double& y) {
+    x = H.nx[H.nd(a, b)];
+    y = H.ny[H.nd(a, b)];
+  };
+  auto interior = [&](int a, int b, double& x, double& y) {
+    double x0, y0, x1, y1, x2, y2, x3, y3;
+    node(a, b, x0, y0);
+    node(a + 1, b, x1, y1);
+    node(a, b + 1, x2, y2);
+    node(a + 1, b + 1, x3, y3);
+    x = 0.25 * (((x0 + x1) + x2) + x3);
+    y = 0.25 * (((y0 + y1) + y2) + y3);
+  };
+  const bool iin = i < H.ni, jin = j >= 0 && j < H.nj;
+  if (iin && jin) {
+    interior(i, j, cx, cy);
     return;
   }
-  const int sc = kind == FV_BC_EXTRAP ? H.nc - 1 : H.nc - g;  // extrapolation or slip wall
-  for (int v = 0; v < NV; ++v) q[v] = H.U(bin, v, j, sc);
-  if (kind == FV_BC_SLIPWALL) {
-    const size_t f = (size_t)j * (H.nc + 1) + H.nc;
-    if (H.curv) mirror(q, H.six[f], H.siy[f]);
-    else mirror(q, 1.0, 0.0);
+  if (!iin && !jin) {
+    cx = cy = 0.0;
+    return;
+  }
+  double x0, y0, x1, y1;
+  if (!iin) {  // beyond the i-max face (never periodic or linked here)
+    node(H.ni, j, x0, y0);
+    node(H.ni, j + 1, x1, y1);
+    double ix, iy;
+    interior(H.ni - 1, j, ix, iy);
+    cx = 2.0 * (0.5 * (x0 + x1)) - ix;
+    cy = 2.0 * (0.5 * (y0 + y1)) - iy;
+    return;
+  }
+  const int side = j < 0 ? 0 : 1;
+  const int w = side == 0 ? 0 : H.nj;
+  node(i, w, x0, y0);
+  node(i + 1, w, x1, y1);
+  const double mx = 0.5 * (x0 + x1), my = 0.5 * (y0 + y1);
+  if (H.bc_kind[2 + side] == FV_BC_PERIODIC) {
+    const int along = side == 0 ? H.nj - 1 : 0, wo = side == 0 ? H.nj : 0;
+    node(i, wo, x0, y0);
+    node(i + 1, wo, x1, y1);
+    const double ox = 0.5 * (x0 + x1), oy = 0.5 * (y0 + y1);
+    interior(i, along, cx, cy);
+    cx += mx - ox;
+    cy += my - oy;
+  } else {
+    interior(i, side == 0 ? 0 : H.nj - 1, cx, cy);
+    cx = 2.0 * mx - cx;
+    cy = 2.0 * my - cy;
   }
 }
 
@@ -214,6 +322,7 @@ struct StageCtx {
   fvk::Recon<double> rc;
   fvk::FluxK<double> K;
   const double* gh;  // the GPU part's columns split-2, split-1: [var][j][2]
+  double mu = 0.0, prandtl = 0.72, kq = 0.0;  // viscosity, Prandtl number, mu/Pr gamma/(gamma-1)
 };
 
 // flux times area across a face from its four cells along the face normal
@@ -245,33 +354,72 @@ inline void face_flux(const StageCtx& X, const HostPart& H, const double* c0, co
 void host_stage(HostPart& H, Pool& pool, const StageCtx& X) {
   const int nj = H.nj, nc = H.nc, nw = pool.size();
   const int bin = X.bin;
+  const bool visc = X.mu > 0.0;
+  // F_nu . S of the face between cells (iL, jL) and (iR, jR) whose nodes A,
+  // B have B - A turned by -90 degrees equal to S: node values are the mean
+  // of the four cells around the node
+  auto node_w = [&](int i, int j, double* o) {
+    for (int k = 0; k < 3; ++k)
+      o[k] = 0.25 * (((H.w(k, i - 1, j - 1) + H.w(k, i, j - 1)) + H.w(k, i - 1, j)) + H.w(k, i, j));
+  };
+  auto visc_face = [&](int iL, int jL, int iR, int jR, int iA, int jA, int iB, int jB, double Sx,
+                       double Sy, double* F) {
+    double wL[3], wR[3], wA[3], wB[3], Fv[4];
+    for (int k = 0; k < 3; ++k) {
+      wL[k] = H.w(k, iL, jL);
+      wR[k] = H.w(k, iR, jR);
+    }
+    node_w(iA, jA, wA);
+    node_w(iB, jB, wB);
+    const double dx = H.cx[H.ce(iR, jR)] - H.cx[H.ce(iL, jL)];
+    const double dy = H.cy[H.ce(iR, jR)] - H.cy[H.ce(iL, jL)];
+    fvk::visc_flux<double>(wL, wR, wA, wB, dx, dy, Sx, Sy, X.mu, X.kq, Fv);
+    for (int v = 0; v < NV; ++v) F[v] -= Fv[v];
+  };
   const bool reads_un = X.mode >= 2, low = X.mode >= 4, norms = X.mode <= 1,
              cfl = X.mode == 3 || X.mode == 6;
   pool.run([&](int w) {
     int lo, hi;
     // 1. padded input: own cells, the GPU's two columns, i-max and j ghosts
+    //    and the corner ghosts (the viscous flux reads those next to the
+    //    part); then (u, v, p/rho) of the cells the viscous flux reads
     share(nj + 4, w, nw, lo, hi);
     for (int jj = lo; jj < hi; ++jj) {
       double q[NV];
+      const int j = jj - 2;
       if (jj < 2 || jj >= nj + 2) {
-        for (int c = 0; c < nc; ++c) {
-          j_ghost(H, bin, jj, c, q);
-          for (int v = 0; v < NV; ++v) H.p(v, jj, c + 2) = q[v];
+        for (int c = 0; c < nc + 4; ++c) {
+          cell_at(H, bin, X.gh, H.s - 2 + c, j, q);
+          for (int v = 0; v < NV; ++v) H.p(v, jj, c) = q[v];
         }
         continue;
       }
-      const int j = jj - 2;
       for (int v = 0; v < NV; ++v) {
         std::memcpy(&H.p(v, jj, 2), &H.U(bin, v, j, 0), sizeof(double) * nc);
         H.p(v, jj, 0) = X.gh[((size_t)v * nj + j) * 2 + 0];
         H.p(v, jj, 1) = X.gh[((size_t)v * nj + j) * 2 + 1];
       }
       for (int g = 1; g <= 2; ++g) {
-        imax_ghost(H, bin, g, j, q);
+        cell_at(H, bin, X.gh, H.ni - 1 + g, j, q);
         for (int v = 0; v < NV; ++v) H.p(v, jj, nc + 1 + g) = q[v];
       }
     }
     pool.barrier();
+    if (visc) {
+      share(nj + 2, w, nw, lo, hi);
+      for (int r = lo; r < hi; ++r)
+        for (int c = 0; c < nc + 2; ++c) {
+          const int i = H.s - 1 + c, j = r - 1;
+          const double rho = H.p(0, r + 1, c + 1);
+          const double ir = 1.0 / rho;
+          const double u = H.p(1, r + 1, c + 1) * ir, v = H.p(2, r + 1, c + 1) * ir;
+          const double pr = (H.gamma - 1.0) * (H.p(3, r + 1, c + 1) - 0.5 * rho * (u * u + v * v));
+          H.w(0, i, j) = u;
+          H.w(1, i, j) = v;
+          H.w(2, i, j) = pr * ir;
+        }
+      pool.barrier();
+    }
     // 2. face fluxes: i-faces of rows, j-faces of face rows
     share(nj, w, nw, lo, hi);
     double c0[NV], c1[NV], c2[NV], c3[NV], F[NV];
@@ -285,6 +433,10 @@ void host_stage(HostPart& H, Pool& pool, const StageCtx& X) {
         }
         const size_t fx = (size_t)j * (nc + 1) + f;
         face_flux(X, H, c0, c1, c2, c3, H.curv ? H.six[fx] : 0.0, H.curv ? H.siy[fx] : 0.0, 0, F);
+        if (visc) {
+          const int i = H.s + f;  // the face at i - 1/2, nodes (i, j) and (i, j+1)
+          visc_face(i - 1, j, i, j, i, j, i, j + 1, H.curv ? H.six[fx] : H.hy, H.curv ? H.siy[fx] : 0.0, F);
+        }
         for (int v = 0; v < NV; ++v) H.fi[((size_t)v * nj + j) * (nc + 1) + f] = F[v];
       }
     share(nj + 1, w, nw, lo, hi);
@@ -298,6 +450,10 @@ void host_stage(HostPart& H, Pool& pool, const StageCtx& X) {
         }
         const size_t fx = (size_t)r * nc + c;
         face_flux(X, H, c0, c1, c2, c3, H.curv ? H.sjx[fx] : 0.0, H.curv ? H.sjy[fx] : 0.0, 1, F);
+        if (visc) {
+          const int i = H.s + c;  // the face at j - 1/2 (j = r), nodes (i+1, j) and (i, j)
+          visc_face(i, r - 1, i, r, i + 1, r, i, r, H.curv ? H.sjx[fx] : 0.0, H.curv ? H.sjy[fx] : H.hx, F);
+        }
         for (int v = 0; v < NV; ++v) H.fj[((size_t)v * (nj + 1) + r) * nc + c] = F[v];
       }
     pool.barrier();
@@ -334,7 +490,8 @@ void host_stage(HostPart& H, Pool& pool, const StageCtx& X) {
         if (cfl) {
           const double Sb[2][3] = {{H.sb[4 * cell + 0], H.sb[4 * cell + 1], 0.0},
                                    {H.sb[4 * cell + 2], H.sb[4 * cell + 3], 0.0}};
-          mn = std::min(mn, fvk::cell_dt_limit<2>(out, Sb, vol, H.gamma, bad));
+          mn = std::min(mn, visc ? fvk::cell_dt_limit_visc(out, Sb, vol, H.gamma, X.mu, X.prandtl, bad)
+                                 : fvk::cell_dt_limit<2>(out, Sb, vol, H.gamma, bad));
         }
       }
       double* rs = &H.rsum[(size_t)j * 6];
@@ -362,8 +519,9 @@ void host_stage(HostPart& H, Pool& pool, const StageCtx& X) {
   }
 }
 
-// time-step bound and physical check of the host part's U^n
-void host_bound(HostPart& H) {
+// time-step bound and physical check of the host part's U^n (with the
+// viscous term for mu > 0)
+void host_bound(HostPart& H, double mu, double prandtl) {
   double mn = INFINITY;
   int bad = 0;
   for (int j = 0; j < H.nj; ++j)
@@ -373,10 +531,13 @@ void host_bound(HostPart& H) {
       for (int v = 0; v < NV; ++v) q[v] = H.U(0, v, j, c);
       const double Sb[2][3] = {{H.sb[4 * cell + 0], H.sb[4 * cell + 1], 0.0},
                                {H.sb[4 * cell + 2], H.sb[4 * cell + 3], 0.0}};
-      mn = std::min(mn, fvk::cell_dt_limit<2>(q, Sb, H.vol[cell], H.gamma, bad));
+      mn = std::min(mn, mu > 0.0 ? fvk::cell_dt_limit_visc(q, Sb, H.vol[cell], H.gamma, mu, prandtl, bad)
+                                 : fvk::cell_dt_limit<2>(q, Sb, H.vol[cell], H.gamma, bad));
     }
   H.raw_min = mn;
   H.bad = bad;
+  H.bound_mu = mu;
+  H.bound_pr = prandtl;
 }
 
 // the grid checks of the split; fills the GPU part's 2-block host grid
@@ -385,8 +546,8 @@ int split_grids(const fv_grid_desc* desc, int split, HostGrid& whole, HostGrid& 
   if (st) return st;
   if (whole.ndim != 2 || whole.nblocks != 1)
     return set_error(FV_E_UNSUPPORTED, "the CPU-GPU split takes one 2D block");
-  if (whole.with_source || whole.has_noslip)
-    return set_error(FV_E_UNSUPPORTED, "the CPU-GPU split runs the Euler stage kernels (no source, no no-slip wall)");
+  if (whole.with_source)
+    return set_error(FV_E_UNSUPPORTED, "the CPU-GPU split takes no source term");
   const fv_block_desc& B = whole.blocks[0];
   for (int f = 0; f < 4; ++f) {
     const int k = B.face[f].kind;
@@ -517,6 +678,11 @@ extern "C" int fv_hetero_create(const fv_grid_desc* desc, int split, int cpu_wor
     H.fi.assign((size_t)NV * H.nj * (H.nc + 1), 0.0);
     H.fj.assign((size_t)NV * (H.nj + 1) * H.nc, 0.0);
     H.rsum.assign((size_t)H.nj * 6, 0.0);
+    H.nx.assign((size_t)(H.nj + 1) * (H.nc + 3), 0.0);
+    H.ny.assign(H.nx.size(), 0.0);
+    H.cx.assign((size_t)(H.nj + 2) * H.cw(), 0.0);
+    H.cy.assign(H.cx.size(), 0.0);
+    H.W.assign(3 * H.cx.size(), 0.0);
     H.vol.assign(ncell, 0.0);
     H.sb.assign(4 * ncell, 0.0);
     if (H.curv) {
@@ -566,8 +732,17 @@ extern "C" int fv_hetero_create(const fv_grid_desc* desc, int split, int cpu_wor
         H.sjy[(size_t)r * H.nc + c] = X(i + 1, r) - X(i, r);
       }
   }
+  // nodes of columns [s-2, ni] (the uniform lattice as the stage kernels
+  // form it) and the cell centres the viscous flux reads
+  for (int j = 0; j <= H.nj; ++j)
+    for (int i = split - 2; i <= B.ni; ++i) {
+      H.nx[H.nd(i, j)] = H.curv ? X(i, j) : B.origin[0] + i * B.h[0];
+      H.ny[H.nd(i, j)] = H.curv ? Y(i, j) : B.origin[1] + j * B.h[1];
+    }
   for (int f = 0; f < 4; ++f) {
     H.bc_kind[f] = B.face[f].kind;
+    if (B.face[f].kind == FV_BC_NOSLIP)
+      for (int a = 1; a <= 3; ++a) H.bcq[f][a] = B.face[f].prim_in[a];  // wall velocity
     if (B.face[f].kind == FV_BC_INFLOW) {
       const double rho = B.face[f].prim_in[0];
       const double u = B.face[f].prim_in[1], v = B.face[f].prim_in[2];
@@ -577,6 +752,8 @@ extern "C" int fv_hetero_create(const fv_grid_desc* desc, int split, int cpu_wor
       H.bcq[f][3] = B.face[f].prim_in[4] / (H.gamma - 1.0) + 0.5 * rho * (u * u + v * v);
     }
   }
+  for (int j = -1; j <= H.nj; ++j)
+    for (int i = split - 1; i <= B.ni; ++i) centre_at(H, i, j, H.cx[H.ce(i, j)], H.cy[H.ce(i, j)]);
   const size_t xb = sizeof(double) * NV * H.nj * 2;
   bool ok = true;
   for (int x = 0; x < 2; ++x)
@@ -613,7 +790,7 @@ extern "C" int fv_hetero_set_state(fv_hetero* h, const double* U) {
     }
   int st = fv_set_state(h->gpu, Ug.data(), 0);
   if (st && st != FV_E_NONPHYSICAL) return st;
-  host_bound(h->H);
+  host_bound(h->H, h->H.bound_mu, h->H.bound_pr);
   h->t = 0.0;
   h->steps = 0;
   h->have_first = 0;
@@ -645,7 +822,6 @@ extern "C" int fv_hetero_step(fv_hetero* h, const fv_params* p, int nsteps, fv_s
   if (!h) return set_error(FV_E_INVAL, "null handle");
   int st = check_params(p);
   if (st) return st;
-  if (p->mu > 0.0) return set_error(FV_E_UNSUPPORTED, "the CPU-GPU split runs the Euler stage kernels (mu = 0)");
   if (!h->have_state) return set_error(FV_E_INVAL, "no state set");
   if (nsteps < 0) return set_error(FV_E_INVAL, "negative step count");
   fv_grid* g = h->gpu;
@@ -677,6 +853,12 @@ extern "C" int fv_hetero_step(fv_hetero* h, const fv_params* p, int nsteps, fv_s
   X.K.efix = p->entropy_fix;
   X.K.iefix = p->entropy_fix > 0.0 ? 1.0 / p->entropy_fix : 0.0;
   X.gh = nullptr;  // set per stage
+  X.mu = p->mu;
+  X.prandtl = p->prandtl;
+  X.kq = p->mu > 0.0 ? p->mu / p->prandtl * H.gamma / (H.gamma - 1.0) : 0.0;
+  // the host part's time-step bound of U^n with this viscosity, as the GPU
+  // part forms its own again in use_params
+  if (H.bound_mu != p->mu || H.bound_pr != p->prandtl) host_bound(H, p->mu, p->prandtl);
   const long long ncell_gpu = (long long)nj * s, ncell_all = (long long)nj * h->ni;
   double t_gpu = 0.0, t_cpu = 0.0, t_x = 0.0;
   int flags = 0;

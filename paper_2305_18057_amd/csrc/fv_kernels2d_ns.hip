@@ -237,36 +237,6 @@ __device__ void ns_centre(const DevBlock* __restrict__ blocks, const DevBlock& B
   }
 }
 
-// viscous flux F_nu . S of a face from u, v, p/rho at its cells L, R and
-// nodes A, B (B - A turned by -90 degrees is S); differences in FP64,
-// the rest in T
-template <typename T>
-__device__ __forceinline__ void visc_flux(const double* wL, const double* wR, const double* wA,
-                                          const double* wB, double dx, double dy, double Sx,
-                                          double Sy, T mu, T kq, T* F) {
-  const T tSx = T(Sx), tSy = T(Sy), tdx = T(dx), tdy = T(dy);
-  const T iD = M<T>::rcp(fmad(tdx, tSx, tdy * tSy));
-  T gx[3], gy[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const T a = T(wR[k] - wL[k]), t = T(wB[k] - wA[k]);
-    gx[k] = fmad(a, tSx, -(t * tdy)) * iD;
-    gy[k] = fmad(a, tSy, t * tdx) * iD;
-  }
-  const T dv = gx[0] + gy[1];
-  const T c23 = T(2.0 / 3.0);
-  const T txx = mu * fmad(T(2), gx[0], -(c23 * dv));
-  const T tyy = mu * fmad(T(2), gy[1], -(c23 * dv));
-  const T txy = mu * (gy[0] + gx[1]);
-  const T uf = T(0.5 * (wL[0] + wR[0])), vf = T(0.5 * (wL[1] + wR[1]));
-  const T thx = fmad(uf, txx, fmad(vf, txy, kq * gx[2]));
-  const T thy = fmad(uf, txy, fmad(vf, tyy, kq * gy[2]));
-  F[0] = T(0);
-  F[1] = fmad(txx, tSx, txy * tSy);
-  F[2] = fmad(txy, tSx, tyy * tSy);
-  F[3] = fmad(thx, tSx, thy * tSy);
-}
-
 template <int LIM, typename T>
 __device__ __forceinline__ void inv_flux(const Recon<T>& rc, const FluxK<T>& K, const double* c0,
                                          const double* c1, const double* c2, const double* c3,

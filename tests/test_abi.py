@@ -267,9 +267,10 @@ def test_viscous_parameters_and_noslip_validation(fvb):
 
 
 def test_hetero_split_validation(fvb):
-    """The CPU-GPU split takes one 2D Euler block cut along i with both parts
-    at least 2 columns wide; everything else is refused before any device
-    work (workspace size 0 and the reason)."""
+    """The CPU-GPU split takes one 2D block (Euler or Navier-Stokes, no
+    source) cut along i with both parts at least 2 columns wide; everything
+    else is refused before any device work (workspace size 0 and the
+    reason)."""
     L = fvb.lib()
     c = CS.inlet_case(64, 16, 1)
     gd = fvb.GridDesc(c)
@@ -289,10 +290,12 @@ def test_hetero_split_validation(fvb):
     ]
     c_ns = CS.inlet_case(64, 16, 1)
     c_ns.blocks[0].bc[2] = CS.BC(CS.NOSLIP)
-    cases.append((c_ns, b"Euler"))
+    c_ns.blocks[0].bc[1] = CS.BC(CS.NOSLIP)
+    g_ns = fvb.GridDesc(c_ns)
+    assert L.fv_hetero_workspace_bytes(C.byref(g_ns.desc), 8) > 0
     c_src = CS.inlet_case(64, 16, 1)
     c_src.source = [np.zeros_like(u) for u in c_src.U0]
-    cases.append((c_src, b"Euler"))
+    cases.append((c_src, b"no source"))
     for case, msg in cases:
         g = fvb.GridDesc(case)
         assert L.fv_hetero_workspace_bytes(C.byref(g.desc), 8) == 0, case.name

@@ -5,6 +5,9 @@ together must reproduce the single-domain solution (FP64 <= 1e-12 relative,
 the bar of Sec. 8 for its CPU and GPU solutions), for cuts next to either
 end and in the middle, with 1 to several host workers, the three RK
 schemes and a t_end landing; FP32-flux on the GPU part within its bars.
+The Navier-Stokes solver (Sec. 8 runs it in this mode too) on curved and
+uniform blocks with no-slip walls, moving and at rest, at every side the
+host part touches.
 """
 import os
 import sys
@@ -168,3 +171,88 @@ def test_inlet_full_size_split(env):
     fv, O = env
     case = CS.inlet_case(2048, 256, 1, name="inlet_2d_1block")
     check(fv, O, case, 2048 - 32, 8, 10)
+
+
+# ---------------------------------------------------------------------------
+# Navier-Stokes
+# ---------------------------------------------------------------------------
+def ns_curved(imax=None, Ni=150, Nj=37):
+    """The curved channel of the Navier-Stokes tests as one block: no-slip
+    wall at rest below, a moving no-slip wall above, inflow at i-min and
+    extrapolation (or the given rule) at i-max; mu = 2e-3."""
+    from tests.test_gpu_ns import curved_channel
+    c = curved_channel(Ni=Ni, Nj=Nj, icut=(), jcut=())
+    if imax is not None:
+        c.blocks[0].bc[1] = imax
+    c.name = "ns_curved" + ("" if imax is None else f"_imax{imax.kind}")
+    return c
+
+
+def ns_uniform():
+    """The uniform channel (periodic in j) with a viscosity."""
+    c = channel()
+    c.params = with_(c.params, mu=4e-3, prandtl=0.72)
+    c.name = "ns_uniform"
+    return c
+
+
+@pytest.mark.parametrize("split,workers", [(2, 1), (77, 4), (148, 3)])
+def test_ns_curved_splits(env, split, workers):
+    fv, O = env
+    check(fv, O, ns_curved(), split, workers, 12)
+
+
+@pytest.mark.parametrize("imax", [CS.BC(CS.NOSLIP, prim=(0.0, 0.0, -0.2, 0.0, 0.0)),
+                                  CS.BC(CS.SLIPWALL)])
+def test_ns_walls_at_imax(env, imax):
+    """A wall closing the host part's far end: its corner ghosts (the i-face
+    rule, then the j-face rule) and reflected ghost centres."""
+    fv, O = env
+    check(fv, O, ns_curved(imax), 100, 3, 12)
+
+
+@pytest.mark.parametrize("split", [3, 90])
+def test_ns_uniform_periodic(env, split):
+    fv, O = env
+    check(fv, O, ns_uniform(), split, 2, 12)
+
+
+@pytest.mark.parametrize("rk", [2, 4])
+def test_ns_rk_schemes(env, rk):
+    fv, O = env
+    case = ns_curved()
+    check(fv, O, case, 60, 3, 8, with_(case.params, rk=rk))
+
+
+def test_ns_noslip_without_viscosity(env):
+    """mu = 0 with no-slip walls: the Navier-Stokes kernel's inviscid path on
+    the GPU part, the no-slip ghosts on both."""
+    fv, O = env
+    case = ns_curved()
+    check(fv, O, case, 70, 2, 10, with_(case.params, mu=0.0))
+
+
+def test_ns_fp32_flux_gpu_part(env):
+    fv, O = env
+    case = ns_curved()
+    p32 = with_(case.params, precision=CS.FP32_FLUX)
+    h, _ = hetero_run(fv, case, 75, 3, 1, p32)
+    ref = O.OracleGrid(case)
+    ref.run(case.params, 1)
+    e1 = P.state_err(case, h.get_state(), ref.get_state())
+    h.step(p32, 19)
+    ref.run(case.params, 19)
+    eN = P.state_err(case, h.get_state(), ref.get_state())
+    say(f"  NS fp32-flux GPU part: 1 step {e1:.2e}, 20 steps {eN:.2e}")
+    assert e1 <= P.FP32_STEP_TOL and eN <= P.FP32_RUN_TOL
+
+
+def test_ns_inlet_full_size_split(env):
+    """The viscous inlet grid (no-slip walls, mu = 1.5e-2) at its full
+    2048 x 256 size as one block, 32 host columns: 6 steps."""
+    fv, O = env
+    case = CS.inlet_case(2048, 256, 1, name="inlet_2d_ns_1block")
+    for f in (2, 3):
+        case.blocks[0].bc[f] = CS.BC(CS.NOSLIP)
+    case.params = with_(case.params, mu=1.5e-2, prandtl=0.72)
+    check(fv, O, case, 2048 - 32, 8, 6)
