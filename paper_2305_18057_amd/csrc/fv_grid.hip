@@ -492,8 +492,9 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
   // of the step sequence), from the saved state; a warm-up, then the best of
   // three batches (a single short batch is too noisy to separate shapes a few
   // per cent apart; the first batch also pays for capturing its graph).
-  // Small grids take longer batches, whose per-step time matches long runs.
-  const int reps = g->hg.ncells < (1LL << 21) ? 64 : 4;
+  // Small grids take longer batches, whose per-step time matches long runs;
+  // large grids take batches of at least about 8 ms.
+  const int reps = g->hg.ncells < (1LL << 21) ? 64 : 8;
   auto time_shape = [&](const TileShape& c, double& per) -> int {
     g->shape = c;
     int e = upload_tiles(g);
@@ -524,6 +525,14 @@ extern "C" int fv_tune(fv_grid* g, const fv_params* p, const char* cache_path) {
                           hipMemcpyHostToDevice, g->stream));
     return e;
   };
+  // The GPU's clocks rise over tens of milliseconds of load: the first
+  // candidate runs untimed for about 60 ms of steps before anything counts
+  // (timed from idle, the first candidates would be measured on the ramp).
+  for (int w = 0, done = 0; w < 32 && done < 60 && !st; ++w) {
+    double per = 0.0;
+    st = time_shape(cands[0], per);
+    done += (int)(per * 4 * reps);
+  }
   // pass 1 over every candidate; pass 2 times the three fastest again in the
   // reverse order (so that a drift of the clocks during tuning cancels) and
   // each keeps its better time
