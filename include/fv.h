@@ -67,9 +67,10 @@ enum {
  *   PERIODIC  ghost = interior cell the same distance in from the opposite
  *             face of the same block
  *   BLOCK     ghost = interior cell of block nbr_block, the same distance in
- *             from its face nbr_face, which must be the opposite face of the
- *             same direction with the same transverse extents (1:1 points,
- *             same orientation)
+ *             from its face nbr_face (1:1 points).  2D: nbr_face is the
+ *             opposite face of the same direction, same orientation.  3D:
+ *             any face, with the transverse indices mapped by orient (see
+ *             fv_bc); the transverse extents must agree under that map
  *   INFLOW    ghost = conserved state of prim_in = (rho, u, v, w, p)
  *   EXTRAP    ghost = nearest interior cell (zeroth-order extrapolation)
  *   SLIPWALL  ghost layer g = interior cell g-1 from the wall with its
