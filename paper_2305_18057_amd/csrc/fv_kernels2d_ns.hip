@@ -305,14 +305,6 @@ __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, 
       L.nx[r][c] = xx;
       L.ny[r][c] = yy;
     }
-    // cell centres of the slab and its ring (ghost centres by their rule)
-    for (int x = tid; x < (nr + 2) * (nc + 2); x += kNsThreads) {
-      const int r = x / (nc + 2), c = x - r * (nc + 2);
-      double cx, cy;
-      ns_centre(blocks, B, i0 - 1 + c, js - 1 + r, cx, cy);
-      L.cx[r][c] = cx;
-      L.cy[r][c] = cy;
-    }
     if constexpr (SK::reads_un) {
       for (int x = tid; x < nr * nc; x += kNsThreads) {
         const int r = x / nc, c = x - r * nc;
@@ -322,8 +314,21 @@ __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, 
       }
     }
     __syncthreads();
+    // u, v, p/rho and the centres of the slab's cells and their ring: a
+    // centre inside the block from the staged nodes (the four around it, in
+    // the order of centre_of), a ghost centre by its rule
     for (int x = tid; x < (nr + 2) * (nc + 2); x += kNsThreads) {
       const int r = x / (nc + 2), c = x - r * (nc + 2);
+      const int ci = i0 - 1 + c, cj = js - 1 + r;
+      double cx, cy;
+      if (ci >= 0 && ci < ni && cj >= 0 && cj < B.nj) {
+        cx = 0.25 * (((L.nx[r][c] + L.nx[r][c + 1]) + L.nx[r + 1][c]) + L.nx[r + 1][c + 1]);
+        cy = 0.25 * (((L.ny[r][c] + L.ny[r][c + 1]) + L.ny[r + 1][c]) + L.ny[r + 1][c + 1]);
+      } else {
+        ns_centre(blocks, B, ci, cj, cx, cy);
+      }
+      L.cx[r][c] = cx;
+      L.cy[r][c] = cy;
       const double rho = L.u.s.q[0][r + 1][c + 1];
       const double ir = M<double>::rcp(rho);
       const double u = L.u.s.q[1][r + 1][c + 1] * ir, v = L.u.s.q[2][r + 1][c + 1] * ir;

@@ -256,3 +256,14 @@ def test_ns_inlet_full_size_split(env):
         case.blocks[0].bc[f] = CS.BC(CS.NOSLIP)
     case.params = with_(case.params, mu=1.5e-2, prandtl=0.72)
     check(fv, O, case, 2048 - 32, 8, 6)
+
+
+def test_ns_workers_do_not_change_results(env):
+    """The viscous host part too: 1 and 5 host workers give bitwise the same
+    state and norms (rows are dealt out, summed in row order)."""
+    fv, _ = env
+    case = ns_curved()
+    h1, i1 = hetero_run(fv, case, 60, 1, 8)
+    h5, i5 = hetero_run(fv, case, 60, 5, 8)
+    assert np.array_equal(h1.get_state(), h5.get_state())
+    assert i1["norm"] == i5["norm"] and i1["t"] == i5["t"]
