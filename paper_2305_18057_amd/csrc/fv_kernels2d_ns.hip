@@ -350,9 +350,9 @@ __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, 
       for (int k = 0; k < 3; ++k)
         o[k] = 0.25 * (((L.u.s.w[k][r - 1][c - 1] + L.u.s.w[k][r - 1][c]) + L.u.s.w[k][r][c - 1]) + L.u.s.w[k][r][c]);
     };
-    // i-face at node column fc (0..nc) of slab row lj
-    auto iface = [&](int fc, double (&F)[4]) {
-      const int qr = lj + 2, wr = lj + 1;
+    // i-face at node column fc (0..nc) of slab row `row`
+    auto iface = [&](int fc, int row, double (&F)[4]) {
+      const int qr = row + 2, wr = row + 1;
       double c0[4], c1[4], c2[4], c3[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
@@ -362,8 +362,8 @@ __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, 
         c3[v] = L.u.s.q[v][qr][fc + 3];
       }
       // area vector: from the nodes, or exactly h_y e_x on a uniform block
-      const double Sx = B.xn ? L.ny[lj + 2][fc + 1] - L.ny[lj + 1][fc + 1] : B.area[0];
-      const double Sy = B.xn ? -(L.nx[lj + 2][fc + 1] - L.nx[lj + 1][fc + 1]) : 0.0;
+      const double Sx = B.xn ? L.ny[row + 2][fc + 1] - L.ny[row + 1][fc + 1] : B.area[0];
+      const double Sy = B.xn ? -(L.nx[row + 2][fc + 1] - L.nx[row + 1][fc + 1]) : 0.0;
       T G[4];
       inv_flux<LIM, T>(rc, K, c0, c1, c2, c3, Sx, Sy, G);
 #pragma unroll
@@ -418,20 +418,23 @@ __device__ void tile_ns(const DevTile& tl, const DevBlock* __restrict__ blocks, 
       }
     };
     double Fl[4], Fb[4], qin[4];
-    if (act) {
-      if (li == nc - 1) {
-        double Fr[4];
-        iface(nc, Fr);
+    // the slab's right-edge i-faces, one row per lane, in wave 0, and its
+    // top-edge j-faces in the top row's wave: each edge costs one wave-wide
+    // flux, where a right-edge face in every wave's last lane cost four
+    if (wv == 0 && lane < nr) {
+      double Fr[4];
+      iface(nc, lane, Fr);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) L.er[v][lj] = Fr[v];
-      }
+      for (int v = 0; v < 4; ++v) L.er[v][lane] = Fr[v];
+    }
+    if (act) {
       if (lj == nr - 1) {
         double Ft[4];
         jface(nr, Ft);
 #pragma unroll
         for (int v = 0; v < 4; ++v) L.et[v][li] = Ft[v];
       }
-      iface(li, Fl);
+      iface(li, lj, Fl);
       jface(lj, Fb);
 #pragma unroll
       for (int v = 0; v < 4; ++v) qin[v] = L.u.s.q[v][lj + 2][li + 2];
