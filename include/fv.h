@@ -181,7 +181,7 @@ typedef struct fv_params {
                           (0 entries count as 1) */
   double mu;           /* dynamic viscosity: > 0 adds the viscous normal flux
                           F_{nu,n} of Sec. 2 to Eq. (residual) (2D grids only;
-                          FV_E_UNSUPPORTED in 3D and on the server).  Stokes's
+                          FV_E_UNSUPPORTED in 3D).  Stokes's
                           hypothesis with constant mu; heat flux by Fourier's law
                           with k = mu c_p / prandtl, i.e. k grad T =
                           (mu/prandtl) gamma/(gamma-1) grad(p/rho); face gradients
@@ -378,9 +378,13 @@ typedef struct fv_server fv_server;
 int fv_server_create(const fv_server_desc* desc, fv_server** out);
 /* Queue a solve (thread-safe): grid, initial state (host), parameters,
  * stop rule (drop <= drop_tol or max_steps steps).  The descriptor and U0
- * are copied.  FV_E_NOMEM if the request can never fit the arena;
- * FV_E_UNSUPPORTED for rk other than 3 (resident instances share one stage
- * sequence). */
+ * are copied.  Any grid of the grid API except one with a source: 2D Euler
+ * and Navier-Stokes (a viscosity or a no-slip face), uniform and general 3D
+ * (curvilinear blocks, oriented links); each kind of grid has its own tile
+ * list and stage kernel in the batched launches.  FV_E_NOMEM if the request
+ * can never fit the arena; FV_E_UNSUPPORTED for rk other than 3 (resident
+ * instances share one stage sequence), a source (with_source), or a
+ * viscosity on a 3D grid. */
 int fv_submit(fv_server* s, const fv_grid_desc* desc, const double* U0, const fv_params* p,
               double drop_tol, long long max_steps, unsigned long long* ticket);
 /* FV_PENDING until done; then the final state (host, cap_doubles >= state

@@ -14,7 +14,10 @@ namespace fvexec {
 
 // tile sets: 2D, 3D with 3 j-rows per tile (4-wave workgroups), 3D with 7
 // (8 waves), general 3D (curvilinear blocks or a source; 4 j-rows, 4 waves)
-enum { kSet2D = 0, kSet3D3 = 1, kSet3D7 = 2, kSet3DG = 3 };
+// kSet2DNS: 2D tiles that always take the Navier-Stokes stage kernel (the
+// server's viscous instances; a grid's own plan chooses by StepPlan::ns)
+enum { kSet2D = 0, kSet3D3 = 1, kSet3D7 = 2, kSet3DG = 3, kSet2DNS = 4 };
+constexpr int kSetKinds = 5;
 // the set kind of a grid: 2D, general 3D, or uniform 3D by its tile rows
 inline int set_kind(int ndim, bool general3d, int ny) {
   if (ndim == 2) return kSet2D;

@@ -36,7 +36,7 @@ static bool graphs_enabled() {
 int launch_grid(const LaunchSet& s, int fp32, bool ns) {
   if (s.ntiles <= 0) return 0;
   int cap;
-  if (s.kind == kSet2D && ns) {
+  if ((s.kind == kSet2D && ns) || s.kind == kSet2DNS) {
     // one 256-thread workgroup per tile
     cap = fvrt::occupancy_blocks(fvk::stage2d_ns_kernel_ptr(fp32), 256);
     cap = std::min(cap, s.ntiles);
@@ -65,7 +65,7 @@ int enqueue_stage(const StepPlan& P, int mode, int fp32, double* rout, hipStream
     const int grid = launch_grid(s, fp32, P.ns);
     const int nfix = s.count_fixed ? s.ntiles : -1;
     hipError_t e;
-    if (s.kind == kSet2D && P.ns)
+    if ((s.kind == kSet2D && P.ns) || s.kind == kSet2DNS)
       e = fvk::launch_stage2d_ns(mode, fp32, grid, st, s.tiles, s.ntiles_dev, nfix, P.blocks, P.insts,
                                  rout);
     else if (s.kind == kSet2D)
@@ -87,7 +87,7 @@ int enqueue_cfl(const StepPlan& P, hipStream_t st) {
   for (const LaunchSet& s : P.sets) {
     if (s.ntiles <= 0) continue;
     hipError_t e;
-    if (s.kind == kSet2D)
+    if (s.kind == kSet2D || s.kind == kSet2DNS)
       e = fvk::launch_cfl2d(std::max(1, std::min((s.ntiles + 3) / 4, 4096)), 256, st, s.tiles,
                             s.ntiles_dev, P.blocks, P.insts);
     else

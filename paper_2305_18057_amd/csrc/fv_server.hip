@@ -31,7 +31,7 @@ using namespace fvrt;
 namespace {
 
 constexpr int kMaxBlocksPerInst = 64;
-constexpr int kKinds = 3;
+constexpr int kKinds = fvexec::kSetKinds;
 
 enum ReqState { RQ_QUEUED = 0, RQ_RESIDENT = 1, RQ_DONE = 2 };
 
@@ -127,11 +127,11 @@ struct fv_server {
   int* d_active = nullptr;
   int* d_newlist = nullptr;
   int* d_counts = nullptr;  // ntiles per kind, then the live instance count
-  fvk::DevTile* d_tiles[kKinds] = {nullptr, nullptr, nullptr};
+  fvk::DevTile* d_tiles[kKinds] = {};
   Arena heap;
   std::vector<fvk::DevInstance> h_inst;
   std::vector<Request*> slot_req;
-  long long tiles_in_use[kKinds] = {0, 0, 0};
+  long long tiles_in_use[kKinds] = {};
   // requests
   std::mutex mu;
   std::condition_variable cv;
@@ -152,8 +152,11 @@ struct fv_server {
 
 namespace {
 
-int kind_of(const HostGrid& g, const TileShape& sh) {
-  if (g.ndim == 2) return fvexec::kSet2D;
+// the tile list (and stage kernel) of an instance: 2D Euler or Navier-Stokes,
+// general 3D (curvilinear blocks or oriented links), or uniform 3D by tile rows
+int kind_of(const HostGrid& g, const TileShape& sh, bool ns) {
+  if (g.ndim == 2) return ns ? fvexec::kSet2DNS : fvexec::kSet2D;
+  if (g.gen3) return fvexec::kSet3DG;
   return sh.ny >= 7 ? fvexec::kSet3D7 : fvexec::kSet3D3;
 }
 
@@ -223,7 +226,8 @@ int rebuild_lists(fv_server* S, const std::vector<Request*>& resident) {
       lists[r->kind].push_back(t);
     }
   }
-  int counts[4] = {0, 0, 0, (int)active.size()};
+  int counts[kKinds + 1] = {};
+  counts[kKinds] = (int)active.size();
   for (int k = 0; k < kKinds; ++k) {
     counts[k] = (int)lists[k].size();
     if (counts[k])
@@ -245,7 +249,7 @@ fvexec::StepPlan plan_of(fv_server* S, unsigned mask) {
   P.insts = S->d_inst;
   P.active = S->d_active;
   P.ninst = S->max_inst;
-  P.ninst_dev = S->d_counts + 3;
+  P.ninst_dev = S->d_counts + kKinds;
   for (int k = 0; k < kKinds; ++k) {
     if (!(mask & (1u << k))) continue;
     fvexec::LaunchSet ls;
@@ -470,7 +474,7 @@ extern "C" int fv_server_create(const fv_server_desc* d, fv_server** out) {
   const size_t o_new = off;
   off += align_up(sizeof(int) * S->max_inst);
   const size_t o_cnt = off;
-  off += align_up(sizeof(int) * 4);
+  off += align_up(sizeof(int) * (kKinds + 1));
   size_t o_t[kKinds];
   for (int k = 0; k < kKinds; ++k) {
     o_t[k] = off;
@@ -494,7 +498,7 @@ extern "C" int fv_server_create(const fv_server_desc* d, fv_server** out) {
     S->d_newlist = (int*)(S->arena + o_new);
     S->d_counts = (int*)(S->arena + o_cnt);
     for (int k = 0; k < kKinds; ++k) S->d_tiles[k] = (fvk::DevTile*)(S->arena + o_t[k]);
-    int zero[4] = {0, 0, 0, 0};
+    int zero[kKinds + 1] = {};
     std::vector<fvk::DevInstance> blank(S->max_inst);
     std::memset(blank.data(), 0, sizeof(fvk::DevInstance) * blank.size());
     for (auto& I : blank) I.stopped = 1;
@@ -520,9 +524,6 @@ extern "C" int fv_submit(fv_server* S, const fv_grid_desc* desc, const double* U
   if (st) return st;
   // resident instances share graph replays of one stage sequence
   if (rk_of(p) != 3) return set_error(FV_E_UNSUPPORTED, "the server runs SSP-RK3 (rk = 3) only");
-  if (p->mu > 0.0)
-    return set_error(FV_E_UNSUPPORTED, "the server runs the Euler stage kernels: viscous solves go "
-                                       "through fv_step / fv_solve");
   if (max_steps < 1) return set_error(FV_E_INVAL, "max_steps must be >= 1");
   if (!(drop_tol >= 0.0)) return set_error(FV_E_INVAL, "drop_tol must be >= 0");
   Request* r = new (std::nothrow) Request();
@@ -536,17 +537,17 @@ extern "C" int fv_submit(fv_server* S, const fv_grid_desc* desc, const double* U
     delete r;
     return set_error(FV_E_UNSUPPORTED, "at most %d blocks per served grid", kMaxBlocksPerInst);
   }
-  if (r->hg.has_noslip) {
+  if (p->mu > 0.0 && r->hg.ndim != 2) {
     delete r;
-    return set_error(FV_E_UNSUPPORTED, "the server runs the Euler stage kernels: grids with no-slip "
-                                       "walls go through fv_step / fv_solve");
+    return set_error(FV_E_UNSUPPORTED, "the viscous flux is provided for 2D grids only");
   }
-  if (r->hg.with_source || r->hg.gen3) {
+  if (r->hg.with_source) {
     delete r;
-    return set_error(FV_E_UNSUPPORTED, "the server runs the Euler stage kernels of uniform 3D and "
-                                       "2D grids: 3D curvilinear grids and source terms go through "
-                                       "fv_step / fv_solve");
+    return set_error(FV_E_UNSUPPORTED, "served grids take no source term (fv_set_source is a grid "
+                                       "call): solves with a source go through fv_step / fv_solve");
   }
+  // 2D instances with a viscosity or a no-slip face take the Navier-Stokes kernel
+  const bool ns = r->hg.ndim == 2 && (p->mu > 0.0 || r->hg.has_noslip);
   r->U0.assign(U0, U0 + r->hg.state_size);
   r->params = *p;
   r->params.precision = S->d.precision;
@@ -555,10 +556,10 @@ extern "C" int fv_submit(fv_server* S, const fv_grid_desc* desc, const double* U
   TileShape sh = default_shape(r->hg);
   TileShape tsh;
   if (tune_lookup(tune_path(S->tune_path.empty() ? nullptr : S->tune_path.c_str()),
-                  tune_key(r->hg, S->d.precision), tsh))
+                  tune_key(r->hg, S->d.precision, ns), tsh))
     sh = tsh;
   r->shape = sh;
-  r->kind = kind_of(r->hg, sh);
+  r->kind = kind_of(r->hg, sh, ns);
   build_tiles(r->hg, sh, 0, 0, r->tiles);
   region_layout(r);
   if (r->footprint > S->heap_cap || (long long)r->tiles.size() > (long long)S->tile_cap) {

@@ -202,3 +202,36 @@ def test_continuous_admission_under_load(env):
     assert all(res[t][0] == fv.FV_OK for t in ts)
     assert [res[t][2]["steps"] for t in ts] == [15 + 3 * k for k in range(12)]
     assert s["admitted"] == 12 and s["launches"] > 0 and s["arena_used"] == 0
+
+
+def test_served_viscous_and_general_3d_mixed(env):
+    """Navier-Stokes instances (a viscosity and no-slip walls, six linked
+    blocks), a 3D curvilinear grid and blocks in rotated frames joined by
+    oriented links, served together with an Euler instance (four tile lists
+    in each batched launch): each bitwise equal to the same grid stepped
+    alone, and within the FP64 bar of the oracle."""
+    fv, O = env
+    from tests.test_gpu_ns import curved_channel
+    from tests.test_gpu_curv3d import rotated
+    c3 = CS.curv3d_case(ni=100, nj=9, nk=11, nblocks=2, amp=0.06, state="random", seed=22)
+    jobs = [(curved_channel(), 17), (c3, 13), (rotated("reversed", walls=True), 11),
+            (CS.inlet_case(256, 64, 4, angle_deg=5.0), 15)]
+    srv = fv.Server(arena_bytes=512 << 20, max_instances=4, precision=CS.FP64, steps_per_launch=10)
+    ts = [srv.submit(c, params=c.params, drop_tol=0.0, max_steps=n) for c, n in jobs]
+    res = drain(srv, ts, timeout=300.0)
+    srv.close()
+    for (c, n), t in zip(jobs, ts):
+        st, U, info = res[t]
+        assert st == fv.FV_OK and info["steps"] == n, (c.name, st, info["steps"])
+        g = fv.Grid(c)
+        g.set_state(c.state_flat())
+        g.step(c.params, n)
+        Ug = g.get_state()
+        g.close()
+        ref = O.OracleGrid(c)
+        ref.run(c.params, n)
+        e = P.state_err(c, U, ref.get_state())
+        P.report("test_served_viscous_and_general_3d_mixed",
+                 f"served {c.name} {n} steps: e_U = {e:.3e}, bitwise = grid: {np.array_equal(U, Ug)}")
+        assert np.array_equal(U, Ug), c.name
+        assert e <= P.FP64_TOL, (c.name, e)

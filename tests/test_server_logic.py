@@ -130,39 +130,43 @@ def test_request_times_and_unknown_ticket(fvb):
     srv.close()
 
 
-def test_server_refuses_viscous_solves(fvb):
-    """The server batches the Euler stage kernels; a viscosity or a no-slip
-    wall is for grids (fv_step / fv_solve), and the server says so."""
-    srv = fvb.Server(arena_bytes=32 << 20, max_instances=4, dry_run=True)
-    case = CS.inlet_case(64, 64, 1)
-    prm = CS.Params(**{**case.params.__dict__, "mu": 1e-3})
-    with pytest.raises(fvb.FVError) as e:
-        srv.submit(case, params=prm, max_steps=10)
-    assert e.value.status == fvb.FV_E_UNSUPPORTED
-    case.blocks[0].bc[2] = CS.BC(CS.NOSLIP)
-    with pytest.raises(fvb.FVError) as e:
-        srv.submit(case, max_steps=10)
-    assert e.value.status == fvb.FV_E_UNSUPPORTED
+def test_server_takes_viscous_and_general_3d_grids(fvb):
+    """Viscous 2D solves, no-slip walls, 3D curvilinear grids and oriented
+    block links are served (the Navier-Stokes and the general 3D stage
+    kernels run their own tile lists); every request completes in the dry
+    run with its exact step count."""
+    srv = fvb.Server(arena_bytes=64 << 20, max_instances=4, steps_per_launch=5, dry_run=True)
+    visc = CS.inlet_case(64, 64, 1)
+    prm = CS.Params(**{**visc.params.__dict__, "mu": 1e-3})
+    wall = CS.inlet_case(64, 32, 2)
+    wall.blocks[0].bc[2] = CS.BC(CS.NOSLIP)
+    jobs = [(visc, prm, 12), (wall, None, 9),
+            (CS.curv3d_case(ni=16, nj=8, nk=8, nblocks=2, state="random"), None, 7),
+            (CS.twisted_box_3d(12), None, 11), (CS.inlet_case(64, 32, 1), None, 6)]
+    tickets = [srv.submit(c, params=p, max_steps=n) for c, p, n in jobs]
+    res = wait_all(srv, tickets)
+    for (c, p, n), t in zip(jobs, tickets):
+        st, U, info = res[t]
+        assert st == fvb.FV_OK and info["steps"] == n
     srv.close()
 
 
-def test_server_refuses_curvilinear_3d_and_sources(fvb):
-    """3D curvilinear grids, source terms and oriented block links run the
-    general stage kernels of the grid API; the server refuses them with
-    FV_E_UNSUPPORTED."""
+def test_server_refuses_sources_and_3d_viscosity(fvb):
+    """A source term is a grid call (fv_set_source) and the viscous flux is
+    2D: the server refuses both with FV_E_UNSUPPORTED."""
     srv = fvb.Server(arena_bytes=64 << 20, max_instances=4, dry_run=True)
-    for state in ("random", "mms"):
-        case = CS.curv3d_case(ni=16, nj=8, nk=8, nblocks=2, state=state)
-        with pytest.raises(fvb.FVError) as e:
-            srv.submit(case, max_steps=10)
-        assert e.value.status == fvb.FV_E_UNSUPPORTED
     c2 = CS.inlet_case(64, 64, 1)
     c2.source = [np.zeros_like(u) for u in c2.U0]
     with pytest.raises(fvb.FVError) as e:
         srv.submit(c2, max_steps=10)
     assert e.value.status == fvb.FV_E_UNSUPPORTED
-    # oriented block links (uniform blocks too) also take the general kernel
+    case = CS.curv3d_case(ni=16, nj=8, nk=8, nblocks=2, state="mms")
     with pytest.raises(fvb.FVError) as e:
-        srv.submit(CS.twisted_box_3d(12), max_steps=10)
+        srv.submit(case, max_steps=10)
+    assert e.value.status == fvb.FV_E_UNSUPPORTED
+    c3 = CS.blobs_case(8, nblobs=1)
+    p3 = CS.Params(**{**c3.params.__dict__, "mu": 1e-3})
+    with pytest.raises(fvb.FVError) as e:
+        srv.submit(c3, params=p3, max_steps=10)
     assert e.value.status == fvb.FV_E_UNSUPPORTED
     srv.close()
