@@ -378,15 +378,22 @@ typedef struct fv_server fv_server;
 int fv_server_create(const fv_server_desc* desc, fv_server** out);
 /* Queue a solve (thread-safe): grid, initial state (host), parameters,
  * stop rule (drop <= drop_tol or max_steps steps).  The descriptor and U0
- * are copied.  Any grid of the grid API except one with a source: 2D Euler
- * and Navier-Stokes (a viscosity or a no-slip face), uniform and general 3D
- * (curvilinear blocks, oriented links); each kind of grid has its own tile
- * list and stage kernel in the batched launches.  FV_E_NOMEM if the request
- * can never fit the arena; FV_E_UNSUPPORTED for rk other than 3 (resident
- * instances share one stage sequence), a source (with_source), or a
- * viscosity on a 3D grid. */
+ * are copied.  Any grid of the grid API: 2D Euler and Navier-Stokes (a
+ * viscosity or a no-slip face), uniform and general 3D (curvilinear blocks,
+ * oriented links); each kind of grid has its own tile list and stage kernel
+ * in the batched launches.  A descriptor with with_source = 1 goes through
+ * fv_submit_with_source (FV_E_INVAL here).  FV_E_NOMEM if the request can
+ * never fit the arena; FV_E_UNSUPPORTED for rk other than 3 (resident
+ * instances share one stage sequence) or a viscosity on a 3D grid. */
 int fv_submit(fv_server* s, const fv_grid_desc* desc, const double* U0, const fv_params* p,
               double drop_tol, long long max_steps, unsigned long long* ticket);
+/* fv_submit for a grid with a cell-averaged source S_h of Eq. (residual)
+ * (Sec. 3.1; the residual gains - |Omega| S_h): desc->with_source must be 1
+ * (FV_E_INVAL otherwise); S_h is host memory in the state layout, copied
+ * with U0 and held in the instance's arena region. */
+int fv_submit_with_source(fv_server* s, const fv_grid_desc* desc, const double* U0,
+                          const double* S_h, const fv_params* p, double drop_tol,
+                          long long max_steps, unsigned long long* ticket);
 /* FV_PENDING until done; then the final state (host, cap_doubles >= state
  * size) and its info, and the request's own status.  Thread-safe. */
 int fv_poll(fv_server* s, unsigned long long ticket, double* U_out, size_t cap_doubles,

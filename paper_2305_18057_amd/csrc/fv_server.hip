@@ -39,6 +39,7 @@ struct Request {
   unsigned long long ticket = 0;
   HostGrid hg;
   std::vector<double> U0;
+  std::vector<double> src;  // S_h in the state layout (grids with a source)
   fv_params params{};
   double drop_tol = 0.0;
   long long max_steps = 0;
@@ -47,7 +48,7 @@ struct Request {
   std::vector<fvk::DevTile> tiles;  // local indices; slot and block offset filled at admission
   std::vector<fvk::DevBlock> blocks;  // device descriptors (kept until the copy has run)
   size_t footprint = 0;
-  size_t off_part = 0, off_nodes = 0, off_u[3] = {0, 0, 0};
+  size_t off_part = 0, off_nodes = 0, off_src = 0, off_u[3] = {0, 0, 0};
   // life cycle
   int state = RQ_QUEUED;
   int status = FV_OK;
@@ -168,6 +169,8 @@ void region_layout(Request* r) {
   off += align_up(sizeof(double) * fvk::kPartStride * std::max<size_t>(1, r->tiles.size()));
   r->off_nodes = off;
   off += align_up(sizeof(double) * (size_t)r->hg.node_doubles);
+  r->off_src = off;
+  off += r->hg.with_source ? align_up(sizeof(double) * (size_t)r->hg.state_size) : 0;
   for (int s = 0; s < 3; ++s) {
     r->off_u[s] = off;
     off += align_up(sizeof(double) * (size_t)r->hg.state_size);
@@ -190,11 +193,15 @@ int upload(fv_server* S, Request* r) {
   const int boff = slot * kMaxBlocksPerInst;
   InstLayout L{};
   L.nodes = r->off_nodes;
+  L.src = r->off_src;
   for (int s = 0; s < 3; ++s) L.u[s] = r->off_u[s];
   build_blocks(r->hg, base, L, slot, r->blocks, boff);
   FV_HIP(hipMemcpyAsync(S->d_blocks + boff, r->blocks.data(), sizeof(fvk::DevBlock) * r->blocks.size(),
                         hipMemcpyHostToDevice, S->stream));
   FV_HIP(upload_nodes(r->hg, base + r->off_nodes, S->stream));
+  if (r->hg.with_source)
+    FV_HIP(hipMemcpyAsync(base + r->off_src, r->src.data(), sizeof(double) * r->src.size(),
+                          hipMemcpyHostToDevice, S->stream));
   FV_HIP(hipMemcpyAsync(base + r->off_u[0], r->U0.data(), sizeof(double) * r->U0.size(),
                         hipMemcpyHostToDevice, S->stream));
   fvk::DevInstance I;
@@ -517,8 +524,10 @@ extern "C" int fv_server_create(const fv_server_desc* d, fv_server** out) {
   return FV_OK;
 }
 
-extern "C" int fv_submit(fv_server* S, const fv_grid_desc* desc, const double* U0, const fv_params* p,
-                         double drop_tol, long long max_steps, unsigned long long* ticket) {
+namespace {
+
+int submit(fv_server* S, const fv_grid_desc* desc, const double* U0, const double* src,
+           const fv_params* p, double drop_tol, long long max_steps, unsigned long long* ticket) {
   if (!S || !U0 || !ticket) return set_error(FV_E_INVAL, "null argument");
   int st = check_params(p);
   if (st) return st;
@@ -541,14 +550,18 @@ extern "C" int fv_submit(fv_server* S, const fv_grid_desc* desc, const double* U
     delete r;
     return set_error(FV_E_UNSUPPORTED, "the viscous flux is provided for 2D grids only");
   }
-  if (r->hg.with_source) {
+  if (r->hg.with_source != (src != nullptr)) {
     delete r;
-    return set_error(FV_E_UNSUPPORTED, "served grids take no source term (fv_set_source is a grid "
-                                       "call): solves with a source go through fv_step / fv_solve");
+    return set_error(FV_E_INVAL, r->hg.with_source
+                                     ? "a grid with with_source = 1 is submitted with its source "
+                                       "(fv_submit_with_source)"
+                                     : "fv_submit_with_source needs a descriptor with with_source = 1");
   }
-  // 2D instances with a viscosity or a no-slip face take the Navier-Stokes kernel
-  const bool ns = r->hg.ndim == 2 && (p->mu > 0.0 || r->hg.has_noslip);
+  // 2D instances with a viscosity, a no-slip face or a source take the
+  // Navier-Stokes kernel (the choice of the grid API)
+  const bool ns = r->hg.ndim == 2 && (p->mu > 0.0 || r->hg.has_noslip || r->hg.with_source);
   r->U0.assign(U0, U0 + r->hg.state_size);
+  if (src) r->src.assign(src, src + r->hg.state_size);
   r->params = *p;
   r->params.precision = S->d.precision;
   r->drop_tol = drop_tol;
@@ -580,6 +593,20 @@ extern "C" int fv_submit(fv_server* S, const fv_grid_desc* desc, const double* U
   *ticket = r->ticket;
   S->cv.notify_all();
   return FV_OK;
+}
+
+}  // namespace
+
+extern "C" int fv_submit(fv_server* S, const fv_grid_desc* desc, const double* U0, const fv_params* p,
+                         double drop_tol, long long max_steps, unsigned long long* ticket) {
+  return submit(S, desc, U0, nullptr, p, drop_tol, max_steps, ticket);
+}
+
+extern "C" int fv_submit_with_source(fv_server* S, const fv_grid_desc* desc, const double* U0,
+                                     const double* S_h, const fv_params* p, double drop_tol,
+                                     long long max_steps, unsigned long long* ticket) {
+  if (!S_h) return set_error(FV_E_INVAL, "null source");
+  return submit(S, desc, U0, S_h, p, drop_tol, max_steps, ticket);
 }
 
 extern "C" int fv_poll(fv_server* S, unsigned long long ticket, double* U_out, size_t cap,

@@ -88,7 +88,8 @@ EXPORTS = [
     "fv_residual",
     "fv_ghost_count", "fv_ghosts", "fv_step", "fv_step_timed", "fv_solve", "fv_tune",
     "fv_grid_get_stats",
-    "fv_server_create", "fv_submit", "fv_poll", "fv_cancel", "fv_request_times",
+    "fv_server_create", "fv_submit", "fv_submit_with_source", "fv_poll", "fv_cancel",
+    "fv_request_times",
     "fv_server_clock", "fv_server_get_stats", "fv_server_destroy",
     "fv_noalloc_scratch_bytes", "fv_step_noalloc",
     "fv_hetero_workspace_bytes", "fv_hetero_create", "fv_hetero_set_state", "fv_hetero_get_state",
@@ -139,6 +140,8 @@ def lib():
     L.fv_server_create.argtypes = [C.POINTER(fv_server_desc), C.POINTER(vp)]
     L.fv_submit.argtypes = [vp, C.POINTER(fv_grid_desc), dp, C.POINTER(fv_params), C.c_double,
                             C.c_longlong, C.POINTER(C.c_ulonglong)]
+    L.fv_submit_with_source.argtypes = [vp, C.POINTER(fv_grid_desc), dp, dp, C.POINTER(fv_params),
+                                        C.c_double, C.c_longlong, C.POINTER(C.c_ulonglong)]
     L.fv_poll.argtypes = [vp, C.c_ulonglong, dp, C.c_size_t, C.POINTER(fv_step_info)]
     L.fv_cancel.argtypes = [vp, C.c_ulonglong]
     L.fv_request_times.argtypes = [vp, C.c_ulonglong, dp]
@@ -419,8 +422,15 @@ class Server:
         U = np.ascontiguousarray(case.state_flat(), dtype=np.float64)
         p = make_params(params or case.params)
         t = C.c_ulonglong()
-        _check(lib().fv_submit(self._h, C.byref(gd.desc), U.ctypes.data_as(C.POINTER(C.c_double)),
-                               C.byref(p), float(drop_tol), int(max_steps), C.byref(t)))
+        Up = U.ctypes.data_as(C.POINTER(C.c_double))
+        if getattr(case, "source", None) is not None:
+            S = np.ascontiguousarray(case.source_flat(), dtype=np.float64)
+            _check(lib().fv_submit_with_source(self._h, C.byref(gd.desc), Up,
+                                               S.ctypes.data_as(C.POINTER(C.c_double)), C.byref(p),
+                                               float(drop_tol), int(max_steps), C.byref(t)))
+        else:
+            _check(lib().fv_submit(self._h, C.byref(gd.desc), Up, C.byref(p), float(drop_tol),
+                                   int(max_steps), C.byref(t)))
         self._sizes[t.value] = U.size
         return t.value
 

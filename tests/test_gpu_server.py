@@ -235,3 +235,32 @@ def test_served_viscous_and_general_3d_mixed(env):
                  f"served {c.name} {n} steps: e_U = {e:.3e}, bitwise = grid: {np.array_equal(U, Ug)}")
         assert np.array_equal(U, Ug), c.name
         assert e <= P.FP64_TOL, (c.name, e)
+
+
+def test_served_sources(env):
+    """Grids with a source S_h (fv_submit_with_source): the manufactured
+    solution on a 3D curvilinear box and a 2D vortex with a seeded source,
+    served with an Euler instance; each bitwise equal to the same grid with
+    its source stepped alone, and within the FP64 bar of the oracle."""
+    fv, O = env
+    from tests.test_gpu_curv3d import curv_mms, vortex_with_source
+    jobs = [(curv_mms(16), 9), (vortex_with_source(), 14), (CS.blobs_case(24, nblobs=2), 7)]
+    srv = fv.Server(arena_bytes=256 << 20, max_instances=3, precision=CS.FP64, steps_per_launch=4)
+    ts = [srv.submit(c, drop_tol=0.0, max_steps=n) for c, n in jobs]
+    res = drain(srv, ts, timeout=300.0)
+    srv.close()
+    for (c, n), t in zip(jobs, ts):
+        st, U, info = res[t]
+        assert st == fv.FV_OK and info["steps"] == n, (c.name, st)
+        g = fv.Grid(c)
+        g.set_state(c.state_flat())
+        g.step(c.params, n)
+        Ug = g.get_state()
+        g.close()
+        ref = O.OracleGrid(c)
+        ref.run(c.params, n)
+        e = P.state_err(c, U, ref.get_state())
+        P.report("test_served_sources", f"served {c.name} {n} steps: e_U = {e:.3e}, bitwise = grid: "
+                 f"{np.array_equal(U, Ug)}")
+        assert np.array_equal(U, Ug), c.name
+        assert e <= P.FP64_TOL, (c.name, e)

@@ -151,22 +151,37 @@ def test_server_takes_viscous_and_general_3d_grids(fvb):
     srv.close()
 
 
-def test_server_refuses_sources_and_3d_viscosity(fvb):
-    """A source term is a grid call (fv_set_source) and the viscous flux is
-    2D: the server refuses both with FV_E_UNSUPPORTED."""
-    srv = fvb.Server(arena_bytes=64 << 20, max_instances=4, dry_run=True)
+def test_server_sources_and_3d_viscosity(fvb):
+    """A grid with a source is served through fv_submit_with_source (the
+    binding passes the case's source); fv_submit refuses such a descriptor
+    and fv_submit_with_source one without it (FV_E_INVAL); a viscosity on a
+    3D grid is FV_E_UNSUPPORTED."""
+    import ctypes as C
+    L = fvb.lib()
+    srv = fvb.Server(arena_bytes=64 << 20, max_instances=4, steps_per_launch=4, dry_run=True)
     c2 = CS.inlet_case(64, 64, 1)
     c2.source = [np.zeros_like(u) for u in c2.U0]
+    c3 = CS.curv3d_case(ni=16, nj=8, nk=8, nblocks=2, state="mms")
+    ts = [srv.submit(c2, max_steps=9), srv.submit(c3, max_steps=6)]
+    res = wait_all(srv, ts)
+    assert [res[t][2]["steps"] for t in ts] == [9, 6]
+    gd = fvb.GridDesc(c3)
+    U = np.ascontiguousarray(c3.state_flat())
+    p = fvb.make_params(c3.params)
+    t = C.c_ulonglong()
+    dp = C.POINTER(C.c_double)
+    assert L.fv_submit(srv._h, C.byref(gd.desc), U.ctypes.data_as(dp), C.byref(p), 0.0, 5,
+                       C.byref(t)) == fvb.FV_E_INVAL
+    assert b"fv_submit_with_source" in L.fv_last_error()
+    c0 = CS.inlet_case(64, 32, 1)
+    g0 = fvb.GridDesc(c0)
+    U0 = np.ascontiguousarray(c0.state_flat())
+    assert L.fv_submit_with_source(srv._h, C.byref(g0.desc), U0.ctypes.data_as(dp),
+                                   U0.ctypes.data_as(dp), C.byref(p), 0.0, 5,
+                                   C.byref(t)) == fvb.FV_E_INVAL
+    c3v = CS.blobs_case(8, nblobs=1)
+    p3 = CS.Params(**{**c3v.params.__dict__, "mu": 1e-3})
     with pytest.raises(fvb.FVError) as e:
-        srv.submit(c2, max_steps=10)
-    assert e.value.status == fvb.FV_E_UNSUPPORTED
-    case = CS.curv3d_case(ni=16, nj=8, nk=8, nblocks=2, state="mms")
-    with pytest.raises(fvb.FVError) as e:
-        srv.submit(case, max_steps=10)
-    assert e.value.status == fvb.FV_E_UNSUPPORTED
-    c3 = CS.blobs_case(8, nblobs=1)
-    p3 = CS.Params(**{**c3.params.__dict__, "mu": 1e-3})
-    with pytest.raises(fvb.FVError) as e:
-        srv.submit(c3, params=p3, max_steps=10)
+        srv.submit(c3v, params=p3, max_steps=10)
     assert e.value.status == fvb.FV_E_UNSUPPORTED
     srv.close()
