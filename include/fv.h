@@ -156,9 +156,10 @@ typedef struct fv_grid_desc {
   double gamma;                 /* ratio of specific heats */
   int with_source;              /* 1: reserve a cell-averaged source S_h (Sec. 2,
                                    the source term; Sec. 3.1, Eq. (residual)),
-                                   zero until fv_set_source; 0: none.  Grid API
-                                   only (FV_E_UNSUPPORTED on the server and in
-                                   fv_step_noalloc). */
+                                   zero until fv_set_source; 0: none.  The
+                                   server takes it with fv_submit_with_source;
+                                   fv_step_noalloc refuses it
+                                   (FV_E_UNSUPPORTED). */
 } fv_grid_desc;
 
 typedef struct fv_params {
