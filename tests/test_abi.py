@@ -82,8 +82,7 @@ def test_workspace_bytes_and_validation(fvb):
 def test_curvilinear_3d_and_source_descriptors(fvb):
     """3D node coordinates and the source buffer enter the workspace size;
     a 2D z, non-finite nodes or a bad with_source flag are refused; the
-    allocation-free path and the server refuse a source (and the server 3D
-    curvilinear grids) before any device work."""
+    allocation-free path refuses a source before any device work."""
     L = fvb.lib()
     c = CS.curv3d_case(ni=16, nj=8, nk=8, nblocks=2, state="random")
     gd = fvb.GridDesc(c)
