@@ -294,11 +294,13 @@ def bench_hetero(fv, cases, tune_cache, steps=20, workers=16, viscous=False):
     inlet-like grid as one 2048 x 256 block, FP64, with the Euler solver or
     (viscous) the Navier-Stokes solver of the viscous inlet workload (no-slip
     walls, mu = 1.5e-2; Sec. 8 measures both): the pure-GPU step time, one
-    host core's time per cell t_I, a sweep of the workload ratio r (the
-    cells of the GPU over the cells of one of `workers` host workers) with
-    the measured time per step, and the model of Sec. 6 fitted to the sweep
-    (r_gc from the pure modes, kappa = (1 + alpha) beta by least squares;
-    alpha quoted for the paper's beta range 0.2 .. 0.5)."""
+    host core's time per cell, a sweep of the workload ratio r (the cells
+    of the GPU over the cells of one of `workers` host workers) with the
+    measured time per step, and the model of Sec. 6 fitted to the sweep:
+    t_I is the rate of one worker among `workers` (the slope of the host
+    part's time over its cells per worker), r_gc the pure GPU's speed over
+    that, kappa = (1 + alpha) beta by least squares; alpha quoted for the
+    paper's beta range 0.2 .. 0.5."""
     from paper_2305_18057_amd import perfmodel as PM
     c = cases.inlet_case(2048, 256, 1, name="inlet_2d_ns_1block" if viscous else "inlet_2d_1block")
     if viscous:
@@ -321,10 +323,10 @@ def bench_hetero(fv, cases, tune_cache, steps=20, workers=16, viscous=False):
         h.close()
         return [t / n * 1e-3 for t in info["times_ms"]]
 
-    # one host core: t_I from the host part's substep time of 16 columns
+    # one host core: its time per cell-step from the host part's substep time
+    # of 16 columns (context; the model takes the workers' own rate, below)
     one = run(Nl - 16, 1)
-    tI = one[1] / (16 * Nw)
-    r_gc = N * tI / t_gpu
+    tI_core = one[1] / (16 * Nw)
     rows = []
     for nc in (2, 4, 8, 16, 32, 64, 128):
         split = Nl - nc
@@ -334,6 +336,14 @@ def bench_hetero(fv, cases, tune_cache, steps=20, workers=16, viscous=False):
                          gpu_ms=round(tm[0] * 1e3, 4), host_ms=round(tm[1] * 1e3, 4),
                          exchange_ms=round(tm[2] * 1e3, 4),
                          ssspnt=round(1e-6 * N * 3 / tm[3], 2)))
+    # t_I of one of the `workers` running together: the slope of the host
+    # part's time per step over its cells per worker (the intercept is the
+    # pool's own per-step cost).  The model's C workers each take t_I per
+    # cell, so the rate they reach together on this host is the one to use.
+    n_w = np.array([x["cpu_columns"] * Nw / workers for x in rows])
+    t_h = np.array([x["host_ms"] * 1e-3 for x in rows])
+    tI, host_fixed = (float(v) for v in np.polyfit(n_w, t_h, 1))
+    r_gc = N * tI / t_gpu
     fit = PM.fit_kappa(Nl, Nw, 1, workers, [x["ratio"] for x in rows],
                        [x["wall_ms"] * 1e-3 for x in rows], r_gc, tI)
     for x in rows:
@@ -342,15 +352,18 @@ def bench_hetero(fv, cases, tune_cache, steps=20, workers=16, viscous=False):
     out = dict(solver="navier-stokes" if viscous else "euler", cells=N, steps=steps,
                workers=workers, pure_gpu_ms=round(t_gpu * 1e3, 4),
                pure_gpu_ssspnt=round(1e-6 * N * 3 / t_gpu, 2),
-               host_core_tI_ns=round(tI * 1e9, 2), host_core_cell_updates_per_s=round(1 / tI, 1),
+               host_core_tI_ns=round(tI_core * 1e9, 2),
+               host_core_cell_updates_per_s=round(1 / tI_core, 1),
+               host_worker_tI_ns=round(tI * 1e9, 2), host_pool_fixed_ms=round(host_fixed * 1e3, 4),
                r_gc=round(r_gc, 1), kappa=round(fit.kappa, 3), fit_rms_rel=round(fit.rms_rel, 4),
                alpha_at_beta_0_2=round(fit.alpha(0.2), 2), alpha_at_beta_0_5=round(fit.alpha(0.5), 2),
                model_balance_ms=round(PM.time_ratio(Nl, Nw, 1, workers, r_gc, r_gc, tI, fit.kappa) * 1e3, 4),
                best=dict(ratio=best["ratio"], wall_ms=best["wall_ms"],
                          vs_pure_gpu=round(t_gpu * 1e3 / best["wall_ms"], 4)),
                sweep=rows)
-    log(f"[bench] hetero {out['solver']}: pure GPU {out['pure_gpu_ms']} ms/step, host core {1e-6 / tI:.2f} M "
-        f"cell-updates/s, r_gc {r_gc:.0f}; best ratio {best['ratio']} at {best['wall_ms']} ms/step "
+    log(f"[bench] hetero {out['solver']}: pure GPU {out['pure_gpu_ms']} ms/step, host core "
+        f"{1e-6 / tI_core:.2f} M cell-updates/s, worker t_I {tI * 1e9:.0f} ns, "
+        f"r_gc {r_gc:.0f}; best ratio {best['ratio']} at {best['wall_ms']} ms/step "
         f"({out['best']['vs_pure_gpu']}x pure GPU); kappa {fit.kappa:.2f} (fit rms {fit.rms_rel:.2f})")
     return out
 
