@@ -340,9 +340,8 @@ def bench_hetero(fv, cases, tune_cache, steps=20, workers=16, viscous=False):
     # part's time per step over its cells per worker (the intercept is the
     # pool's own per-step cost).  The model's C workers each take t_I per
     # cell, so the rate they reach together on this host is the one to use.
-    n_w = np.array([x["cpu_columns"] * Nw / workers for x in rows])
-    t_h = np.array([x["host_ms"] * 1e-3 for x in rows])
-    tI, host_fixed = (float(v) for v in np.polyfit(n_w, t_h, 1))
+    tI, host_fixed = PM.worker_tI([x["cpu_columns"] * Nw / workers for x in rows],
+                                  [x["host_ms"] * 1e-3 for x in rows])
     r_gc = N * tI / t_gpu
     fit = PM.fit_kappa(Nl, Nw, 1, workers, [x["ratio"] for x in rows],
                        [x["wall_ms"] * 1e-3 for x in rows], r_gc, tI)

@@ -29,7 +29,8 @@ takes its own time and the slower one sets the pace:
   n_c = N_l N_w / (G r + C)  (cells of one CPU worker),
 
 which is Eq. (beta) at r = r_gc.  This is the reading the measured ratio
-sweeps are compared with.
+sweeps are compared with; t_I there is the rate of one worker as the C
+workers run together (worker_tI), and r_gc the GPU's speed over it.
 """
 from __future__ import annotations
 
@@ -110,6 +111,17 @@ def fit_kappa(Nl, Nw, G, C, ratios: Sequence[float], times: Sequence[float], r_g
     pred = a + kappa * b
     rms = float(np.sqrt(np.mean(((pred - T) / T) ** 2)))
     return Fit(tI=tI, r_gc=r_gc, kappa=kappa, rms_rel=rms)
+
+
+def worker_tI(cells_per_worker: Sequence[float], host_times: Sequence[float]):
+    """t_I of one CPU worker as the C workers run together, and the pool's
+    fixed time per step: the least-squares line of the host part's time per
+    step over its cells per worker (slope, intercept).  The model gives each
+    of its C CPUs the rate t_I, so this is the rate it takes on a host whose
+    workers do not keep one core's speed when they run together."""
+    slope, icpt = np.polyfit(np.asarray(cells_per_worker, dtype=np.float64),
+                             np.asarray(host_times, dtype=np.float64), 1)
+    return float(slope), float(icpt)
 
 
 def best_ratio(Nl, Nw, G, C, r_gc, tI, kappa, ratios: Iterable[float]):

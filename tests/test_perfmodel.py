@@ -68,3 +68,17 @@ def test_fit_recovers_kappa():
     assert PM.best_ratio(Nl, Nw, G, C, r_gc, tI, kappa, rs) == rs[int(np.argmin(T))]
     # with no boundary cost the balance point wins
     assert PM.best_ratio(Nl, Nw, G, C, r_gc, tI, 0.0, rs + [r_gc]) == r_gc
+
+
+def test_worker_rate_and_fit_from_a_sweep():
+    """The bench's procedure on a sweep the model itself generates: the
+    workers' t_I is the slope of the host time over cells per worker (a
+    fixed pool cost is the intercept), and kappa comes back exactly."""
+    C, tI_w, r_gc, kappa, fixed = 16, 7.9e-7, 5900.0, 0.49, 8.6e-5
+    cols = [2, 4, 8, 16, 32, 64, 128]
+    tI, icpt = PM.worker_tI([c * Nw / C for c in cols], [c * Nw / C * tI_w + fixed for c in cols])
+    assert tI == pytest.approx(tI_w, rel=1e-12) and icpt == pytest.approx(fixed, rel=1e-9)
+    ratios = [(Nl - c) * C / c for c in cols]
+    T = [PM.time_ratio(Nl, Nw, 1, C, r, r_gc, tI_w, kappa) for r in ratios]
+    f = PM.fit_kappa(Nl, Nw, 1, C, ratios, T, r_gc, tI)
+    assert f.kappa == pytest.approx(kappa, rel=1e-9) and f.rms_rel < 1e-9
