@@ -551,8 +551,9 @@ int submit(fv_server* S, const fv_grid_desc* desc, const double* U0, const doubl
     return set_error(FV_E_UNSUPPORTED, "the viscous flux is provided for 2D grids only");
   }
   if (r->hg.with_source != (src != nullptr)) {
+    const bool reserved = r->hg.with_source;
     delete r;
-    return set_error(FV_E_INVAL, r->hg.with_source
+    return set_error(FV_E_INVAL, reserved
                                      ? "a grid with with_source = 1 is submitted with its source "
                                        "(fv_submit_with_source)"
                                      : "fv_submit_with_source needs a descriptor with with_source = 1");
