@@ -300,28 +300,39 @@ def bench_hetero(fv, cases, tune_cache, steps=20, workers=16, viscous=False):
     t_I is the rate of one worker among `workers` (the slope of the host
     part's time over its cells per worker), r_gc the pure GPU's speed over
     that, kappa = (1 + alpha) beta by least squares; alpha quoted for the
-    paper's beta range 0.2 .. 0.5."""
+    paper's beta range 0.2 .. 0.5.  With the Navier-Stokes solver also the
+    influence of the problem size (Sec. 8): the ratio sweep on a quarter
+    and on twice the cells."""
     from paper_2305_18057_amd import perfmodel as PM
-    c = cases.inlet_case(2048, 256, 1, name="inlet_2d_ns_1block" if viscous else "inlet_2d_1block")
-    if viscous:
-        for f in (2, 3):
-            c.blocks[0].bc[f] = cases.BC(cases.NOSLIP)
-        c.params = cases.Params(**{**c.params.__dict__, "mu": 1.5e-2, "prandtl": 0.72})
-    Nl, Nw, N = 2048, 256, c.ncells
-    p = cases.Params(**{**c.params.__dict__, "precision": cases.FP64})
-    gx, _, _, dx, _, _ = time_grid(fv, c, p, steps, 5, tune_cache, stage_times=False)
-    gx.close()
-    t_gpu = dx / steps * 1e-3
-    U0 = c.state_flat()
 
-    def run(split, nw, n=steps):
-        h = fv.Hetero(c, split, nw)
-        h.set_state(U0)
-        h.step(p, 3)
-        h.set_state(U0)
-        info = h.step(p, n)
-        h.close()
-        return [t / n * 1e-3 for t in info["times_ms"]]
+    def setup(Nl, Nw):
+        c = cases.inlet_case(Nl, Nw, 1, name=("inlet_2d_ns_1block" if viscous else "inlet_2d_1block"))
+        if viscous:
+            for f in (2, 3):
+                c.blocks[0].bc[f] = cases.BC(cases.NOSLIP)
+            c.params = cases.Params(**{**c.params.__dict__, "mu": 1.5e-2, "prandtl": 0.72})
+        p = cases.Params(**{**c.params.__dict__, "precision": cases.FP64})
+        gx, _, _, dx, _, _ = time_grid(fv, c, p, steps, 5, tune_cache, stage_times=False)
+        gx.close()
+        return c, p, dx / steps * 1e-3
+
+    def runner(c, p):
+        U0 = c.state_flat()
+
+        def run(split, nw, n=steps):
+            h = fv.Hetero(c, split, nw)
+            h.set_state(U0)
+            h.step(p, 3)
+            h.set_state(U0)
+            info = h.step(p, n)
+            h.close()
+            return [t / n * 1e-3 for t in info["times_ms"]]
+        return run
+
+    Nl, Nw = 2048, 256
+    c, p, t_gpu = setup(Nl, Nw)
+    N = c.ncells
+    run = runner(c, p)
 
     # one host core: its time per cell-step from the host part's substep time
     # of 16 columns (context; the model takes the workers' own rate, below)
@@ -360,6 +371,30 @@ def bench_hetero(fv, cases, tune_cache, steps=20, workers=16, viscous=False):
                best=dict(ratio=best["ratio"], wall_ms=best["wall_ms"],
                          vs_pure_gpu=round(t_gpu * 1e3 / best["wall_ms"], 4)),
                sweep=rows)
+    if viscous:
+        # the influence of the problem size: the same sweep on a quarter and
+        # on twice the cells (host columns scaled with N_l; finer along i
+        # only: refined across the no-slip walls, the impulsive Mach 4 start
+        # turns non-physical)
+        sizes = []
+        for sl, sw in ((1024, 128), (4096, 256)):
+            cs, ps, tg = setup(sl, sw)
+            rs = runner(cs, ps)
+            pts = []
+            for ncs in sorted({max(2, nc * sl // Nl) for nc in (2, 4, 8, 16, 32, 64, 128)}):
+                tm = rs(sl - ncs, workers)
+                pts.append(dict(cpu_columns=ncs, ratio=round((sl - ncs) * workers / ncs, 1),
+                                wall_ms=round(tm[3] * 1e3, 4),
+                                ssspnt=round(1e-6 * cs.ncells * 3 / tm[3], 2)))
+            b = min(pts, key=lambda x: x["wall_ms"])
+            sizes.append(dict(cells=cs.ncells, shape=[sl, sw], pure_gpu_ms=round(tg * 1e3, 4),
+                              pure_gpu_ssspnt=round(1e-6 * cs.ncells * 3 / tg, 2),
+                              best=dict(ratio=b["ratio"], wall_ms=b["wall_ms"],
+                                        vs_pure_gpu=round(tg * 1e3 / b["wall_ms"], 4)),
+                              sweep=pts))
+            log(f"[bench] hetero navier-stokes {sl} x {sw}: pure GPU {tg * 1e3:.4f} ms/step, best "
+                f"ratio {b['ratio']} at {b['wall_ms']} ms/step ({tg * 1e3 / b['wall_ms']:.3f}x)")
+        out["problem_sizes"] = sizes
     log(f"[bench] hetero {out['solver']}: pure GPU {out['pure_gpu_ms']} ms/step, host core "
         f"{1e-6 / tI_core:.2f} M cell-updates/s, worker t_I {tI * 1e9:.0f} ns, "
         f"r_gc {r_gc:.0f}; best ratio {best['ratio']} at {best['wall_ms']} ms/step "
