@@ -355,9 +355,9 @@ void host_stage(HostPart& H, Pool& pool, const StageCtx& X) {
   const int nj = H.nj, nc = H.nc, nw = pool.size();
   const int bin = X.bin;
   const bool visc = X.mu > 0.0;
-  // F_nu . S of the face between cells (iL, jL) and (iR, jR) whose nodes A,
-  // B have B - A turned by -90 degrees equal to S: node values are the mean
-  // of the four cells around the node
+  // F -= F_nu . S for the face between cells (iL, jL) and (iR, jR) whose
+  // nodes A, B have B - A turned by -90 degrees equal to S; a node's value
+  // is the mean of the four cells around it
   auto node_w = [&](int i, int j, double* o) {
     for (int k = 0; k < 3; ++k)
       o[k] = 0.25 * (((H.w(k, i - 1, j - 1) + H.w(k, i, j - 1)) + H.w(k, i - 1, j)) + H.w(k, i, j));
