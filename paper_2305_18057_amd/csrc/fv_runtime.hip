@@ -2,6 +2,8 @@
 // work-list construction, autotune table, parameter marshalling.
 #include "fv_runtime.h"
 
+#include <new>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -31,7 +33,7 @@ static void trans(const fv_block_desc& b, int d, int& n1, int& n2) {
   else { n1 = b.ni; n2 = b.nj; }
 }
 
-int validate_and_copy(const fv_grid_desc* d, HostGrid& g) {
+static int validate_and_copy_impl(const fv_grid_desc* d, HostGrid& g) {
   if (!d) return set_error(FV_E_INVAL, "null grid descriptor");
   if (d->ndim != 2 && d->ndim != 3) return set_error(FV_E_INVAL, "ndim must be 2 or 3 (got %d)", d->ndim);
   if (d->nblocks <= 0 || !d->blocks) return set_error(FV_E_INVAL, "no blocks");
@@ -140,6 +142,17 @@ int validate_and_copy(const fv_grid_desc* d, HostGrid& g) {
   g.state_size = g.ncells * g.nv;
   if (g.ndim == 3 && g.with_source) g.gen3 = true;
   return FV_OK;
+}
+
+// the host copies of a large grid can exhaust host memory: that is an error
+// return, never an exception through the C interface
+int validate_and_copy(const fv_grid_desc* d, HostGrid& g) {
+  try {
+    return validate_and_copy_impl(d, g);
+  } catch (const std::bad_alloc&) {
+    g = HostGrid();
+    return set_error(FV_E_NOMEM, "host allocation failed while copying the grid descriptor");
+  }
 }
 
 static const int kMinRows2D = 2, kMinPlanes3D = 4, kMinNy3D = 3;

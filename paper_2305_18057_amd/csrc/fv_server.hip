@@ -20,6 +20,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <new>
 #include <thread>
 #include <vector>
 
@@ -561,8 +562,6 @@ int submit(fv_server* S, const fv_grid_desc* desc, const double* U0, const doubl
   // 2D instances with a viscosity, a no-slip face or a source take the
   // Navier-Stokes kernel (the choice of the grid API)
   const bool ns = r->hg.ndim == 2 && (p->mu > 0.0 || r->hg.has_noslip || r->hg.with_source);
-  r->U0.assign(U0, U0 + r->hg.state_size);
-  if (src) r->src.assign(src, src + r->hg.state_size);
   r->params = *p;
   r->params.precision = S->d.precision;
   r->drop_tol = drop_tol;
@@ -574,12 +573,25 @@ int submit(fv_server* S, const fv_grid_desc* desc, const double* U0, const doubl
     sh = tsh;
   r->shape = sh;
   r->kind = kind_of(r->hg, sh, ns);
-  build_tiles(r->hg, sh, 0, 0, r->tiles);
+  try {
+    r->U0.assign(U0, U0 + r->hg.state_size);
+    if (src) r->src.assign(src, src + r->hg.state_size);
+    build_tiles(r->hg, sh, 0, 0, r->tiles);
+  } catch (const std::bad_alloc&) {
+    delete r;
+    return set_error(FV_E_NOMEM, "host allocation failed");
+  }
   region_layout(r);
-  if (r->footprint > S->heap_cap || (long long)r->tiles.size() > (long long)S->tile_cap) {
+  if (r->footprint > S->heap_cap) {
     const size_t need = r->footprint;
     delete r;
     return set_error(FV_E_NOMEM, "request needs %zu arena bytes, the arena holds %zu", need, S->heap_cap);
+  }
+  if ((long long)r->tiles.size() > (long long)S->tile_cap) {
+    const size_t need = r->tiles.size();
+    delete r;
+    return set_error(FV_E_NOMEM, "request needs %zu tiles, the server's tile list holds %zu", need,
+                     S->tile_cap);
   }
   std::lock_guard<std::mutex> lk(S->mu);
   if (S->stop) {

@@ -82,6 +82,7 @@ def test_oversize_request_rejected(fvb):
     with pytest.raises(fvb.FVError) as e:
         srv.submit(CS.inlet_case(2048, 1024, 4), max_steps=10)
     assert e.value.status == fvb.FV_E_NOMEM
+    assert "arena bytes" in str(e.value)
     srv.close()
 
 
