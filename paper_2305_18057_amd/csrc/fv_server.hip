@@ -518,9 +518,14 @@ extern "C" int fv_server_create(const fv_server_desc* d, fv_server** out) {
       return set_error(FV_E_DEVICE, "arena header initialisation failed");
     }
   }
-  S->h_inst.assign(S->max_inst, fvk::DevInstance{});
-  S->slot_req.assign(S->max_inst, nullptr);
-  S->worker = std::thread(worker_main, S);
+  try {
+    S->h_inst.assign(S->max_inst, fvk::DevInstance{});
+    S->slot_req.assign(S->max_inst, nullptr);
+    S->worker = std::thread(worker_main, S);
+  } catch (const std::exception&) {
+    delete S;
+    return set_error(FV_E_NOMEM, "the serving thread could not be started");
+  }
   *out = S;
   return FV_OK;
 }
