@@ -54,7 +54,8 @@ enum {
   FV_OK = 0,
   FV_PENDING = 1,          /* fv_poll: request not finished yet */
   FV_E_INVAL = -1,         /* bad argument or descriptor */
-  FV_E_NOMEM = -2,         /* workspace or arena too small */
+  FV_E_NOMEM = -2,         /* workspace, arena or tile list too small, or a host
+                              allocation (descriptor copy, serving thread) failed */
   FV_E_DEVICE = -3,        /* a HIP call failed */
   FV_E_NONPHYSICAL = -4,   /* rho <= 0, p <= 0 or a non-finite state value */
   FV_E_UNSUPPORTED = -5,   /* valid request this build does not provide */
@@ -384,7 +385,8 @@ int fv_server_create(const fv_server_desc* desc, fv_server** out);
  * oriented links); each kind of grid has its own tile list and stage kernel
  * in the batched launches.  A descriptor with with_source = 1 goes through
  * fv_submit_with_source (FV_E_INVAL here).  FV_E_NOMEM if the request can
- * never fit the arena; FV_E_UNSUPPORTED for rk other than 3 (resident
+ * never fit the arena or the server's tile list, or if its host copy
+ * fails; FV_E_UNSUPPORTED for rk other than 3 (resident
  * instances share one stage sequence) or a viscosity on a 3D grid. */
 int fv_submit(fv_server* s, const fv_grid_desc* desc, const double* U0, const fv_params* p,
               double drop_tol, long long max_steps, unsigned long long* ticket);
