@@ -332,22 +332,26 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
 
   // ---- prologue: planes k0-2 .. k0+1 of the own column (the right-edge
   //      i-face of each plane comes from the helper wave)
-  double qa[5], qm1[5], q0[5], qn[5], un[5] = {0, 0, 0, 0, 0};
+  // the k-window: planes k-1, k, k+1 and the incoming k+2 live in the four
+  // buffers qb0..qb3, the + side extrapolations of planes k-1 and k in eb0,
+  // eb1; the buffers' roles rotate (below), the values stay in place
+  double qa[5], qb0[5], qb1[5], qb2[5], qb3[5], un[5] = {0, 0, 0, 0, 0};
   const Src3 sa = src3_k(blocks, B, bin, ic, jc, k0 - 2);
   const Src3 sb = src3_k(blocks, B, bin, ic, jc, k0 - 1);
   const Src3 sd = src3_k(blocks, B, bin, ic, jc, k0 + 1);
   load3(sa.p, sa.vs, qa);
-  load3(sb.p, sb.vs, qm1);
-  col_load(Q, k0, q0);
-  load3(sd.p, sd.vs, qn);
+  load3(sb.p, sb.vs, qb0);
+  col_load(Q, k0, qb1);
+  load3(sd.p, sd.vs, qb2);
   fix3(sa.kind, sa.f, B, qa);
-  fix3(sb.kind, sb.f, B, qm1);
-  fix3(sd.kind, sd.f, B, qn);
-  T epm1[5];
+  fix3(sb.kind, sb.f, B, qb0);
+  fix3(sd.kind, sd.f, B, qb2);
+  T eb0[5], eb1[5];
 #pragma unroll
   for (int v = 0; v < 5; ++v) {
     T em;
-    extrap<LIM>(rc, T(qm1[v]) - T(qa[v]), T(q0[v]) - T(qm1[v]), epm1[v], em);
+    extrap<LIM>(rc, T(qb0[v]) - T(qa[v]), T(qb1[v]) - T(qb0[v]), eb0[v], em);
+    eb1[v] = T(0);
   }
   double rg[5] = {0, 0, 0, 0, 0};
   double nacc[5] = {0, 0, 0, 0, 0};
@@ -357,18 +361,23 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
   // plane k0 into buffer 0 (the helper stages its halo alongside)
   if (rowact && act) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) sm.q[0][qr][v][lane + 2] = T(q0[v]);
+    for (int v = 0; v < 5; ++v) sm.q[0][qr][v][lane + 2] = T(qb1[v]);
   }
   __syncthreads();
 
-  auto step = [&](auto first_t, auto last_t, int r) {
+  // one plane; qm1, q0, qn: planes k-1, k, k+1, q2 receives plane k+2;
+  // epm1 / ep0: + side extrapolations of planes k-1 / k (ep0 is written).
+  // ROT: end by moving the window down one buffer (qm1 <- q0 <- qn <- q2,
+  // epm1 <- ep0); without it the caller passes the next plane's roles.
+  auto step = [&](auto first_t, auto last_t, auto rot_t, int r, double (&qm1)[5], double (&q0)[5],
+                  double (&qn)[5], double (&q2)[5], T (&epm1)[5], T (&ep0)[5]) {
     constexpr bool FIRST = decltype(first_t)::value;
     constexpr bool LASTP = decltype(last_t)::value;
+    constexpr bool ROT = decltype(rot_t)::value;
     const int k = k0 + r;
     const int b = r & 1;
     T* const qrow = &sm.q[b][qr][0][0];
     // ---- (1) the plane k+2 of the own column
-    double q2[5];
     Src3 s2;
     if constexpr (!LASTP) {
       if (k + 2 < nk) {
@@ -381,7 +390,7 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
       }
     }
     // ---- (2) plane k is in LDS buffer b (staged one plane ahead)
-    T Gk[5] = {T(0), T(0), T(0), T(0), T(0)}, ep0[5] = {T(0), T(0), T(0), T(0), T(0)};
+    T Gk[5] = {T(0), T(0), T(0), T(0), T(0)};
     T Gi[5];
     // ---- (3) k-face at k-1/2, and (in-plane) j-face at j-1/2 and i-face at
     //      i-1/2 from LDS: independent, their arithmetic interleaves
@@ -491,23 +500,36 @@ __device__ void tile3d(const DevTile& tl, const DevBlock* __restrict__ blocks, D
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // ---- (6) rotate
+      // ---- (6) ghost correction of the incoming plane; rotate
       if (k + 2 >= nk) fix3(s2.kind, s2.f, B, q2);
+      if constexpr (ROT) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        qm1[v] = q0[v];
-        q0[v] = qn[v];
-        qn[v] = q2[v];
-        epm1[v] = ep0[v];
+        for (int v = 0; v < 5; ++v) {
+          qm1[v] = q0[v];
+          q0[v] = qn[v];
+          qn[v] = q2[v];
+          epm1[v] = ep0[v];
+        }
       }
     }
   };
 
   using F = std::integral_constant<bool, false>;
   using Tr = std::integral_constant<bool, true>;
-  step(Tr(), F(), 0);
-  for (int r = 1; r < n; ++r) step(F(), F(), r);
-  step(F(), Tr(), n);
+  step(Tr(), F(), Tr(), 0, qb0, qb1, qb2, qb3, eb0, eb1);
+  // four planes per pass with the roles renamed, so that the window needs no
+  // register moves; after four planes the roles are back where they started.
+  // The stage kinds with the time-step limit keep the moves: with the limit's
+  // registers the renamed pass would spill.
+  int r = 1;
+  for (; !SK::cfl && r + 4 <= n; r += 4) {
+    step(F(), F(), F(), r, qb0, qb1, qb2, qb3, eb0, eb1);
+    step(F(), F(), F(), r + 1, qb1, qb2, qb3, qb0, eb1, eb0);
+    step(F(), F(), F(), r + 2, qb2, qb3, qb0, qb1, eb0, eb1);
+    step(F(), F(), F(), r + 3, qb3, qb0, qb1, qb2, eb1, eb0);
+  }
+  for (; r < n; ++r) step(F(), F(), Tr(), r, qb0, qb1, qb2, qb3, eb0, eb1);
+  step(F(), Tr(), F(), n, qb0, qb1, qb2, qb3, eb0, eb1);
 
   // ---- per-tile partials of this row wave
   if (SK::norms || SK::cfl) {
